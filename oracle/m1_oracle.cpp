@@ -1,0 +1,906 @@
+// m1_oracle.cpp -- TEST INFRASTRUCTURE ONLY.
+//
+// Plain, slow, double-precision CPU implementation ("the oracle") of one explicit
+// transport + implicit interaction step of the multigroup two-moment (M1) radiation
+// equations in a static medium, following Skinner, Dolence, Burrows, Radice & Vartanyan,
+// "FORNAX: a Flexible Code for Multiphysics Astrophysical Simulations" (ApJS 2019).
+//
+// Only the tests, the smoke check and the CPU-baseline leg of the benchmark may load this
+// library.  It shares no code, header, table or helper with the GPU library, and the GPU
+// library never calls it.
+//
+// Parity with the original FORNAX code is unpinned: no FORNAX code or output exists to
+// compare with.  This oracle is pinned instead against closed forms, limits and invariants
+// (tests/test_oracle_*.py).  Where the paper leaves a detail open, the reading taken is
+// named in a comment starting with "Reading".
+//
+// Build: g++ -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math), so that every
+// operation rounds once, in source order.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+// ------------------------------------------------------------------------------------
+// Scalars: double, and a forward-mode dual number so that the same step code yields
+// exact Jacobian-vector products (used to check the GPU adjoint).
+// ------------------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+  Dual() : v(0.0), d(0.0) {}
+  Dual(double a) : v(a), d(0.0) {}
+  Dual(double a, double b) : v(a), d(b) {}
+};
+static inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+static inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+static inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+static inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+static inline Dual operator/(Dual a, Dual b) {
+  double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+static inline Dual sqrt(Dual a) {
+  double s = std::sqrt(a.v);
+  return Dual(s, a.d / (2.0 * s));
+}
+static inline double val(double a) { return a; }
+static inline double val(const Dual& a) { return a.v; }
+static inline double der(double) { return 0.0; }
+static inline double der(const Dual& a) { return a.d; }
+
+// ------------------------------------------------------------------------------------
+// Problem description (the oracle's own; not shared with the GPU library)
+// ------------------------------------------------------------------------------------
+enum { OC_CART = 0, OC_SPH_LOGR = 1 };
+enum { OB_OUTFLOW = 0, OB_PERIODIC = 1, OB_REFLECT = 2, OB_INFLOW = 3, OB_AXIS = 4 };
+enum { OL_MINMOD = 0, OL_MC = 1, OL_CONST = 2 };
+
+extern "C" {
+struct OrcDesc {
+  int32_t ndim;       // 1, 2 or 3 active directions
+  int32_t n[3];       // zones per direction (1 for inactive directions)
+  int32_t G;          // energy groups
+  int32_t coord;      // OC_CART, or OC_SPH_LOGR: x1 = ln r, x2 = theta, x3 = phi
+  double lo[3], hi[3];
+  int32_t bc_lo[3], bc_hi[3];
+  int32_t limiter;    // OL_MINMOD (default), OL_MC, OL_CONST (piecewise constant)
+  int32_t closure;    // 0 = M1 (Levermore), 1 = Eddington (P = E/3 I)
+  int32_t eps_mode;   // 0 = eq:epsilon as in the paper; 1 = epsilon forced to 1 (plain HLL)
+  double c;           // (reduced) speed of light
+  int32_t nthreads;   // OpenMP threads (0 = runtime default)
+};
+}
+
+static const int NG = 2;  // ghost layers required by linear reconstruction
+
+// Romberg integration of a smooth function on [a, b] (the paper precomputes the volume
+// averages of the coordinates and connection coefficients this way; Appendix, general
+// spherical metric).
+static double romberg(const std::function<double(double)>& f, double a, double b) {
+  if (a == b) return 0.0;
+  const int KMAX = 16;
+  double R[KMAX][KMAX];
+  double h = b - a;
+  R[0][0] = 0.5 * h * (f(a) + f(b));
+  for (int k = 1; k < KMAX; ++k) {
+    h *= 0.5;
+    double s = 0.0;
+    long m = 1L << (k - 1);
+    for (long i = 1; i <= m; ++i) s += f(a + (2 * i - 1) * h);
+    R[k][0] = 0.5 * R[k - 1][0] + h * s;
+    double p = 1.0;
+    for (int j = 1; j <= k; ++j) {
+      p *= 4.0;
+      R[k][j] = R[k][j - 1] + (R[k][j - 1] - R[k - 1][j - 1]) / (p - 1.0);
+    }
+    double diff = std::fabs(R[k][k] - R[k - 1][k - 1]);
+    if (k >= 4 && diff <= 1e-15 * std::fabs(R[k][k])) return R[k][k];
+  }
+  return R[KMAX - 1][KMAX - 1];
+}
+
+// ------------------------------------------------------------------------------------
+// Geometry (Numerical Discretization; Appendix: general spherical metric, connection
+// coefficients).  Both coordinate systems have a separable volume element
+// sqrt(g) = w_1(x1) w_2(x2) w_3(x3):
+//   Cartesian:            w = 1, h = 1, all connection coefficients vanish;
+//   spherical, x1 = ln r: r = e^{x1}, g_11 = g_22 = r^2, g_33 = r^2 sin^2(theta),
+//                         sqrt(g) = r^3 sin(theta)   (w_1 = e^{3 x1}, w_2 = |sin x2|, w_3 = 1).
+// Per-axis tables cover the extended zone range [-NG, n+NG) so that ghost zones have
+// geometry too (uniform continuation of the coordinate grid; |sin| for zones mirrored
+// across the polar axis).
+// ------------------------------------------------------------------------------------
+struct Geom {
+  OrcDesc D;
+  int n[3];
+  std::vector<double> xf[3];   // face coordinate x_{i-1/2}, i in [-NG, n+NG]   (index i+NG)
+  std::vector<double> xc[3];   // coordinate centre of zone i                   (index i+NG)
+  std::vector<double> W[3];    // integral of w_d over the zone
+  std::vector<double> X[3];    // volume centroid <x^d> of the zone
+  std::vector<double> wf[3];   // w_d at face i-1/2 (exactly 0 on a polar-axis boundary face)
+  std::vector<double> r2;      // <r^2> over the zone (axis 0), spherical only
+  std::vector<double> s2;      // <sin^2 theta> over the zone (axis 1), spherical only
+  // volume-averaged connection coefficients that depend on theta (axis 1):
+  std::vector<double> G323;    // <Gamma^3_23> = <cot theta>
+  std::vector<double> G133;    // <Gamma^1_33>  (after the angular-momentum override)
+  std::vector<double> G233;    // <Gamma^2_33>  (after the angular-momentum override)
+  std::vector<double> G222;    // <Gamma^2_22>  (after the d_2 P = 0 balance override)
+
+  bool sph() const { return D.coord == OC_SPH_LOGR; }
+
+  double w(int d, double x) const {
+    if (!sph()) return 1.0;
+    if (d == 0) return std::exp(3.0 * x);
+    if (d == 1) return std::fabs(std::sin(x));
+    return 1.0;
+  }
+
+  void build(const OrcDesc& desc) {
+    D = desc;
+    for (int d = 0; d < 3; ++d) n[d] = desc.n[d];
+    for (int d = 0; d < 3; ++d) {
+      int m = n[d] + 2 * NG;
+      double dx = (D.hi[d] - D.lo[d]) / n[d];
+      xf[d].assign(m + 1, 0.0);
+      xc[d].assign(m, 0.0);
+      W[d].assign(m, 0.0);
+      X[d].assign(m, 0.0);
+      wf[d].assign(m + 1, 0.0);
+      for (int e = 0; e <= m; ++e) xf[d][e] = D.lo[d] + (e - NG) * dx;
+      for (int e = 0; e < m; ++e) {
+        double a = xf[d][e], b = xf[d][e + 1];
+        xc[d][e] = 0.5 * (a + b);
+        auto wd = [&](double x) { return w(d, x); };
+        W[d][e] = romberg(wd, a, b);
+        X[d][e] = romberg([&](double x) { return x * w(d, x); }, a, b) / W[d][e];
+      }
+      for (int e = 0; e <= m; ++e) wf[d][e] = w(d, xf[d][e]);
+      // Reading: a face on the polar axis has zero area (sin theta = 0 there); the
+      // floating-point sin(pi) is not exactly 0, so the axis faces are set to 0 exactly.
+      if (sph() && d == 1) {
+        if (D.bc_lo[1] == OB_AXIS) wf[1][NG] = 0.0;
+        if (D.bc_hi[1] == OB_AXIS) wf[1][NG + n[1]] = 0.0;
+      }
+    }
+    if (sph()) {
+      int m0 = n[0] + 2 * NG, m1 = n[1] + 2 * NG;
+      r2.assign(m0, 0.0);
+      for (int e = 0; e < m0; ++e)
+        r2[e] = romberg([&](double x) { return std::exp(2.0 * x) * w(0, x); }, xf[0][e], xf[0][e + 1]) / W[0][e];
+      s2.assign(m1, 0.0);
+      G323.assign(m1, 0.0);
+      G133.assign(m1, 0.0);
+      G233.assign(m1, 0.0);
+      G222.assign(m1, 0.0);
+      for (int e = 0; e < m1; ++e) {
+        double a = xf[1][e], b = xf[1][e + 1];
+        double Wt = W[1][e];
+        s2[e] = romberg([&](double x) { double s = std::sin(x); return s * s * w(1, x); }, a, b) / Wt;
+        if (e < NG || e >= NG + n[1]) continue;  // connection coefficients: active zones only
+        // <Gamma^3_23> = <d_2 ln h_3> = <cot theta>; integrand cot(theta) sin(theta), theta in [0, pi]
+        G323[e] = romberg([&](double x) { return std::cos(x); }, a, b) / Wt;
+        // Angular-momentum override (eq:angmom and the two settings that follow it):
+        // <Gamma^1_33> = -<g33>/<g11> <Gamma^3_13>, <Gamma^2_33> = -<g33>/<g22> <Gamma^3_23>,
+        // with <Gamma^3_13> = <d_1 ln h_3> = 1 and <g33>/<g11> = <g33>/<g22> = <sin^2 theta>.
+        double G313 = 1.0;
+        G133[e] = -s2[e] * G313;
+        G233[e] = -s2[e] * G323[e];
+        // Balance override (eq:grad2P): <Gamma^2_22> = Delta A_2 / Delta V - <Gamma^3_32>,
+        // A_2 = int sqrt(g) dx1 dx3, so Delta A_2 / Delta V = Delta(w_2) / W_2.
+        double wa = std::fabs(std::sin(a)), wb = std::fabs(std::sin(b));
+        if (D.bc_lo[1] == OB_AXIS && e == NG) wa = 0.0;
+        if (D.bc_hi[1] == OB_AXIS && e == NG + n[1] - 1) wb = 0.0;
+        G222[e] = (wb - wa) / Wt - G323[e];
+      }
+    }
+  }
+
+  // scale factors h_k at a point (x1, x2)
+  void h_point(double x1, double x2, double h[3]) const {
+    if (!sph()) { h[0] = h[1] = h[2] = 1.0; return; }
+    double r = std::exp(x1);
+    h[0] = r;
+    h[1] = r;
+    h[2] = r * std::fabs(std::sin(x2));
+  }
+  // cell-centred scale factors h_k = sqrt(<g_kk>) of zone (i, j) (extended indices allowed)
+  void h_cell(int i, int j, double h[3]) const {
+    if (!sph()) { h[0] = h[1] = h[2] = 1.0; return; }
+    double rr = std::sqrt(r2[i + NG]);
+    h[0] = rr;
+    h[1] = rr;
+    h[2] = rr * std::sqrt(s2[j + NG]);
+  }
+  double volume(int i, int j, int k) const { return W[0][i + NG] * W[1][j + NG] * W[2][k + NG]; }
+  // coordinate area int sqrt(g) d^2x of the d-face at index f along d (face f-1/2),
+  // the other two indices being zone indices
+  double area(int d, const int idx[3]) const {
+    double a = 1.0;
+    for (int e = 0; e < 3; ++e) a *= (e == d) ? wf[e][idx[e] + NG] : W[e][idx[e] + NG];
+    return a;
+  }
+  // proper length of zone idx across direction d: h_d (cell-centred) * Delta x^d
+  double dlen(int d, const int idx[3]) const {
+    double h[3];
+    h_cell(idx[0], idx[1], h);
+    return h[d] * (xf[d][idx[d] + NG + 1] - xf[d][idx[d] + NG]);
+  }
+  // volume-averaged connection coefficients <Gamma^l_{k m}> of active zone (i, j),
+  // indices 0-based (l, k, m in 0..2).  Spherical (x1 = ln r) values from eq:Gamma:
+  //   Gamma^1_11 = d_1 ln h_1 = 1, Gamma^2_12 = d_1 ln h_2 = 1, Gamma^3_13 = d_1 ln h_3 = 1,
+  //   Gamma^3_23 = d_2 ln h_3 = cot theta, Gamma^1_22 = -g_22,1/(2 g_11) = -1,
+  //   Gamma^1_33 = -g_33,1/(2 g_11) = -sin^2 theta, Gamma^2_33 = -g_33,2/(2 g_22) = -sin cos,
+  //   Gamma^2_22 = d_2 ln h_2 = 0; symmetric in the lower pair; the rest vanish.
+  // theta-dependent ones come from the tables above (with the paper's overrides).
+  void gamma(int i, int j, double Gm[3][3][3]) const {
+    (void)i;
+    std::memset(Gm, 0, sizeof(double) * 27);
+    if (!sph()) return;
+    int e = j + NG;
+    Gm[0][0][0] = 1.0;                                  // Gamma^1_11
+    Gm[1][0][1] = Gm[1][1][0] = 1.0;                    // Gamma^2_12
+    Gm[2][0][2] = Gm[2][2][0] = 1.0;                    // Gamma^3_13
+    Gm[2][1][2] = Gm[2][2][1] = G323[e];                // Gamma^3_23
+    Gm[0][1][1] = -1.0;                                 // Gamma^1_22
+    Gm[0][2][2] = G133[e];                              // Gamma^1_33
+    Gm[1][2][2] = G233[e];                              // Gamma^2_33
+    Gm[1][1][1] = G222[e];                              // Gamma^2_22
+  }
+};
+
+// ------------------------------------------------------------------------------------
+// One step
+// ------------------------------------------------------------------------------------
+template <class T>
+struct Ctx {
+  const OrcDesc* D;
+  const Geom* geo;
+  int n[3], G, ndim;
+  double c, dt;
+  const T* E;
+  const T* F[3];
+  const T* kap;
+  const double* sig;
+  const double* B;
+  const double* inflow;  // [G][1+ndim]: E and physical flux components of the inflow ghosts
+  size_t zone(const int m[3]) const { return ((size_t)m[2] * n[1] + m[1]) * n[0] + m[0]; }
+};
+
+// State (E, F_1, F_2, F_3) and total opacity of a zone, one index of which may lie in the
+// ghost range along one direction.  Ghost rules: Boundary Conditions subsection (periodic
+// map, polar-axis copy with a shift of N_phi/2 and sign flips of the theta and phi vector
+// components, outflow, Dirichlet inflow).
+// Reading: outflow copies the edge zone (zero gradient) for E and every F component;
+// reflecting mirrors the zone and flips the normal flux; an inflow ghost holds the
+// prescribed E and physical flux (covariant F_k = h_k F^_k with the ghost's own h), and its
+// opacity is the edge zone's.
+template <class T>
+static void zone_state(const Ctx<T>& C, const int idx[3], int g, T q[4], T* ks) {
+  int m[3] = {idx[0], idx[1], idx[2]};
+  double sg[4] = {1.0, 1.0, 1.0, 1.0};
+  int inflow_dir = -1;
+  for (int d = 0; d < 3; ++d) {
+    int nd = C.n[d];
+    if (m[d] >= 0 && m[d] < nd) continue;
+    bool low = m[d] < 0;
+    int bc = low ? C.D->bc_lo[d] : C.D->bc_hi[d];
+    switch (bc) {
+      case OB_PERIODIC:
+        m[d] = ((m[d] % nd) + nd) % nd;
+        break;
+      case OB_OUTFLOW:
+        m[d] = low ? 0 : nd - 1;
+        break;
+      case OB_REFLECT:
+        m[d] = low ? -1 - m[d] : 2 * nd - 1 - m[d];
+        sg[1 + d] = -1.0;
+        break;
+      case OB_INFLOW:
+        inflow_dir = d;
+        m[d] = low ? 0 : nd - 1;
+        break;
+      case OB_AXIS:
+        m[d] = low ? -1 - m[d] : 2 * nd - 1 - m[d];
+        m[2] = (m[2] + C.n[2] / 2) % C.n[2];
+        sg[2] = -1.0;
+        sg[3] = -1.0;
+        break;
+    }
+  }
+  size_t z = C.zone(m);
+  size_t zg = z * C.G + g;
+  if (ks) *ks = C.kap[zg] + C.sig[zg];
+  if (inflow_dir >= 0) {
+    double h[3];
+    C.geo->h_cell(idx[0], idx[1], h);
+    const double* in = C.inflow + (size_t)g * (1 + C.ndim);
+    q[0] = T(in[0]);
+    for (int k = 0; k < 3; ++k) q[1 + k] = T(k < C.ndim ? h[k] * in[1 + k] : 0.0);
+    return;
+  }
+  q[0] = C.E[zg];
+  for (int k = 0; k < 3; ++k) q[1 + k] = (k < C.ndim) ? T(sg[1 + k]) * C.F[k][zg] : T(0.0);
+}
+
+// scale factors at the centre of the d-face at face index f (face f-1/2 along d) of the
+// zone row given by idx (other indices = that zone's)
+template <class T>
+static void face_h(const Ctx<T>& C, int d, const int idx[3], int f, double h[3]) {
+  const Geom& G = *C.geo;
+  double x1 = (d == 0) ? G.xf[0][f + NG] : G.xc[0][idx[0] + NG];
+  double x2 = (d == 1) ? G.xf[1][f + NG] : G.xc[1][idx[1] + NG];
+  G.h_point(x1, x2, h);
+}
+
+template <class T>
+static T minmod2(T a, T b) {
+  if (val(a) * val(b) <= 0.0) return T(0.0);
+  return (std::fabs(val(a)) <= std::fabs(val(b))) ? a : b;
+}
+template <class T>
+static T minmod3(T a, T b, T cc) { return minmod2(a, minmod2(b, cc)); }
+
+// Reading (the paper does not discuss non-realizable face states): a face state is
+// realizable when E > 0 and |F^| <= c E, with physical components F^_k = F_k / h_k at the
+// face centre.  Faces of zero area (the polar axis) carry no flux and are not checked.
+template <class T>
+static bool realizable(const Ctx<T>& C, const T q[4], const double h[3]) {
+  if (!(val(q[0]) > 0.0)) return false;
+  double f2 = 0.0;
+  for (int k = 0; k < C.ndim; ++k) {
+    double fk = val(q[1 + k]) / h[k];
+    f2 += fk * fk;
+  }
+  double cE = C.c * val(q[0]);
+  return f2 <= cE * cE;
+}
+
+// Linear reconstruction along d in the volume coordinate (Reconstruction subsection,
+// eq:recon_constraints with n = 1; the paper reconstructs radiation with linear profiles):
+// p(x) = q_i + s (x - <x>_i) has the zone's volume average, and the slope s is the minmod
+// of the one-sided differences taken between volume centroids.  Face states are
+// p(x_{i-1/2}) and p(x_{i+1/2}).
+// Reading (non-realizable face states): if either face state of the zone fails the
+// realizability test, the zone falls back to piecewise-constant in direction d.
+template <class T>
+static void reconstruct(const Ctx<T>& C, int d, const int idx[3], int g, T lo[4], T hi[4]) {
+  const Geom& G = *C.geo;
+  int im[3] = {idx[0], idx[1], idx[2]}, ip[3] = {idx[0], idx[1], idx[2]};
+  im[d] -= 1;
+  ip[d] += 1;
+  T qm[4], q0[4], qp[4];
+  zone_state(C, im, g, qm, (T*)nullptr);
+  zone_state(C, idx, g, q0, (T*)nullptr);
+  zone_state(C, ip, g, qp, (T*)nullptr);
+  double Xm = G.X[d][im[d] + NG], X0 = G.X[d][idx[d] + NG], Xp = G.X[d][ip[d] + NG];
+  double xlo = G.xf[d][idx[d] + NG], xhi = G.xf[d][idx[d] + NG + 1];
+  for (int cpt = 0; cpt < 4; ++cpt) {
+    T s = T(0.0);
+    if (cpt <= C.ndim) {
+      if (C.D->limiter == OL_MINMOD) {
+        T a = (q0[cpt] - qm[cpt]) / T(X0 - Xm);
+        T b = (qp[cpt] - q0[cpt]) / T(Xp - X0);
+        s = minmod2(a, b);
+      } else if (C.D->limiter == OL_MC) {
+        T a = (q0[cpt] - qm[cpt]) / T(X0 - Xm);
+        T b = (qp[cpt] - q0[cpt]) / T(Xp - X0);
+        T ce = (qp[cpt] - qm[cpt]) / T(Xp - Xm);
+        s = minmod3(T(2.0) * a, T(2.0) * b, ce);
+      }
+    }
+    lo[cpt] = q0[cpt] + s * T(xlo - X0);
+    hi[cpt] = q0[cpt] + s * T(xhi - X0);
+  }
+  double hlo[3], hhi[3];
+  face_h(C, d, idx, idx[d], hlo);
+  face_h(C, d, idx, idx[d] + 1, hhi);
+  int flo[3] = {idx[0], idx[1], idx[2]}, fhi[3] = {idx[0], idx[1], idx[2]};
+  fhi[d] += 1;
+  bool ok_lo = (G.area(d, flo) == 0.0) || realizable(C, lo, hlo);
+  bool ok_hi = (G.area(d, fhi) == 0.0) || realizable(C, hi, hhi);
+  if (!(ok_lo && ok_hi)) {
+    for (int cpt = 0; cpt < 4; ++cpt) lo[cpt] = hi[cpt] = q0[cpt];
+  }
+}
+
+// M1 closure (Formulation: radiation; the paper uses the M1 tensor closure of Dubroca &
+// Feugeas / Levermore).  With f = |F^|/(cE) and unit direction n,
+//   P^ = E [ (1 - chi)/2 I + (3 chi - 1)/2 n n ],  chi(f) = (3 + 4 f^2) / (5 + 2 sqrt(4 - 3 f^2)),
+// which tends to the Eddington closure P^ = E/3 I as f -> 0 (Interaction Terms subsection).
+// Reading: f^2 is clamped to 1; for E <= 0 the Eddington value is used.
+// Returns the full 3x3 physical-component tensor P^.
+template <class T>
+static void closure(const Ctx<T>& C, const T q[4], const double h[3], T P[3][3]) {
+  T E = q[0];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) P[a][b] = T(0.0);
+  if (C.D->closure == 1 || !(val(E) > 0.0)) {
+    for (int a = 0; a < 3; ++a) P[a][a] = E / T(3.0);
+    return;
+  }
+  T Fh[3];
+  for (int k = 0; k < 3; ++k) Fh[k] = q[1 + k] / T(h[k] != 0.0 ? h[k] : 1.0);
+  T F2 = Fh[0] * Fh[0] + Fh[1] * Fh[1] + Fh[2] * Fh[2];
+  T cE = T(C.c) * E;
+  T f2 = F2 / (cE * cE);
+  if (val(f2) > 1.0) f2 = T(1.0);
+  T chi = (T(3.0) + T(4.0) * f2) / (T(5.0) + T(2.0) * sqrt(T(4.0) - T(3.0) * f2));
+  T iso = (T(1.0) - chi) / T(2.0);
+  T ani = (T(3.0) * chi - T(1.0)) / T(2.0);
+  for (int a = 0; a < 3; ++a) P[a][a] = E * iso;
+  if (val(F2) > 0.0) {
+    T Fm = sqrt(F2);
+    T nn[3] = {Fh[0] / Fm, Fh[1] / Fm, Fh[2] / Fm};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) P[a][b] = P[a][b] + E * ani * nn[a] * nn[b];
+  }
+}
+
+// Numerical flux across the d-face at face index f (between zones f-1 and f along d) of
+// the row idx.  Riemann Solvers subsection: HLL fluxes for the radiation subsystem, the
+// energy flux corrected as in eq:hll with epsilon = min(1, 1/tau_cell) (eq:epsilon).
+// Written in coordinate components, as in the finite-volume form eq:finite_vol:
+//   E   : flux F^d = F^_d / h_d,
+//   F_k : flux c^2 P^d_k = c^2 P^^{dk} h_k / h_d      (mixed components of the pressure).
+// Reading (wavespeeds, not given in the paper): S_R = +c, S_L = -c physical, i.e. +-c/h_d
+// in the coordinate x^d.  Reading (tau_cell): arithmetic mean of (kappa + sigma) of the two
+// zones times the mean proper zone width h_d Delta x^d of the two.  Reading: epsilon enters
+// the energy flux only ("a correction to the energy fluxes").
+// A face of zero area returns a zero flux.
+
+template <class T>
+static void face_flux(const Ctx<T>& C, int d, const int row[3], int f, int g, T flux[4]) {
+  const Geom& G = *C.geo;
+  for (int k = 0; k < 4; ++k) flux[k] = T(0.0);
+  int fi[3] = {row[0], row[1], row[2]};
+  fi[d] = f;
+  if (G.area(d, fi) == 0.0) return;
+  int ia[3] = {row[0], row[1], row[2]}, ib[3] = {row[0], row[1], row[2]};
+  ia[d] = f - 1;
+  ib[d] = f;
+  T alo[4], ahi[4], blo[4], bhi[4];
+  reconstruct(C, d, ia, g, alo, ahi);
+  reconstruct(C, d, ib, g, blo, bhi);
+  const T* qL = ahi;  // left state: upper face of zone f-1
+  const T* qR = blo;  // right state: lower face of zone f
+  double h[3];
+  face_h(C, d, fi, f, h);
+  T PL[3][3], PR[3][3];
+  closure(C, qL, h, PL);
+  closure(C, qR, h, PR);
+  // wavespeeds in the coordinate x^d
+  double SR = C.c / h[d], SL = -C.c / h[d];
+  // epsilon (eq:epsilon)
+  T ksa, ksb, tmp[4];
+  zone_state(C, ia, g, tmp, &ksa);
+  zone_state(C, ib, g, tmp, &ksb);
+  double dl = 0.5 * (G.dlen(d, ia) + G.dlen(d, ib));
+  T tau = T(0.5) * (ksa + ksb) * T(dl);
+  T eps = T(1.0);
+  if (C.D->eps_mode == 0 && val(tau) > 1.0) eps = T(1.0) / tau;
+  // energy: F^d_{L,R} = F^_d / h_d = F_d / h_d^2 (coordinate contravariant component)
+  T FdL = qL[1 + d] / T(h[d] * h[d]);
+  T FdR = qR[1 + d] / T(h[d] * h[d]);
+  flux[0] = (T(SR) * FdL - T(SL) * FdR + eps * T(SR * SL) * (qR[0] - qL[0])) / T(SR - SL);
+  // flux components: conserved F_k, flux c^2 P^d_k, plain HLL
+  for (int k = 0; k < C.ndim; ++k) {
+    double hk = h[k] != 0.0 ? h[k] : 1.0;
+    T PdkL = T(C.c * C.c) * PL[d][k] * T(hk / h[d]);
+    T PdkR = T(C.c * C.c) * PR[d][k] * T(hk / h[d]);
+    flux[1 + k] = (T(SR) * PdkL - T(SL) * PdkR + T(SR * SL) * (qR[1 + k] - qL[1 + k])) / T(SR - SL);
+  }
+}
+
+// Explicit update of one zone-group (Algorithmic Steps, step 1, radiation rows, v = 0):
+// dU/dt = -(1/V) sum_d [A_d F^d]_{i-1/2}^{i+1/2} (eq:finite_vol) plus, for the covariant
+// flux components, the volume-averaged geometric source c^2 <Gamma^l_{km}> P^m_l(<U>)
+// (Numerical Discretization; covariant form of the momentum equation).  Forward Euler push.
+template <class T>
+static void explicit_update(const Ctx<T>& C, const int idx[3], int g, T Um[4]) {
+  const Geom& G = *C.geo;
+  T q[4];
+  zone_state(C, idx, g, q, (T*)nullptr);
+  double V = G.volume(idx[0], idx[1], idx[2]);
+  T div[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
+  for (int d = 0; d < C.ndim; ++d) {
+    T flo[4], fhi[4];
+    face_flux(C, d, idx, idx[d], g, flo);
+    face_flux(C, d, idx, idx[d] + 1, g, fhi);
+    int ilo[3] = {idx[0], idx[1], idx[2]}, ihi[3] = {idx[0], idx[1], idx[2]};
+    ihi[d] += 1;
+    double Alo = G.area(d, ilo), Ahi = G.area(d, ihi);
+    for (int k = 0; k <= C.ndim; ++k) div[k] = div[k] + (T(Ahi) * fhi[k] - T(Alo) * flo[k]);
+  }
+  for (int k = 0; k <= C.ndim; ++k) Um[k] = q[k] - T(C.dt) * div[k] / T(V);
+  for (int k = C.ndim + 1; k < 4; ++k) Um[k] = T(0.0);
+  if (G.sph()) {
+    // geometric source c^2 sum_{l,m} <Gamma^l_{km}> P^m_l, P^m_l = P^^{ml} h_l / h_m,
+    // cell-centred h_k = sqrt(<g_kk>)
+    double h[3], Gm[3][3][3];
+    G.h_cell(idx[0], idx[1], h);
+    G.gamma(idx[0], idx[1], Gm);
+    T P[3][3];
+    closure(C, q, h, P);
+    for (int k = 0; k < C.ndim; ++k) {
+      T s = T(0.0);
+      for (int l = 0; l < 3; ++l)
+        for (int m = 0; m < 3; ++m)
+          if (Gm[l][k][m] != 0.0) s = s + T(Gm[l][k][m]) * P[m][l] * T(h[l] / h[m]);
+      Um[1 + k] = Um[1 + k] + T(C.dt) * T(C.c * C.c) * s;
+    }
+  }
+}
+
+// Implicit interaction update (Interaction Terms subsection): backward Euler for each group,
+// eq:be_update with a prescribed emissivity j = c kappa B (Reading: the emission is given as
+// a group-integrated source function B, Kirchhoff's law, so that E -> B in the thick limit),
+// and the flux update F^{n+1} = F^- / (1 + c dt (kappa + sigma)).
+template <class T>
+static void implicit_source(T E_m, const T F_m[3], T kap, double sig, double B, double c, double dt, int ndim,
+                            T& E1, T F1[3]) {
+  T j = T(c) * kap * T(B);
+  E1 = (E_m + T(dt) * j) / (T(1.0) + T(c * dt) * kap);
+  for (int k = 0; k < 3; ++k)
+    F1[k] = (k < ndim) ? F_m[k] / (T(1.0) + T(c * dt) * (kap + T(sig))) : T(0.0);
+}
+
+template <class T>
+static void zone_step(const Ctx<T>& C, const int idx[3], int g, T Un1[4], T* Em_out) {
+  T Um[4];
+  explicit_update(C, idx, g, Um);
+  size_t zg = C.zone(idx) * C.G + g;
+  T Fm[3] = {Um[1], Um[2], Um[3]}, F1[3];
+  T E1;
+  implicit_source(Um[0], Fm, C.kap[zg], C.sig[zg], C.B[zg], C.c, C.dt, C.ndim, E1, F1);
+  Un1[0] = E1;
+  for (int k = 0; k < 3; ++k) Un1[1 + k] = F1[k];
+  if (Em_out) *Em_out = Um[0];
+}
+
+static void set_threads(const OrcDesc* D) {
+#ifdef _OPENMP
+  if (D->nthreads > 0) omp_set_num_threads(D->nthreads);
+#else
+  (void)D;
+#endif
+}
+
+// diagnostics record (oracle's own layout)
+extern "C" {
+struct OrcDiag {
+  double energy_total;     // sum_i V_i sum_g E_g^{n+1}
+  double max_f;            // max |F^|/(cE) over zone-groups with E > 0 (cell-centred h)
+  int64_t n_unrealizable;  // #(|F^| > cE (1 + 8u)), u = 2^-53
+  int64_t n_nonpositive;   // #(E <= 0)
+};
+}
+
+// One full step on every zone.  E, F[k], kappa, sigma, B: [n2][n1][n0][G] (G innermost).
+template <class T>
+static void full_step(const OrcDesc* D, const Geom& geo, const T* E, const T* const* F, const T* kap, const double* sig,
+                      const double* B, const double* inflow, double dt, T* Eo, T* const* Fo, double* dEm,
+                      OrcDiag* diag) {
+  Ctx<T> C;
+  C.D = D;
+  C.geo = &geo;
+  for (int d = 0; d < 3; ++d) C.n[d] = D->n[d];
+  C.G = D->G;
+  C.ndim = D->ndim;
+  C.c = D->c;
+  C.dt = dt;
+  C.E = E;
+  for (int k = 0; k < 3; ++k) C.F[k] = (k < D->ndim) ? F[k] : nullptr;
+  C.kap = kap;
+  C.sig = sig;
+  C.B = B;
+  C.inflow = inflow;
+  long nz = (long)C.n[0] * C.n[1] * C.n[2];
+  std::vector<double> Em_all(nz * C.G);
+  set_threads(D);
+#pragma omp parallel for schedule(static)
+  for (long z = 0; z < nz; ++z) {
+    int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
+    for (int g = 0; g < C.G; ++g) {
+      T U1[4], Em;
+      zone_step(C, idx, g, U1, &Em);
+      size_t zg = (size_t)z * C.G + g;
+      Eo[zg] = U1[0];
+      for (int k = 0; k < D->ndim; ++k) Fo[k][zg] = U1[1 + k];
+      Em_all[zg] = val(Em);
+    }
+  }
+  // diagnostics, summed serially in zone-major then group order
+  if (diag || dEm) {
+    double etot = 0.0, maxf = 0.0;
+    int64_t nun = 0, nnp = 0;
+    const double u = std::ldexp(1.0, -53);
+    for (long z = 0; z < nz; ++z) {
+      int i = (int)(z % C.n[0]), j = (int)((z / C.n[0]) % C.n[1]), k = (int)(z / ((long)C.n[0] * C.n[1]));
+      double V = geo.volume(i, j, k);
+      double h[3];
+      geo.h_cell(i, j, h);
+      double esum = 0.0, dsum = 0.0;
+      for (int g = 0; g < C.G; ++g) {
+        size_t zg = (size_t)z * C.G + g;
+        double e = val(Eo[zg]);
+        esum += e;
+        dsum += e - Em_all[zg];
+        double F2 = 0.0;
+        for (int kk = 0; kk < D->ndim; ++kk) {
+          double fk = val(Fo[kk][zg]) / h[kk];
+          F2 += fk * fk;
+        }
+        double Fm = std::sqrt(F2);
+        if (e > 0.0) maxf = std::max(maxf, Fm / (C.c * e));
+        if (!(e > 0.0)) nnp++;
+        if (Fm > C.c * e * (1.0 + 8.0 * u)) nun++;
+      }
+      etot += V * esum;
+      if (dEm) dEm[z] = -dsum;
+    }
+    if (diag) {
+      diag->energy_total = etot;
+      diag->max_f = maxf;
+      diag->n_unrealizable = nun;
+      diag->n_nonpositive = nnp;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// C API used by the tests (through ctypes)
+// ------------------------------------------------------------------------------------
+extern "C" {
+
+// Largest stable time step for a given CFL number.
+// Reading (the paper only says the light-crossing time of a zone sets the step):
+//   dt = cfl / max_i sum_d c / (h_d Delta x^d)_i  over active zones.
+double orc_max_dt(const OrcDesc* D, double cfl) {
+  Geom geo;
+  geo.build(*D);
+  double worst = 0.0;
+  for (int k = 0; k < D->n[2]; ++k)
+    for (int j = 0; j < D->n[1]; ++j)
+      for (int i = 0; i < D->n[0]; ++i) {
+        int idx[3] = {i, j, k};
+        double s = 0.0;
+        for (int d = 0; d < D->ndim; ++d) s += D->c / geo.dlen(d, idx);
+        worst = std::max(worst, s);
+      }
+  return cfl / worst;
+}
+
+// nsteps full steps.  F and Fo are arrays of ndim pointers.  dEm (per zone, nullable) and
+// diag (nullable) describe the last step.
+int orc_run(const OrcDesc* D, const double* E, const double* const* F, const double* kap, const double* sig,
+            const double* B, const double* inflow, double dt, int nsteps, double* Eo, double* const* Fo, double* dEm,
+            OrcDiag* diag) {
+  Geom geo;
+  geo.build(*D);
+  size_t nzg = (size_t)D->n[0] * D->n[1] * D->n[2] * D->G;
+  std::vector<double> Ea(E, E + nzg), Eb(nzg);
+  std::vector<std::vector<double>> Fa(3), Fb(3);
+  for (int k = 0; k < D->ndim; ++k) {
+    Fa[k].assign(F[k], F[k] + nzg);
+    Fb[k].assign(nzg, 0.0);
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    const double* Fin[3] = {nullptr, nullptr, nullptr};
+    double* Fout[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < D->ndim; ++k) {
+      Fin[k] = Fa[k].data();
+      Fout[k] = Fb[k].data();
+    }
+    bool last = (s == nsteps - 1);
+    full_step<double>(D, geo, Ea.data(), Fin, kap, sig, B, inflow, dt, Eb.data(), Fout, last ? dEm : nullptr,
+                      last ? diag : nullptr);
+    std::swap(Ea, Eb);
+    for (int k = 0; k < D->ndim; ++k) std::swap(Fa[k], Fb[k]);
+  }
+  std::memcpy(Eo, Ea.data(), nzg * sizeof(double));
+  for (int k = 0; k < D->ndim; ++k) std::memcpy(Fo[k], Fa[k].data(), nzg * sizeof(double));
+  return 0;
+}
+
+// One step evaluated only at the listed zones (flat zone index z = (k n1 + j) n0 + i).
+// Outputs U^{n+1} as [nsel][G] per component, and U^- (after the explicit update) likewise.
+int orc_step_zones(const OrcDesc* D, const double* E, const double* const* F, const double* kap, const double* sig,
+                   const double* B, const double* inflow, double dt, int nsel, const int64_t* zones, double* Eo,
+                   double* const* Fo, double* Em_out) {
+  Geom geo;
+  geo.build(*D);
+  Ctx<double> C;
+  C.D = D;
+  C.geo = &geo;
+  for (int d = 0; d < 3; ++d) C.n[d] = D->n[d];
+  C.G = D->G;
+  C.ndim = D->ndim;
+  C.c = D->c;
+  C.dt = dt;
+  C.E = E;
+  for (int k = 0; k < 3; ++k) C.F[k] = (k < D->ndim) ? F[k] : nullptr;
+  C.kap = kap;
+  C.sig = sig;
+  C.B = B;
+  C.inflow = inflow;
+  set_threads(D);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int s = 0; s < nsel; ++s) {
+    long z = (long)zones[s];
+    int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
+    for (int g = 0; g < C.G; ++g) {
+      double U1[4], Em;
+      zone_step(C, idx, g, U1, &Em);
+      Eo[(size_t)s * C.G + g] = U1[0];
+      for (int k = 0; k < D->ndim; ++k) Fo[k][(size_t)s * C.G + g] = U1[1 + k];
+      if (Em_out) Em_out[(size_t)s * C.G + g] = Em;
+    }
+  }
+  return 0;
+}
+
+// Numerical face fluxes (coordinate flux densities, area not included) for direction d.
+// out: [faces along d][G][1+ndim], faces enumerated with the d index running 0..n_d and the
+// other two indices over the active zones, x fastest.
+int orc_flux(const OrcDesc* D, const double* E, const double* const* F, const double* kap, const double* sig,
+             const double* B, const double* inflow, int d, double* out) {
+  Geom geo;
+  geo.build(*D);
+  Ctx<double> C;
+  C.D = D;
+  C.geo = &geo;
+  for (int e = 0; e < 3; ++e) C.n[e] = D->n[e];
+  C.G = D->G;
+  C.ndim = D->ndim;
+  C.c = D->c;
+  C.dt = 0.0;
+  C.E = E;
+  for (int k = 0; k < 3; ++k) C.F[k] = (k < D->ndim) ? F[k] : nullptr;
+  C.kap = kap;
+  C.sig = sig;
+  C.B = B;
+  C.inflow = inflow;
+  int m[3] = {D->n[0], D->n[1], D->n[2]};
+  m[d] += 1;
+  long nf = (long)m[0] * m[1] * m[2];
+  int nc = 1 + D->ndim;
+  set_threads(D);
+#pragma omp parallel for schedule(static)
+  for (long f = 0; f < nf; ++f) {
+    int idx[3] = {(int)(f % m[0]), (int)((f / m[0]) % m[1]), (int)(f / ((long)m[0] * m[1]))};
+    int row[3] = {idx[0], idx[1], idx[2]};
+    for (int g = 0; g < D->G; ++g) {
+      double fl[4];
+      face_flux(C, d, row, idx[d], g, fl);
+      for (int k = 0; k < nc; ++k) out[((size_t)f * D->G + g) * nc + k] = fl[k];
+    }
+  }
+  return 0;
+}
+
+// Implicit interaction update alone, in place.  dEm (nullable): -sum_g (E^{n+1} - E^-) per zone.
+int orc_source(const OrcDesc* D, double* E, double* const* F, const double* kap, const double* sig, const double* B,
+               double dt, double* dEm) {
+  long nz = (long)D->n[0] * D->n[1] * D->n[2];
+  for (long z = 0; z < nz; ++z) {
+    double dsum = 0.0;
+    for (int g = 0; g < D->G; ++g) {
+      size_t zg = (size_t)z * D->G + g;
+      double Fm[3] = {0, 0, 0}, F1[3], E1;
+      for (int k = 0; k < D->ndim; ++k) Fm[k] = F[k][zg];
+      implicit_source<double>(E[zg], Fm, kap[zg], sig[zg], B[zg], D->c, dt, D->ndim, E1, F1);
+      dsum += E1 - E[zg];
+      E[zg] = E1;
+      for (int k = 0; k < D->ndim; ++k) F[k][zg] = F1[k];
+    }
+    if (dEm) dEm[z] = -dsum;
+  }
+  return 0;
+}
+
+// Forward-mode derivative of nsteps steps: U0 + t dU0 and kappa + t dkappa, returns U_N and
+// dU_N/dt (exact, via dual numbers).
+int orc_jvp(const OrcDesc* D, const double* E, const double* const* F, const double* dE, const double* const* dF,
+            const double* kap, const double* dkap, const double* sig, const double* B, const double* inflow, double dt,
+            int nsteps, double* Eo, double* const* Fo, double* dEo, double* const* dFo) {
+  Geom geo;
+  geo.build(*D);
+  size_t nzg = (size_t)D->n[0] * D->n[1] * D->n[2] * D->G;
+  std::vector<Dual> Ea(nzg), Eb(nzg), K(nzg);
+  std::vector<std::vector<Dual>> Fa(3), Fb(3);
+  for (size_t i = 0; i < nzg; ++i) {
+    Ea[i] = Dual(E[i], dE ? dE[i] : 0.0);
+    K[i] = Dual(kap[i], dkap ? dkap[i] : 0.0);
+  }
+  for (int k = 0; k < D->ndim; ++k) {
+    Fa[k].resize(nzg);
+    Fb[k].resize(nzg);
+    for (size_t i = 0; i < nzg; ++i) Fa[k][i] = Dual(F[k][i], (dF && dF[k]) ? dF[k][i] : 0.0);
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    const Dual* Fin[3] = {nullptr, nullptr, nullptr};
+    Dual* Fout[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < D->ndim; ++k) {
+      Fin[k] = Fa[k].data();
+      Fout[k] = Fb[k].data();
+    }
+    full_step<Dual>(D, geo, Ea.data(), Fin, K.data(), sig, B, inflow, dt, Eb.data(), Fout, nullptr, nullptr);
+    std::swap(Ea, Eb);
+    for (int k = 0; k < D->ndim; ++k) std::swap(Fa[k], Fb[k]);
+  }
+  for (size_t i = 0; i < nzg; ++i) {
+    Eo[i] = Ea[i].v;
+    dEo[i] = Ea[i].d;
+  }
+  for (int k = 0; k < D->ndim; ++k)
+    for (size_t i = 0; i < nzg; ++i) {
+      Fo[k][i] = Fa[k][i].v;
+      dFo[k][i] = Fa[k][i].d;
+    }
+  return 0;
+}
+
+// Geometry tables for tests: per zone volume (active zones), per face coordinate areas for
+// each direction, and for spherical grids the per-theta-zone connection coefficients
+// [<Gamma^3_23>, <Gamma^1_33>, <Gamma^2_33>, <Gamma^2_22>] and per-zone cell-centred h.
+int orc_geometry(const OrcDesc* D, double* vol, double* area0, double* area1, double* area2, double* gam_theta,
+                 double* hcell, double* centroid0, double* centroid1) {
+  Geom geo;
+  geo.build(*D);
+  int n0 = D->n[0], n1 = D->n[1], n2 = D->n[2];
+  for (int k = 0; k < n2; ++k)
+    for (int j = 0; j < n1; ++j)
+      for (int i = 0; i < n0; ++i) {
+        size_t z = ((size_t)k * n1 + j) * n0 + i;
+        if (vol) vol[z] = geo.volume(i, j, k);
+        if (hcell) geo.h_cell(i, j, hcell + 3 * z);
+      }
+  double* areas[3] = {area0, area1, area2};
+  for (int d = 0; d < 3; ++d) {
+    if (!areas[d]) continue;
+    int m[3] = {n0, n1, n2};
+    m[d] += 1;
+    for (int k = 0; k < m[2]; ++k)
+      for (int j = 0; j < m[1]; ++j)
+        for (int i = 0; i < m[0]; ++i) {
+          int idx[3] = {i, j, k};
+          areas[d][((size_t)k * m[1] + j) * m[0] + i] = geo.area(d, idx);
+        }
+  }
+  if (gam_theta && geo.sph())
+    for (int j = 0; j < n1; ++j) {
+      gam_theta[4 * j + 0] = geo.G323[j + NG];
+      gam_theta[4 * j + 1] = geo.G133[j + NG];
+      gam_theta[4 * j + 2] = geo.G233[j + NG];
+      gam_theta[4 * j + 3] = geo.G222[j + NG];
+    }
+  if (centroid0)
+    for (int i = 0; i < n0; ++i) centroid0[i] = geo.X[0][i + NG];
+  if (centroid1)
+    for (int j = 0; j < n1; ++j) centroid1[j] = geo.X[1][j + NG];
+  return 0;
+}
+
+// Closure alone, for tests: physical-component P^ (3x3, row-major) of a state (E, F^ phys).
+int orc_closure(const OrcDesc* D, double E, const double* Fphys, double* P) {
+  Geom geo;  // unused, Cartesian scale factors
+  Ctx<double> C;
+  C.D = D;
+  C.c = D->c;
+  C.ndim = 3;
+  double q[4] = {E, Fphys[0], Fphys[1], Fphys[2]}, h[3] = {1.0, 1.0, 1.0};
+  double Pm[3][3];
+  closure(C, q, h, Pm);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) P[3 * a + b] = Pm[a][b];
+  (void)geo;
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,266 @@
+"""ctypes wrapper of the CPU FP64 oracle (``oracle/m1_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()`` and by the
+CPU-baseline leg of ``bench.py``.  The product library never imports or calls it.
+
+All arrays are float64 NumPy arrays in the layout ``[n2][n1][n0][G]`` (group innermost);
+flux components are covariant ``F_k`` (equal to the physical components on Cartesian grids).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "m1_oracle.cpp")
+_LIB = os.path.join(_HERE, "libm1_oracle.so")
+
+CART, SPH_LOGR = 0, 1
+OUTFLOW, PERIODIC, REFLECT, INFLOW, AXIS = 0, 1, 2, 3, 4
+MINMOD, MC, CONST = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["g++", "-O2", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class OrcDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("G", ctypes.c_int32),
+        ("coord", ctypes.c_int32),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("bc_lo", ctypes.c_int32 * 3),
+        ("bc_hi", ctypes.c_int32 * 3),
+        ("limiter", ctypes.c_int32),
+        ("closure", ctypes.c_int32),
+        ("eps_mode", ctypes.c_int32),
+        ("c", ctypes.c_double),
+        ("nthreads", ctypes.c_int32),
+    ]
+
+
+class OrcDiag(ctypes.Structure):
+    _fields_ = [
+        ("energy_total", ctypes.c_double),
+        ("max_f", ctypes.c_double),
+        ("n_unrealizable", ctypes.c_int64),
+        ("n_nonpositive", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        P = ctypes.POINTER
+        d = ctypes.c_double
+        vp = ctypes.c_void_p
+        _lib.orc_max_dt.restype = d
+        _lib.orc_max_dt.argtypes = [P(OrcDesc), d]
+        _lib.orc_run.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, d, ctypes.c_int, vp, vp, vp, P(OrcDiag)]
+        _lib.orc_step_zones.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, d, ctypes.c_int, vp, vp, vp, vp]
+        _lib.orc_flux.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
+        _lib.orc_source.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, d, vp]
+        _lib.orc_jvp.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, vp, vp, vp, d, ctypes.c_int, vp, vp, vp, vp]
+        _lib.orc_geometry.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, vp, vp]
+        _lib.orc_closure.argtypes = [P(OrcDesc), d, vp, vp]
+    return _lib
+
+
+@dataclass
+class Problem:
+    """Grid and method options (the oracle's own description of a problem)."""
+
+    ndim: int
+    n: tuple
+    G: int
+    coord: int = CART
+    lo: tuple = (0.0, 0.0, 0.0)
+    hi: tuple = (1.0, 1.0, 1.0)
+    bc_lo: tuple = (OUTFLOW, OUTFLOW, OUTFLOW)
+    bc_hi: tuple = (OUTFLOW, OUTFLOW, OUTFLOW)
+    limiter: int = MINMOD
+    closure: int = 0
+    eps_mode: int = 0
+    c: float = 1.0
+    nthreads: int = 0
+    extra: dict = field(default_factory=dict)
+
+    def desc(self) -> OrcDesc:
+        d = OrcDesc()
+        d.ndim = self.ndim
+        n = list(self.n) + [1] * (3 - len(self.n))
+        d.n[:] = n
+        d.G = self.G
+        d.coord = self.coord
+        d.lo[:] = list(self.lo)
+        d.hi[:] = list(self.hi)
+        d.bc_lo[:] = list(self.bc_lo)
+        d.bc_hi[:] = list(self.bc_hi)
+        d.limiter = self.limiter
+        d.closure = self.closure
+        d.eps_mode = self.eps_mode
+        d.c = self.c
+        d.nthreads = self.nthreads
+        return d
+
+    @property
+    def shape(self):
+        n = list(self.n) + [1] * (3 - len(self.n))
+        return (n[2], n[1], n[0], self.G)
+
+    @property
+    def nzones(self):
+        s = self.shape
+        return s[0] * s[1] * s[2]
+
+
+def _c(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _ptrs(arrs):
+    arr = (ctypes.c_void_p * 3)()
+    for k, a in enumerate(arrs):
+        arr[k] = a.ctypes.data if a is not None else None
+    return arr
+
+
+def max_dt(p: Problem, cfl: float) -> float:
+    d = p.desc()
+    return lib().orc_max_dt(ctypes.byref(d), cfl)
+
+
+def run(p: Problem, E, F, kappa, sigma, B, dt, nsteps=1, inflow=None, want_dEm=False):
+    """nsteps full steps. Returns (E, [F_k], diag dict[, dE_matter])."""
+    d = p.desc()
+    E = _c(E)
+    F = [_c(f) for f in F]
+    kappa, sigma, B = _c(kappa), _c(sigma), _c(B)
+    inflow = None if inflow is None else _c(inflow)
+    Eo = np.empty_like(E)
+    Fo = [np.empty_like(E) for _ in range(p.ndim)]
+    dEm = np.empty(p.nzones) if want_dEm else None
+    diag = OrcDiag()
+    lib().orc_run(ctypes.byref(d), _ptr(E), _ptrs(F), _ptr(kappa), _ptr(sigma), _ptr(B), _ptr(inflow), dt, nsteps,
+                  _ptr(Eo), _ptrs(Fo), _ptr(dEm), ctypes.byref(diag))
+    dg = dict(energy_total=diag.energy_total, max_f=diag.max_f, n_unrealizable=diag.n_unrealizable,
+              n_nonpositive=diag.n_nonpositive)
+    if want_dEm:
+        return Eo, Fo, dg, dEm
+    return Eo, Fo, dg
+
+
+def step_zones(p: Problem, E, F, kappa, sigma, B, dt, zones, inflow=None):
+    """One step evaluated at flat zone indices; returns (E1 [nsel,G], [F1_k], Em [nsel,G])."""
+    d = p.desc()
+    zones = np.ascontiguousarray(zones, dtype=np.int64)
+    nsel = zones.size
+    E = _c(E)
+    F = [_c(f) for f in F]
+    kappa, sigma, B = _c(kappa), _c(sigma), _c(B)
+    inflow = None if inflow is None else _c(inflow)
+    Eo = np.empty((nsel, p.G))
+    Fo = [np.empty((nsel, p.G)) for _ in range(p.ndim)]
+    Em = np.empty((nsel, p.G))
+    lib().orc_step_zones(ctypes.byref(d), _ptr(E), _ptrs(F), _ptr(kappa), _ptr(sigma), _ptr(B), _ptr(inflow), dt,
+                         nsel, _ptr(zones), _ptr(Eo), _ptrs(Fo), _ptr(Em))
+    return Eo, Fo, Em
+
+
+def flux(p: Problem, E, F, kappa, sigma, B, d, inflow=None):
+    """Face fluxes along direction d: array [faces..., G, 1+ndim] with the d extent n_d+1."""
+    desc = p.desc()
+    E = _c(E)
+    F = [_c(f) for f in F]
+    kappa, sigma, B = _c(kappa), _c(sigma), _c(B)
+    inflow = None if inflow is None else _c(inflow)
+    s = list(p.shape[:3])
+    s[2 - d] += 1
+    out = np.empty(tuple(s) + (p.G, 1 + p.ndim))
+    lib().orc_flux(ctypes.byref(desc), _ptr(E), _ptrs(F), _ptr(kappa), _ptr(sigma), _ptr(B), _ptr(inflow), d,
+                   _ptr(out))
+    return out
+
+
+def source(p: Problem, E, F, kappa, sigma, B, dt):
+    """Implicit interaction update alone. Returns (E, [F_k], dE_matter)."""
+    desc = p.desc()
+    E = _c(E).copy()
+    F = [_c(f).copy() for f in F]
+    kappa, sigma, B = _c(kappa), _c(sigma), _c(B)
+    dEm = np.empty(p.nzones)
+    lib().orc_source(ctypes.byref(desc), _ptr(E), _ptrs(F), _ptr(kappa), _ptr(sigma), _ptr(B), dt, _ptr(dEm))
+    return E, F, dEm
+
+
+def jvp(p: Problem, E, F, kappa, sigma, B, dt, nsteps, dE=None, dF=None, dkappa=None, inflow=None):
+    """Exact forward-mode derivative: returns (E_N, [F_N], dE_N, [dF_N])."""
+    desc = p.desc()
+    E = _c(E)
+    F = [_c(f) for f in F]
+    kappa, sigma, B = _c(kappa), _c(sigma), _c(B)
+    dE = None if dE is None else _c(dE)
+    dF = None if dF is None else [_c(f) for f in dF]
+    dkappa = None if dkappa is None else _c(dkappa)
+    inflow = None if inflow is None else _c(inflow)
+    Eo = np.empty_like(E)
+    Fo = [np.empty_like(E) for _ in range(p.ndim)]
+    dEo = np.empty_like(E)
+    dFo = [np.empty_like(E) for _ in range(p.ndim)]
+    lib().orc_jvp(ctypes.byref(desc), _ptr(E), _ptrs(F), _ptr(dE), _ptrs(dF) if dF is not None else None,
+                  _ptr(kappa), _ptr(dkappa), _ptr(sigma), _ptr(B), _ptr(inflow), dt, nsteps, _ptr(Eo), _ptrs(Fo),
+                  _ptr(dEo), _ptrs(dFo))
+    return Eo, Fo, dEo, dFo
+
+
+def geometry(p: Problem):
+    desc = p.desc()
+    n = list(p.n) + [1] * (3 - len(p.n))
+    vol = np.empty(p.nzones)
+    areas = []
+    for d in range(3):
+        m = list(n)
+        m[d] += 1
+        areas.append(np.empty(m[0] * m[1] * m[2]))
+    gam = np.zeros(4 * n[1])
+    hcell = np.empty(3 * p.nzones)
+    c0 = np.empty(n[0])
+    c1 = np.empty(n[1])
+    lib().orc_geometry(ctypes.byref(desc), _ptr(vol), _ptr(areas[0]), _ptr(areas[1]), _ptr(areas[2]), _ptr(gam),
+                       _ptr(hcell), _ptr(c0), _ptr(c1))
+    return dict(vol=vol.reshape(n[2], n[1], n[0]),
+                area=[a.reshape(*(list(reversed([n[e] + (1 if e == d else 0) for e in range(3)])))) for d, a in
+                      enumerate(areas)],
+                gamma_theta=gam.reshape(n[1], 4), hcell=hcell.reshape(n[2], n[1], n[0], 3), centroid0=c0,
+                centroid1=c1)
+
+
+def closure(E, Fphys, c=1.0, eddington=False):
+    """Physical-component pressure tensor P^ (3x3) of one state (Cartesian scale factors)."""
+    p = Problem(ndim=3, n=(1, 1, 1), G=1, c=c, closure=1 if eddington else 0)
+    desc = p.desc()
+    F = np.ascontiguousarray(np.asarray(Fphys, dtype=np.float64).reshape(3))
+    P = np.empty(9)
+    lib().orc_closure(ctypes.byref(desc), float(E), _ptr(F), _ptr(P))
+    return P.reshape(3, 3)
