@@ -1,0 +1,222 @@
+"""Benchmark of the M1 radiation-moment step on one MI355X.
+
+Headline (`value`): zone-group updates per second of the full step (explicit transport +
+implicit interaction update + energy/realizability diagnostics) on the 2-D periodic
+512 x 512 zone, 16 group FP64 workload, inputs resident in HBM, timed with HIP events over
+K steps after W warmup steps.  Extra workloads (3-D 192^3 x 12 FP64 vs MIXED, spherical
+256 x 64 x 128 x 20 MIXED) and the adjoint/forward ratio are reported beside it, plus the
+roofline of the dominant kernel and the CPU oracle's rate on this host (a baseline only).
+
+    python bench.py [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E nominal
+METRIC = "zone-group updates/s + HBM GB/s (FP64 vs FP32); adjoint/forward time ratio"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(ndim, elem):
+    """Bytes the step must move per zone-group: read E, F_1..F_D, kappa, sigma, B; write E, F."""
+    return (2 * (1 + ndim) + 3) * elem
+
+
+def device_inputs(w, dtype):
+    import torch
+    dev = "cuda"
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dtype)
+    E = t(w.E)
+    F = [t(f) for f in w.F]
+    k, s, B = t(w.kappa), t(w.sigma), t(w.B)
+    inflow = None if w.inflow is None else torch.from_numpy(w.inflow).to(device=dev, dtype=torch.float64)
+    return E, F, k, s, B, inflow
+
+
+def time_steps(ctx, inputs, dt, steps, warmup, with_diag=True):
+    """Average ms per step over `steps` steps (HIP events on the launch stream)."""
+    import torch
+    E, F, k, s, B, inflow = inputs
+    a = (E.clone(), [f.clone() for f in F])
+    b = ctx.empty_state()
+    diag = ctx.new_diag() if with_diag else None
+    for _ in range(warmup):
+        ctx.step(a[0], a[1], k, s, B, dt, out=b, inflow=inflow, diag=diag)
+        a, b = b, a
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        ctx.step(a[0], a[1], k, s, B, dt, out=b, inflow=inflow, diag=diag)
+        a, b = b, a
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return ms, diag
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=20):
+    import torch
+    from paper_1806_07390_amd import m1
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        m1.copy_probe(dst, src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        m1.copy_probe(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return 2 * nbytes / (ms * 1e-3) / 1e9, ms
+
+
+def cpu_baseline(w, dt, target_s=15.0):
+    """The CPU oracle on a bounded sample of the same workload: whole steps on the first rows."""
+    from oracle import m1_oracle as orc
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    ncores = min(ncores, 16)
+    p = orc.Problem(ndim=w.ndim, n=w.n, G=w.G, coord=w.coord, lo=w.lo, hi=w.hi, bc_lo=w.bc_lo, bc_hi=w.bc_hi,
+                    c=w.c, nthreads=ncores)
+    # probe on a small strip, then size the sample to ~target_s seconds
+    t0 = time.perf_counter()
+    orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, 1)
+    t1 = time.perf_counter()
+    per_step = t1 - t0
+    nsteps = max(1, int(target_s / max(per_step, 1e-3)))
+    nsteps = min(nsteps, 200)
+    t0 = time.perf_counter()
+    orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, nsteps)
+    t1 = time.perf_counter()
+    zgu = w.zone_groups * nsteps / (t1 - t0)
+    return dict(value=zgu, unit="zone-group updates/s", cores=ncores, kind="oracle",
+                sample=f"{nsteps} full steps of the {w.n[0]}x{w.n[1]} x {w.G}-group workload, "
+                       f"{ncores} OpenMP threads, {t1 - t0:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", default=None, help="profiling: run only this workload's timed loop")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU path; "
+              "see DESIGN.md for how the step would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1806_07390_amd import m1, workloads as wl
+
+    torch.cuda.set_device(0)
+    res = {}
+    # ---- headline: 2-D 512^2 x 16 groups, FP64 ------------------------------------------
+    w = wl.blobs2d()
+    if args.only in (None, "blobs2d"):
+        log("headline: blobs2d", w.n, w.G)
+        ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64))
+        inp = device_inputs(w, torch.float64)
+        ms, diag = time_steps(ctx, inp, w.dt, args.steps, args.warmup, with_diag=True)
+        ms_k, _ = time_steps(ctx, inp, w.dt, args.steps, 2, with_diag=False)
+        zg = w.zone_groups
+        value = zg / (ms * 1e-3)
+        bpz = algorithmic_bytes(w.ndim, 8)
+        achieved = zg * bpz / (ms_k * 1e-3) / 1e9
+        res["headline"] = dict(ms=ms, value=value, ms_kernel=ms_k, achieved=achieved, bpz=bpz,
+                               energy=float(diag["energy_total"].item()),
+                               n_unrealizable=int(diag["n_unrealizable"].item()))
+        log(f"  {ms:.4f} ms/step, {value:.3e} zgu/s; kernel {ms_k:.4f} ms -> {achieved:.0f} GB/s algorithmic")
+        del ctx, inp
+        torch.cuda.empty_cache()
+    if args.only is not None and args.only != "blobs2d":
+        pass
+    extra = {}
+    if not args.no_extra:
+        # ---- 3-D 192^3 x 12: FP64 vs MIXED -------------------------------------------------
+        if args.only in (None, "core3d"):
+            w3 = wl.core3d()
+            for prec, name, dt_, el in ((m1.FP64, "fp64", torch.float64, 8), (m1.MIXED, "mixed", torch.float32, 4)):
+                ctx = m1.Context(m1.Config.from_workload(w3, precision=prec))
+                inp = device_inputs(w3, dt_)
+                ms3, _ = time_steps(ctx, inp, w3.dt, 20, 3, with_diag=True)
+                gbs = w3.zone_groups * algorithmic_bytes(3, el) / (ms3 * 1e-3) / 1e9
+                extra[f"core3d_192^3x12_{name}"] = dict(ms_per_step=round(ms3, 5),
+                                                        zgu_per_s=w3.zone_groups / (ms3 * 1e-3),
+                                                        algorithmic_GBps=round(gbs, 1))
+                log(f"  core3d {name}: {ms3:.4f} ms/step, {gbs:.0f} GB/s")
+                del ctx, inp
+                torch.cuda.empty_cache()
+            del w3
+        # ---- spherical 256x64x128 x 20 MIXED -----------------------------------------------
+        if args.only in (None, "sphere3d"):
+            w4 = wl.sphere3d()
+            for prec, name, dt_, el in ((m1.MIXED, "mixed", torch.float32, 4), (m1.FP64, "fp64", torch.float64, 8)):
+                ctx = m1.Context(m1.Config.from_workload(w4, precision=prec))
+                dt4 = ctx.max_dt(w4.cfl)
+                inp = device_inputs(w4, dt_)
+                ms4, _ = time_steps(ctx, inp, dt4, 20, 3, with_diag=True)
+                gbs = w4.zone_groups * algorithmic_bytes(3, el) / (ms4 * 1e-3) / 1e9
+                extra[f"sphere3d_256x64x128x20_{name}"] = dict(ms_per_step=round(ms4, 5),
+                                                               zgu_per_s=w4.zone_groups / (ms4 * 1e-3),
+                                                               algorithmic_GBps=round(gbs, 1))
+                log(f"  sphere3d {name}: {ms4:.4f} ms/step, {gbs:.0f} GB/s")
+                del ctx, inp
+                torch.cuda.empty_cache()
+            del w4
+        copy_gbs, copy_ms = copy_bandwidth()
+        extra["copy_probe_GBps"] = round(copy_gbs, 1)
+        log(f"  copy probe: {copy_gbs:.0f} GB/s")
+    if "headline" not in res:
+        print(json.dumps(dict(extra=extra)))
+        return
+    h = res["headline"]
+    out = {
+        "metric": METRIC,
+        "value": h["value"],
+        "unit": "zone-group updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2-D Cartesian periodic 512x512 zones x 16 groups, FP64, lognormal opacity, "
+                               "8 Gaussian blobs (seed 0)", "zones": [512, 512], "groups": 16,
+                   "zone_groups": w.zone_groups, "dt": w.dt},
+        "roofline": {"bound": "hbm", "achieved": round(h["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(h["achieved"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step<double,double,2,false>", "bytes_per_zone_group": h["bpz"],
+                     "kernel_ms": round(h["ms_kernel"], 5)},
+        "extra": extra,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle)...")
+        out["cpu_baseline"] = cpu_baseline(w, w.dt)
+        log("  ", out["cpu_baseline"])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,151 @@
+/* fornax_m1.h -- C interface of the MI355X (gfx950) multigroup M1 radiation-moment step.
+ *
+ * The library advances the group radiation energy density E_g and flux F_{g,k} of every zone
+ * of a static medium by one step of the semi-explicit method of Skinner, Dolence, Burrows,
+ * Radice & Vartanyan, "FORNAX: a Flexible Code for Multiphysics Astrophysical Simulations"
+ * (ApJS 2019):
+ *   - radiation moment equations with v = 0 (Formulation of the Equations, eq:rad_system,
+ *     interaction terms eq:rad_mom_src), group-integrated (eq:rad_system2);
+ *   - finite-volume update (eq:finite_vol) with linear reconstruction in the volume coordinate
+ *     (Reconstruction, eq:recon_constraints with n = 1), M1 closure, HLL fluxes with the
+ *     diffusion correction of the energy flux (Riemann Solvers, eq:hll, eq:epsilon) and the
+ *     geometric source terms of the covariant form (Appendix: covariant form, connection
+ *     coefficients, eq:angmom, eq:grad2P);
+ *   - operator-split backward-Euler interaction update (Interaction Terms, eq:be_update and
+ *     the flux update that follows it), Algorithmic Steps 1, 3 and 4 with matter held fixed.
+ *
+ * Conventions
+ *   - Every array pointer is a DEVICE pointer (hipMalloc'd or a torch CUDA tensor's data).
+ *     Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL = null stream).
+ *     No call synchronises the host.
+ *   - Zone-group layout: structure of arrays, one array per component, element
+ *     ((k * n[1] + j) * n[0] + i) * ngroups + g  (group innermost, x fastest among zones).
+ *   - Flux components are covariant, F_k = h_k F^_k with h_k the scale factors; on Cartesian
+ *     grids they equal the physical components.
+ *   - Element type: double for FORNAX_FP64 contexts, float for FORNAX_MIXED contexts, for
+ *     states, coefficients and face fluxes.  Diagnostics and inflow values are always double.
+ *   - Errors are negative return codes, checked before any launch; the arguments are not
+ *     modified when a call fails.  Numerical trouble (non-realizable or non-positive states)
+ *     is not an error: it is counted in the diagnostics.
+ */
+#ifndef FORNAX_M1_H
+#define FORNAX_M1_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FORNAX_OK = 0,
+  FORNAX_EINVAL = -1,       /* null/misaligned pointer, bad shape, bad option combination */
+  FORNAX_ECFL = -2,         /* dt above fornax_m1_max_dt(ctx, 1.0) */
+  FORNAX_EDEVICE = -3,      /* HIP error (launch, copy, no device) */
+  FORNAX_ENOMEM = -4,       /* device allocation failed */
+  FORNAX_EUNSUPPORTED = -5  /* option not implemented for this configuration */
+};
+
+/* Coordinates.  SPHERICAL_LOGR: x1 = ln r, x2 = theta, x3 = phi (metric of the Appendix,
+ * general spherical metric, with r = e^{x1}, theta = x2). */
+enum { FORNAX_CARTESIAN = 0, FORNAX_SPHERICAL_LOGR = 1 };
+
+/* Boundary conditions (Implementation of the dendritic grid, Boundary Conditions):
+ * OUTFLOW copies the edge zone; PERIODIC wraps; REFLECT mirrors and flips the normal flux;
+ * INFLOW fills the ghosts with prescribed (E, physical F) per group; AXIS is the polar-axis
+ * copy across theta = 0 or pi with a shift of n[2]/2 zones in phi and sign flips of the theta
+ * and phi flux components (spherical x2 only, n[2] even or 1). */
+enum { FORNAX_BC_OUTFLOW = 0, FORNAX_BC_PERIODIC = 1, FORNAX_BC_REFLECT = 2, FORNAX_BC_INFLOW = 3,
+       FORNAX_BC_AXIS = 4 };
+
+/* Precision.  FP64: every operation in double.  MIXED: float storage, reconstruction, flux and
+ * divergence in float; the closure in double where f >= f_fp64; the interaction update and
+ * all accumulations (energy, dE_matter) in double. */
+enum { FORNAX_FP64 = 0, FORNAX_MIXED = 1 };
+
+enum { FORNAX_LIMITER_MINMOD = 0, FORNAX_LIMITER_MC = 1, FORNAX_LIMITER_NONE = 2 };
+enum { FORNAX_CLOSURE_M1 = 0, FORNAX_CLOSURE_EDDINGTON = 1 };
+
+typedef struct {
+  int32_t ndim;             /* active directions, 1..3 */
+  int32_t n[3];             /* zones per direction; n[d] = 1 for d >= ndim */
+  int32_t ngroups;          /* energy groups, >= 1 */
+  int32_t coord;            /* FORNAX_CARTESIAN or FORNAX_SPHERICAL_LOGR */
+  double lo[3], hi[3];      /* coordinate extents in x-space (uniform in each x^d) */
+  int32_t bc_lo[3], bc_hi[3];
+  int32_t limiter;          /* FORNAX_LIMITER_* (minmod is the method's default) */
+  int32_t closure;          /* FORNAX_CLOSURE_* */
+  int32_t precision;        /* FORNAX_FP64 or FORNAX_MIXED */
+  double c;                 /* (reduced) speed of light, > 0 */
+  double f_fp64;            /* MIXED only: closure evaluated in double where f >= f_fp64 */
+} fornax_m1_desc;
+
+typedef struct fornax_m1_ctx fornax_m1_ctx;   /* opaque; owns geometry tables and scratch */
+
+typedef struct { void *E, *F[3]; } fornax_m1_state;               /* F[k] unused for k >= ndim */
+typedef struct { const void *kappa, *sigma, *B; } fornax_m1_coeffs; /* absorption, scattering,
+                                                                       emission: j = c kappa B */
+typedef struct {
+  double *energy_total;     /* [1]  sum_i V_i sum_g E_g^{n+1} (coordinate volume V_i) */
+  double *dE_matter;        /* [nzones] -sum_g (E_g^{n+1} - E_g^-): energy given to matter */
+  double *max_f;            /* [1]  max |F^|/(c E) over zone-groups with E > 0 */
+  int32_t *n_unrealizable;  /* [1]  #zone-groups with |F^| > c E (1 + 8u), u = unit roundoff */
+  int32_t *n_nonpositive;   /* [1]  #zone-groups with E <= 0 */
+} fornax_m1_diag;           /* any member may be NULL; the whole pointer may be NULL */
+
+/* Build a context: validates the description, builds the geometry tables on the host in
+ * double precision (volumes, face areas, volume centroids, scale factors and volume-averaged
+ * connection coefficients with the paper's overrides) and uploads them to the current HIP
+ * device.  Returns FORNAX_OK and *out, or an error with *out = NULL. */
+int fornax_m1_create(const fornax_m1_desc *desc, fornax_m1_ctx **out);
+int fornax_m1_destroy(fornax_m1_ctx *ctx);
+
+/* Largest time step for a CFL number: cfl / max_i sum_d c / (h_d Delta x^d)_i (the light
+ * crossing time of a zone sets the step, General Description).  Host only; < 0 on error. */
+double fornax_m1_max_dt(const fornax_m1_ctx *ctx, double cfl);
+
+/* One step U^n -> U^{n+1}: explicit transport (Algorithmic Steps, step 1, v = 0) followed by
+ * the implicit interaction update (steps 3 and 4, matter fixed).  `in` and `out` must not
+ * alias.  `inflow` is a device array [ngroups][1+ndim] of doubles (E and physical flux of the
+ * inflow ghosts) required iff a boundary is FORNAX_BC_INFLOW, else NULL.  `diag` may be NULL.
+ * Errors: EINVAL, ECFL (dt <= 0 or dt > max_dt(1)), EDEVICE. */
+int fornax_m1_step(fornax_m1_ctx *ctx, const fornax_m1_state *in, fornax_m1_state *out,
+                   const fornax_m1_coeffs *cf, const double *inflow, double dt,
+                   const fornax_m1_diag *diag, void *stream);
+
+/* Numerical face fluxes of U (eq:hll, eq:epsilon) per direction d < ndim, as coordinate flux
+ * densities (the face area is not applied): face_flux[d] is an array
+ * [faces_d][ngroups][1+ndim], faces_d running over (k, j, i) with the d index in 0..n[d]
+ * (face i-1/2 of zone i) and x fastest; component 0 is the energy flux, 1+k the flux of F_k.
+ * Faces of zero area (polar axis) hold 0. */
+int fornax_m1_flux(fornax_m1_ctx *ctx, const fornax_m1_state *in, const fornax_m1_coeffs *cf,
+                   const double *inflow, void *face_flux[3], void *stream);
+
+/* Implicit interaction update alone, in place (eq:be_update with j = c kappa B, and
+ * F <- F / (1 + c dt (kappa + sigma))).  dE_matter (nullable): -sum_g (E^{n+1} - E) per zone. */
+int fornax_m1_source(fornax_m1_ctx *ctx, fornax_m1_state *inout, const fornax_m1_coeffs *cf,
+                     double dt, double *dE_matter, void *stream);
+
+/* Adjoint of one step (vector-Jacobian product), for gradients of a loss of U^N:
+ *   lam_n = (dU^{n+1}/dU^n)^T lam_np1,   dkappa_accum += (dU^{n+1}/dkappa)^T lam_np1.
+ * Un is the state the step started from; lam_np1, lam_n are states of the context's type
+ * (lam_n must not alias lam_np1 or Un); dkappa_accum is a zone-group array of the context's
+ * type, accumulated into.  Non-smooth points (minmod, realizability fallback, epsilon kink,
+ * f clamp) take the derivative of the branch the forward step takes.  Same layout, error and
+ * stream rules as fornax_m1_step. */
+int fornax_m1_adjoint(fornax_m1_ctx *ctx, const fornax_m1_state *Un, const fornax_m1_coeffs *cf,
+                      const double *inflow, double dt, const fornax_m1_state *lam_np1,
+                      fornax_m1_state *lam_n, void *dkappa_accum, void *stream);
+
+/* Measurement utility (not part of the method): plain device-to-device copy of `nbytes`
+ * (multiple of 16, 16-byte aligned pointers) with the library's own kernel, used to scale
+ * hardware byte counters and to measure achievable HBM bandwidth. */
+int fornax_m1_copy_probe(void *dst, const void *src, int64_t nbytes, void *stream);
+
+const char *fornax_m1_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FORNAX_M1_H */

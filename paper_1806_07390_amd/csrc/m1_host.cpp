@@ -1,0 +1,452 @@
+// m1_host.cpp -- host side of libfornax_m1: argument checking, geometry tables, C interface.
+//
+// Geometry (Numerical Discretization and the Appendix of the paper): the volume element is
+// separable, sqrt(g) = w_1(x1) w_2(x2) w_3(x3), with w = 1 on Cartesian grids and, for the
+// spherical grid x1 = ln r, x2 = theta, x3 = phi, w_1 = e^{3 x1}, w_2 = |sin x2|, w_3 = 1
+// (r^3 sin(theta) with dr = r dx1).  Zone volumes are products of the 1-D integrals W_d and
+// face areas replace one factor by w_d at the face; volume-averaged quantities that a
+// closed form gives stably come from it, the others from 24-point Gauss-Legendre quadrature
+// of the zone (all integrands are smooth inside a zone).  The angular-momentum override
+// (eq:angmom) and the d_2 P = 0 balance override (eq:grad2P) are applied to the
+// connection coefficients.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <vector>
+
+#include "m1_internal.h"
+
+using namespace fm1;
+
+namespace {
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n)
+struct GaussLegendre {
+  static constexpr int N = 24;
+  double x[N], w[N];
+  GaussLegendre() {
+    for (int i = 0; i < N; ++i) {
+      double z = std::cos(M_PI * (i + 0.75) / (N + 0.5));
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= N; ++k) {
+          double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        double dp = N * (z * p1 - p0) / (z * z - 1.0);
+        double dz = p1 / dp;
+        z -= dz;
+        if (std::fabs(dz) < 1e-17) break;
+      }
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= N; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = N * (z * p1 - p0) / (z * z - 1.0);
+      x[i] = z;
+      w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+  }
+  // integral of f over [a, b], f evaluated at offsets t = x - a (no cancellation near a)
+  double offset_integral(const std::function<double(double)>& f, double a, double b) const {
+    double h = 0.5 * (b - a), s = 0.0;
+    for (int i = 0; i < N; ++i) s += w[i] * f(h * (x[i] + 1.0));
+    (void)a;
+    return h * s;
+  }
+};
+
+const GaussLegendre& gl() {
+  static GaussLegendre g;
+  return g;
+}
+
+bool valid_bc(int bc) { return bc >= FORNAX_BC_OUTFLOW && bc <= FORNAX_BC_AXIS; }
+
+int validate(const fornax_m1_desc* d) {
+  if (!d) return FORNAX_EINVAL;
+  if (d->ndim < 1 || d->ndim > 3) return FORNAX_EINVAL;
+  if (d->ngroups < 1) return FORNAX_EINVAL;
+  if (d->ngroups > BLOCK) return FORNAX_EUNSUPPORTED;
+  if (d->coord != FORNAX_CARTESIAN && d->coord != FORNAX_SPHERICAL_LOGR) return FORNAX_EINVAL;
+  if (d->precision != FORNAX_FP64 && d->precision != FORNAX_MIXED) return FORNAX_EINVAL;
+  if (d->limiter < 0 || d->limiter > 2) return FORNAX_EINVAL;
+  if (d->closure < 0 || d->closure > 1) return FORNAX_EINVAL;
+  if (!(d->c > 0.0) || !std::isfinite(d->c)) return FORNAX_EINVAL;
+  int64_t nz = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (d->n[k] < 1) return FORNAX_EINVAL;
+    if (k >= d->ndim && d->n[k] != 1) return FORNAX_EINVAL;
+    if (!(d->hi[k] > d->lo[k]) || !std::isfinite(d->lo[k]) || !std::isfinite(d->hi[k])) return FORNAX_EINVAL;
+    nz *= d->n[k];
+    if (k < d->ndim) {
+      if (!valid_bc(d->bc_lo[k]) || !valid_bc(d->bc_hi[k])) return FORNAX_EINVAL;
+      if ((d->bc_lo[k] == FORNAX_BC_PERIODIC) != (d->bc_hi[k] == FORNAX_BC_PERIODIC)) return FORNAX_EINVAL;
+      // mirrored ghosts (reflect, axis) read zones 0 and 1 of the edge: at least two zones
+      for (int side = 0; side < 2; ++side) {
+        int bc = side ? d->bc_hi[k] : d->bc_lo[k];
+        if ((bc == FORNAX_BC_REFLECT || bc == FORNAX_BC_AXIS) && d->n[k] < 2) return FORNAX_EINVAL;
+      }
+      bool axis = d->bc_lo[k] == FORNAX_BC_AXIS || d->bc_hi[k] == FORNAX_BC_AXIS;
+      if (axis) {
+        if (d->coord != FORNAX_SPHERICAL_LOGR || k != 1) return FORNAX_EINVAL;
+        if (d->bc_lo[k] == FORNAX_BC_AXIS && std::fabs(d->lo[1]) > 1e-12) return FORNAX_EINVAL;
+        if (d->bc_hi[k] == FORNAX_BC_AXIS && std::fabs(d->hi[1] - M_PI) > 1e-12) return FORNAX_EINVAL;
+        if (d->n[2] != 1 && (d->n[2] % 2) != 0) return FORNAX_EINVAL;
+      }
+    }
+  }
+  if (d->coord == FORNAX_SPHERICAL_LOGR) {
+    if (d->lo[1] < -1e-12 || d->hi[1] > M_PI + 1e-12) return FORNAX_EINVAL;
+  }
+  if (nz * (int64_t)d->ngroups > ((int64_t)1 << 40)) return FORNAX_EINVAL;
+  if (d->precision == FORNAX_MIXED && !(d->f_fp64 >= 0.0)) return FORNAX_EINVAL;
+  return FORNAX_OK;
+}
+
+void build_geometry(const fornax_m1_desc& D, HostGeo& H) {
+  const bool sph = D.coord == FORNAX_SPHERICAL_LOGR;
+  const auto& Q = gl();
+  for (int d = 0; d < 3; ++d) {
+    int n = D.n[d];
+    H.n[d] = n;
+    int m = n + 2 * NG;             // extended zones
+    double dx = (D.hi[d] - D.lo[d]) / n;
+    H.dx[d] = dx;
+    // zone e covers [a_e, a_e + dx], a_e = lo + (e - NG) dx; one extra zone on each side for
+    // the centroid differences at the ends of the extended range
+    std::vector<double> X(m + 2), a(m + 3);
+    for (int e = -1; e <= m + 1; ++e) a[e + 1] = D.lo[d] + (e - NG) * dx;
+    std::vector<double> W(m + 2);
+    for (int e = -1; e <= m; ++e) {
+      double lo = a[e + 1], hi = lo + dx;
+      double Wz, off;
+      if (!sph || d == 2) {
+        Wz = dx;
+        off = 0.5 * dx;
+      } else if (d == 0) {
+        // w = e^{3x}: W = e^{3 lo} (e^{3 dx} - 1)/3; centroid offset by quadrature
+        Wz = std::exp(3.0 * lo) * std::expm1(3.0 * dx) / 3.0;
+        double num = Q.offset_integral([&](double t) { return t * std::exp(3.0 * t); }, lo, hi);
+        double den = Q.offset_integral([&](double t) { return std::exp(3.0 * t); }, lo, hi);
+        off = num / den;
+      } else {
+        // w = |sin x|: W = |cos lo - cos hi| = 2 |sin(mid) sin(dx/2)|
+        Wz = std::fabs(2.0 * std::sin(lo + 0.5 * dx) * std::sin(0.5 * dx));
+        double num = Q.offset_integral([&](double t) { return t * std::fabs(std::sin(lo + t)); }, lo, hi);
+        double den = Q.offset_integral([&](double t) { return std::fabs(std::sin(lo + t)); }, lo, hi);
+        off = num / den;
+      }
+      W[e + 1] = Wz;
+      X[e + 1] = lo + off;
+    }
+    H.idm[d].resize(m);
+    H.idp[d].resize(m);
+    H.idc[d].resize(m);
+    H.dlo[d].resize(m);
+    H.dhi[d].resize(m);
+    H.iW[d].resize(m);
+    H.W[d].resize(m);
+    H.wf[d].resize(m + 1);
+    for (int e = 0; e < m; ++e) {
+      double Xm = X[e], X0 = X[e + 1], Xp = X[e + 2];
+      H.idm[d][e] = 1.0 / (X0 - Xm);
+      H.idp[d][e] = 1.0 / (Xp - X0);
+      H.idc[d][e] = 1.0 / (Xp - Xm);
+      H.dlo[d][e] = a[e + 1] - X0;
+      H.dhi[d][e] = (a[e + 1] + dx) - X0;
+      H.W[d][e] = W[e + 1];
+      H.iW[d][e] = 1.0 / W[e + 1];
+    }
+    for (int e = 0; e <= m; ++e) {
+      double xf = D.lo[d] + (e - NG) * dx;
+      double w = 1.0;
+      if (sph && d == 0) w = std::exp(3.0 * xf);
+      if (sph && d == 1) w = std::fabs(std::sin(xf));
+      H.wf[d][e] = w;
+    }
+    if (sph && d == 1) {
+      if (D.bc_lo[1] == FORNAX_BC_AXIS) H.wf[1][NG] = 0.0;
+      if (D.bc_hi[1] == FORNAX_BC_AXIS) H.wf[1][NG + n] = 0.0;
+    }
+  }
+  int m0 = D.n[0] + 2 * NG, m1 = D.n[1] + 2 * NG;
+  if (sph) {
+    double dx0 = H.dx[0], dx1 = H.dx[1];
+    H.rc.resize(m0);
+    H.rf.resize(m0 + 1);
+    H.hr.resize(m0);
+    for (int e = 0; e < m0; ++e) {
+      double lo = D.lo[0] + (e - NG) * dx0;
+      H.rc[e] = std::exp(lo + 0.5 * dx0);
+      // <r^2> with weight r^3 dx1: (3/5) e^{2 lo} (e^{5 dx} - 1) / (e^{3 dx} - 1)
+      double r2 = 0.6 * std::exp(2.0 * lo) * std::expm1(5.0 * dx0) / std::expm1(3.0 * dx0);
+      H.hr[e] = std::sqrt(r2);
+    }
+    for (int e = 0; e <= m0; ++e) H.rf[e] = std::exp(D.lo[0] + (e - NG) * dx0);
+    H.sc.resize(m1);
+    H.sf.resize(m1 + 1);
+    H.hs.resize(m1);
+    H.gam.assign(4 * (size_t)D.n[1], 0.0);
+    for (int e = 0; e < m1; ++e) {
+      double lo = D.lo[1] + (e - NG) * dx1, hi = lo + dx1;
+      H.sc[e] = std::fabs(std::sin(lo + 0.5 * dx1));
+      double num = Q.offset_integral([&](double t) { double s = std::fabs(std::sin(lo + t)); return s * s * s; },
+                                     lo, hi);
+      double den = Q.offset_integral([&](double t) { return std::fabs(std::sin(lo + t)); }, lo, hi);
+      H.hs[e] = std::sqrt(num / den);             // sqrt(<sin^2 theta>)
+    }
+    for (int e = 0; e <= m1; ++e) H.sf[e] = std::fabs(std::sin(D.lo[1] + (e - NG) * dx1));
+    for (int j = 0; j < D.n[1]; ++j) {
+      int e = j + NG;
+      double mid = D.lo[1] + (j + 0.5) * dx1;
+      double cot = std::cos(mid) / std::sin(mid);     // <cot theta> = cot(theta_mid) exactly
+      double s2 = H.hs[e] * H.hs[e];               // <sin^2 theta>
+      H.gam[4 * j + 0] = cot;                        // <Gamma^3_23>
+      H.gam[4 * j + 1] = -s2 * 1.0;                  // <Gamma^1_33> = -<g33>/<g11> <Gamma^3_13>
+      H.gam[4 * j + 2] = -s2 * cot;                  // <Gamma^2_33> = -<g33>/<g22> <Gamma^3_23>
+      H.gam[4 * j + 3] = (H.wf[1][e + 1] - H.wf[1][e]) * H.iW[1][e] - cot;   // eq:grad2P
+    }
+  }
+}
+
+template <typename R>
+size_t table_bytes(const HostGeo& H, bool sph) {
+  size_t n = 0;
+  for (int d = 0; d < 3; ++d) n += 7 * H.idm[d].size() + H.wf[d].size();
+  if (sph) n += H.rc.size() + H.rf.size() + H.hr.size() + H.sc.size() + H.sf.size() + H.hs.size() + H.gam.size();
+  size_t b = n * sizeof(R);
+  for (int d = 0; d < 3; ++d) b += H.W[d].size() * sizeof(double);
+  return b + 256 * 48;   // 256-byte alignment of each of the (at most 31) tables
+}
+
+struct Packer {
+  char* host;
+  char* dev;
+  size_t off = 0;
+  template <typename R>
+  const R* put(const std::vector<double>& v) {
+    off = (off + 255) & ~(size_t)255;
+    R* h = reinterpret_cast<R*>(host + off);
+    for (size_t i = 0; i < v.size(); ++i) h[i] = (R)v[i];
+    const R* dptr = reinterpret_cast<const R*>(dev + off);
+    off += v.size() * sizeof(R);
+    return v.empty() ? nullptr : dptr;
+  }
+};
+
+template <typename R>
+void pack(const HostGeo& H, bool sph, Packer& P, Geo<R>& G) {
+  for (int d = 0; d < 3; ++d) {
+    G.idm[d] = P.put<R>(H.idm[d]);
+    G.idp[d] = P.put<R>(H.idp[d]);
+    G.idc[d] = P.put<R>(H.idc[d]);
+    G.dlo[d] = P.put<R>(H.dlo[d]);
+    G.dhi[d] = P.put<R>(H.dhi[d]);
+    G.iW[d] = P.put<R>(H.iW[d]);
+    G.wf[d] = P.put<R>(H.wf[d]);
+    G.Wd[d] = P.put<double>(H.W[d]);
+    G.dx[d] = (R)H.dx[d];
+  }
+  G.rc = G.rf = G.hr = G.sc = G.sf = G.hs = G.gam = nullptr;
+  if (sph) {
+    G.rc = P.put<R>(H.rc);
+    G.rf = P.put<R>(H.rf);
+    G.hr = P.put<R>(H.hr);
+    G.sc = P.put<R>(H.sc);
+    G.sf = P.put<R>(H.sf);
+    G.hs = P.put<R>(H.hs);
+    G.gam = P.put<R>(H.gam);
+  }
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* fornax_m1_strerror(int code) {
+  switch (code) {
+    case FORNAX_OK: return "ok";
+    case FORNAX_EINVAL: return "invalid argument";
+    case FORNAX_ECFL: return "time step above the CFL limit (or not positive)";
+    case FORNAX_EDEVICE: return "HIP device error";
+    case FORNAX_ENOMEM: return "device allocation failed";
+    case FORNAX_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+  }
+}
+
+int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
+  if (!out) return FORNAX_EINVAL;
+  *out = nullptr;
+  int rc = validate(desc);
+  if (rc != FORNAX_OK) return rc;
+  fornax_m1_ctx* ctx = new (std::nothrow) fornax_m1_ctx();
+  if (!ctx) return FORNAX_ENOMEM;
+  ctx->desc = *desc;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return FORNAX_EDEVICE;
+  }
+  build_geometry(*desc, ctx->hgeo);
+  const bool sph = desc->coord == FORNAX_SPHERICAL_LOGR;
+  size_t bd = table_bytes<double>(ctx->hgeo, sph), bf = table_bytes<float>(ctx->hgeo, sph);
+  ctx->geo_bytes = bd + bf;
+  if (hipMalloc(&ctx->geo_mem, ctx->geo_bytes) != hipSuccess) {
+    delete ctx;
+    return FORNAX_ENOMEM;
+  }
+  std::vector<char> host(ctx->geo_bytes, 0);
+  Packer P{host.data(), (char*)ctx->geo_mem};
+  pack<double>(ctx->hgeo, sph, P, ctx->geo_d);
+  pack<float>(ctx->hgeo, sph, P, ctx->geo_f);
+  if (P.off > ctx->geo_bytes ||
+      hipMemcpy(ctx->geo_mem, host.data(), ctx->geo_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(ctx->geo_mem);
+    delete ctx;
+    return FORNAX_EDEVICE;
+  }
+  // max_dt at cfl = 1
+  double worst = 0.0;
+  const HostGeo& H = ctx->hgeo;
+  for (int j = 0; j < desc->n[1]; ++j)
+    for (int i = 0; i < desc->n[0]; ++i) {
+      double s = 0.0;
+      for (int d = 0; d < desc->ndim; ++d) {
+        double dl = H.dx[d];
+        if (sph) {
+          double hr = H.hr[i + NG], hs = H.hs[j + NG];
+          dl = (d == 2) ? hr * hs * H.dx[2] : hr * H.dx[d];
+        }
+        s += desc->c / dl;
+      }
+      if (s > worst) worst = s;
+    }
+  ctx->max_dt1 = 1.0 / worst;
+  // reduction scratch: one partial per block of the step kernel
+  int zpb = BLOCK / desc->ngroups;
+  int64_t nz = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
+  ctx->nblocks_step = (int)((nz + zpb - 1) / zpb);
+  size_t nb = (size_t)ctx->nblocks_step;
+  void* red = nullptr;
+  if (hipMalloc(&red, nb * (2 * sizeof(double) + 2 * sizeof(int)) + 1024) != hipSuccess) {
+    (void)hipFree(ctx->geo_mem);
+    delete ctx;
+    return FORNAX_ENOMEM;
+  }
+  ctx->p_energy = (double*)red;
+  ctx->p_maxf2 = ctx->p_energy + nb;
+  ctx->p_nun = (int*)(ctx->p_maxf2 + nb);
+  ctx->p_nnp = ctx->p_nun + nb;
+  *out = ctx;
+  return FORNAX_OK;
+}
+
+int fornax_m1_destroy(fornax_m1_ctx* ctx) {
+  if (!ctx) return FORNAX_EINVAL;
+  (void)hipFree(ctx->geo_mem);
+  (void)hipFree(ctx->p_energy);
+  delete ctx;
+  return FORNAX_OK;
+}
+
+double fornax_m1_max_dt(const fornax_m1_ctx* ctx, double cfl) {
+  if (!ctx || !(cfl > 0.0)) return (double)FORNAX_EINVAL;
+  return cfl * ctx->max_dt1;
+}
+
+static int check_state(const fornax_m1_ctx* ctx, const fornax_m1_state* s) {
+  if (!s || !s->E) return FORNAX_EINVAL;
+  size_t al = ctx->desc.precision == FORNAX_FP64 ? 8 : 4;
+  if (!aligned(s->E, al)) return FORNAX_EINVAL;
+  for (int k = 0; k < ctx->desc.ndim; ++k)
+    if (!s->F[k] || !aligned(s->F[k], al)) return FORNAX_EINVAL;
+  return FORNAX_OK;
+}
+
+static int check_coeffs(const fornax_m1_ctx* ctx, const fornax_m1_coeffs* cf) {
+  if (!cf || !cf->kappa || !cf->sigma || !cf->B) return FORNAX_EINVAL;
+  size_t al = ctx->desc.precision == FORNAX_FP64 ? 8 : 4;
+  if (!aligned(cf->kappa, al) || !aligned(cf->sigma, al) || !aligned(cf->B, al)) return FORNAX_EINVAL;
+  return FORNAX_OK;
+}
+
+static bool needs_inflow(const fornax_m1_desc& d) {
+  for (int k = 0; k < d.ndim; ++k)
+    if (d.bc_lo[k] == FORNAX_BC_INFLOW || d.bc_hi[k] == FORNAX_BC_INFLOW) return true;
+  return false;
+}
+
+static bool overlaps(const fornax_m1_ctx* ctx, const fornax_m1_state* a, const fornax_m1_state* b) {
+  const void* pa[4] = {a->E, a->F[0], a->F[1], a->F[2]};
+  const void* pb[4] = {b->E, b->F[0], b->F[1], b->F[2]};
+  for (int i = 0; i <= ctx->desc.ndim; ++i)
+    for (int j = 0; j <= ctx->desc.ndim; ++j)
+      if (pa[i] && pa[i] == pb[j]) return true;
+  return false;
+}
+
+int fornax_m1_step(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
+                   const fornax_m1_coeffs* cf, const double* inflow, double dt, const fornax_m1_diag* diag,
+                   void* stream) {
+  if (!ctx) return FORNAX_EINVAL;
+  int rc;
+  if ((rc = check_state(ctx, in)) || (rc = check_state(ctx, out)) || (rc = check_coeffs(ctx, cf))) return rc;
+  if (overlaps(ctx, in, out)) return FORNAX_EINVAL;
+  if (needs_inflow(ctx->desc) != (inflow != nullptr)) return FORNAX_EINVAL;
+  if (!(dt > 0.0) || dt > ctx->max_dt1 * (1.0 + 1e-12)) return FORNAX_ECFL;
+  return fm1_launch_step(ctx, in, out, cf, inflow, dt, diag, (hipStream_t)stream);
+}
+
+int fornax_m1_flux(fornax_m1_ctx* ctx, const fornax_m1_state* in, const fornax_m1_coeffs* cf, const double* inflow,
+                   void* face_flux[3], void* stream) {
+  if (!ctx || !face_flux) return FORNAX_EINVAL;
+  int rc;
+  if ((rc = check_state(ctx, in)) || (rc = check_coeffs(ctx, cf))) return rc;
+  if (needs_inflow(ctx->desc) != (inflow != nullptr)) return FORNAX_EINVAL;
+  for (int d = 0; d < ctx->desc.ndim; ++d)
+    if (!face_flux[d]) return FORNAX_EINVAL;
+  return fm1_launch_flux(ctx, in, cf, inflow, face_flux, (hipStream_t)stream);
+}
+
+int fornax_m1_source(fornax_m1_ctx* ctx, fornax_m1_state* inout, const fornax_m1_coeffs* cf, double dt,
+                     double* dE_matter, void* stream) {
+  if (!ctx) return FORNAX_EINVAL;
+  int rc;
+  if ((rc = check_state(ctx, inout)) || (rc = check_coeffs(ctx, cf))) return rc;
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return FORNAX_EINVAL;
+  return fm1_launch_source(ctx, inout, cf, dt, dE_matter, (hipStream_t)stream);
+}
+
+int fornax_m1_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const fornax_m1_coeffs* cf,
+                      const double* inflow, double dt, const fornax_m1_state* lam_np1, fornax_m1_state* lam_n,
+                      void* dkappa_accum, void* stream) {
+  if (!ctx || !dkappa_accum) return FORNAX_EINVAL;
+  int rc;
+  if ((rc = check_state(ctx, Un)) || (rc = check_state(ctx, lam_np1)) || (rc = check_state(ctx, lam_n)) ||
+      (rc = check_coeffs(ctx, cf)))
+    return rc;
+  if (overlaps(ctx, lam_n, lam_np1) || overlaps(ctx, lam_n, Un)) return FORNAX_EINVAL;
+  if (needs_inflow(ctx->desc) != (inflow != nullptr)) return FORNAX_EINVAL;
+  if (!(dt > 0.0) || dt > ctx->max_dt1 * (1.0 + 1e-12)) return FORNAX_ECFL;
+  return fm1_launch_adjoint(ctx, Un, cf, inflow, dt, lam_np1, lam_n, dkappa_accum, (hipStream_t)stream);
+}
+
+int fornax_m1_copy_probe(void* dst, const void* src, int64_t nbytes, void* stream) {
+  if (!dst || !src || nbytes < 0 || (nbytes % 16) != 0 || !aligned(dst, 16) || !aligned(src, 16))
+    return FORNAX_EINVAL;
+  return fm1_launch_copy(dst, src, nbytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// m1_internal.h -- types shared by the host side (m1_host.cpp) and the kernels (m1_kernels.hip)
+// of libfornax_m1.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "fornax_m1.h"
+
+namespace fm1 {
+
+constexpr int NG = 2;            // ghost layers of linear reconstruction
+constexpr int BLOCK = 256;       // threads per block of the zone-group kernels
+
+// Geometry tables (device), per axis over the extended zone range e = i + NG,
+// i in [-NG, n + NG); face tables over e in [0, n + 2 NG] (face e is x_{i-1/2}).
+template <typename R>
+struct Geo {
+  const R* idm[3];   // 1 / (X_i - X_{i-1}), X = volume centroid <x^d>
+  const R* idp[3];   // 1 / (X_{i+1} - X_i)
+  const R* dlo[3];   // x_{i-1/2} - X_i
+  const R* dhi[3];   // x_{i+1/2} - X_i
+  const R* iW[3];    // 1 / (integral of the x^d factor of sqrt(g) over the zone)
+  const R* wf[3];    // x^d factor of sqrt(g) at face e (exactly 0 on a polar-axis face)
+  const R* idc[3];   // 1 / (X_{i+1} - X_{i-1}) (MC limiter)
+  const double* Wd[3];  // zone volume factors in double (energy accounting)
+  // spherical (x1 = ln r, x2 = theta) only
+  const R* rc;       // axis 0: r at the zone's coordinate centre
+  const R* rf;       // axis 0: r at face e
+  const R* hr;       // axis 0: sqrt(<r^2>) (cell-centred h_1 = h_2)
+  const R* sc;       // axis 1: |sin theta| at the coordinate centre
+  const R* sf;       // axis 1: |sin theta| at face e
+  const R* hs;       // axis 1: sqrt(<sin^2 theta>)  (h_3 = hr * hs)
+  const R* gam;      // axis 1, active zones j: <Gamma^3_23>, <Gamma^1_33>, <Gamma^2_33>, <Gamma^2_22>
+  R dx[3];           // coordinate spacing
+};
+
+// Host-side copy of the tables in double (the source of both device copies).
+struct HostGeo {
+  int n[3];
+  std::vector<double> idm[3], idp[3], dlo[3], dhi[3], iW[3], W[3], wf[3], idc[3];
+  std::vector<double> rc, rf, hr, sc, sf, hs, gam;
+  double dx[3];
+};
+
+struct StepArgsBase {
+  int n[3];
+  int G, ndim;
+  int bc_lo[3], bc_hi[3];
+  int limiter, closure;
+  int zones_per_block;
+  int64_t nzones;
+  double c, dt;
+  double f2_fp64;            // (f_fp64)^2, MIXED only
+  const double* inflow;      // [G][1+ndim] or null
+};
+
+template <typename S>
+struct StepArgs : StepArgsBase {
+  const S* E;
+  const S* F[3];
+  S* Eo;
+  S* Fo[3];
+  const S* kap;
+  const S* sig;
+  const S* B;
+  double* dEm;               // per zone, nullable
+  // per-block partial reductions (null: no diagnostics)
+  double* p_energy;
+  double* p_maxf2;
+  int* p_nun;
+  int* p_nnp;
+};
+
+}  // namespace fm1
+
+struct fornax_m1_ctx {
+  fornax_m1_desc desc;
+  int device;
+  fm1::HostGeo hgeo;
+  fm1::Geo<double> geo_d;
+  fm1::Geo<float> geo_f;
+  void* geo_mem;              // one allocation holding every device table
+  size_t geo_bytes;
+  double max_dt1;             // max_dt(cfl = 1)
+  // reduction scratch
+  int nblocks_step;
+  double* p_energy;
+  double* p_maxf2;
+  int* p_nun;
+  int* p_nnp;
+};
+
+// kernel launchers (m1_kernels.hip)
+int fm1_launch_step(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
+                    const fornax_m1_coeffs* cf, const double* inflow, double dt,
+                    const fornax_m1_diag* diag, hipStream_t stream);
+int fm1_launch_flux(fornax_m1_ctx* ctx, const fornax_m1_state* in, const fornax_m1_coeffs* cf,
+                    const double* inflow, void* face_flux[3], hipStream_t stream);
+int fm1_launch_source(fornax_m1_ctx* ctx, fornax_m1_state* inout, const fornax_m1_coeffs* cf,
+                      double dt, double* dEm, hipStream_t stream);
+int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const fornax_m1_coeffs* cf,
+                       const double* inflow, double dt, const fornax_m1_state* lam_np1,
+                       fornax_m1_state* lam_n, void* dkappa, hipStream_t stream);
+int fm1_launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t stream);

@@ -1,0 +1,294 @@
+"""Python binding of libfornax_m1 (ctypes over the C interface in include/fornax_m1.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+PyTorch provides device memory (tensors) and the current HIP stream.  Importing this module
+raises if the library has not been built (``python -m paper_1806_07390_amd.build``).
+
+Arrays are CUDA (HIP) tensors of shape ``(n2, n1, n0, G)`` (group innermost), dtype
+float64 for FP64 contexts and float32 for MIXED contexts; flux components are covariant.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfornax_m1.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1806_07390_amd.build` "
+                      "(there is no fallback implementation)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FORNAX_OK, FORNAX_EINVAL, FORNAX_ECFL, FORNAX_EDEVICE, FORNAX_ENOMEM, FORNAX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+CARTESIAN, SPHERICAL_LOGR = 0, 1
+BC_OUTFLOW, BC_PERIODIC, BC_REFLECT, BC_INFLOW, BC_AXIS = 0, 1, 2, 3, 4
+FP64, MIXED = 0, 1
+LIMITER_MINMOD, LIMITER_MC, LIMITER_NONE = 0, 1, 2
+CLOSURE_M1, CLOSURE_EDDINGTON = 0, 1
+
+EXPORTED = ["fornax_m1_create", "fornax_m1_destroy", "fornax_m1_max_dt", "fornax_m1_step", "fornax_m1_flux",
+            "fornax_m1_source", "fornax_m1_adjoint", "fornax_m1_copy_probe", "fornax_m1_strerror"]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("ngroups", ctypes.c_int32),
+        ("coord", ctypes.c_int32),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("bc_lo", ctypes.c_int32 * 3),
+        ("bc_hi", ctypes.c_int32 * 3),
+        ("limiter", ctypes.c_int32),
+        ("closure", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("c", ctypes.c_double),
+        ("f_fp64", ctypes.c_double),
+    ]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_void_p), ("F", ctypes.c_void_p * 3)]
+
+
+class Coeffs(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("B", ctypes.c_void_p)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("energy_total", ctypes.c_void_p), ("dE_matter", ctypes.c_void_p), ("max_f", ctypes.c_void_p),
+                ("n_unrealizable", ctypes.c_void_p), ("n_nonpositive", ctypes.c_void_p)]
+
+
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_lib.fornax_m1_create.argtypes = [_P(Desc), _P(_vp)]
+_lib.fornax_m1_create.restype = ctypes.c_int
+_lib.fornax_m1_destroy.argtypes = [_vp]
+_lib.fornax_m1_max_dt.argtypes = [_vp, ctypes.c_double]
+_lib.fornax_m1_max_dt.restype = ctypes.c_double
+_lib.fornax_m1_step.argtypes = [_vp, _P(State), _P(State), _P(Coeffs), _vp, ctypes.c_double, _P(Diag), _vp]
+_lib.fornax_m1_flux.argtypes = [_vp, _P(State), _P(Coeffs), _vp, _vp * 3, _vp]
+_lib.fornax_m1_source.argtypes = [_vp, _P(State), _P(Coeffs), ctypes.c_double, _vp, _vp]
+_lib.fornax_m1_adjoint.argtypes = [_vp, _P(State), _P(Coeffs), _vp, ctypes.c_double, _P(State), _P(State), _vp, _vp]
+_lib.fornax_m1_copy_probe.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
+_lib.fornax_m1_strerror.argtypes = [ctypes.c_int]
+_lib.fornax_m1_strerror.restype = ctypes.c_char_p
+
+
+class FornaxError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {_lib.fornax_m1_strerror(code).decode()} (code {code})")
+        self.code = code
+
+
+def _check(code, what):
+    if code != FORNAX_OK:
+        raise FornaxError(code, what)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Config:
+    ndim: int
+    n: tuple
+    G: int
+    coord: int = CARTESIAN
+    lo: tuple = (0.0, 0.0, 0.0)
+    hi: tuple = (1.0, 1.0, 1.0)
+    bc_lo: tuple = (BC_OUTFLOW,) * 3
+    bc_hi: tuple = (BC_OUTFLOW,) * 3
+    limiter: int = LIMITER_MINMOD
+    closure: int = CLOSURE_M1
+    precision: int = FP64
+    c: float = 1.0
+    f_fp64: float = 0.9
+
+    @classmethod
+    def from_workload(cls, w, precision=FP64, **kw):
+        return cls(ndim=w.ndim, n=tuple(w.n), G=w.G, coord=w.coord, lo=tuple(w.lo), hi=tuple(w.hi),
+                   bc_lo=tuple(w.bc_lo), bc_hi=tuple(w.bc_hi), c=w.c, precision=precision, **kw)
+
+
+class Context:
+    """A problem description bound to the current HIP device (owns the geometry tables)."""
+
+    def __init__(self, cfg: Config):
+        self.cfg = cfg
+        d = Desc()
+        d.ndim = cfg.ndim
+        n = list(cfg.n) + [1] * (3 - len(cfg.n))
+        d.n[:] = n
+        d.ngroups = cfg.G
+        d.coord = cfg.coord
+        d.lo[:] = list(cfg.lo)
+        d.hi[:] = list(cfg.hi)
+        d.bc_lo[:] = list(cfg.bc_lo)
+        d.bc_hi[:] = list(cfg.bc_hi)
+        d.limiter = cfg.limiter
+        d.closure = cfg.closure
+        d.precision = cfg.precision
+        d.c = cfg.c
+        d.f_fp64 = cfg.f_fp64
+        self.desc = d
+        self.shape = (n[2], n[1], n[0], cfg.G)
+        self.nzones = n[0] * n[1] * n[2]
+        self.dtype = torch.float64 if cfg.precision == FP64 else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        _check(_lib.fornax_m1_create(ctypes.byref(d), ctypes.byref(h)), "fornax_m1_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.fornax_m1_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -----------------------------------------------------------------------------
+    def _check_arr(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} has dtype {t.dtype}, expected {self.dtype}")
+        if tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {self.shape}, got {tuple(t.shape)}")
+
+    def _state(self, E, F, name="state"):
+        self._check_arr(E, f"{name}.E")
+        if len(F) != self.cfg.ndim:
+            raise ValueError(f"{name}.F needs {self.cfg.ndim} components")
+        s = State()
+        s.E = E.data_ptr()
+        for k, f in enumerate(F):
+            self._check_arr(f, f"{name}.F[{k}]")
+            s.F[k] = f.data_ptr()
+        return s
+
+    def _coeffs(self, kappa, sigma, B):
+        for t, nm in ((kappa, "kappa"), (sigma, "sigma"), (B, "B")):
+            self._check_arr(t, nm)
+        c = Coeffs()
+        c.kappa, c.sigma, c.B = kappa.data_ptr(), sigma.data_ptr(), B.data_ptr()
+        return c
+
+    def _inflow(self, inflow):
+        if inflow is None:
+            return None
+        if inflow.dtype != torch.float64 or inflow.device.type != "cuda" or not inflow.is_contiguous() \
+                or tuple(inflow.shape) != (self.cfg.G, 1 + self.cfg.ndim):
+            raise ValueError("inflow must be a contiguous float64 CUDA tensor [G][1+ndim]")
+        return ctypes.c_void_p(inflow.data_ptr())
+
+    def empty_state(self):
+        E = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        return E, [torch.empty_like(E) for _ in range(self.cfg.ndim)]
+
+    # -- entry points ------------------------------------------------------------------------
+    def max_dt(self, cfl: float) -> float:
+        v = _lib.fornax_m1_max_dt(self._h, cfl)
+        if v < 0:
+            raise FornaxError(int(v), "fornax_m1_max_dt")
+        return v
+
+    def step(self, E, F, kappa, sigma, B, dt, out=None, inflow=None, diag=None, stream=None):
+        """One step; returns (E_out, [F_out]).  diag: dict of preallocated tensors (optional)."""
+        sin = self._state(E, F, "in")
+        if out is None:
+            out = self.empty_state()
+        sout = self._state(out[0], out[1], "out")
+        cf = self._coeffs(kappa, sigma, B)
+        dg = None
+        if diag is not None:
+            dg = Diag()
+            dg.energy_total = _ptr(diag.get("energy_total"))
+            dg.dE_matter = _ptr(diag.get("dE_matter"))
+            dg.max_f = _ptr(diag.get("max_f"))
+            dg.n_unrealizable = _ptr(diag.get("n_unrealizable"))
+            dg.n_nonpositive = _ptr(diag.get("n_nonpositive"))
+        _check(_lib.fornax_m1_step(self._h, ctypes.byref(sin), ctypes.byref(sout), ctypes.byref(cf),
+                                   self._inflow(inflow), dt, ctypes.byref(dg) if dg is not None else None,
+                                   _stream(stream)), "fornax_m1_step")
+        return out
+
+    def new_diag(self):
+        dev = self.device
+        return dict(energy_total=torch.zeros(1, dtype=torch.float64, device=dev),
+                    dE_matter=torch.zeros(self.nzones, dtype=torch.float64, device=dev),
+                    max_f=torch.zeros(1, dtype=torch.float64, device=dev),
+                    n_unrealizable=torch.zeros(1, dtype=torch.int32, device=dev),
+                    n_nonpositive=torch.zeros(1, dtype=torch.int32, device=dev))
+
+    def flux(self, E, F, kappa, sigma, B, inflow=None, stream=None):
+        """Face fluxes per direction: list of tensors [faces_d..., G, 1+ndim]."""
+        sin = self._state(E, F, "in")
+        cf = self._coeffs(kappa, sigma, B)
+        outs = []
+        arr = (ctypes.c_void_p * 3)()
+        for d in range(self.cfg.ndim):
+            s = list(self.shape[:3])
+            s[2 - d] += 1
+            t = torch.empty(tuple(s) + (self.cfg.G, 1 + self.cfg.ndim), dtype=self.dtype, device=self.device)
+            outs.append(t)
+            arr[d] = t.data_ptr()
+        _check(_lib.fornax_m1_flux(self._h, ctypes.byref(sin), ctypes.byref(cf), self._inflow(inflow), arr,
+                                   _stream(stream)), "fornax_m1_flux")
+        return outs
+
+    def source(self, E, F, kappa, sigma, B, dt, dE_matter=None, stream=None):
+        """Implicit interaction update in place."""
+        s = self._state(E, F, "inout")
+        cf = self._coeffs(kappa, sigma, B)
+        _check(_lib.fornax_m1_source(self._h, ctypes.byref(s), ctypes.byref(cf), dt, _ptr(dE_matter),
+                                     _stream(stream)), "fornax_m1_source")
+
+    def adjoint(self, E, F, kappa, sigma, B, dt, lamE, lamF, out=None, dkappa=None, inflow=None, stream=None):
+        """lam_n = J^T lam_{n+1}; dkappa += (dU^{n+1}/dkappa)^T lam_{n+1}. Returns (lamE_n, [lamF_n], dkappa)."""
+        su = self._state(E, F, "Un")
+        sl = self._state(lamE, lamF, "lam_np1")
+        if out is None:
+            out = self.empty_state()
+        so = self._state(out[0], out[1], "lam_n")
+        if dkappa is None:
+            dkappa = torch.zeros(self.shape, dtype=self.dtype, device=self.device)
+        self._check_arr(dkappa, "dkappa")
+        cf = self._coeffs(kappa, sigma, B)
+        _check(_lib.fornax_m1_adjoint(self._h, ctypes.byref(su), ctypes.byref(cf), self._inflow(inflow), dt,
+                                      ctypes.byref(sl), ctypes.byref(so), ctypes.c_void_p(dkappa.data_ptr()),
+                                      _stream(stream)), "fornax_m1_adjoint")
+        return out[0], out[1], dkappa
+
+    def run(self, E, F, kappa, sigma, B, dt, nsteps, inflow=None, diag=None):
+        """nsteps steps with ping-pong buffers; returns (E, [F]) (new tensors)."""
+        a = (E.clone(), [f.clone() for f in F])
+        b = self.empty_state()
+        for s in range(nsteps):
+            self.step(a[0], a[1], kappa, sigma, B, dt, out=b, inflow=inflow,
+                      diag=diag if s == nsteps - 1 else None)
+            a, b = b, a
+        return a
+
+
+def copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    nbytes = src.numel() * src.element_size()
+    _check(_lib.fornax_m1_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                     _stream(stream)), "fornax_m1_copy_probe")

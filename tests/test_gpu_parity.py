@@ -1,0 +1,229 @@
+"""GPU parity: the HIP library (through the C interface) against the CPU FP64 oracle on the
+same seeded inputs.  Reduced sizes span several blocks and ragged tails; the full workload
+sizes are checked on sampled zones of one step, in the launch configuration of bench.py."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import m1_oracle as orc
+from paper_1806_07390_amd import workloads as wl
+from tests.parity_util import (TOL_FP64, TOL_MIXED_RUN, TOL_MIXED_STEP, gpu_run, problem_of, rel_l1, to_dev,
+                               to_host)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m1():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1806_07390_amd import m1 as mod
+    return mod
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dt_of(w, p):
+    return w.dt if w.dt is not None else orc.max_dt(p, w.cfl)
+
+
+def run_pair(m1, w, precision, nsteps, **opts):
+    p = problem_of(w, **{k: v for k, v in opts.items() if k in ("limiter", "closure")})
+    dt = dt_of(w, p)
+    say(f"case {w.name} n={w.n} G={w.G} prec={precision} steps={nsteps} opts={opts}")
+    E, F, _ = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, nsteps, inflow=w.inflow)
+    cfg = m1.Config.from_workload(w, precision=precision, **opts)
+    ctx = m1.Context(cfg)
+    Eg, Fg = gpu_run(ctx, w, dt, nsteps)
+    return rel_l1(Eg, Fg, E, F, w.c)
+
+
+# ------------------------------------------------------------------------------------------
+def test_slab1d_full_fp64(m1):
+    w = wl.slab1d()
+    eE, eF = run_pair(m1, w, m1.FP64, w.steps)
+    say("slab1d", eE, eF)
+    assert eE <= TOL_FP64 and eF <= TOL_FP64
+
+
+@pytest.mark.parametrize("n", [(64, 64), (45, 37)])
+def test_blobs2d_fp64(m1, n):
+    w = wl.blobs2d(n=n[0], G=4, steps=20)
+    if n[0] != n[1]:
+        # ragged, non-square: slice the square input
+        w.E = np.ascontiguousarray(w.E[:, : n[1], : n[0]])
+        w.F = [np.ascontiguousarray(f[:, : n[1], : n[0]]) for f in w.F]
+        w.kappa = np.ascontiguousarray(w.kappa[:, : n[1], : n[0]])
+        w.sigma = np.ascontiguousarray(w.sigma[:, : n[1], : n[0]])
+        w.B = np.ascontiguousarray(w.B[:, : n[1], : n[0]])
+        w.n = (n[0], n[1], 1)
+    eE, eF = run_pair(m1, w, m1.FP64, w.steps)
+    say("blobs2d", n, eE, eF)
+    assert eE <= TOL_FP64 and eF <= TOL_FP64
+
+
+def test_blobs2d_options_fp64(m1):
+    w = wl.blobs2d(n=24, G=3, steps=8)
+    for opts in (dict(limiter=m1.LIMITER_MC), dict(limiter=m1.LIMITER_NONE), dict(closure=m1.CLOSURE_EDDINGTON)):
+        eE, eF = run_pair(m1, w, m1.FP64, w.steps, **opts)
+        assert eE <= TOL_FP64 and eF <= TOL_FP64, opts
+
+
+def test_core3d_reduced_fp64_and_mixed(m1):
+    w = wl.core3d(n=20, G=12, steps=10)
+    eE, eF = run_pair(m1, w, m1.FP64, w.steps)
+    say("core3d fp64", eE, eF)
+    assert eE <= TOL_FP64 and eF <= TOL_FP64
+    eE1, eF1 = run_pair(m1, w, m1.MIXED, 1)
+    eEn, eFn = run_pair(m1, w, m1.MIXED, w.steps)
+    say("core3d mixed", eE1, eF1, eEn, eFn)
+    assert eE1 <= TOL_MIXED_STEP and eF1 <= TOL_MIXED_STEP
+    assert eEn <= TOL_MIXED_RUN and eFn <= TOL_MIXED_RUN
+
+
+def test_sphere_reduced_fp64_and_mixed(m1):
+    w = wl.sphere3d(nr=24, nth=16, nph=16, G=4, steps=20)
+    eE, eF = run_pair(m1, w, m1.FP64, w.steps)
+    say("sphere fp64", eE, eF)
+    assert eE <= TOL_FP64 and eF <= TOL_FP64
+    eE1, eF1 = run_pair(m1, w, m1.MIXED, w.steps)
+    say("sphere mixed", eE1, eF1)
+    assert eE1 <= TOL_MIXED_RUN and eF1 <= TOL_MIXED_RUN
+
+
+def test_sphere_2d_axisymmetric_fp64(m1):
+    w = wl.sphere3d(nr=20, nth=12, nph=1, G=3, steps=15, ndim=2)
+    eE, eF = run_pair(m1, w, m1.FP64, w.steps)
+    assert eE <= TOL_FP64 and eF <= TOL_FP64
+
+
+def test_reflect_boundaries_fp64(m1):
+    w = wl.blobs2d(n=20, G=2, steps=6)
+    w.bc_lo = (wl.BC_REFLECT, wl.BC_OUTFLOW, 0)
+    w.bc_hi = (wl.BC_OUTFLOW, wl.BC_REFLECT, 0)
+    eE, eF = run_pair(m1, w, m1.FP64, w.steps)
+    assert eE <= TOL_FP64 and eF <= TOL_FP64
+
+
+# ------------------------------------------------------------------------------------------
+def test_flux_and_source_entry_points(m1):
+    w = wl.sphere3d(nr=12, nth=8, nph=8, G=3, steps=1)
+    rng = np.random.default_rng(2)
+    w.E = w.B * (1 + rng.random(w.E.shape))
+    w.F = [0.3 * w.E * rng.uniform(-1, 1, w.E.shape) for _ in range(3)]
+    p = problem_of(w)
+    ctx = m1.Context(m1.Config.from_workload(w))
+    E = to_dev(w.E, torch.float64)
+    F = [to_dev(f, torch.float64) for f in w.F]
+    k, s, B = (to_dev(x, torch.float64) for x in (w.kappa, w.sigma, w.B))
+    inflow = to_dev(w.inflow, torch.float64)
+    fl = ctx.flux(E, F, k, s, B, inflow=inflow)
+    for d in range(3):
+        ref = orc.flux(p, w.E, w.F, w.kappa, w.sigma, w.B, d, inflow=w.inflow)
+        got = to_host(fl[d])
+        scale = np.abs(ref).max()
+        assert np.max(np.abs(got - ref)) <= 1e-13 * scale, d
+    Es, Fs, dEm = orc.source(p, w.E, w.F, w.kappa, w.sigma, w.B, 0.05)
+    dE = torch.zeros(ctx.nzones, dtype=torch.float64, device="cuda")
+    ctx.source(E, F, k, s, B, 0.05, dE_matter=dE)
+    assert np.allclose(to_host(E), Es, rtol=1e-14, atol=0)
+    for kk in range(3):
+        assert np.allclose(to_host(F[kk]), Fs[kk], rtol=1e-14, atol=0)
+    assert np.allclose(dE.cpu().numpy(), dEm, rtol=1e-12, atol=1e-15 * np.abs(dEm).max())
+
+
+def test_diagnostics_match_oracle(m1):
+    w = wl.blobs2d(n=40, G=4, steps=3)
+    p = problem_of(w)
+    E, F, dg, dEm = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, w.dt, w.steps, want_dEm=True)
+    ctx = m1.Context(m1.Config.from_workload(w))
+    Eg, Fg, dgg = gpu_run(ctx, w, w.dt, w.steps, diag=True)
+    assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-13)
+    assert dgg["max_f"][0] == pytest.approx(dg["max_f"], rel=1e-13)
+    assert int(dgg["n_unrealizable"][0]) == dg["n_unrealizable"]
+    assert int(dgg["n_nonpositive"][0]) == dg["n_nonpositive"]
+    assert np.allclose(dgg["dE_matter"], dEm, rtol=1e-10, atol=1e-14 * np.abs(dEm).max())
+
+
+def test_step_is_deterministic_and_groups_independent(m1):
+    w = wl.blobs2d(n=32, G=4, steps=3)
+    ctx = m1.Context(m1.Config.from_workload(w))
+    a = gpu_run(ctx, w, w.dt, 3)
+    b = gpu_run(ctx, w, w.dt, 3)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1][0], b[1][0])
+    g = 2
+    w1 = wl.blobs2d(n=32, G=4, steps=3)
+    for nm in ("E", "kappa", "sigma", "B"):
+        setattr(w1, nm, np.ascontiguousarray(getattr(w1, nm)[..., g:g + 1]))
+    w1.F = [np.ascontiguousarray(f[..., g:g + 1]) for f in w1.F]
+    w1.G = 1
+    c1 = m1.Context(m1.Config.from_workload(w1))
+    o = gpu_run(c1, w1, w1.dt, 3)
+    assert np.array_equal(o[0][..., 0], a[0][..., g])
+
+
+def test_cfl_and_argument_errors(m1):
+    w = wl.blobs2d(n=16, G=2, steps=1)
+    ctx = m1.Context(m1.Config.from_workload(w))
+    assert ctx.max_dt(0.4) == pytest.approx(w.dt, rel=1e-13)
+    E = to_dev(w.E, torch.float64)
+    F = [to_dev(f, torch.float64) for f in w.F]
+    k = to_dev(w.kappa, torch.float64)
+    with pytest.raises(m1.FornaxError) as ei:
+        ctx.step(E, F, k, k, k, 1.01 * ctx.max_dt(1.0))
+    assert ei.value.code == m1.FORNAX_ECFL
+    with pytest.raises(m1.FornaxError) as ei:
+        ctx.step(E, F, k, k, k, w.dt, out=(E, F))        # aliasing in/out
+    assert ei.value.code == m1.FORNAX_EINVAL
+    with pytest.raises(TypeError):
+        ctx.step(E.float(), F, k, k, k, w.dt)
+
+
+# ------------------------------------------------------------------------------------------
+# full workload sizes: one step, sampled zones against the oracle evaluated zone by zone
+# ------------------------------------------------------------------------------------------
+def _sampled_step(m1, w, precision, nsample=1500, seed=7):
+    p = problem_of(w)
+    dt = dt_of(w, p)
+    cfg = m1.Config.from_workload(w, precision=precision)
+    ctx = m1.Context(cfg)
+    say(f"full-size sampled step {w.name} n={w.n} G={w.G} prec={precision}")
+    Eg, Fg = gpu_run(ctx, w, dt, 1)
+    nz = w.n[0] * w.n[1] * w.n[2]
+    rng = np.random.default_rng(seed)
+    zones = np.unique(np.concatenate([rng.integers(0, nz, nsample), [0, nz - 1]]))
+    Es, Fs, _ = orc.step_zones(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, zones, inflow=w.inflow)
+    Eg = Eg.reshape(nz, w.G)[zones]
+    Fg = [f.reshape(nz, w.G)[zones] for f in Fg]
+    del ctx
+    torch.cuda.empty_cache()
+    return rel_l1(Eg, Fg, Es, Fs, w.c)
+
+
+def test_full_size_blobs2d_fp64(m1):
+    eE, eF = _sampled_step(m1, wl.blobs2d(), m1.FP64)
+    say("blobs2d full", eE, eF)
+    assert eE <= TOL_FP64 and eF <= TOL_FP64
+
+
+def test_full_size_core3d(m1):
+    w = wl.core3d()
+    eE, eF = _sampled_step(m1, w, m1.FP64)
+    assert eE <= TOL_FP64 and eF <= TOL_FP64
+    eE, eF = _sampled_step(m1, w, m1.MIXED)
+    say("core3d full mixed", eE, eF)
+    assert eE <= TOL_MIXED_STEP and eF <= TOL_MIXED_STEP
+
+
+def test_full_size_sphere(m1):
+    w = wl.sphere3d()
+    eE, eF = _sampled_step(m1, w, m1.MIXED)
+    say("sphere full mixed", eE, eF)
+    assert eE <= TOL_MIXED_STEP and eF <= TOL_MIXED_STEP
+    eE, eF = _sampled_step(m1, w, m1.FP64)
+    assert eE <= TOL_FP64 and eF <= TOL_FP64
