@@ -53,16 +53,15 @@ def time_steps(ctx, inputs, dt, steps, warmup, with_diag=True):
     a = (E.clone(), [f.clone() for f in F])
     b = ctx.empty_state()
     diag = ctx.new_diag() if with_diag else None
+    step, _ = ctx.stepper(a, b, k, s, B, dt, inflow=inflow, diag=diag)
     for _ in range(warmup):
-        ctx.step(a[0], a[1], k, s, B, dt, out=b, inflow=inflow, diag=diag)
-        a, b = b, a
+        step()
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(steps):
-        ctx.step(a[0], a[1], k, s, B, dt, out=b, inflow=inflow, diag=diag)
-        a, b = b, a
+        step()
     e1.record(st)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -207,7 +206,7 @@ def main():
                    "zone_groups": w.zone_groups, "dt": w.dt},
         "roofline": {"bound": "hbm", "achieved": round(h["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(h["achieved"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_step<double,double,2,false>", "bytes_per_zone_group": h["bpz"],
+                     "kernel": "k_step_tiled<double,double,2,false>", "bytes_per_zone_group": h["bpz"],
                      "kernel_ms": round(h["ms_kernel"], 5)},
         "extra": extra,
     }

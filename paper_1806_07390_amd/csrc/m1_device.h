@@ -1,0 +1,415 @@
+// m1_device.h -- device functions of the M1 step shared by the kernels of libfornax_m1:
+// ghost-zone rules, linear reconstruction with the realizability fallback, the M1 closure,
+// the HLL flux with the diffusion correction, the geometric source terms and the implicit
+// interaction update.  ND (1..3) is the number of active directions and flux components;
+// components beyond ND are identically zero and never computed.
+//
+// Method (Skinner et al. 2019, FORNAX): eq:finite_vol, eq:recon_constraints (n = 1, minmod
+// limited), the M1 closure, eq:hll / eq:epsilon, the covariant geometric sources with the
+// overrides eq:angmom / eq:grad2P, eq:be_update.  Readings of details the paper leaves open:
+// wavespeeds +-c (physical), i.e. +-c/h_d in x^d; tau_cell = mean (kappa + sigma) of the two
+// zones times their mean proper width; epsilon on the energy flux only; a zone whose face
+// state in direction d is not realizable (E <= 0 or |F^| > cE) is piecewise constant in d;
+// emissivity j = c kappa B; f^2 clamped to 1, Eddington value for E <= 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "m1_internal.h"
+
+namespace fm1 {
+
+template <typename R>
+__device__ __forceinline__ R minmod(R a, R b) {
+  return (a * b <= R(0)) ? R(0) : (fabs(a) <= fabs(b) ? a : b);
+}
+
+// 1/x: the hardware estimate refined by two Newton-Raphson steps (double; within a couple of
+// ulp for the normal, finite, non-zero arguments used here), or the 1-ulp float estimate.
+__device__ __forceinline__ double rcp_(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// sqrt(x) for normal positive arguments: reciprocal square-root estimate, two coupled
+// Newton steps for (sqrt x, 1/(2 sqrt x)) and a final residual correction (double), or the
+// hardware float square root.
+__device__ __forceinline__ double sqrt_(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// cell-centred scale factors sqrt(<g_kk>) at extended indices (ei, ej)
+template <typename R, bool SPH>
+__device__ __forceinline__ void cell_h(const Geo<R>& geo, int ei, int ej, R h[3]) {
+  if constexpr (SPH) {
+    R r = geo.hr[ei];
+    h[0] = r;
+    h[1] = r;
+    h[2] = r * geo.hs[ej];
+  } else {
+    h[0] = h[1] = h[2] = R(1);
+  }
+}
+
+// scale factors at the centre of a d-face with extended face index ef, zone row (ei, ej)
+template <typename R, bool SPH>
+__device__ __forceinline__ void face_h(const Geo<R>& geo, int d, int ei, int ej, int ef, R h[3]) {
+  if constexpr (SPH) {
+    R r = (d == 0) ? geo.rf[ef] : geo.rc[ei];
+    R s = (d == 1) ? geo.sf[ef] : geo.sc[ej];
+    h[0] = r;
+    h[1] = r;
+    h[2] = r * s;
+  } else {
+    h[0] = h[1] = h[2] = R(1);
+  }
+}
+
+// Proper width h_d Delta x^d of the zone with extended indices (ei, ej) along d.
+template <typename R, bool SPH>
+__device__ __forceinline__ R proper_width(const Geo<R>& geo, int d, int ei, int ej) {
+  if constexpr (SPH) {
+    R r = geo.hr[ei];
+    return (d == 2) ? r * geo.hs[ej] * geo.dx[2] : r * geo.dx[d];
+  } else {
+    return geo.dx[d];
+  }
+}
+
+// State of the zone whose index along d is m (possibly a ghost) in the row of (i, j, k), and
+// optionally its total opacity.  Ghost rules: periodic wrap, outflow copy, reflection with
+// the normal flux flipped, prescribed inflow (E, physical F) with the ghost's own scale
+// factors, and the polar-axis copy (mirror in theta, shift n2/2 in phi, flip F_theta, F_phi).
+// Zone-group indices fit in 32 bits (checked when the context is created).
+template <typename S, typename R, bool SPH, int ND>
+__device__ __forceinline__ void fetch(const StepArgs<S>& a, const Geo<R>& geo, int d, int m, int i, int j, int k,
+                                      int grp, R q[4], R* ks) {
+  int mm[3] = {i, j, k};
+  mm[d] = m;
+  R sg[3] = {R(1), R(1), R(1)};
+  bool infl = false;
+  const int nd = a.n[d];
+  if (m < 0 || m >= nd) {
+    const bool low = m < 0;
+    const int bc = low ? a.bc_lo[d] : a.bc_hi[d];
+    if (bc == FORNAX_BC_PERIODIC) {
+      mm[d] = low ? m + nd : m - nd;
+      if (mm[d] < 0 || mm[d] >= nd) mm[d] = ((m % nd) + nd) % nd;
+    } else if (bc == FORNAX_BC_OUTFLOW) {
+      mm[d] = low ? 0 : nd - 1;
+    } else if (bc == FORNAX_BC_REFLECT) {
+      mm[d] = low ? -1 - m : 2 * nd - 1 - m;
+      sg[d] = R(-1);
+    } else if (bc == FORNAX_BC_INFLOW) {
+      mm[d] = low ? 0 : nd - 1;
+      infl = true;
+    } else {  // polar axis
+      mm[d] = low ? -1 - m : 2 * nd - 1 - m;
+      mm[2] = (mm[2] + a.n[2] / 2) % a.n[2];
+      sg[1] = R(-1);
+      sg[2] = R(-1);
+    }
+  }
+  const int zg = ((mm[2] * a.n[1] + mm[1]) * a.n[0] + mm[0]) * a.G + grp;
+  if (ks) *ks = R(a.kap[zg]) + R(a.sig[zg]);
+  if (infl) {
+    const double* in = a.inflow + grp * (1 + ND);
+    R h[3];
+    cell_h<R, SPH>(geo, (d == 0 ? m : i) + NG, (d == 1 ? m : j) + NG, h);
+    q[0] = R(in[0]);
+    for (int c = 0; c < ND; ++c) q[1 + c] = h[c] * R(in[1 + c]);
+  } else {
+    q[0] = R(a.E[zg]);
+    for (int c = 0; c < ND; ++c) q[1 + c] = sg[c] * R(a.F[c][zg]);
+  }
+  for (int c = ND; c < 3; ++c) q[1 + c] = R(0);
+}
+
+// E > 0 and |F^| <= cE with F^_k = F_k / h_k
+template <typename R, bool SPH, int ND>
+__device__ __forceinline__ bool realizable(const R q[4], const R h[3], R c) {
+  R F2 = R(0);
+  for (int k = 0; k < ND; ++k) {
+    R fk = SPH ? q[1 + k] * rcp_(h[k]) : q[1 + k];
+    F2 += fk * fk;
+  }
+  R cE = c * q[0];
+  return (q[0] > R(0)) && (F2 <= cE * cE);
+}
+
+// Linear reconstruction of one zone along d (extended index e): face states at its lower
+// and upper faces, with the piecewise-constant fallback when either is not realizable.
+template <typename R, bool SPH, int ND>
+__device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>& geo, int d, int e, const R qm[4],
+                                            const R q0[4], const R qp[4], const R hlo[3], const R hhi[3],
+                                            bool lo_open, bool hi_open, R lo[4], R hi[4]) {
+  const R c = R(a.c);
+  R s[4];
+  R dl = R(-0.5), dh = R(0.5);
+  if constexpr (SPH) {
+    // slopes between volume centroids, face offsets from the centroid
+    const R idm = geo.idm[d][e], idp = geo.idp[d][e];
+    dl = geo.dlo[d][e];
+    dh = geo.dhi[d][e];
+    for (int cp = 0; cp <= ND; ++cp) {
+      const R sa = (q0[cp] - qm[cp]) * idm, sb = (qp[cp] - q0[cp]) * idp;
+      if (a.limiter == FORNAX_LIMITER_MINMOD) {
+        s[cp] = minmod(sa, sb);
+      } else if (a.limiter == FORNAX_LIMITER_MC) {
+        s[cp] = minmod(R(2) * sa, minmod(R(2) * sb, (qp[cp] - qm[cp]) * geo.idc[d][e]));
+      } else {
+        s[cp] = R(0);
+      }
+    }
+  } else {
+    // uniform Cartesian zones: centroid = centre, faces at -+ dx/2 (slope times dx)
+    (void)geo;
+    (void)d;
+    (void)e;
+    for (int cp = 0; cp <= ND; ++cp) {
+      const R dm = q0[cp] - qm[cp], dp = qp[cp] - q0[cp];
+      if (a.limiter == FORNAX_LIMITER_MINMOD) {
+        s[cp] = minmod(dm, dp);
+      } else if (a.limiter == FORNAX_LIMITER_MC) {
+        s[cp] = minmod(R(2) * dm, minmod(R(2) * dp, R(0.5) * (dm + dp)));
+      } else {
+        s[cp] = R(0);
+      }
+    }
+  }
+  for (int cp = 0; cp <= ND; ++cp) {
+    lo[cp] = q0[cp] + s[cp] * dl;
+    hi[cp] = q0[cp] + s[cp] * dh;
+  }
+  const bool ok = (!lo_open || realizable<R, SPH, ND>(lo, hlo, c)) && (!hi_open || realizable<R, SPH, ND>(hi, hhi, c));
+  for (int cp = 0; cp <= ND; ++cp) {
+    lo[cp] = ok ? lo[cp] : q0[cp];
+    hi[cp] = ok ? hi[cp] : q0[cp];
+  }
+  for (int cp = ND + 1; cp < 4; ++cp) lo[cp] = hi[cp] = R(0);
+}
+
+// M1 closure: P^ = E [ (1 - f^2)/(1 + s) I + 3/(2 + s) f f ], s = sqrt(4 - 3 f^2), f = F^/(cE)
+// (algebraically the Levermore form chi = (3 + 4 f^2)/(5 + 2 s), written without
+// cancellation as f -> 1).  Physical components.  Full tensor (row-major 3x3) for the
+// geometric sources.
+template <typename R, bool SPH, int ND>
+__device__ __forceinline__ void closure_full(const R q[4], const R h[3], R c, int eddington, R P[9]) {
+  const R E = q[0];
+  for (int t = 0; t < 9; ++t) P[t] = R(0);
+  if (eddington || !(E > R(0))) {
+    P[0] = P[4] = P[8] = E * R(1.0 / 3.0);
+    return;
+  }
+  R f[3] = {R(0), R(0), R(0)};
+  const R icE = rcp_(c * E);
+  R f2 = R(0);
+  for (int k = 0; k < ND; ++k) {
+    f[k] = (SPH ? q[1 + k] * rcp_(h[k]) : q[1 + k]) * icE;
+    f2 += f[k] * f[k];
+  }
+  if (f2 > R(1)) {
+    const R sc = rcp_(sqrt_(f2));
+    for (int k = 0; k < ND; ++k) f[k] *= sc;
+    f2 = R(1);
+  }
+  const R s = sqrt_(R(4) - R(3) * f2);
+  const R r = rcp_((R(1) + s) * (R(2) + s));
+  const R iso = E * (R(1) - f2) * (R(2) + s) * r;
+  const R ani = E * R(3) * (R(1) + s) * r;
+  for (int p = 0; p < 3; ++p)
+    for (int q2 = 0; q2 < 3; ++q2) P[3 * p + q2] = ani * f[p] * f[q2];
+  P[0] += iso;
+  P[4] += iso;
+  P[8] += iso;
+}
+
+// Row d of the closure, P^^{dk} for k < ND.  In the MIXED path (R = float) the closure is
+// evaluated in double where f^2 >= f2_fp64.
+template <typename R, bool SPH, int ND>
+__device__ __forceinline__ void closure_row(const R q[4], const R h[3], int d, R c, int eddington, double f2_fp64,
+                                            R P[3]) {
+  const R E = q[0];
+  for (int k = 0; k < 3; ++k) P[k] = R(0);
+  if (eddington || !(E > R(0))) {
+    P[d] = E * R(1.0 / 3.0);
+    return;
+  }
+  R f[3] = {R(0), R(0), R(0)};
+  const R icE = rcp_(c * E);
+  R f2 = R(0);
+  for (int k = 0; k < ND; ++k) {
+    f[k] = (SPH ? q[1 + k] * rcp_(h[k]) : q[1 + k]) * icE;
+    f2 += f[k] * f[k];
+  }
+  if constexpr (sizeof(R) == 4) {
+    if ((double)f2 >= f2_fp64) {
+      double fd[3] = {0.0, 0.0, 0.0}, f2d = 0.0;
+      const double icEd = rcp_((double)c * (double)E);
+      for (int k = 0; k < ND; ++k) {
+        fd[k] = (SPH ? (double)q[1 + k] * rcp_((double)h[k]) : (double)q[1 + k]) * icEd;
+        f2d += fd[k] * fd[k];
+      }
+      if (f2d > 1.0) {
+        const double sc = rcp_(sqrt_(f2d));
+        for (int k = 0; k < ND; ++k) fd[k] *= sc;
+        f2d = 1.0;
+      }
+      const double s = sqrt_(4.0 - 3.0 * f2d);
+      const double r = rcp_((1.0 + s) * (2.0 + s));
+      const double iso = (double)E * (1.0 - f2d) * (2.0 + s) * r;
+      const double ani = (double)E * 3.0 * (1.0 + s) * r;
+      for (int k = 0; k < ND; ++k) P[k] = (R)(ani * fd[d] * fd[k] + (k == d ? iso : 0.0));
+      return;
+    }
+  }
+  if (f2 > R(1)) {
+    const R sc = rcp_(sqrt_(f2));
+    for (int k = 0; k < ND; ++k) f[k] *= sc;
+    f2 = R(1);
+  }
+  const R s = sqrt_(R(4) - R(3) * f2);
+  const R r = rcp_((R(1) + s) * (R(2) + s));
+  const R iso = E * (R(1) - f2) * (R(2) + s) * r;
+  const R ani = E * R(3) * (R(1) + s) * r;
+  for (int k = 0; k < ND; ++k) P[k] = ani * f[d] * f[k] + (k == d ? iso : R(0));
+}
+
+// HLL flux (coordinate components) across a d-face with face scale factors h, left/right
+// states qL, qR and the correction factor eps of the energy flux.
+template <typename R, bool SPH, int ND>
+__device__ __forceinline__ void hll(const StepArgsBase& a, int d, const R qL[4], const R qR[4], const R h[3], R eps,
+                                    R flux[4]) {
+  const R c = R(a.c);
+  R PL[3], PR[3];
+  closure_row<R, SPH, ND>(qL, h, d, c, a.closure, a.f2_fp64, PL);
+  closure_row<R, SPH, ND>(qR, h, d, c, a.closure, a.f2_fp64, PR);
+  R ihd = R(1), S = c;
+  if constexpr (SPH) {
+    ihd = rcp_(h[d]);
+    S = c * ihd;
+  }
+  const R half = R(0.5);
+  // energy: F^d = F_d / h_d^2; S_R = -S_L = S
+  flux[0] = half * ((qL[1 + d] + qR[1 + d]) * (ihd * ihd)) - half * eps * S * (qR[0] - qL[0]);
+  // covariant flux components: c^2 P^d_k = c^2 P^^{dk} h_k / h_d
+  for (int k = 0; k < ND; ++k) {
+    const R hk = SPH ? h[k] * ihd : R(1);
+    flux[1 + k] = half * c * c * (PL[k] + PR[k]) * hk - half * S * (qR[1 + k] - qL[1 + k]);
+  }
+  for (int k = ND; k < 3; ++k) flux[1 + k] = R(0);
+}
+
+template <typename R>
+__device__ __forceinline__ R epsilon_of(R ksL, R ksR, R dlL, R dlR) {
+  const R tau = R(0.5) * (ksL + ksR) * (R(0.5) * (dlL + dlR));
+  return (tau > R(1)) ? rcp_(tau) : R(1);
+}
+
+// Flux through the d-face with index f (face f-1/2 of zone f along d) of the row (i, j), from
+// q[] holding zones f-2 .. f+1 and the opacities of zones f-1, f.
+template <typename S, typename R, bool SPH, int ND>
+__device__ __forceinline__ void face_flux(const StepArgs<S>& a, const Geo<R>& geo, int d, int f, int i, int j,
+                                          const R q[4][4], R ksL, R ksR, R flux[4]) {
+  const int ef = f + NG;
+  for (int c = 0; c < 4; ++c) flux[c] = R(0);
+  if (SPH && geo.wf[d][ef] == R(0)) return;
+  const int ei = i + NG, ej = j + NG;
+  R h0[3], h1[3], h2[3];
+  face_h<R, SPH>(geo, d, ei, ej, ef - 1, h0);
+  face_h<R, SPH>(geo, d, ei, ej, ef, h1);
+  face_h<R, SPH>(geo, d, ei, ej, ef + 1, h2);
+  const bool o0 = !SPH || geo.wf[d][ef - 1] != R(0), o2 = !SPH || geo.wf[d][ef + 1] != R(0);
+  R Llo[4], Lhi[4], Rlo[4], Rhi[4];
+  reconstruct<R, SPH, ND>(a, geo, d, ef - 1, q[0], q[1], q[2], h0, h1, o0, true, Llo, Lhi);
+  reconstruct<R, SPH, ND>(a, geo, d, ef, q[1], q[2], q[3], h1, h2, true, o2, Rlo, Rhi);
+  const int eL = ef - 1;
+  const R dlL = proper_width<R, SPH>(geo, d, d == 0 ? eL : ei, d == 1 ? eL : ej);
+  const R dlR = proper_width<R, SPH>(geo, d, d == 0 ? ef : ei, d == 1 ? ef : ej);
+  const R eps = epsilon_of(ksL, ksR, dlL, dlR);
+  hll<R, SPH, ND>(a, d, Lhi, Rlo, h1, eps, flux);
+}
+
+// geometric source c^2 sum_{l,m} <Gamma^l_{km}> P^m_l for the covariant flux components of a
+// spherical (ln r, theta, phi) zone, P^m_l = P^^{ml} h_l / h_m with cell-centred h
+template <typename R>
+__device__ __forceinline__ void geometric_source(const R P[9], const R h[3], const R* gam, R c, R Sg[3]) {
+  const R G323 = gam[0], G133 = gam[1], G233 = gam[2], G222 = gam[3];
+  const R c2 = c * c;
+  // F_1: Gamma^1_11 = Gamma^2_12 = Gamma^3_13 = 1
+  Sg[0] = c2 * (P[0] + P[4] + P[8]);
+  // F_2: Gamma^1_22 = -1, Gamma^2_21 = 1, <Gamma^2_22>, <Gamma^3_23>
+  const R ih0 = rcp_(h[0]), ih1 = rcp_(h[1]), ih2 = rcp_(h[2]);
+  Sg[1] = c2 * (-P[3] * (h[0] * ih1) + P[1] * (h[1] * ih0) + G222 * P[4] + G323 * P[8]);
+  // F_3: <Gamma^1_33>, <Gamma^2_33>, Gamma^3_31 = 1, <Gamma^3_32>
+  Sg[2] = c2 * (G133 * P[6] * (h[0] * ih2) + G233 * P[7] * (h[1] * ih2) + P[2] * (h[2] * ih0) +
+                G323 * P[5] * (h[2] * ih1));
+}
+
+// Implicit interaction update of one zone-group in double (eq:be_update with j = c kappa B and
+// F^{n+1} = F^- / (1 + c dt (kappa + sigma))), store, and the zone-group's diagnostics
+// contributions: V E^{n+1}, f^2 = (|F^|/cE)^2, realizability and positivity counts.  Returns
+// E^{n+1} - E^- (energy handed to matter, with the sign reversed).
+struct ZoneDiag {
+  double energy = 0.0, maxf2 = 0.0;
+  int nun = 0, nnp = 0;
+};
+
+template <typename S, typename R, bool SPH, int ND>
+__device__ __forceinline__ double finish_zone(const StepArgs<S>& a, const Geo<R>& geo, int zg, int i, int j, int k,
+                                              const R Um[4], bool want_diag, ZoneDiag& zd) {
+  const double kd = (double)a.kap[zg], sd = (double)a.sig[zg], Bd = (double)a.B[zg];
+  const double c = a.c, dt = a.dt;
+  const double Emd = (double)Um[0];
+  const double E1 = (Emd + dt * (c * kd * Bd)) * rcp_(1.0 + (c * dt) * kd);
+  const double ifden = rcp_(1.0 + (c * dt) * (kd + sd));
+  const S E1s = (S)E1;
+  a.Eo[zg] = E1s;
+  double F1s[3] = {0.0, 0.0, 0.0};
+  for (int cc = 0; cc < ND; ++cc) {
+    const S v = (S)((double)Um[1 + cc] * ifden);
+    a.Fo[cc][zg] = v;
+    F1s[cc] = (double)v;
+  }
+  const double E1d = (double)E1s;
+  if (want_diag) {
+    const double V = geo.Wd[0][i + NG] * geo.Wd[1][j + NG] * geo.Wd[2][k + NG];
+    zd.energy += V * E1d;
+    double hd[3] = {1.0, 1.0, 1.0};
+    if constexpr (SPH) {
+      hd[0] = hd[1] = (double)geo.hr[i + NG];
+      hd[2] = hd[0] * (double)geo.hs[j + NG];
+    }
+    double F2 = 0.0;
+    for (int cc = 0; cc < ND; ++cc) {
+      const double fk = SPH ? F1s[cc] * rcp_(hd[cc]) : F1s[cc];
+      F2 += fk * fk;
+    }
+    const double cE = c * E1d;
+    if (E1d > 0.0) {
+      const double icE = rcp_(cE);
+      zd.maxf2 = fmax(zd.maxf2, F2 * (icE * icE));
+    }
+    const double u = (sizeof(S) == 8) ? 0x1p-53 : 0x1p-24;
+    const double lim = cE * (1.0 + 8.0 * u);
+    zd.nun += (F2 > lim * lim) ? 1 : 0;
+    zd.nnp += (E1d > 0.0) ? 0 : 1;
+  }
+  return E1d - Emd;
+}
+
+}  // namespace fm1

@@ -14,12 +14,15 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <functional>
 #include <new>
 #include <vector>
 
 #include "m1_internal.h"
+#include "m1_step.h"
 
 using namespace fm1;
 
@@ -107,7 +110,10 @@ int validate(const fornax_m1_desc* d) {
   if (d->coord == FORNAX_SPHERICAL_LOGR) {
     if (d->lo[1] < -1e-12 || d->hi[1] > M_PI + 1e-12) return FORNAX_EINVAL;
   }
-  if (nz * (int64_t)d->ngroups > ((int64_t)1 << 40)) return FORNAX_EINVAL;
+  // zone-group and face-group indices are 32-bit in the kernels
+  int64_t nf = 0;
+  for (int k = 0; k < d->ndim; ++k) nf = std::max<int64_t>(nf, nz / d->n[k] * (d->n[k] + 1));
+  if (std::max(nz, nf) * (int64_t)d->ngroups * (1 + d->ndim) >= ((int64_t)1 << 31)) return FORNAX_EUNSUPPORTED;
   if (d->precision == FORNAX_MIXED && !(d->f_fp64 >= 0.0)) return FORNAX_EINVAL;
   return FORNAX_OK;
 }
@@ -334,11 +340,24 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
       if (s > worst) worst = s;
     }
   ctx->max_dt1 = 1.0 / worst;
-  // reduction scratch: one partial per block of the step kernel
+  // tiling of the step kernel (FORNAX_M1_TILE="TXB,TYB,TM" overrides the default choice)
+  ctx->tile = choose_tile(*desc, desc->precision == FORNAX_FP64 ? sizeof(double) : sizeof(float));
+  if (const char* env = std::getenv("FORNAX_M1_TILE")) {
+    int tx = 0, ty = 0, tm = 0;
+    if (std::sscanf(env, "%d,%d,%d", &tx, &ty, &tm) == 3 && tx >= 2 && ty >= 2 && tm >= 1 &&
+        tx * (desc->ndim == 3 ? ty : 1) * desc->ngroups <= 512) {
+      Tile t = make_tile(*desc, tx, ty, tm);
+      if (halo_slots_fit(t, desc->ndim) &&
+          tile_lds_bytes(t, desc->ndim, desc->ngroups, desc->precision == FORNAX_FP64 ? 8 : 4, true) <= 65536)
+        ctx->tile = t;
+    }
+  }
+  // reduction scratch: one partial per block of the step kernel, and per block of the
+  // zone-block kernels (source)
   int zpb = BLOCK / desc->ngroups;
   int64_t nz = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
   ctx->nblocks_step = (int)((nz + zpb - 1) / zpb);
-  size_t nb = (size_t)ctx->nblocks_step;
+  size_t nb = (size_t)std::max(ctx->nblocks_step, ctx->tile.nblocks);
   void* red = nullptr;
   if (hipMalloc(&red, nb * (2 * sizeof(double) + 2 * sizeof(int)) + 1024) != hipSuccess) {
     (void)hipFree(ctx->geo_mem);

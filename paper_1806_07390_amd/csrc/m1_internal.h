@@ -76,6 +76,17 @@ struct StepArgs : StepArgsBase {
 
 }  // namespace fm1
 
+namespace fm1 {
+struct Tile {
+  int TXB, TYB;        // zone columns per block in x and in y (y: 3-D only, else 1)
+  int TM;              // planes per block along the march direction (1 for 1-D)
+  int ntx, nty, ntm;   // tiles per direction
+  int nblocks;
+  int xq, xr;          // nblocks = 8 xq + xr (XCD renumbering)
+  int nthreads;        // TXB * TYB * G
+};
+}  // namespace fm1
+
 struct fornax_m1_ctx {
   fornax_m1_desc desc;
   int device;
@@ -85,7 +96,8 @@ struct fornax_m1_ctx {
   void* geo_mem;              // one allocation holding every device table
   size_t geo_bytes;
   double max_dt1;             // max_dt(cfl = 1)
-  // reduction scratch
+  fm1::Tile tile;              // tiling of the fused step kernel
+  // reduction scratch (one partial per block of the step kernel)
   int nblocks_step;
   double* p_energy;
   double* p_maxf2;

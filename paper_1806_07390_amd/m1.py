@@ -277,6 +277,45 @@ class Context:
                                       _stream(stream)), "fornax_m1_adjoint")
         return out[0], out[1], dkappa
 
+    def stepper(self, A, Bst, kappa, sigma, B, dt, inflow=None, diag=None, stream=None):
+        """Pre-bound ping-pong stepping between two states A = (E, [F]) and Bst: each call of
+        the returned function advances one step (A -> Bst, then Bst -> A, ...) with the C
+        arguments built once.  Returns (step_fn, current_state_fn)."""
+        sa = self._state(A[0], A[1], "A")
+        sb = self._state(Bst[0], Bst[1], "B")
+        cf = self._coeffs(kappa, sigma, B)
+        dg = None
+        if diag is not None:
+            dg = Diag()
+            dg.energy_total = _ptr(diag.get("energy_total"))
+            dg.dE_matter = _ptr(diag.get("dE_matter"))
+            dg.max_f = _ptr(diag.get("max_f"))
+            dg.n_unrealizable = _ptr(diag.get("n_unrealizable"))
+            dg.n_nonpositive = _ptr(diag.get("n_nonpositive"))
+        infl = self._inflow(inflow)
+        st = _stream(stream)
+        pa, pb, pc = ctypes.byref(sa), ctypes.byref(sb), ctypes.byref(cf)
+        pd = ctypes.byref(dg) if dg is not None else None
+        h = self._h
+        fn = _lib.fornax_m1_step
+        parity = [0]
+
+        def step():
+            if parity[0] == 0:
+                rc = fn(h, pa, pb, pc, infl, dt, pd, st)
+            else:
+                rc = fn(h, pb, pa, pc, infl, dt, pd, st)
+            if rc != FORNAX_OK:
+                raise FornaxError(rc, "fornax_m1_step")
+            parity[0] ^= 1
+
+        def current():
+            return A if parity[0] == 0 else Bst
+
+        # keep the structures alive with the closure
+        step._keep = (sa, sb, cf, dg)
+        return step, current
+
     def run(self, E, F, kappa, sigma, B, dt, nsteps, inflow=None, diag=None):
         """nsteps steps with ping-pong buffers; returns (E, [F]) (new tensors)."""
         a = (E.clone(), [f.clone() for f in F])
