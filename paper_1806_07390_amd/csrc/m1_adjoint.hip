@@ -1,0 +1,490 @@
+// m1_adjoint.hip -- adjoint (vector-Jacobian product) of one M1 step for gfx950.
+//
+//   lam_n = (dU^{n+1}/dU^n)^T lam_{n+1},   dkappa += (dU^{n+1}/dkappa)^T lam_{n+1}
+//
+// The step is U^{n+1} = S(U^-), U^- = U^n + dt L(U^n) with the implicit interaction update S
+// (zone-local) and the flux divergence L.  With mu = (dS/dU^-)^T lam_{n+1}, the adjoint of
+// the flux at face f between zones L and R is nu_f = dt (mu_R - mu_L) / dx, and
+//   lam_n(z) = mu(z) + sum over the four faces whose stencil holds z of (d flux_f / d U_z)^T nu_f.
+//
+// Kernel layout mirrors the forward step: lanes = (zone column, group); a block owns TXB zone
+// columns in x and marches along y (2-D).  The thread of column cx recomputes the face
+// x0 - 1 + cx (forward flux and its VJP) and exchanges through LDS; along the march a
+// register ring carries the contributions of the last four faces.  Each tile finalises
+// TXB - 3 columns.  Tiles also cover the two ghost layers on each side: contributions to a
+// ghost zone go to a per-direction ghost buffer that k_adj_fold maps back through the
+// boundary rule (periodic wrap, outflow copy, reflection with the normal flux flipped;
+// inflow ghosts are constant, so only their opacity dependence folds).  No atomics: every
+// sum is taken in a fixed order, so the result is deterministic.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "m1_adjoint_device.h"
+#include "m1_device.h"
+#include "m1_internal.h"
+
+namespace fm1 {
+
+template <typename S>
+struct AdjArgs : StepArgs<S> {
+  const S* lam[3 + 1];    // lambda^{n+1}: E, F_1..F_ND
+  S* lamo[3 + 1];         // lambda^n
+  S* dk;                  // dkappa accumulator
+  const S* U1[3 + 1];     // U^{n+1} of the step (E, F_1..F_ND), from the forward kernel
+  double* gbuf[3];        // ghost adjoints per direction: [side][layer][plane][G][NC+1]
+  int gplane[3];          // zones of the plane normal to direction d
+};
+
+struct AdjTile {
+  int TXB, W;             // thread columns, finalised columns per tile (TXB - 3)
+  int TM;                 // planes per tile along the march (2-D)
+  int ntx, ntm, nblocks;
+  int xq, xr;
+  int nthreads;
+};
+
+// mu = (dS/dU^-)^T lam and the source part of dkappa, for an in-domain zone-group, in double
+template <typename S, int ND>
+__device__ __forceinline__ void source_adjoint(const AdjArgs<S>& a, int zg, const double lam[4], double mu[4],
+                                               const double* U1, double& dk_src) {
+  const double kd = (double)a.kap[zg], sd = (double)a.sig[zg], Bd = (double)a.B[zg];
+  const double cdt = a.c * a.dt;
+  const double aE = rcp_(1.0 + cdt * kd), aF = rcp_(1.0 + cdt * (kd + sd));
+  mu[0] = lam[0] * aE;
+  for (int k = 0; k < ND; ++k) mu[1 + k] = lam[1 + k] * aF;
+  if (U1) {
+    double s = cdt * aE * lam[0] * (Bd - U1[0]);
+    for (int k = 0; k < ND; ++k) s -= cdt * aF * lam[1 + k] * U1[1 + k];
+    dk_src = s;
+  }
+}
+
+template <typename S, typename R, int DIM>
+__device__ __forceinline__ void load_mu(const AdjArgs<S>& a, int zg, R mu[4]) {
+  double lam[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0}, dummy = 0.0;
+  lam[0] = (double)a.lam[0][zg];
+  for (int k = 0; k < DIM; ++k) lam[1 + k] = (double)a.lam[1 + k][zg];
+  source_adjoint<S, DIM>(a, zg, lam, m, nullptr, dummy);
+  for (int k = 0; k < 4; ++k) mu[k] = (R)m[k];
+}
+
+template <typename S, typename R, int DIM>
+__global__ void __launch_bounds__(512) k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NC = 1 + DIM;
+  constexpr int NV = 2 * NC + 1;     // state, total opacity, mu
+  constexpr int MD = DIM - 1;
+  const int G = a.G;
+  const int t = threadIdx.x;
+  const int grp = t % G;
+  const int cx = t / G;
+  const int TXB = tl.TXB, W = tl.W;
+  const int COLS = TXB + 3;
+  R* PV = reinterpret_cast<R*>(smem);                  // [NV][COLS][G]
+  R* CX = PV + (size_t)NV * COLS * G;                  // [4][NC][TXB][G]
+  R* DKX = CX + (size_t)4 * NC * TXB * G;              // [2][TXB][G]
+  auto pv = [&](int v, int colL) -> R& { return PV[((size_t)v * COLS + colL) * G + grp]; };
+  auto cxr = [&](int p, int v, int col) -> R& { return CX[(((size_t)p * NC + v) * TXB + col) * G + grp]; };
+
+  const int b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3;
+  const int Lb = xcd * tl.xq + min(xcd, tl.xr) + slot;
+  const int tx = Lb % tl.ntx;
+  const int tm = Lb / tl.ntx;
+  const int n0 = a.n[0];
+  const int nM = (DIM >= 2) ? a.n[MD] : 1;
+  const int x0 = -2 + tx * W;
+  const int mbeg = (DIM >= 2) ? -2 + tm * tl.TM : 0;
+  const int mend = (DIM >= 2) ? min(mbeg + tl.TM, nM + 2) : 1;
+  const int gx = x0 + cx;
+  const bool colin = gx >= 0 && gx < n0;            // column inside the domain
+  const bool fin = cx < W && gx >= -2 && gx < n0 + 2; // this thread finalises (gx, m)
+  const R c = R(a.c);
+  const R dx0 = geo.dx[0];
+  const R nux = R(a.dt) * rcp_(dx0);
+
+  // zone-group index of (x, m), both inside the domain
+  auto zgi = [&](int x, int m) -> int { return (DIM >= 2) ? (m * n0 + x) * G + grp : x * G + grp; };
+  // state and total opacity of zone (x, m) with at most one index outside the domain
+  auto state = [&](int x, int m, R q[4], R& ks) {
+    for (int v = 0; v < 4; ++v) q[v] = R(0);
+    ks = R(0);
+    if (x < -2 || x > n0 + 1 || m < -2 || m > nM + 1) return;
+    const bool xin = x >= 0 && x < n0, min_ = m >= 0 && m < nM;
+    if (!xin && !min_) return;
+    if (!xin) fetch<S, R, false, DIM>(a, geo, 0, x, x, (DIM >= 2 ? m : 0), 0, grp, q, &ks);
+    else fetch<S, R, false, DIM>(a, geo, MD < 0 ? 0 : MD, (DIM >= 2 ? m : x), x, (DIM >= 2 ? m : 0), 0, grp, q, &ks);
+  };
+
+  // ---------------- march-direction state (DIM 2) ----------------
+  R wq[4][4], wks[4], wmu[4][4];           // planes m .. m+3 of this column
+  R racc[4][4];                            // adjoint contributions to zones m .. m+3
+  R rdk[4];                                // dkappa contributions to zones m .. m+3
+  for (int i = 0; i < 4; ++i) {
+    wks[i] = rdk[i] = R(0);
+    for (int v = 0; v < 4; ++v) wq[i][v] = wmu[i][v] = racc[i][v] = R(0);
+  }
+  const R nuy = (DIM >= 2) ? R(a.dt) * rcp_(geo.dx[MD]) : R(0);
+  auto load_plane_w = [&](int p, R q[4], R& ks, R mu[4]) {
+    state(gx, p, q, ks);
+    for (int v = 0; v < 4; ++v) mu[v] = R(0);
+    if (p >= 0 && p < nM) load_mu<S, R, DIM>(a, zgi(gx, p), mu);
+  };
+  // march face f (between planes f-1 and f) from window planes f-2 .. f+1 in wq[0..3]
+  auto march_face = [&](int f, R fl[4], R C[4][4], R& dkL, R& dkR) {
+    for (int v = 0; v < 4; ++v) fl[v] = R(0);
+    for (int p = 0; p < 4; ++p)
+      for (int v = 0; v < 4; ++v) C[p][v] = R(0);
+    dkL = dkR = R(0);
+    if (f < 0 || f > nM) return;
+    R nu[4] = {R(0), R(0), R(0), R(0)};
+    for (int v = 0; v < NC; ++v) nu[v] = nuy * (wmu[2][v] - wmu[1][v]);
+    face_vjp_cart<R, DIM>(a, MD < 0 ? 0 : MD, geo.dx[MD < 0 ? 0 : MD], wq, wks[1], wks[2], nu, fl, C, dkL, dkR);
+  };
+  if constexpr (DIM >= 2) {
+    if (colin) {
+      // faces mbeg-1, mbeg, mbeg+1 fill the rings; window planes start at mbeg-3
+      for (int i = 0; i < 4; ++i) load_plane_w(mbeg - 3 + i, wq[i], wks[i], wmu[i]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int f = mbeg - 1 + i;
+        if (i > 0) {
+          for (int i2 = 0; i2 < 3; ++i2) {
+            for (int v = 0; v < 4; ++v) {
+              wq[i2][v] = wq[i2 + 1][v];
+              wmu[i2][v] = wmu[i2 + 1][v];
+            }
+            wks[i2] = wks[i2 + 1];
+          }
+          load_plane_w(f + 1, wq[3], wks[3], wmu[3]);
+        }
+        R fl[4], C[4][4], dkL, dkR;
+        march_face(f, fl, C, dkL, dkR);
+        // face f contributes to zones f-2+p, i.e. ring slot i-3+p
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int r = i - 3 + p;
+          if (r >= 0)
+            for (int v = 0; v < NC; ++v) racc[r][v] += C[p][v];
+        }
+        if (i == 1) rdk[0] += dkR;
+        if (i == 2) {
+          rdk[0] += dkL;
+          rdk[1] += dkR;
+        }
+      }
+      // window now holds planes mbeg-1 .. mbeg+2; shift so that it holds mbeg .. mbeg+2
+      for (int i = 0; i < 3; ++i) {
+        for (int v = 0; v < 4; ++v) {
+          wq[i][v] = wq[i + 1][v];
+          wmu[i][v] = wmu[i + 1][v];
+        }
+        wks[i] = wks[i + 1];
+      }
+    }
+  }
+
+  for (int m = mbeg; m < mend; ++m) {
+    const bool rowin = (DIM < 2) || (m >= 0 && m < nM);
+    // ---- march: load plane m+3, face m+2 ----
+    if constexpr (DIM >= 2) {
+      if (colin) {
+        load_plane_w(m + 3, wq[3], wks[3], wmu[3]);
+        R fl[4], C[4][4], dkL, dkR;
+        march_face(m + 2, fl, C, dkL, dkR);
+        for (int p = 0; p < 4; ++p)
+          for (int v = 0; v < NC; ++v) racc[p][v] += C[p][v];
+        rdk[1] += dkL;
+        rdk[2] += dkR;
+      }
+    }
+    // ---- stage plane m: own column (LDS col cx + 3) and halo columns 0..2 ----
+    if (rowin) {
+      R q[4], ks, mu[4] = {R(0), R(0), R(0), R(0)};
+      if ((DIM >= 2) && colin) {
+        for (int v = 0; v < 4; ++v) {
+          q[v] = wq[0][v];
+          mu[v] = wmu[0][v];
+        }
+        ks = wks[0];
+      } else {
+        state(gx, m, q, ks);
+        if (colin) load_mu<S, R, DIM>(a, zgi(gx, m), mu);
+      }
+      for (int v = 0; v < NC; ++v) {
+        pv(v, cx + 3) = q[v];
+        pv(NC + 1 + v, cx + 3) = mu[v];
+      }
+      pv(NC, cx + 3) = ks;
+      if (cx < 3) {
+        const int hx = x0 - 3 + cx;
+        R hq[4], hks, hmu[4] = {R(0), R(0), R(0), R(0)};
+        state(hx, m, hq, hks);
+        if (hx >= 0 && hx < n0) load_mu<S, R, DIM>(a, zgi(hx, m), hmu);
+        for (int v = 0; v < NC; ++v) {
+          pv(v, cx) = hq[v];
+          pv(NC + 1 + v, cx) = hmu[v];
+        }
+        pv(NC, cx) = hks;
+      }
+    }
+    __syncthreads();
+    // ---- x face x0 - 1 + cx ----
+    {
+      const int f = x0 - 1 + cx;
+      R fl[4] = {R(0), R(0), R(0), R(0)}, C[4][4], dkL = R(0), dkR = R(0);
+      for (int p = 0; p < 4; ++p)
+        for (int v = 0; v < 4; ++v) C[p][v] = R(0);
+      if (rowin && f >= 0 && f <= n0) {
+        R q[4][4];
+        for (int o = 0; o < 4; ++o) {
+          for (int v = 0; v < NC; ++v) q[o][v] = pv(v, cx + o);
+          for (int v = NC; v < 4; ++v) q[o][v] = R(0);
+        }
+        R nu[4] = {R(0), R(0), R(0), R(0)};
+        for (int v = 0; v < NC; ++v) nu[v] = nux * (pv(NC + 1 + v, cx + 2) - pv(NC + 1 + v, cx + 1));
+        face_vjp_cart<R, DIM>(a, 0, dx0, q, pv(NC, cx + 1), pv(NC, cx + 2), nu, fl, C, dkL, dkR);
+      }
+      for (int p = 0; p < 4; ++p)
+        for (int v = 0; v < NC; ++v) cxr(p, v, cx) = C[p][v];
+      DKX[((size_t)0 * TXB + cx) * G + grp] = dkL;
+      DKX[((size_t)1 * TXB + cx) * G + grp] = dkR;
+    }
+    __syncthreads();
+    // ---- finalise zone (gx, m) ----
+    if (fin) {
+      R gsum[4] = {R(0), R(0), R(0), R(0)};
+      R dks = R(0);
+      if (rowin) {
+        for (int p = 0; p < 4; ++p)
+          for (int v = 0; v < NC; ++v) gsum[v] += cxr(p, v, cx + 3 - p);
+        dks += DKX[((size_t)1 * TXB + cx + 1) * G + grp] + DKX[((size_t)0 * TXB + cx + 2) * G + grp];
+      }
+      if constexpr (DIM >= 2) {
+        if (colin) {
+          for (int v = 0; v < NC; ++v) gsum[v] += racc[0][v];
+          dks += rdk[0];
+        }
+      }
+      if (colin && rowin) {
+        // U^{n+1} of this zone (written by the forward step) for the source derivative
+        const int zg = zgi(gx, m);
+        double U1[4] = {0, 0, 0, 0};
+        for (int v = 0; v < NC; ++v) U1[v] = (double)a.U1[v][zg];
+        double lam[4] = {0, 0, 0, 0}, mu[4] = {0, 0, 0, 0}, dk_src = 0.0;
+        lam[0] = (double)a.lam[0][zg];
+        for (int k = 0; k < DIM; ++k) lam[1 + k] = (double)a.lam[1 + k][zg];
+        source_adjoint<S, DIM>(a, zg, lam, mu, U1, dk_src);
+        for (int v = 0; v < NC; ++v) a.lamo[v][zg] = (S)(mu[v] + (double)gsum[v]);
+        a.dk[zg] = (S)((double)a.dk[zg] + dk_src + (double)dks);
+      } else if (colin != rowin) {
+        // ghost zone (exactly one index outside the domain)
+        const int d = colin ? MD : 0;
+        const int gi = colin ? m : gx;
+        const int nd = colin ? nM : n0;
+        const int side = gi < 0 ? 0 : 1;
+        const int layer = gi < 0 ? -1 - gi : gi - nd;
+        const int pidx = colin ? gx : ((DIM >= 2) ? m : 0);
+        double* gb = a.gbuf[d] + ((((size_t)side * 2 + layer) * a.gplane[d] + pidx) * G + grp) * (NC + 1);
+        for (int v = 0; v < NC; ++v) gb[v] = (double)gsum[v];
+        gb[NC] = (double)dks;
+      }
+    }
+    // ---- advance the march rings ----
+    if constexpr (DIM >= 2) {
+      for (int i = 0; i < 3; ++i) {
+        for (int v = 0; v < 4; ++v) {
+          wq[i][v] = wq[i + 1][v];
+          wmu[i][v] = wmu[i + 1][v];
+          racc[i][v] = racc[i + 1][v];
+        }
+        wks[i] = wks[i + 1];
+        rdk[i] = rdk[i + 1];
+      }
+      for (int v = 0; v < 4; ++v) racc[3][v] = R(0);
+      rdk[3] = R(0);
+    }
+    __syncthreads();
+  }
+}
+
+// Fold the ghost-zone adjoints of direction d into the zones they copy.  One thread per
+// (candidate destination zone along d, plane, group); the four ghost entries are visited in
+// a fixed order.
+template <typename S, int ND>
+__global__ void __launch_bounds__(256) k_adj_fold(AdjArgs<S> a, int d) {
+  constexpr int NC = 1 + ND;
+  const int G = a.G;
+  const int np = a.gplane[d];
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  if (id >= 4 * np * G) return;
+  const int grp = id % G;
+  const int pidx = (id / G) % np;
+  const int cand = id / (G * np);
+  const int nd = a.n[d];
+  const int cands[4] = {0, 1, nd - 2, nd - 1};
+  const int dst = cands[cand];
+  if (dst < 0 || dst >= nd) return;
+  for (int c2 = 0; c2 < cand; ++c2)
+    if (cands[c2] == dst) return;   // duplicate candidate (small n)
+  double acc[4] = {0, 0, 0, 0}, dka = 0.0;
+  bool any = false;
+  for (int side = 0; side < 2; ++side) {
+    const int bc = side ? a.bc_hi[d] : a.bc_lo[d];
+    for (int layer = 0; layer < 2; ++layer) {
+      const int gi = side ? nd + layer : -1 - layer;
+      int src;
+      double sgn_d = 1.0;
+      bool state_dep = true;
+      if (bc == FORNAX_BC_PERIODIC) {
+        src = ((gi % nd) + nd) % nd;
+      } else if (bc == FORNAX_BC_REFLECT) {
+        src = side ? 2 * nd - 1 - gi : -1 - gi;
+        sgn_d = -1.0;
+      } else if (bc == FORNAX_BC_INFLOW) {
+        src = side ? nd - 1 : 0;
+        state_dep = false;
+      } else {  // outflow
+        src = side ? nd - 1 : 0;
+      }
+      if (src != dst) continue;
+      const double* gb = a.gbuf[d] + ((((size_t)side * 2 + layer) * np + pidx) * G + grp) * (NC + 1);
+      if (state_dep)
+        for (int v = 0; v < NC; ++v) acc[v] += (v == 1 + d ? sgn_d : 1.0) * gb[v];
+      dka += gb[NC];
+      any = true;
+    }
+  }
+  if (!any) return;
+  // zone-group index of (dst along d, pidx in the normal plane)
+  int zg;
+  if (ND == 1) {
+    zg = dst * G + grp;
+  } else {   // 2-D: d = 0 -> plane index is the row; d = 1 -> plane index is the column
+    zg = (d == 0) ? ((pidx * a.n[0] + dst) * G + grp) : ((dst * a.n[0] + pidx) * G + grp);
+  }
+  for (int v = 0; v < NC; ++v) a.lamo[v][zg] = (S)((double)a.lamo[v][zg] + acc[v]);
+  a.dk[zg] = (S)((double)a.dk[zg] + dka);
+}
+
+// ------------------------------------------------------------------------------------------
+static AdjTile make_adj_tile(const fornax_m1_desc& D, int TM) {
+  AdjTile tl;
+  const int G = D.ngroups;
+  tl.TXB = std::max(4, 256 / G);
+  if (tl.TXB * G > 512) tl.TXB = 512 / G;
+  tl.W = tl.TXB - 3;
+  tl.TM = TM;
+  tl.ntx = (D.n[0] + 4 + tl.W - 1) / tl.W;
+  const int nM = (D.ndim >= 2) ? D.n[D.ndim - 1] : 1;
+  tl.ntm = (D.ndim >= 2) ? (nM + 4 + TM - 1) / TM : 1;
+  tl.nblocks = tl.ntx * tl.ntm;
+  tl.xq = tl.nblocks / 8;
+  tl.xr = tl.nblocks % 8;
+  tl.nthreads = tl.TXB * G;
+  return tl;
+}
+
+static size_t adj_lds_bytes(const AdjTile& tl, int dim, int G, size_t rsize) {
+  const int NC = 1 + dim, NV = 2 * NC + 1;
+  size_t n = (size_t)NV * (tl.TXB + 3) * G + (size_t)4 * NC * tl.TXB * G + (size_t)2 * tl.TXB * G;
+  return n * rsize;
+}
+
+template <typename S, typename R>
+static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* Un,
+                            const fornax_m1_coeffs* cf, const double* inflow, double dt,
+                            const fornax_m1_state* lam_np1, fornax_m1_state* lam_n, void* dkappa, hipStream_t st) {
+  const fornax_m1_desc& D = ctx->desc;
+  // U^{n+1} of the step, by the forward kernel, into the context's adjoint scratch
+  fornax_m1_state u1;
+  const size_t nzg = (size_t)D.n[0] * D.n[1] * D.n[2] * D.ngroups;
+  u1.E = ctx->adj_u1;
+  for (int k = 0; k < 3; ++k) u1.F[k] = (k < D.ndim) ? (char*)ctx->adj_u1 + (1 + k) * nzg * sizeof(S) : nullptr;
+  int rc = fm1_launch_step(ctx, Un, &u1, cf, inflow, dt, nullptr, st);
+  if (rc != FORNAX_OK) return rc;
+  AdjArgs<S> a;
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = D.n[d];
+    a.bc_lo[d] = D.bc_lo[d];
+    a.bc_hi[d] = D.bc_hi[d];
+  }
+  a.G = D.ngroups;
+  a.ndim = D.ndim;
+  a.limiter = D.limiter;
+  a.closure = D.closure;
+  a.zones_per_block = 0;
+  a.nzones = (int64_t)D.n[0] * D.n[1] * D.n[2];
+  a.c = D.c;
+  a.dt = dt;
+  a.f2_fp64 = D.f_fp64 * D.f_fp64;
+  a.inflow = inflow;
+  a.E = (const S*)Un->E;
+  a.Eo = nullptr;
+  for (int k = 0; k < 3; ++k) {
+    a.F[k] = (k < D.ndim) ? (const S*)Un->F[k] : nullptr;
+    a.Fo[k] = nullptr;
+  }
+  a.kap = (const S*)cf->kappa;
+  a.sig = (const S*)cf->sigma;
+  a.B = (const S*)cf->B;
+  a.dEm = nullptr;
+  a.p_energy = a.p_maxf2 = nullptr;
+  a.p_nun = a.p_nnp = nullptr;
+  a.lam[0] = (const S*)lam_np1->E;
+  a.lamo[0] = (S*)lam_n->E;
+  for (int k = 0; k < 3; ++k) {
+    a.lam[1 + k] = (k < D.ndim) ? (const S*)lam_np1->F[k] : nullptr;
+    a.lamo[1 + k] = (k < D.ndim) ? (S*)lam_n->F[k] : nullptr;
+  }
+  a.dk = (S*)dkappa;
+  a.U1[0] = (const S*)u1.E;
+  for (int k = 0; k < 3; ++k) a.U1[1 + k] = (const S*)u1.F[k];
+  for (int d = 0; d < 3; ++d) {
+    a.gbuf[d] = ctx->adj_gbuf[d];
+    a.gplane[d] = ctx->adj_gplane[d];
+  }
+  AdjTile tl = make_adj_tile(D, 8);
+  const size_t lds = adj_lds_bytes(tl, D.ndim, D.ngroups, sizeof(R));
+  if (lds > 65536) return FORNAX_EUNSUPPORTED;
+  if (D.ndim == 1)
+    hipLaunchKernelGGL((k_adjoint<S, R, 1>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a, geo, tl);
+  else
+    hipLaunchKernelGGL((k_adjoint<S, R, 2>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a, geo, tl);
+  if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
+  for (int d = 0; d < D.ndim; ++d) {
+    const int nt = 4 * a.gplane[d] * a.G;
+    if (D.ndim == 1)
+      hipLaunchKernelGGL((k_adj_fold<S, 1>), dim3((nt + 255) / 256), dim3(256), 0, st, a, d);
+    else
+      hipLaunchKernelGGL((k_adj_fold<S, 2>), dim3((nt + 255) / 256), dim3(256), 0, st, a, d);
+    if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
+  }
+  return FORNAX_OK;
+}
+
+}  // namespace fm1
+
+using namespace fm1;
+
+int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const fornax_m1_coeffs* cf,
+                       const double* inflow, double dt, const fornax_m1_state* lam_np1, fornax_m1_state* lam_n,
+                       void* dkappa, hipStream_t stream) {
+  const fornax_m1_desc& D = ctx->desc;
+  if (D.coord != FORNAX_CARTESIAN || D.ndim > 2 || D.ngroups > 128) return FORNAX_EUNSUPPORTED;
+  if (!ctx->adj_gbuf[0]) return FORNAX_ENOMEM;
+  if (!ctx->adj_u1) {
+    // first adjoint call on this context: scratch for U^{n+1}
+    const size_t es = D.precision == FORNAX_FP64 ? sizeof(double) : sizeof(float);
+    const size_t bytes = (size_t)(1 + D.ndim) * D.n[0] * D.n[1] * D.n[2] * D.ngroups * es;
+    if (hipMalloc(&ctx->adj_u1, bytes) != hipSuccess) {
+      ctx->adj_u1 = nullptr;
+      return FORNAX_ENOMEM;
+    }
+  }
+  if (D.precision == FORNAX_FP64)
+    return launch_adjoint_t<double, double>(ctx, ctx->geo_d, Un, cf, inflow, dt, lam_np1, lam_n, dkappa, stream);
+  return launch_adjoint_t<float, float>(ctx, ctx->geo_f, Un, cf, inflow, dt, lam_np1, lam_n, dkappa, stream);
+}

@@ -368,6 +368,24 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   ctx->p_maxf2 = ctx->p_energy + nb;
   ctx->p_nun = (int*)(ctx->p_maxf2 + nb);
   ctx->p_nnp = ctx->p_nun + nb;
+  // adjoint ghost buffers (the adjoint supports 1-D and 2-D Cartesian grids)
+  ctx->adj_u1 = nullptr;
+  for (int d = 0; d < 3; ++d) {
+    ctx->adj_gbuf[d] = nullptr;
+    ctx->adj_gplane[d] = (int)(nz / desc->n[d]);
+  }
+  if (desc->coord == FORNAX_CARTESIAN && desc->ndim <= 2) {
+    for (int d = 0; d < desc->ndim; ++d) {
+      size_t bytes = (size_t)4 * ctx->adj_gplane[d] * desc->ngroups * (desc->ndim + 2) * sizeof(double);
+      if (hipMalloc((void**)&ctx->adj_gbuf[d], bytes) != hipSuccess) {
+        for (int e = 0; e < d; ++e) (void)hipFree(ctx->adj_gbuf[e]);
+        (void)hipFree(red);
+        (void)hipFree(ctx->geo_mem);
+        delete ctx;
+        return FORNAX_ENOMEM;
+      }
+    }
+  }
   *out = ctx;
   return FORNAX_OK;
 }
@@ -376,6 +394,9 @@ int fornax_m1_destroy(fornax_m1_ctx* ctx) {
   if (!ctx) return FORNAX_EINVAL;
   (void)hipFree(ctx->geo_mem);
   (void)hipFree(ctx->p_energy);
+  for (int d = 0; d < 3; ++d)
+    if (ctx->adj_gbuf[d]) (void)hipFree(ctx->adj_gbuf[d]);
+  if (ctx->adj_u1) (void)hipFree(ctx->adj_u1);
   delete ctx;
   return FORNAX_OK;
 }

@@ -103,6 +103,10 @@ struct fornax_m1_ctx {
   double* p_maxf2;
   int* p_nun;
   int* p_nnp;
+  // adjoint: ghost-zone adjoint buffers per direction, [side][layer][plane][G][1+ndim+1]
+  double* adj_gbuf[3];
+  int adj_gplane[3];
+  void* adj_u1;               // U^{n+1} scratch of the adjoint (allocated by its first call)
 };
 
 // kernel launchers (m1_kernels.hip)

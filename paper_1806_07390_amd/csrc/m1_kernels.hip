@@ -270,11 +270,6 @@ int fm1_launch_source(fornax_m1_ctx* ctx, fornax_m1_state* inout, const fornax_m
   return launch_source_t<float>(ctx, inout, cf, dt, dEm, stream);
 }
 
-int fm1_launch_adjoint(fornax_m1_ctx*, const fornax_m1_state*, const fornax_m1_coeffs*, const double*, double,
-                       const fornax_m1_state*, fornax_m1_state*, void*, hipStream_t) {
-  return FORNAX_EUNSUPPORTED;
-}
-
 int fm1_launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t stream) {
   int64_t n = nbytes / 16;
   if (n == 0) return FORNAX_OK;

@@ -331,3 +331,59 @@ def copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):
     nbytes = src.numel() * src.element_size()
     _check(_lib.fornax_m1_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
                                      _stream(stream)), "fornax_m1_copy_probe")
+
+
+class M1Steps(torch.autograd.Function):
+    """N steps of the M1 update as a differentiable function of the initial state and of the
+    absorption opacity: (E_N, F_N) = M1Steps.apply(ctx, dt, nsteps, ckpt_every, inflow,
+    kappa, sigma, B, E0, *F0).
+
+    Forward: the library's fused step, keeping a copy of the state every `ckpt_every` steps.
+    Backward: for each checkpoint segment in reverse, recompute the segment's states from its
+    checkpoint and apply fornax_m1_adjoint step by step, accumulating dL/dkappa.  Gradients
+    with respect to sigma, B and dt are not provided (None)."""
+
+    @staticmethod
+    def forward(fctx, ctx, dt, nsteps, ckpt_every, inflow, kappa, sigma, B, E0, *F0):
+        if ckpt_every < 1:
+            raise ValueError("ckpt_every must be >= 1")
+        a = (E0.detach().clone(), [f.detach().clone() for f in F0])
+        b = ctx.empty_state()
+        ckpts = []
+        step, current = ctx.stepper(a, b, kappa.detach(), sigma.detach(), B.detach(), dt, inflow=inflow)
+        for s in range(nsteps):
+            if s % ckpt_every == 0:
+                cur = current()
+                ckpts.append((s, cur[0].clone(), [f.clone() for f in cur[1]]))
+            step()
+        out = current()
+        fctx.m1 = (ctx, dt, nsteps, ckpt_every, inflow, ckpts)
+        fctx.save_for_backward(kappa, sigma, B)
+        return (out[0].clone(),) + tuple(f.clone() for f in out[1])
+
+    @staticmethod
+    def backward(fctx, gE, *gF):
+        ctx, dt, nsteps, ckpt_every, inflow, ckpts = fctx.m1
+        kappa, sigma, B = fctx.saved_tensors
+        kappa, sigma, B = kappa.detach(), sigma.detach(), B.detach()
+        zeros = lambda: torch.zeros(ctx.shape, dtype=ctx.dtype, device=ctx.device)
+        lam = ((gE if gE is not None else zeros()).contiguous().clone(),
+               [(g if g is not None else zeros()).contiguous().clone() for g in gF])
+        nxt = ctx.empty_state()
+        dk = zeros()
+        for (s0, E, F) in reversed(ckpts):
+            s1 = min(s0 + ckpt_every, nsteps)
+            states = [(E, F)]
+            for _ in range(s0, s1 - 1):
+                prev = states[-1]
+                states.append(ctx.step(prev[0], prev[1], kappa, sigma, B, dt, inflow=inflow))
+            for st in reversed(states):
+                ctx.adjoint(st[0], st[1], kappa, sigma, B, dt, lam[0], lam[1], out=nxt, dkappa=dk, inflow=inflow)
+                lam, nxt = nxt, lam
+        return (None, None, None, None, None, dk, None, None, lam[0]) + tuple(lam[1])
+
+
+def run_differentiable(ctx, E0, F0, kappa, sigma, B, dt, nsteps, ckpt_every=8, inflow=None):
+    """Differentiable N-step run (see M1Steps); returns (E_N, [F_N])."""
+    out = M1Steps.apply(ctx, dt, nsteps, ckpt_every, inflow, kappa, sigma, B, E0, *F0)
+    return out[0], list(out[1:])
