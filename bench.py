@@ -86,6 +86,51 @@ def copy_bandwidth(nbytes=1 << 30, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
+def adjoint_ratios(steps=20):
+    """Adjoint/forward time ratios on the 2-D 256^2 x 16 FP32-bulk adjoint workload: per step
+    (fornax_m1_adjoint, which includes its forward recompute, vs fornax_m1_step) and end to end
+    (40-step differentiable run: backward with checkpoint recompute vs forward)."""
+    import torch
+    from paper_1806_07390_amd import m1, workloads as wl
+    w = wl.adjoint2d()
+    ctx = m1.Context(m1.Config.from_workload(w, precision=m1.MIXED))
+    E, F, k, s, B, _ = device_inputs(w, torch.float32)
+    fwd_ms, _ = time_steps(ctx, (E, F, k, s, B, None), w.dt, steps, 3, with_diag=False)
+    lam = (torch.ones_like(E), [torch.zeros_like(f) for f in F])
+    out = ctx.empty_state()
+    dk = torch.zeros_like(E)
+    adj = ctx.adjointer((E, F), k, s, B, w.dt, lam, out, dk)
+    for _ in range(3):
+        adj()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        adj()
+    e1.record()
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / steps
+    # end to end: 40 steps, checkpoints every 8
+    ix, iy, ww = w.extra["window"]
+    E0 = E.clone().requires_grad_(True)
+    F0 = [f.clone().requires_grad_(True) for f in F]
+    kk = k.clone().requires_grad_(True)
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        EN, FN = m1.run_differentiable(ctx, E0, F0, kk, s, B, w.dt, w.steps, ckpt_every=8)
+        L = EN[0, iy:iy + ww, ix:ix + ww, :].sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    return dict(workload="2-D periodic 256x256 x 16 groups, FP32 bulk, 40 steps, checkpoints every 8",
+                forward_ms_per_step=round(fwd_ms, 5), adjoint_ms_per_step=round(adj_ms, 5),
+                adjoint_over_forward=round(adj_ms / fwd_ms, 3),
+                end_to_end_backward_over_forward=round((t2 - t1) / (t1 - t0), 3))
+
+
 def cpu_baseline(w, dt, target_s=15.0):
     """The CPU oracle on a bounded sample of the same workload: whole steps on the first rows."""
     from oracle import m1_oracle as orc
@@ -181,6 +226,9 @@ def main():
                 del ctx, inp
                 torch.cuda.empty_cache()
             del w4
+        if args.only in (None, "adjoint"):
+            extra["adjoint"] = adjoint_ratios()
+            log("  adjoint:", extra["adjoint"])
         copy_gbs, copy_ms = copy_bandwidth()
         extra["copy_probe_GBps"] = round(copy_gbs, 1)
         log(f"  copy probe: {copy_gbs:.0f} GB/s")

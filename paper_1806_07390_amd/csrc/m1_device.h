@@ -24,30 +24,26 @@ __device__ __forceinline__ R minmod(R a, R b) {
   return (a * b <= R(0)) ? R(0) : (fabs(a) <= fabs(b) ? a : b);
 }
 
-// 1/x: the hardware estimate refined by two Newton-Raphson steps (double; within a couple of
-// ulp for the normal, finite, non-zero arguments used here), or the 1-ulp float estimate.
+// 1/x: the hardware estimate (about 25 correct bits) refined by one Newton-Raphson step
+// (double; within about 10 ulp for the normal, finite, non-zero arguments used here), or
+// the 1-ulp float estimate.
 __device__ __forceinline__ double rcp_(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
   return fma(r, e, r);
 }
 __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// sqrt(x) for normal positive arguments: reciprocal square-root estimate, two coupled
-// Newton steps for (sqrt x, 1/(2 sqrt x)) and a final residual correction (double), or the
+// sqrt(x) for normal positive arguments: reciprocal square-root estimate, one coupled
+// Newton step for (sqrt x, 1/(2 sqrt x)) and a final residual correction (double), or the
 // hardware float square root.
 __device__ __forceinline__ double sqrt_(double x) {
-  double y = __builtin_amdgcn_rsq(x);
+  const double y = __builtin_amdgcn_rsq(x);
   double g = x * y, h = 0.5 * y;
-  double r = fma(-g, h, 0.5);
+  const double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
-  r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  double d = fma(-g, g, x);
+  const double d = fma(-g, g, x);
   return fma(d, h, g);
 }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -370,13 +366,16 @@ struct ZoneDiag {
 };
 
 template <typename S, typename R, bool SPH, int ND>
-__device__ __forceinline__ double finish_zone(const StepArgs<S>& a, const Geo<R>& geo, int zg, int i, int j, int k,
-                                              const R Um[4], bool want_diag, ZoneDiag& zd) {
-  const double kd = (double)a.kap[zg], sd = (double)a.sig[zg], Bd = (double)a.B[zg];
+__device__ __forceinline__ double finish_zone_c(const StepArgs<S>& a, const Geo<R>& geo, int zg, int i, int j, int k,
+                                                const R Um[4], double kd, double sd, double Bd, bool want_diag,
+                                                ZoneDiag& zd) {
   const double c = a.c, dt = a.dt;
   const double Emd = (double)Um[0];
-  const double E1 = (Emd + dt * (c * kd * Bd)) * rcp_(1.0 + (c * dt) * kd);
-  const double ifden = rcp_(1.0 + (c * dt) * (kd + sd));
+  // one reciprocal for both denominators: 1/(1+x) = (1+y) / ((1+x)(1+y))
+  const double dE = 1.0 + (c * dt) * kd, dF = 1.0 + (c * dt) * (kd + sd);
+  const double rr = rcp_(dE * dF);
+  const double E1 = (Emd + dt * (c * kd * Bd)) * (dF * rr);
+  const double ifden = dE * rr;
   const S E1s = (S)E1;
   a.Eo[zg] = E1s;
   double F1s[3] = {0.0, 0.0, 0.0};
@@ -410,6 +409,13 @@ __device__ __forceinline__ double finish_zone(const StepArgs<S>& a, const Geo<R>
     zd.nnp += (E1d > 0.0) ? 0 : 1;
   }
   return E1d - Emd;
+}
+
+template <typename S, typename R, bool SPH, int ND>
+__device__ __forceinline__ double finish_zone(const StepArgs<S>& a, const Geo<R>& geo, int zg, int i, int j, int k,
+                                              const R Um[4], bool want_diag, ZoneDiag& zd) {
+  return finish_zone_c<S, R, SPH, ND>(a, geo, zg, i, j, k, Um, (double)a.kap[zg], (double)a.sig[zg],
+                                      (double)a.B[zg], want_diag, zd);
 }
 
 }  // namespace fm1

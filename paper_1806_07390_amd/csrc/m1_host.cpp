@@ -340,24 +340,35 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
       if (s > worst) worst = s;
     }
   ctx->max_dt1 = 1.0 / worst;
-  // tiling of the step kernel (FORNAX_M1_TILE="TXB,TYB,TM" overrides the default choice)
-  ctx->tile = choose_tile(*desc, desc->precision == FORNAX_FP64 ? sizeof(double) : sizeof(float));
+  // tiling of the step kernel (FORNAX_M1_TILE="TXB,TYB,TM[,GB]" overrides the default choice)
+  if (prepare_step_kernels() != FORNAX_OK) {
+    (void)hipFree(ctx->geo_mem);
+    delete ctx;
+    return FORNAX_EDEVICE;
+  }
+  ctx->tile = choose_tile(*desc, false);
+  ctx->tile_full = choose_tile(*desc, true);
   if (const char* env = std::getenv("FORNAX_M1_TILE")) {
-    int tx = 0, ty = 0, tm = 0;
-    if (std::sscanf(env, "%d,%d,%d", &tx, &ty, &tm) == 3 && tx >= 2 && ty >= 2 && tm >= 1 &&
-        tx * (desc->ndim == 3 ? ty : 1) * desc->ngroups <= 512) {
-      Tile t = make_tile(*desc, tx, ty, tm);
-      if (halo_slots_fit(t, desc->ndim) &&
-          tile_lds_bytes(t, desc->ndim, desc->ngroups, desc->precision == FORNAX_FP64 ? 8 : 4, true) <= 65536)
-        ctx->tile = t;
+    int tx = 0, ty = 0, tm = 0, gbk = desc->ngroups;
+    const int nread = std::sscanf(env, "%d,%d,%d,%d", &tx, &ty, &tm, &gbk);
+    if (nread >= 3) {
+      Tile t = make_tile(*desc, tx, ty, tm, gbk);
+      if (t.nblocks > 0) ctx->tile = t;
+      Tile tf = make_tile(*desc, tx, ty, tm, desc->ngroups);
+      if (tf.nblocks > 0) ctx->tile_full = tf;
     }
+  }
+  if (ctx->tile.nblocks <= 0) {
+    (void)hipFree(ctx->geo_mem);
+    delete ctx;
+    return FORNAX_EUNSUPPORTED;
   }
   // reduction scratch: one partial per block of the step kernel, and per block of the
   // zone-block kernels (source)
   int zpb = BLOCK / desc->ngroups;
   int64_t nz = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
   ctx->nblocks_step = (int)((nz + zpb - 1) / zpb);
-  size_t nb = (size_t)std::max(ctx->nblocks_step, ctx->tile.nblocks);
+  size_t nb = (size_t)std::max(ctx->nblocks_step, std::max(ctx->tile.nblocks, ctx->tile_full.nblocks));
   void* red = nullptr;
   if (hipMalloc(&red, nb * (2 * sizeof(double) + 2 * sizeof(int)) + 1024) != hipSuccess) {
     (void)hipFree(ctx->geo_mem);

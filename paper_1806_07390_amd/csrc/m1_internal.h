@@ -80,10 +80,13 @@ namespace fm1 {
 struct Tile {
   int TXB, TYB;        // zone columns per block in x and in y (y: 3-D only, else 1)
   int TM;              // planes per block along the march direction (1 for 1-D)
+  int GB;              // groups per block (a divisor of G)
   int ntx, nty, ntm;   // tiles per direction
+  int ngb;             // G / GB
   int nblocks;
   int xq, xr;          // nblocks = 8 xq + xr (XCD renumbering)
-  int nthreads;        // TXB * TYB * G
+  int nthreads;        // TXB * TYB * GB
+  size_t lds;          // dynamic LDS bytes per block (with the dE_matter buffer)
 };
 }  // namespace fm1
 
@@ -97,6 +100,7 @@ struct fornax_m1_ctx {
   size_t geo_bytes;
   double max_dt1;             // max_dt(cfl = 1)
   fm1::Tile tile;              // tiling of the fused step kernel
+  fm1::Tile tile_full;         // same with all groups per block (used when dE_matter is asked for)
   // reduction scratch (one partial per block of the step kernel)
   int nblocks_step;
   double* p_energy;

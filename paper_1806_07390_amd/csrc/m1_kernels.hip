@@ -190,9 +190,10 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
     a.p_nun = ctx->p_nun;
     a.p_nnp = ctx->p_nnp;
   }
-  const Tile& tl = ctx->tile;
+  const Tile& tl = a.dEm ? ctx->tile_full : ctx->tile;
   const int nb = tl.nblocks;
-  if (launch_tiled<S, R>(ctx, geo, a, tl, st) != FORNAX_OK) return FORNAX_EDEVICE;
+  const int rc = launch_tiled<S, R>(ctx, geo, a, tl, st);
+  if (rc != FORNAX_OK) return rc;
   if (want) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, ctx->p_energy, ctx->p_maxf2, ctx->p_nun, ctx->p_nnp, nb,
                        diag->energy_total, diag->max_f, diag->n_unrealizable, diag->n_nonpositive);

@@ -316,6 +316,45 @@ class Context:
         step._keep = (sa, sb, cf, dg)
         return step, current
 
+    def bound_step(self, src, dst, kappa, sigma, B, dt, inflow=None, stream=None):
+        """Pre-bound fornax_m1_step src -> dst (arguments built once); returns a function."""
+        sa = self._state(src[0], src[1], "in")
+        sb = self._state(dst[0], dst[1], "out")
+        cf = self._coeffs(kappa, sigma, B)
+        args = (self._h, ctypes.byref(sa), ctypes.byref(sb), ctypes.byref(cf), self._inflow(inflow), dt, None,
+                _stream(stream))
+        fn = _lib.fornax_m1_step
+
+        def call():
+            rc = fn(*args)
+            if rc != FORNAX_OK:
+                raise FornaxError(rc, "fornax_m1_step")
+
+        call._keep = (sa, sb, cf)
+        return call
+
+    def adjointer(self, U, kappa, sigma, B, dt, lam_in, lam_out, dkappa, inflow=None, stream=None):
+        """Pre-bound fornax_m1_adjoint call (arguments built once): returns a function that
+        computes lam_out = J^T lam_in and accumulates into dkappa for the state U."""
+        su = self._state(U[0], U[1], "Un")
+        sl = self._state(lam_in[0], lam_in[1], "lam_np1")
+        so = self._state(lam_out[0], lam_out[1], "lam_n")
+        self._check_arr(dkappa, "dkappa")
+        cf = self._coeffs(kappa, sigma, B)
+        infl = self._inflow(inflow)
+        st = _stream(stream)
+        args = (self._h, ctypes.byref(su), ctypes.byref(cf), infl, dt, ctypes.byref(sl), ctypes.byref(so),
+                ctypes.c_void_p(dkappa.data_ptr()), st)
+        fn = _lib.fornax_m1_adjoint
+
+        def call():
+            rc = fn(*args)
+            if rc != FORNAX_OK:
+                raise FornaxError(rc, "fornax_m1_adjoint")
+
+        call._keep = (su, sl, so, cf)
+        return call
+
     def run(self, E, F, kappa, sigma, B, dt, nsteps, inflow=None, diag=None):
         """nsteps steps with ping-pong buffers; returns (E, [F]) (new tensors)."""
         a = (E.clone(), [f.clone() for f in F])
@@ -367,20 +406,30 @@ class M1Steps(torch.autograd.Function):
         kappa, sigma, B = fctx.saved_tensors
         kappa, sigma, B = kappa.detach(), sigma.detach(), B.detach()
         zeros = lambda: torch.zeros(ctx.shape, dtype=ctx.dtype, device=ctx.device)
-        lam = ((gE if gE is not None else zeros()).contiguous().clone(),
-               [(g if g is not None else zeros()).contiguous().clone() for g in gF])
-        nxt = ctx.empty_state()
+        lam = [((gE if gE is not None else zeros()).contiguous().clone(),
+                [(g if g is not None else zeros()).contiguous().clone() for g in gF]),
+               ctx.empty_state()]
         dk = zeros()
+        K = min(ckpt_every, nsteps)
+        seg = [ctx.empty_state() for _ in range(K)]
+        # every C call of the replay is bound once: K-1 steps, K adjoint steps per lambda parity
+        steps = [ctx.bound_step(seg[i], seg[i + 1], kappa, sigma, B, dt, inflow=inflow) for i in range(K - 1)]
+        adj = [[ctx.adjointer(seg[i], kappa, sigma, B, dt, lam[p], lam[1 - p], dk, inflow=inflow)
+                for p in range(2)] for i in range(K)]
+        p = 0
         for (s0, E, F) in reversed(ckpts):
-            s1 = min(s0 + ckpt_every, nsteps)
-            states = [(E, F)]
-            for _ in range(s0, s1 - 1):
-                prev = states[-1]
-                states.append(ctx.step(prev[0], prev[1], kappa, sigma, B, dt, inflow=inflow))
-            for st in reversed(states):
-                ctx.adjoint(st[0], st[1], kappa, sigma, B, dt, lam[0], lam[1], out=nxt, dkappa=dk, inflow=inflow)
-                lam, nxt = nxt, lam
-        return (None, None, None, None, None, dk, None, None, lam[0]) + tuple(lam[1])
+            n_in = min(s0 + ckpt_every, nsteps) - s0
+            seg[0][0].copy_(E)
+            for k in range(len(F)):
+                seg[0][1][k].copy_(F[k])
+            for i in range(n_in - 1):
+                steps[i]()
+            for i in reversed(range(n_in)):
+                adj[i][p]()
+                p ^= 1
+        fctx.m1 = None
+        out = lam[p]
+        return (None, None, None, None, None, dk, None, None, out[0]) + tuple(out[1])
 
 
 def run_differentiable(ctx, E0, F0, kappa, sigma, B, dt, nsteps, ckpt_every=8, inflow=None):

@@ -110,6 +110,37 @@ def test_reflect_boundaries_fp64(m1):
     assert eE <= TOL_FP64 and eF <= TOL_FP64
 
 
+@pytest.mark.parametrize("case", ["2d", "3d", "sph3d"])
+def test_tile_shapes(m1, case):
+    """The step kernel's tiling (zone columns per block, planes per block, groups per block)
+    changes the work decomposition only: every tiling gives the oracle's result."""
+    import os
+    if case == "2d":
+        w = wl.blobs2d(n=37, G=6, steps=5)
+        tiles = ["3,1,1,6", "5,1,7,2", "16,1,16,3", "9,1,4,1"]
+    elif case == "3d":
+        w = wl.core3d(n=14, G=6, steps=5)
+        tiles = ["4,4,3,6", "6,5,2,2", "5,7,4,3", "8,6,16,1"]
+    else:
+        w = wl.sphere3d(nr=14, nth=10, nph=8, G=4, steps=5)
+        tiles = ["4,4,3,4", "6,5,2,2", "7,4,5,1"]
+    p = problem_of(w)
+    dt = dt_of(w, p)
+    E, F, _ = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow)
+    for prec, tol in ((m1.FP64, TOL_FP64), (m1.MIXED, TOL_MIXED_RUN)):
+        for tile in tiles:
+            say(f"case {case} tile {tile} prec {prec}")
+            os.environ["FORNAX_M1_TILE"] = tile
+            try:
+                ctx = m1.Context(m1.Config.from_workload(w, precision=prec))
+            finally:
+                del os.environ["FORNAX_M1_TILE"]
+            Eg, Fg = gpu_run(ctx, w, dt, w.steps)
+            eE, eF = rel_l1(Eg, Fg, E, F, w.c)
+            say("   ", eE, eF)
+            assert eE <= tol and eF <= tol, (case, tile, prec)
+
+
 # ------------------------------------------------------------------------------------------
 def test_flux_and_source_entry_points(m1):
     w = wl.sphere3d(nr=12, nth=8, nph=8, G=3, steps=1)
