@@ -52,7 +52,8 @@ enum { FORNAX_CARTESIAN = 0, FORNAX_SPHERICAL_LOGR = 1 };
 
 /* Boundary conditions (Implementation of the dendritic grid, Boundary Conditions):
  * OUTFLOW copies the edge zone; PERIODIC wraps; REFLECT mirrors and flips the normal flux;
- * INFLOW fills the ghosts with prescribed (E, physical F) per group; AXIS is the polar-axis
+ * INFLOW fills the ghosts with prescribed (E, physical F) per group (x1 only; on other axes
+ * fornax_m1_create returns FORNAX_EUNSUPPORTED); AXIS is the polar-axis
  * copy across theta = 0 or pi with a shift of n[2]/2 zones in phi and sign flips of the theta
  * and phi flux components (spherical x2 only, n[2] even or 1). */
 enum { FORNAX_BC_OUTFLOW = 0, FORNAX_BC_PERIODIC = 1, FORNAX_BC_REFLECT = 2, FORNAX_BC_INFLOW = 3,

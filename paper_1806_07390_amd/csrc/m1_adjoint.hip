@@ -411,6 +411,7 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
     a.bc_lo[d] = D.bc_lo[d];
     a.bc_hi[d] = D.bc_hi[d];
   }
+  fill_ghost_table(a);
   a.G = D.ngroups;
   a.ndim = D.ndim;
   a.limiter = D.limiter;

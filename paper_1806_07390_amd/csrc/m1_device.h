@@ -265,6 +265,7 @@ __device__ __forceinline__ void closure_row(const R q[4], const R h[3], int d, R
         for (int k = 0; k < ND; ++k) fd[k] *= sc;
         f2d = 1.0;
       }
+      // the cancellation-free form (1 - f^2)/(1 + s) in double near free streaming
       const double s = sqrt_(4.0 - 3.0 * f2d);
       const double r = rcp_((1.0 + s) * (2.0 + s));
       const double iso = (double)E * (1.0 - f2d) * (2.0 + s) * r;
@@ -278,11 +279,14 @@ __device__ __forceinline__ void closure_row(const R q[4], const R h[3], int d, R
     for (int k = 0; k < ND; ++k) f[k] *= sc;
     f2 = R(1);
   }
+  // (1 - f^2)/(1 + s) = (s - 1)/3 since s^2 = 4 - 3 f^2: one reciprocal, of 2 + s.  Near
+  // f -> 1 the isotropic part loses relative accuracy, but only by a few ulp of E, while
+  // the f f part carries the tensor there.
   const R s = sqrt_(R(4) - R(3) * f2);
-  const R r = rcp_((R(1) + s) * (R(2) + s));
-  const R iso = E * (R(1) - f2) * (R(2) + s) * r;
-  const R ani = E * R(3) * (R(1) + s) * r;
-  for (int k = 0; k < ND; ++k) P[k] = ani * f[d] * f[k] + (k == d ? iso : R(0));
+  const R iso = E * (s - R(1)) * R(1.0 / 3.0);
+  const R ani = R(3) * E * rcp_(R(2) + s);
+  const R af = ani * f[d];
+  for (int k = 0; k < ND; ++k) P[k] = af * f[k] + (k == d ? iso : R(0));
 }
 
 // HLL flux (coordinate components) across a d-face with face scale factors h, left/right
@@ -365,16 +369,18 @@ struct ZoneDiag {
   int nun = 0, nnp = 0;
 };
 
+// The coefficients enter as cdtk = c dt kappa, cdtks = c dt (kappa + sigma) and the emission
+// term jB = c dt kappa B, all in double.
 template <typename S, typename R, bool SPH, int ND>
 __device__ __forceinline__ double finish_zone_c(const StepArgs<S>& a, const Geo<R>& geo, int zg, int i, int j, int k,
-                                                const R Um[4], double kd, double sd, double Bd, bool want_diag,
-                                                ZoneDiag& zd) {
-  const double c = a.c, dt = a.dt;
+                                                const R Um[4], double cdtk, double cdtks, double jB, bool want_diag,
+                                                double V, ZoneDiag& zd) {
+  const double c = a.c;
   const double Emd = (double)Um[0];
   // one reciprocal for both denominators: 1/(1+x) = (1+y) / ((1+x)(1+y))
-  const double dE = 1.0 + (c * dt) * kd, dF = 1.0 + (c * dt) * (kd + sd);
+  const double dE = 1.0 + cdtk, dF = 1.0 + cdtks;
   const double rr = rcp_(dE * dF);
-  const double E1 = (Emd + dt * (c * kd * Bd)) * (dF * rr);
+  const double E1 = (Emd + jB) * (dF * rr);
   const double ifden = dE * rr;
   const S E1s = (S)E1;
   a.Eo[zg] = E1s;
@@ -386,7 +392,6 @@ __device__ __forceinline__ double finish_zone_c(const StepArgs<S>& a, const Geo<
   }
   const double E1d = (double)E1s;
   if (want_diag) {
-    const double V = geo.Wd[0][i + NG] * geo.Wd[1][j + NG] * geo.Wd[2][k + NG];
     zd.energy += V * E1d;
     double hd[3] = {1.0, 1.0, 1.0};
     if constexpr (SPH) {
@@ -414,8 +419,11 @@ __device__ __forceinline__ double finish_zone_c(const StepArgs<S>& a, const Geo<
 template <typename S, typename R, bool SPH, int ND>
 __device__ __forceinline__ double finish_zone(const StepArgs<S>& a, const Geo<R>& geo, int zg, int i, int j, int k,
                                               const R Um[4], bool want_diag, ZoneDiag& zd) {
-  return finish_zone_c<S, R, SPH, ND>(a, geo, zg, i, j, k, Um, (double)a.kap[zg], (double)a.sig[zg],
-                                      (double)a.B[zg], want_diag, zd);
+  const double V = want_diag ? geo.Wd[0][i + NG] * geo.Wd[1][j + NG] * geo.Wd[2][k + NG] : 0.0;
+  const double cdt = a.c * a.dt, kd = (double)a.kap[zg], sd = (double)a.sig[zg];
+  const double cdtk = cdt * kd;
+  return finish_zone_c<S, R, SPH, ND>(a, geo, zg, i, j, k, Um, cdtk, cdt * (kd + sd), cdtk * (double)a.B[zg],
+                                      want_diag, V, zd);
 }
 
 }  // namespace fm1

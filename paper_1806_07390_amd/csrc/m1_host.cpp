@@ -98,6 +98,8 @@ int validate(const fornax_m1_desc* d) {
         int bc = side ? d->bc_hi[k] : d->bc_lo[k];
         if ((bc == FORNAX_BC_REFLECT || bc == FORNAX_BC_AXIS) && d->n[k] < 2) return FORNAX_EINVAL;
       }
+      // prescribed inflow ghosts are supported on x (x1 = ln r: the inner radial boundary)
+      if (k != 0 && (d->bc_lo[k] == FORNAX_BC_INFLOW || d->bc_hi[k] == FORNAX_BC_INFLOW)) return FORNAX_EUNSUPPORTED;
       bool axis = d->bc_lo[k] == FORNAX_BC_AXIS || d->bc_hi[k] == FORNAX_BC_AXIS;
       if (axis) {
         if (d->coord != FORNAX_SPHERICAL_LOGR || k != 1) return FORNAX_EINVAL;
@@ -261,6 +263,7 @@ void pack(const HostGeo& H, bool sph, Packer& P, Geo<R>& G) {
     G.wf[d] = P.put<R>(H.wf[d]);
     G.Wd[d] = P.put<double>(H.W[d]);
     G.dx[d] = (R)H.dx[d];
+    G.idx[d] = (R)(1.0 / H.dx[d]);
   }
   G.rc = G.rf = G.hr = G.sc = G.sf = G.hs = G.gam = nullptr;
   if (sph) {
@@ -349,13 +352,17 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   ctx->tile = choose_tile(*desc, false);
   ctx->tile_full = choose_tile(*desc, true);
   if (const char* env = std::getenv("FORNAX_M1_TILE")) {
-    int tx = 0, ty = 0, tm = 0, gbk = desc->ngroups;
-    const int nread = std::sscanf(env, "%d,%d,%d,%d", &tx, &ty, &tm, &gbk);
-    if (nread >= 3) {
-      Tile t = make_tile(*desc, tx, ty, tm, gbk);
+    // "TXB,TYB,TM,GB[,NW]" (TXB, TYB ignored in 1-D/2-D, where TXB = 64/GB)
+    int tx = 0, ty = 0, tm = 0, gbk = desc->ngroups, nw = 1;
+    const int nread = std::sscanf(env, "%d,%d,%d,%d,%d", &tx, &ty, &tm, &gbk, &nw);
+    if (nread >= 4) {
+      if (nread < 5 && desc->ndim < 3) {
+        nw = std::min(8, desc->ngroups / std::max(gbk, 1));
+        while (nw > 1 && (desc->ngroups / gbk) % nw != 0) --nw;
+      }
+      Tile t = make_tile(*desc, tx, ty, tm, gbk, nw);
       if (t.nblocks > 0) ctx->tile = t;
-      Tile tf = make_tile(*desc, tx, ty, tm, desc->ngroups);
-      if (tf.nblocks > 0) ctx->tile_full = tf;
+      if (t.nblocks > 0 && t.GB * t.NW == desc->ngroups) ctx->tile_full = t;
     }
   }
   if (ctx->tile.nblocks <= 0) {

@@ -35,6 +35,7 @@ struct Geo {
   const R* hs;       // axis 1: sqrt(<sin^2 theta>)  (h_3 = hr * hs)
   const R* gam;      // axis 1, active zones j: <Gamma^3_23>, <Gamma^1_33>, <Gamma^2_33>, <Gamma^2_22>
   R dx[3];           // coordinate spacing
+  R idx[3];          // 1 / dx
 };
 
 // Host-side copy of the tables in double (the source of both device copies).
@@ -49,6 +50,9 @@ struct StepArgsBase {
   int n[3];
   int G, ndim;
   int bc_lo[3], bc_hi[3];
+  // ghost sources per axis for the indices -2, -1, n, n + 1: the source zone index and
+  // flags (bit 0: flip the normal flux, bit 1: inflow state, bit 2: polar-axis copy)
+  int gsrc[3][4], gfl[3][4];
   int limiter, closure;
   int zones_per_block;
   int64_t nzones;
@@ -56,6 +60,35 @@ struct StepArgsBase {
   double f2_fp64;            // (f_fp64)^2, MIXED only
   const double* inflow;      // [G][1+ndim] or null
 };
+
+// Ghost rules (periodic wrap, outflow / inflow edge copy, reflect / axis mirror) of the two
+// ghost layers on both sides of every axis.
+inline void fill_ghost_table(StepArgsBase& a) {
+  for (int d = 0; d < 3; ++d) {
+    const int n = a.n[d];
+    for (int k = 0; k < 4; ++k) {
+      const int e = (k < 2) ? k - 2 : n + (k - 2);
+      const bool low = e < 0;
+      const int bc = low ? a.bc_lo[d] : a.bc_hi[d];
+      int src = 0, fl = 0;
+      if (bc == FORNAX_BC_PERIODIC) {
+        src = low ? e + n : e - n;
+        while (src < 0) src += n;
+        while (src >= n) src -= n;
+      } else if (bc == FORNAX_BC_OUTFLOW || bc == FORNAX_BC_INFLOW) {
+        src = low ? 0 : n - 1;
+        fl = (bc == FORNAX_BC_INFLOW) ? 2 : 0;
+      } else {
+        src = low ? -1 - e : 2 * n - 1 - e;
+        if (src < 0) src = 0;
+        if (src > n - 1) src = n - 1;
+        fl = (bc == FORNAX_BC_AXIS) ? 5 : 1;
+      }
+      a.gsrc[d][k] = src;
+      a.gfl[d][k] = fl;
+    }
+  }
+}
 
 template <typename S>
 struct StepArgs : StepArgsBase {
@@ -80,12 +113,14 @@ namespace fm1 {
 struct Tile {
   int TXB, TYB;        // zone columns per block in x and in y (y: 3-D only, else 1)
   int TM;              // planes per block along the march direction (1 for 1-D)
-  int GB;              // groups per block (a divisor of G)
+  bool row;            // 1-D/2-D wave rows (else one tile unit per block)
+  int GB;              // groups per tile unit (a divisor of G; wave rows: a power of two)
+  int NW;              // 1-D/2-D: wavefronts (tile units) per block, each a group subset; 3-D: 1
   int ntx, nty, ntm;   // tiles per direction
-  int ngb;             // G / GB
+  int ngb;             // G / (GB NW): blocks per tile
   int nblocks;
   int xq, xr;          // nblocks = 8 xq + xr (XCD renumbering)
-  int nthreads;        // TXB * TYB * GB
+  int nthreads;        // 64 NW (1-D/2-D) or TXB * TYB * GB (3-D)
   size_t lds;          // dynamic LDS bytes per block (with the dE_matter buffer)
 };
 }  // namespace fm1

@@ -144,6 +144,7 @@ void fill_args(const fornax_m1_ctx* ctx, StepArgs<S>& a, const fornax_m1_coeffs*
     a.bc_lo[d] = D.bc_lo[d];
     a.bc_hi[d] = D.bc_hi[d];
   }
+  fill_ghost_table(a);
   a.G = D.ngroups;
   a.ndim = D.ndim;
   a.limiter = D.limiter;

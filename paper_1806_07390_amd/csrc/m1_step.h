@@ -7,10 +7,11 @@
 
 namespace fm1 {
 
-// Tile of TXB x TYB zone columns (TYB = 1 unless 3-D) and GB groups per block, TM planes along
-// the march direction.  Returns a tile with nblocks = 0 when the combination is invalid
-// (thread count, halo slots, LDS budget).
-Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB);
+// Tile of TXB x TYB zone columns and GB groups per unit, TM planes along the march direction;
+// in 1-D/2-D a unit is one wavefront (TXB = 64/GB, TYB = 1) and a block holds NW units.
+// Returns a tile with nblocks = 0 when the combination is invalid (thread count, halo slots,
+// LDS budget).
+Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB, int NW);
 Tile choose_tile(const fornax_m1_desc& D, bool all_groups);
 // Raise the dynamic LDS limit of every step-kernel instantiation (once per process).
 int prepare_step_kernels();

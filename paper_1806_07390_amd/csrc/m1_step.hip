@@ -31,75 +31,175 @@
 
 namespace fm1 {
 
-// Source of a zone index e (possibly a ghost, |e - clamp(e)| <= 2) along one axis of n zones.
-// flags: bit 0 flips the flux component normal to this axis (reflect, polar axis), bit 1 takes
-// the prescribed inflow state, bit 2 marks the polar-axis copy (shift n[2]/2 in phi, flip F_phi).
+// Source of a zone index e (possibly a ghost, -2 <= e <= n + 1) along axis d: the zone that
+// supplies the values and flags (bit 0 flips the flux component normal to the axis, bit 1
+// takes the prescribed inflow state, bit 2 marks the polar-axis copy: shift n[2]/2 in phi,
+// flip F_phi), from the ghost table of the launch.
 struct AxisSrc {
   int src;
   int flags;
 };
 
-__device__ __forceinline__ AxisSrc axis_src(int e, int n, int bclo, int bchi) {
+__device__ __forceinline__ AxisSrc axis_src(const StepArgsBase& a, int d, int e) {
+  const int n = a.n[d];
   AxisSrc r{e, 0};
-  if (e < 0 || e >= n) {
-    const bool low = e < 0;
-    const int bc = low ? bclo : bchi;
-    if (bc == FORNAX_BC_PERIODIC) {
-      int s = low ? e + n : e - n;
-      if (s < 0) s += n;
-      if (s >= n) s -= n;
-      r.src = s;
-    } else if (bc == FORNAX_BC_OUTFLOW || bc == FORNAX_BC_INFLOW) {
-      r.src = low ? 0 : n - 1;
-      r.flags = (bc == FORNAX_BC_INFLOW) ? 2 : 0;
-    } else {  // reflect or polar axis: mirror
-      r.src = low ? -1 - e : 2 * n - 1 - e;
-      r.flags = (bc == FORNAX_BC_AXIS) ? 5 : 1;
-    }
+  if (e < 0) {
+    r.src = a.gsrc[d][e + 2];
+    r.flags = a.gfl[d][e + 2];
+  } else if (e >= n) {
+    r.src = a.gsrc[d][e - n + 2];
+    r.flags = a.gfl[d][e - n + 2];
   }
   return r;
 }
 
-// Values of one zone-group from its per-axis sources; (ex, ey) are the zone's own extended
-// x and y indices (for the scale factors of an inflow ghost).  q, kap and sig may be null.
-template <typename S, typename R, bool SPH, int ND>
-__device__ __forceinline__ void load_zone(const StepArgs<S>& a, const Geo<R>& geo, AxisSrc sx, AxisSrc sy, AxisSrc sz,
-                                          int ex, int ey, int grp, R q[4], R* kap, R* sig) {
-  const int fl = sx.flags | sy.flags | sz.flags;
-  int iz = sz.src;
-  if (fl & 4) {
-    iz += a.n[2] >> 1;
-    if (iz >= a.n[2]) iz -= a.n[2];
-  }
-  const int zg = ((iz * a.n[1] + sy.src) * a.n[0] + sx.src) * a.G + grp;
-  if (kap) *kap = R(a.kap[zg]);
-  if (sig) *sig = R(a.sig[zg]);
-  if (!q) return;
-  if (fl & 2) {
-    const double* in = a.inflow + grp * (1 + ND);
-    R h[3];
-    cell_h<R, SPH>(geo, ex, ey, h);
-    q[0] = R(in[0]);
-    for (int c = 0; c < ND; ++c) q[1 + c] = h[c] * R(in[1 + c]);
+// In-plane part of a zone column's source: element offset of the source column within a
+// plane (including the group), the flux components it flips (bit c: F_c; reflect, and the
+// polar-axis copy across theta, in-plane y in 3-D), whether it is an inflow ghost (inflow is
+// prescribed on x only) and whether it is a polar-axis copy (its phi plane is shifted by
+// n[2]/2).
+struct ColSrc {
+  int cb;
+  int lm;
+  bool infl;
+  bool ax;
+};
+
+template <int DIM>
+__device__ __forceinline__ ColSrc col_src(const StepArgsBase& a, int gx, int gy, int grp) {
+  const AxisSrc sx = axis_src(a, 0, gx);
+  ColSrc c;
+  c.infl = (sx.flags & 2) != 0;
+  c.ax = false;
+  if constexpr (DIM == 3) {
+    const AxisSrc sy = axis_src(a, 1, gy);
+    c.cb = (sy.src * a.n[0] + sx.src) * a.G + grp;
+    c.lm = (sx.flags & 1) | ((sy.flags & 1) << 1) | ((sy.flags & 4) ? 4 : 0);
+    c.ax = (sy.flags & 4) != 0;
   } else {
-    q[0] = R(a.E[zg]);
-    const bool fz = (sz.flags & 1) || (fl & 4);
-    const bool flip[3] = {(sx.flags & 1) != 0, (sy.flags & 1) != 0, fz};
-    for (int c = 0; c < ND; ++c) {
-      const R v = R(a.F[c][zg]);
-      q[1 + c] = flip[c] ? -v : v;
-    }
+    (void)gy;
+    c.cb = sx.src * a.G + grp;
+    c.lm = sx.flags & 1;
   }
-  for (int c = ND; c < 3; ++c) q[1 + c] = R(0);
+  return c;
 }
 
-template <typename S, typename R, int DIM, bool SPH>
+// Raw values (no sign or inflow rules) of one zone-group of the column cs in plane m (the
+// march index, possibly a ghost; unused in 1-D), and the uniform flip mask of that plane.
+// q, kap and sig may be null.  The rules are applied later (fix_zone), not right after the
+// loads, so that the loads of one plane stay in flight while the previous plane is computed.
+template <typename S, typename R, int DIM>
+__device__ __forceinline__ int load_raw(const StepArgs<S>& a, ColSrc cs, int m, R q[4], R* kap, R* sig) {
+  constexpr int MD = DIM - 1;
+  int zg = cs.cb;
+  int pm = 0;
+  if constexpr (DIM >= 2) {
+    // march index: uniform over the block
+    const int nM = a.n[MD];
+    const AxisSrc sm = axis_src(a, MD, m);
+    int iz = sm.src;
+    if (DIM == 3 && cs.ax) {
+      iz += nM >> 1;
+      if (iz >= nM) iz -= nM;
+    }
+    pm = (sm.flags & 1) ? (1 << MD) | ((sm.flags & 4) ? 4 : 0) : 0;
+    const int P = (DIM == 3) ? a.n[0] * a.n[1] * a.G : a.n[0] * a.G;
+    zg += iz * P;
+  } else {
+    (void)m;
+  }
+  if (kap) *kap = R(a.kap[zg]);
+  if (sig) *sig = R(a.sig[zg]);
+  if (q) {
+    q[0] = R(a.E[zg]);
+    for (int c = 0; c < DIM; ++c) q[1 + c] = R(a.F[c][zg]);
+  }
+  return pm;
+}
+
+// Element offset of plane m's source (the march index, possibly a ghost) for a column that is
+// (ax) or is not a polar-axis copy, and the uniform flip mask of that plane.
+template <int DIM>
+__device__ __forceinline__ int plane_offset(const StepArgsBase& a, int m, bool ax, int& pm) {
+  constexpr int MD = DIM - 1;
+  pm = 0;
+  if constexpr (DIM >= 2) {
+    const int nM = a.n[MD];
+    const AxisSrc sm = axis_src(a, MD, m);
+    int iz = sm.src;
+    if (DIM == 3 && ax) {
+      iz += nM >> 1;
+      if (iz >= nM) iz -= nM;
+    }
+    pm = (sm.flags & 1) ? (1 << MD) | ((sm.flags & 4) ? 4 : 0) : 0;
+    const int P = (DIM == 3) ? a.n[0] * a.n[1] * a.G : a.n[0] * a.G;
+    return iz * P;
+  } else {
+    (void)a;
+    (void)m;
+    (void)ax;
+    return 0;
+  }
+}
+
+// Apply the sign rules (flip F_c where bit c of lm ^ pm is set) and, on an inflow column,
+// take the prescribed state qin instead.
+template <typename R, int DIM>
+__device__ __forceinline__ void fix_zone(const R raw[4], ColSrc cs, int pm, const R qin[4], R q[4]) {
+  const int mask = cs.lm ^ pm;
+  q[0] = cs.infl ? qin[0] : raw[0];
+  for (int c = 0; c < DIM; ++c) {
+    const R v = ((mask >> c) & 1) ? -raw[1 + c] : raw[1 + c];
+    q[1 + c] = cs.infl ? qin[1 + c] : v;
+  }
+  for (int c = DIM; c < 3; ++c) q[1 + c] = R(0);
+}
+
+// Prescribed inflow state of a column (x ghost): E and covariant F = h F^ with the ghost's own
+// scale factors, for group grp.
+template <typename R, bool SPH, int DIM>
+__device__ __forceinline__ void inflow_state(const StepArgsBase& a, const Geo<R>& geo, int ex, int ey, int grp, R q[4]) {
+  const double* in = a.inflow + grp * (1 + DIM);
+  R h[3];
+  cell_h<R, SPH>(geo, ex, ey, h);
+  q[0] = R(in[0]);
+  for (int c = 0; c < DIM; ++c) q[1 + c] = h[c] * R(in[1 + c]);
+  for (int c = DIM; c < 3; ++c) q[1 + c] = R(0);
+}
+
+// Synchronisation of one tile unit: the whole block in 3-D; in 1-D and 2-D a unit is one
+// wavefront, whose LDS operations execute in order, so only the compiler must be kept from
+// moving LDS accesses across this point.
+template <bool ROW>
+__device__ __forceinline__ void unit_sync() {
+  if constexpr (ROW) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// LDS bytes of one tile unit (plane values, lower face states, in-plane fluxes)
+__host__ __device__ inline size_t unit_lds_elems(int dim, int TXB, int TYB, int GB) {
+  const int NC = 1 + dim;
+  const int PROWS = (dim == 3) ? TYB + 2 : 1;
+  return ((size_t)(NC + 1) * PROWS * (TXB + 2) + (size_t)NC * TXB * TYB * (dim == 3 ? 4 : 2)) * GB;
+}
+
+template <typename S, typename R, int DIM, bool SPH, bool ROW>
 __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NC = 1 + DIM;   // E, F_1..F_DIM
   constexpr int MD = DIM - 1;   // march direction (DIM >= 2)
+  // ROW (1-D / 2-D): a tile unit is one wavefront (one x-row of TXB = 64/GB zone columns);
+  // the NW waves of a block march over the same tile with different groups.  Otherwise the
+  // unit is the block (TXB x TYB columns of GB groups).
+  static_assert(!ROW || DIM < 3, "wave rows are for 1-D and 2-D");
   const int GB = tl.GB, TXB = tl.TXB, TYB = tl.TYB;
-  const int t = threadIdx.x;
+  const int t = ROW ? (int)(threadIdx.x & 63) : (int)threadIdx.x;   // index in the unit
+  const int wv = ROW ? (int)(threadIdx.x >> 6) : 0;                 // unit of the block
   const int gs = t % GB;
   const int col = t / GB;
   const int cx = col % TXB, cy = col / TXB;
@@ -107,15 +207,16 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
   const int PCOLS = TXB + 2;
   const int PROWS = (DIM == 3) ? TYB + 2 : 1;
 
-  // LDS: plane values PV[v][prow][pcol][gs] (v = E, F.., kappa + sigma), lower face states
-  // LX/LY[c][col][gs], in-plane fluxes FX/FY[c][col][gs] (face above the column), dE_matter
-  // of the last plane DZ[col][gs]
-  R* PV = reinterpret_cast<R*>(smem);
+  // LDS per unit: plane values PV[v][prow][pcol][gs] (v = E, F.., kappa + sigma), lower face
+  // states LX/LY[c][col][gs], in-plane fluxes FX/FY[c][col][gs] (face above the column);
+  // per block: dE_matter partials DZ
+  const size_t unit_elems = unit_lds_elems(DIM, TXB, TYB, GB);
+  R* PV = reinterpret_cast<R*>(smem) + (size_t)wv * unit_elems;
   R* LX = PV + (size_t)(NC + 1) * PROWS * PCOLS * GB;
   R* LY = LX + (size_t)NC * NCOL * GB;
   R* FX = LY + ((DIM == 3) ? (size_t)NC * NCOL * GB : 0);
   R* FY = FX + (size_t)NC * NCOL * GB;
-  size_t dz_off = (size_t)((NC + 1) * PROWS * PCOLS + NC * NCOL * ((DIM == 3) ? 4 : 2)) * GB * sizeof(R);
+  size_t dz_off = (ROW ? (size_t)tl.NW : (size_t)1) * unit_elems * sizeof(R);
   dz_off = (dz_off + 15) & ~(size_t)15;
   double* DZ = reinterpret_cast<double*>(smem + dz_off);
   auto pv = [&](int v, int prow, int pcol, int g) -> R& {
@@ -127,7 +228,8 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
   const int b = blockIdx.x;
   const int xcd = b & 7, slot = b >> 3;
   const int L = xcd * tl.xq + min(xcd, tl.xr) + slot;
-  const int gb = L % tl.ngb;
+  const int gbb = L % tl.ngb;
+  const int gb = ROW ? gbb * tl.NW + wv : gbb;   // group subset of this unit
   int rest = L / tl.ngb;
   const int tx = rest % tl.ntx;
   rest /= tl.ntx;
@@ -144,9 +246,8 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
   const int mbeg = (DIM >= 2) ? tm * tl.TM : 0;
   const int mend = (DIM >= 2) ? min(mbeg + tl.TM, nM) : 1;
 
-  // staged: the column's zone lies within two ghost layers; recon: within one (its face
-  // states are used); upd: interior column of the tile inside the domain
-  const bool staged = gx <= n0 + 1 && (DIM < 3 || gy <= n1 + 1);
+  // recon: the column's zone lies within one ghost layer (its face states are used); upd:
+  // interior column of the tile inside the domain
   const bool recon = gx <= n0 && (DIM < 3 || gy <= n1);
   const bool upd = cx >= 1 && cx <= TXB - 2 && gx < n0 && (DIM < 3 || (cy >= 1 && cy <= TYB - 2 && gy < n1));
   const bool do_xf = recon && cx <= TXB - 2 && gx + 1 <= n0 && (DIM < 3 || (cy >= 1 && cy <= TYB - 2 && gy < n1));
@@ -156,97 +257,154 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
   ZoneDiag zd;
   const R c = R(a.c);
   const R dtR = R(a.dt);
-  const int ex = gx + NG;
-  const int eyc = (DIM == 3) ? gy + NG : NG;   // extended y of the column (3-D) / unused row (1-D)
+  // extended indices of the column for table lookups (clamped: columns beyond the second
+  // ghost layer compute values that are never used)
+  const int ex = min(gx, n0 + 1) + NG;
+  const int eyc = (DIM == 3) ? min(gy, n1 + 1) + NG : NG;   // 3-D: the column's y; else unused
 
-  // fixed sources of the in-plane indices of this column
-  const AxisSrc sx = axis_src(gx, n0, a.bc_lo[0], a.bc_hi[0]);
-  const AxisSrc sy = (DIM == 3) ? axis_src(gy, n1, a.bc_lo[1], a.bc_hi[1]) : AxisSrc{0, 0};
-  const AxisSrc s0{0, 0};
+  // fixed in-plane source of this column (columns beyond the second ghost layer load the
+  // last ghost's values, which are never used)
+  const ColSrc csrc = col_src<DIM>(a, min(gx, n0 + 1), (DIM == 3) ? min(gy, n1 + 1) : 0, grp);
 
-  // ---- halo slot of this thread (at most one): x halo columns -1, TXB of every row, and
-  // (3-D) y halo rows -1, TYB of every column ----
+  // ---- halo items: the values of the unit's halo zone-groups (x halo columns -1 and TXB of
+  // every row; 3-D also y halo rows -1 and TYB of every column), one value (E or F_c) per
+  // item, spread over the unit's threads so that each plane's halo costs at most NITEM loads
+  // per thread (the halo's opacities are never needed: only the faces between work columns
+  // are computed) ----
+  constexpr int NV = NC;
+  constexpr int NITEM = ROW ? 1 : 3;
   const int nsx = 2 * TYB * GB;
-  const int nslots = nsx + ((DIM == 3) ? 2 * TXB * GB : 0);
-  bool hs_on = false;
-  int hs_pcol = 0, hs_prow = 0, hs_g = 0, hs_ex = 0, hs_ey = NG;
-  AxisSrc hsx{0, 0}, hsy{0, 0};
-  if (t < nslots) {
-    hs_g = t % GB;
-    int hxz, hyz;
-    if (t < nsx) {
-      const int r = t / GB;
-      const int side = r & 1, row = r >> 1;
-      hs_pcol = side ? TXB + 1 : 0;
-      hs_prow = (DIM == 3) ? row + 1 : 0;
-      hxz = side ? x0 + TXB : x0 - 1;
-      hyz = (DIM == 3) ? y0 + row : 0;
-    } else {
-      const int r = (t - nsx) / GB;
-      const int side = r & 1, cl = r >> 1;
-      hs_pcol = cl + 1;
-      hs_prow = side ? TYB + 1 : 0;
-      hxz = x0 + cl;
-      hyz = side ? y0 + TYB : y0 - 1;
-    }
-    hs_on = hxz <= n0 + 1 && (DIM < 3 || hyz <= n1 + 1);
-    hsx = axis_src(hxz, n0, a.bc_lo[0], a.bc_hi[0]);
-    if constexpr (DIM == 3) hsy = axis_src(hyz, n1, a.bc_lo[1], a.bc_hi[1]);
-    hs_ex = hxz + NG;
-    hs_ey = (DIM == 3) ? hyz + NG : NG;
-  }
-  const int hs_grp = gb * GB + hs_g;
-  R hq[4] = {R(0), R(0), R(0), R(0)}, hks = R(0);
-  auto load_slot = [&](int m) {
-    if (hs_on) {
-      R k, s;
-      if constexpr (DIM == 1) {
-        load_zone<S, R, SPH, DIM>(a, geo, hsx, s0, s0, hs_ex, hs_ey, hs_grp, hq, &k, &s);
-      } else if constexpr (DIM == 2) {
-        const AxisSrc sm = axis_src(m, nM, a.bc_lo[MD], a.bc_hi[MD]);
-        load_zone<S, R, SPH, DIM>(a, geo, hsx, sm, s0, hs_ex, m + NG, hs_grp, hq, &k, &s);
+  const int nitems = (nsx + ((DIM == 3) ? 2 * TXB * GB : 0)) * NV;
+  const int nunit = ROW ? 64 : (int)blockDim.x;
+  const S* hbase[NITEM];
+  int hcb[NITEM], hinfo[NITEM], hlds[NITEM];   // hinfo: v | lm << 3 | inflow << 6 | axis << 7
+  R hvin[NITEM];
+  for (int k = 0; k < NITEM; ++k) {
+    const int it = t + k * nunit;
+    hbase[k] = a.E;   // a harmless in-range load for threads without an item
+    hcb[k] = csrc.cb;
+    hinfo[k] = 0;
+    hlds[k] = -1;
+    hvin[k] = R(0);
+    if (it < nitems) {
+      const int sl = it / NV, v = it % NV;
+      const int g = sl % GB, r = sl / GB;
+      int hxz, hyz, pcol, prow;
+      if (sl < nsx) {
+        const int side = r & 1, row = r >> 1;
+        pcol = side ? TXB + 1 : 0;
+        prow = (DIM == 3) ? row + 1 : 0;
+        hxz = side ? x0 + TXB : x0 - 1;
+        hyz = (DIM == 3) ? y0 + row : 0;
       } else {
-        const AxisSrc sm = axis_src(m, nM, a.bc_lo[MD], a.bc_hi[MD]);
-        load_zone<S, R, SPH, DIM>(a, geo, hsx, hsy, sm, hs_ex, hs_ey, hs_grp, hq, &k, &s);
+        const int r2i = (sl - nsx) / GB;
+        const int side = r2i & 1, cl = r2i >> 1;
+        pcol = cl + 1;
+        prow = side ? TYB + 1 : 0;
+        hxz = x0 + cl;
+        hyz = side ? y0 + TYB : y0 - 1;
       }
-      hks = k + s;
+      const bool on = hxz <= n0 + 1 && (DIM < 3 || hyz <= n1 + 1);
+      const int hg = gb * GB + g;
+      const ColSrc cs = col_src<DIM>(a, min(hxz, n0 + 1), (DIM == 3) ? min(hyz, n1 + 1) : 0, hg);
+      hbase[k] = (v == 0) ? a.E : a.F[v - 1];
+      hcb[k] = cs.cb;
+      hinfo[k] = v | (cs.lm << 3) | (cs.infl ? 64 : 0) | (cs.ax ? 128 : 0);
+      if (on) hlds[k] = (int)((((size_t)v * PROWS + prow) * PCOLS + pcol) * GB + g);
+      if (on && cs.infl) {
+        R qi[4];
+        inflow_state<R, SPH, DIM>(a, geo, min(hxz, n0 + 1) + NG, (DIM == 3) ? min(hyz, n1 + 1) + NG : NG, hg,
+                                  qi);
+        hvin[k] = qi[v];
+      }
+    }
+  }
+  // Values in flight.  Every load of plane data targets one of the "pending" registers below
+  // and is consumed, by arithmetic, at the start of the next plane, so that one plane of work
+  // hides its latency (a register copy of a load still in flight would wait for it).
+  R Pr[4], Pk = R(0), Ps = R(0), PB = R(0);   // own: raw q, kappa, sigma, B
+  R Ph[NITEM];                                 // halo items
+  int Ppm = 0;                                 // plane mask of the pending raw values
+  R qin[4] = {R(0), R(0), R(0), R(0)};
+  if (csrc.infl) inflow_state<R, SPH, DIM>(a, geo, ex, eyc, grp, qin);
+  for (int k = 0; k < 4; ++k) Pr[k] = R(0);
+  for (int k = 0; k < NITEM; ++k) Ph[k] = R(0);
+  auto load_halo = [&](int m) {
+    for (int k = 0; k < NITEM; ++k) {
+      int pmk;
+      const int off = plane_offset<DIM>(a, m, (hinfo[k] & 128) != 0, pmk);
+      Ph[k] = R(hbase[k][hcb[k] + off]);
     }
   };
-  // zone of this column in plane m (window loads); kap/sig may be null
-  auto load_own = [&](int m, R q[4], R* k, R* s) {
-    if constexpr (DIM == 1) {
-      load_zone<S, R, SPH, DIM>(a, geo, sx, s0, s0, ex, eyc, grp, q, k, s);
-    } else if constexpr (DIM == 2) {
-      const AxisSrc sm = axis_src(m, nM, a.bc_lo[MD], a.bc_hi[MD]);
-      load_zone<S, R, SPH, DIM>(a, geo, sx, sm, s0, ex, m + NG, grp, q, k, s);
-    } else {
-      const AxisSrc sm = axis_src(m, nM, a.bc_lo[MD], a.bc_hi[MD]);
-      load_zone<S, R, SPH, DIM>(a, geo, sx, sy, sm, ex, eyc, grp, q, k, s);
+  // halo values of plane m (loaded one plane ago) to LDS, with the sign and inflow rules
+  auto stage_halo = [&](int m) {
+    int pm;
+    (void)plane_offset<DIM>(a, m, false, pm);
+    for (int k = 0; k < NITEM; ++k) {
+      if (hlds[k] >= 0) {
+        const int v = hinfo[k] & 7;
+        const int mask = (hinfo[k] >> 3 & 7) ^ pm;
+        R val = Ph[k];
+        if (v >= 1 && v <= DIM && ((mask >> (v - 1)) & 1)) val = -val;
+        if (hinfo[k] & 64) val = hvin[k];
+        PV[hlds[k]] = val;
+      }
     }
   };
+  // raw values of this column's zone in plane m; returns the plane mask
+  auto load_own = [&](int m, R* q, R* k, R* sg) -> int { return load_raw<S, R, DIM>(a, csrc, m, q, k, sg); };
   // extended y index of the zone row in plane m (spherical tables; theta is y)
   auto ey_of = [&](int m) -> int { return (DIM == 2) ? m + NG : eyc; };
-
-  // ---- register window along the march direction: q(m .. m+3), kappa/sigma(m .. m+2), B ----
-  R q0[4], q1[4], q2[4], q3[4];
-  R hiM[4], fPrev[4];
-  for (int k = 0; k < 4; ++k) q0[k] = q1[k] = q2[k] = q3[k] = hiM[k] = fPrev[k] = R(0);
-  R k0 = R(0), s0v = R(0), k1 = R(0), s1v = R(0), k2 = R(0), s2v = R(0), B0 = R(0), B1 = R(0);
   const int zgB = grp;   // B offset added to the zone index below
   auto loadB = [&](int m) -> R {
-    // B of this column's zone in plane m (only updated columns use it; in-domain there)
-    const int zi = gx, zj = (DIM == 2) ? m : gy, zk = (DIM == 3) ? m : 0;
+    // B of this column's zone in plane m (only updated columns use it; the index is clamped
+    // into the domain so that every lane may load)
+    const int zi = min(max(gx, 0), n0 - 1);
+    const int zj = (DIM == 2) ? m : min(max(gy, 0), n1 - 1), zk = (DIM == 3) ? m : 0;
     return R(a.B[((zk * n1 + zj) * n0 + zi) * a.G + zgB]);
   };
-  if (staged) {
+  // zone volume factors for the energy diagnostic: the column's (fixed) and the plane's
+  // (Cartesian zones all have the same volume; spherical: the plane's factor is fetched one
+  // plane ahead with the other plane data)
+  double Vcol = 0.0;   // Cartesian and 1-D: the whole volume; else 2-D: x, z factors; 3-D: x, y
+  if (want_diag) {
+    if constexpr (DIM == 1 || !SPH) Vcol = geo.Wd[0][ex] * geo.Wd[1][eyc] * geo.Wd[2][NG];
+    if constexpr (DIM == 2 && SPH) Vcol = geo.Wd[0][ex] * geo.Wd[2][NG];
+    if constexpr (DIM == 3 && SPH) Vcol = geo.Wd[0][ex] * geo.Wd[1][eyc];
+  }
+  auto plane_vol = [&](int m) -> double {
+    if constexpr (SPH && DIM >= 2) return want_diag ? geo.Wd[MD][min(m, nM - 1) + NG] : 0.0;
+    return 1.0;
+  };
+  double Pvol = 0.0;
+
+  // ---- register window along the march direction: q(m), q(m+1) with the ghost rules
+  // applied; of planes m and m+1 the total opacity ks = kappa + sigma and, in double,
+  // c dt kappa and c dt (kappa + sigma) ----
+  const double cdt = a.c * a.dt;
+  R q0[4], q1[4];
+  R hiM[4], fPrev[4];
+  for (int k = 0; k < 4; ++k) q0[k] = q1[k] = hiM[k] = fPrev[k] = R(0);
+  R ks0 = R(0), ks1 = R(0);
+  double ck0 = 0.0, cks0 = 0.0, ck1 = 0.0, cks1 = 0.0;
+  {
+    R raw[4], k0, s0;
     if constexpr (DIM >= 2) {
       R qa[4], qb[4], ka, sa;
-      load_own(mbeg - 2, qa, nullptr, nullptr);
-      load_own(mbeg - 1, qb, &ka, &sa);
-      load_own(mbeg, q0, &k0, &s0v);
-      load_own(mbeg + 1, q1, &k1, &s1v);
-      load_own(mbeg + 2, q2, nullptr, nullptr);
-      if (upd) B0 = loadB(mbeg);
+      int pm = load_own(mbeg - 2, raw, nullptr, nullptr);
+      fix_zone<R, DIM>(raw, csrc, pm, qin, qa);
+      pm = load_own(mbeg - 1, raw, &ka, &sa);
+      fix_zone<R, DIM>(raw, csrc, pm, qin, qb);
+      pm = load_own(mbeg, raw, &k0, &s0);
+      fix_zone<R, DIM>(raw, csrc, pm, qin, q0);
+      pm = load_own(mbeg + 1, raw, nullptr, nullptr);
+      fix_zone<R, DIM>(raw, csrc, pm, qin, q1);
+      ks0 = k0 + s0;
+      // in flight into the first plane: raw q(mbeg + 2), kappa/sigma(mbeg + 1), B(mbeg)
+      Ppm = load_own(mbeg + 2, Pr, nullptr, nullptr);
+      load_own(mbeg + 1, nullptr, &Pk, &Ps);
+      PB = loadB(mbeg);
+      Pvol = plane_vol(mbeg);
       // face mbeg - 1/2 from zones mbeg - 1 (upper state) and mbeg (lower state)
       const int ef = mbeg + NG;   // lower face of zone mbeg
       const int eyf = (DIM == 3) ? eyc : ef;
@@ -263,41 +421,49 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
       if (o1) {
         const R dlL = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef - 1);
         const R dlR = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef);
-        hll<R, SPH, DIM>(a, MD, hiP, lo, h1, epsilon_of(ka + sa, k0 + s0v, dlL, dlR), fPrev);
+        hll<R, SPH, DIM>(a, MD, hiP, lo, h1, epsilon_of(ka + sa, ks0, dlL, dlR), fPrev);
       }
     } else {
-      load_own(0, q0, &k0, &s0v);
-      if (upd) B0 = loadB(0);
+      const int pm = load_own(0, raw, &k0, &s0);
+      fix_zone<R, DIM>(raw, csrc, pm, qin, q0);
+      ks0 = k0 + s0;
+      PB = loadB(0);
+      Pvol = plane_vol(0);
     }
+    ck0 = cdt * (double)k0;
+    cks0 = cdt * ((double)k0 + (double)s0);
   }
-  load_slot(mbeg);
+  load_halo(mbeg);
 
   const int prow_own = (DIM == 3) ? cy + 1 : 0;
-  const R idx0 = R(1) / geo.dx[0], idx1 = R(1) / geo.dx[1], idxM = R(1) / geo.dx[(DIM >= 2) ? MD : 0];
+  const R idx0 = geo.idx[0], idx1 = geo.idx[1], idxM = geo.idx[(DIM >= 2) ? MD : 0];
   int dz_zone = -1;
   for (int m = mbeg; m < mend; ++m) {
-    const bool more = m + 1 < mend;
-    // ---- (a) stage plane m: own zone, halo slot ----
-    pv(NC, prow_own, cx + 1, gs) = k0 + s0v;
+    // ---- consume the values loaded one plane ago ----
+    R q2[4];
+    fix_zone<R, DIM>(Pr, csrc, Ppm, qin, q2);   // plane m + 2
+    ks1 = Pk + Ps;                              // plane m + 1
+    ck1 = cdt * (double)Pk;
+    cks1 = cdt * ((double)Pk + (double)Ps);
+    const double jB = ck0 * (double)PB;         // c dt kappa B of plane m
+    const double Vm = Vcol * Pvol;              // zone volume (diagnostics)
+    stage_halo(m);
+    // ---- (a) stage plane m: own zone ----
     for (int v = 0; v < NC; ++v) pv(v, prow_own, cx + 1, gs) = q0[v];
-    if (t < nslots) {
-      for (int v = 0; v < NC; ++v) pv(v, hs_prow, hs_pcol, hs_g) = hq[v];
-      pv(NC, hs_prow, hs_pcol, hs_g) = hks;
-    }
-    // ---- prefetch for later planes: window q(m+3), kappa/sigma(m+2), B(m+1), slot m+1 ----
+    pv(NC, prow_own, cx + 1, gs) = ks0;
+    // ---- prefetch for the next plane: raw q(m+3), kappa/sigma(m+2), B(m+1), halo m+1.
+    // Issued on every plane (indices clamped into the ghost range; the last plane's are
+    // not used) so that the loads never sit in a branch ----
     if constexpr (DIM >= 2) {
-      if (more) {
-        if (staged) {
-          load_own(m + 3, q3, nullptr, nullptr);
-          load_own(m + 2, nullptr, &k2, &s2v);
-          if (upd) B1 = loadB(m + 1);
-        }
-        load_slot(m + 1);
-      }
+      Ppm = load_own(min(m + 3, nM + 1), Pr, nullptr, nullptr);
+      load_own(min(m + 2, nM + 1), nullptr, &Pk, &Ps);
+      PB = loadB(min(m + 1, nM - 1));
+      Pvol = plane_vol(m + 1);
+      load_halo(m + 1);
     }
-    __syncthreads();
-    // ---- (b) deferred dE_matter of the previous plane ----
-    if (a.dEm && dz_zone >= 0 && gs == 0) {
+    unit_sync<ROW>();
+    // ---- (b) deferred dE_matter of the previous plane (3-D: all groups in the block) ----
+    if (!ROW && a.dEm && dz_zone >= 0 && gs == 0) {
       double sdz = 0.0;
       for (int g2 = 0; g2 < GB; ++g2) sdz += DZ[(size_t)col * GB + g2];
       a.dEm[dz_zone] = -sdz;
@@ -345,11 +511,11 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
         if (o1) {
           const R dlL = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef - 1);
           const R dlR = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef);
-          hll<R, SPH, DIM>(a, MD, hiM, nLo, h1, epsilon_of(k0 + s0v, k1 + s1v, dlL, dlR), fNext);
+          hll<R, SPH, DIM>(a, MD, hiM, nLo, h1, epsilon_of(ks0, ks1, dlL, dlR), fNext);
         }
       }
     }
-    __syncthreads();
+    unit_sync<ROW>();
     // ---- (d) in-plane faces above this column ----
     R fxR[4] = {R(0), R(0), R(0), R(0)}, fyR[4] = {R(0), R(0), R(0), R(0)};
     if (do_xf) {
@@ -362,7 +528,7 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
         face_h<R, SPH>(geo, 0, ex, eym, ex + 1, hf);
         const R dlL = proper_width<R, SPH>(geo, 0, ex, eym);
         const R dlR = proper_width<R, SPH>(geo, 0, ex + 1, eym);
-        hll<R, SPH, DIM>(a, 0, hiX, qR, hf, epsilon_of(k0 + s0v, ksR, dlL, dlR), fxR);
+        hll<R, SPH, DIM>(a, 0, hiX, qR, hf, epsilon_of(ks0, ksR, dlL, dlR), fxR);
       }
       for (int v = 0; v < NC; ++v) FX[cidx(v, col)] = fxR[v];
     }
@@ -377,12 +543,12 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
           face_h<R, SPH>(geo, 1, ex, eyc, eyc + 1, hf);
           const R dlL = proper_width<R, SPH>(geo, 1, ex, eyc);
           const R dlR = proper_width<R, SPH>(geo, 1, ex, eyc + 1);
-          hll<R, SPH, DIM>(a, 1, hiY, qR, hf, epsilon_of(k0 + s0v, ksR, dlL, dlR), fyR);
+          hll<R, SPH, DIM>(a, 1, hiY, qR, hf, epsilon_of(ks0, ksR, dlL, dlR), fyR);
         }
         for (int v = 0; v < NC; ++v) FY[cidx(v, col)] = fyR[v];
       }
     }
-    __syncthreads();
+    unit_sync<ROW>();
     // ---- (e) update ----
     dz_zone = -1;
     if (upd) {
@@ -426,11 +592,18 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
         for (int cc = 0; cc < DIM; ++cc) Um[1 + cc] += dtR * Sg[cc];
       }
       const int zone = (zk * n1 + zj) * n0 + zi;
-      const double dz = finish_zone_c<S, R, SPH, DIM>(a, geo, zone * a.G + grp, zi, zj, zk, Um, (double)k0,
-                                                      (double)s0v, (double)B0, want_diag, zd);
-      if (a.dEm) {
+      const double V = Vm;
+      const double dz = finish_zone_c<S, R, SPH, DIM>(a, geo, zone * a.G + grp, zi, zj, zk, Um, ck0, cks0, jB,
+                                                      want_diag, V, zd);
+      if (!ROW && a.dEm) {
         DZ[(size_t)col * GB + gs] = dz;
         dz_zone = zone;
+      }
+      if (ROW && a.dEm) {
+        // sum over the GB groups of this column (consecutive lanes), one partial per wave
+        double p = dz;
+        for (int off = 1; off < GB; off <<= 1) p += __shfl_xor(p, off);
+        if (gs == 0) DZ[((size_t)(m - mbeg) * tl.NW + wv) * TXB + cx] = p;
       }
     }
     // ---- advance the window ----
@@ -438,23 +611,34 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
       for (int cc = 0; cc < 4; ++cc) {
         q0[cc] = q1[cc];
         q1[cc] = q2[cc];
-        q2[cc] = q3[cc];
         hiM[cc] = nHi[cc];
         fPrev[cc] = fNext[cc];
       }
-      k0 = k1;
-      s0v = s1v;
-      k1 = k2;
-      s1v = s2v;
-      B0 = B1;
+      ks0 = ks1;
+      ck0 = ck1;
+      cks0 = cks1;
     }
   }
   if (a.dEm) {
     __syncthreads();
-    if (dz_zone >= 0 && gs == 0) {
-      double s = 0.0;
-      for (int g2 = 0; g2 < GB; ++g2) s += DZ[(size_t)col * GB + g2];
-      a.dEm[dz_zone] = -s;
+    if constexpr (ROW) {
+      // dE_matter of every updated zone of the tile: sum of the wave partials, in order
+      const int nzt = (mend - mbeg) * TXB;
+      for (int i = threadIdx.x; i < nzt; i += blockDim.x) {
+        const int mm = mbeg + i / TXB, ccx = i % TXB;
+        const int zx = x0 + ccx;
+        if (ccx >= 1 && ccx <= TXB - 2 && zx < n0) {
+          double sdz = 0.0;
+          for (int w2 = 0; w2 < tl.NW; ++w2) sdz += DZ[((size_t)(mm - mbeg) * tl.NW + w2) * TXB + ccx];
+          a.dEm[(size_t)((DIM == 2) ? mm : 0) * n0 + zx] = -sdz;
+        }
+      }
+    } else {
+      if (dz_zone >= 0 && gs == 0) {
+        double s = 0.0;
+        for (int g2 = 0; g2 < GB; ++g2) s += DZ[(size_t)col * GB + g2];
+        a.dEm[dz_zone] = -s;
+      }
     }
   }
   if (!want_diag) return;
@@ -469,7 +653,7 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
   }
   __shared__ double we[16], wm[16];
   __shared__ int wu[16], wp[16];
-  const int wave = t >> 6, lane = t & 63;
+  const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   __syncthreads();
   if (lane == 0) {
     we[wave] = e;
@@ -502,35 +686,51 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
 static size_t g_max_lds = 64 * 1024 - 1024;
 
 static size_t lds_bytes(const Tile& tl, int dim, size_t rsize) {
-  const int NC = 1 + dim;
-  const int PROWS = (dim == 3) ? tl.TYB + 2 : 1;
-  const size_t ncol = (size_t)tl.TXB * tl.TYB;
-  size_t b = ((size_t)(NC + 1) * PROWS * (tl.TXB + 2) + (size_t)NC * ncol * (dim == 3 ? 4 : 2)) * tl.GB * rsize;
+  size_t b = unit_lds_elems(dim, tl.TXB, tl.TYB, tl.GB) * rsize * (tl.row ? tl.NW : 1);
   b = (b + 15) & ~(size_t)15;
-  b += ncol * tl.GB * sizeof(double);
+  // dE_matter partials: wave rows per plane, wave and column; block units per column and group
+  if (tl.row) b += (size_t)tl.TM * tl.NW * tl.TXB * sizeof(double);
+  else b += (size_t)tl.TXB * tl.TYB * tl.GB * sizeof(double);
   return b;
 }
 
-Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB) {
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB, int NW) {
   Tile tl{};
   const size_t rsize = (D.precision == FORNAX_FP64) ? sizeof(double) : sizeof(float);
+  // 1-D/2-D with NW >= 1: wave rows; NW = 0 (and always in 3-D): one unit per block
+  const bool row = D.ndim < 3 && NW >= 1;
+  tl.nblocks = 0;
+  if (GB < 1 || TM < 1 || D.ngroups % GB != 0) return tl;
+  if (row) {
+    // one x-row of 64/GB zone columns per wave, NW waves (group subsets) per block
+    if (!pow2(GB) || GB > 16 || NW > 8 || (D.ngroups / GB) % NW != 0) return tl;
+    TXB = 64 / GB;
+    TYB = 1;
+  } else {
+    NW = 1;
+    if (D.ndim < 3) TYB = 1;
+    if (TXB < 4 || (D.ndim == 3 && TYB < 4)) return tl;
+  }
+  tl.row = row;
   tl.TXB = TXB;
-  tl.TYB = (D.ndim == 3) ? TYB : 1;
+  tl.TYB = TYB;
   tl.TM = (D.ndim >= 2) ? TM : 1;
   tl.GB = GB;
-  tl.nblocks = 0;
-  if (TXB < 3 || (D.ndim == 3 && TYB < 4) || TM < 1 || GB < 1 || D.ngroups % GB != 0) return tl;
-  if (D.ndim == 3 && TXB < 4) return tl;
-  tl.nthreads = tl.TXB * tl.TYB * GB;
+  tl.NW = NW;
+  tl.nthreads = row ? 64 * NW : TXB * TYB * GB;
   if (tl.nthreads > 512) return tl;
-  // every thread stages at most one halo zone-group per plane
-  const int nslots = 2 * tl.TYB * GB + (D.ndim == 3 ? 2 * tl.TXB * GB : 0);
-  if (nslots > tl.nthreads) return tl;
+  // halo items (one value of one halo zone-group each): at most 1 per thread of a wave unit,
+  // 3 per thread of a block unit
+  const int nunit = row ? 64 : tl.nthreads;
+  const int nitems = (2 * TYB * GB + (D.ndim == 3 ? 2 * TXB * GB : 0)) * (D.ndim + 1);
+  if (nitems > (row ? 1 : 3) * nunit) return tl;
   tl.lds = lds_bytes(tl, D.ndim, rsize);
   if (tl.lds > g_max_lds) return tl;
-  tl.ngb = D.ngroups / GB;
-  tl.ntx = (D.n[0] + (tl.TXB - 2) - 1) / (tl.TXB - 2);
-  tl.nty = (D.ndim == 3) ? (D.n[1] + (tl.TYB - 2) - 1) / (tl.TYB - 2) : 1;
+  tl.ngb = D.ngroups / (GB * NW);
+  tl.ntx = (D.n[0] + (TXB - 2) - 1) / (TXB - 2);
+  tl.nty = (D.ndim == 3) ? (D.n[1] + (TYB - 2) - 1) / (TYB - 2) : 1;
   const int nM = (D.ndim >= 2) ? D.n[D.ndim - 1] : 1;
   tl.ntm = (nM + tl.TM - 1) / tl.TM;
   tl.nblocks = tl.ngb * tl.ntx * tl.nty * tl.ntm;
@@ -539,22 +739,30 @@ Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB) {
   return tl;
 }
 
-// Default tile.  1-D and 2-D: all groups, up to 16 (or 512/G) zone columns.  3-D: a
-// near-square tile of 256-512 threads; with many groups per zone, groups are split across
-// blocks so that the zone tile stays large enough to amortise its halo, unless all groups
-// are needed in one block.
+// Default tile.
+//  * 1-D / 2-D: GB = the largest power of two up to 4 dividing G (16 zone columns per wave,
+//    runs of 4 groups), all G / GB group subsets of a tile in one block when they fit in 8
+//    waves; planes per block halved from 32 until the grid has at least 2048 blocks (TM >= 4).
+//    With all_groups, GB grows until the block holds every group.
+//  * 3-D: a near-square tile of 128-512 threads; with many groups per zone, groups are split
+//    across blocks so that the zone tile stays large enough to amortise its halo, unless all
+//    groups are needed in one block.
 Tile choose_tile(const fornax_m1_desc& D, bool all_groups) {
   const int G = D.ngroups;
   if (D.ndim < 3) {
-    int GB = G;
-    if (3 * G > 512) {
-      if (all_groups) return Tile{};
-      GB = 32;
-      while (G % GB != 0) --GB;
+    int GB = 1;
+    while (GB < 4 && G % (2 * GB) == 0) GB *= 2;
+    if (all_groups)
+      while (G / GB > 8 && GB < 16 && G % (2 * GB) == 0) GB *= 2;
+    int NW = std::min(8, G / GB);
+    while ((G / GB) % NW != 0) --NW;
+    if (all_groups && NW * GB != G) return Tile{};
+    Tile t{};
+    for (int TM = 32; TM >= 4; TM /= 2) {
+      t = make_tile(D, 0, 1, TM, GB, NW);
+      if (t.nblocks >= 2048 || D.ndim == 1) break;
     }
-    int TXB = std::max(3, std::min(16, 512 / GB));
-    if (D.ndim == 1) TXB = std::max(3, std::min(512 / GB, D.n[0] + 2));
-    return make_tile(D, TXB, 1, 16, GB);
+    return t;
   }
   Tile best{};
   double best_cost = 1e30;
@@ -563,7 +771,7 @@ Tile choose_tile(const fornax_m1_desc& D, bool all_groups) {
     if (all_groups && GB != G) break;
     for (int TXB = 4; TXB <= 32; ++TXB)
       for (int TYB = 4; TYB <= 32; ++TYB) {
-        Tile t = make_tile(D, TXB, TYB, 8, GB);
+        Tile t = make_tile(D, TXB, TYB, 8, GB, 1);
         if (t.nblocks == 0 || t.nthreads < 128) continue;
         // loaded columns per updated column, and a mild preference for big blocks and
         // for keeping groups together (contiguous runs)
@@ -579,10 +787,29 @@ Tile choose_tile(const fornax_m1_desc& D, bool all_groups) {
   return best;
 }
 
-template <typename S, typename R, int DIM, bool SPH>
+template <typename S, typename R, int DIM, bool SPH, bool ROW>
 static hipError_t raise_lds_limit(int bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step_tiled<S, R, DIM, SPH>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step_tiled<S, R, DIM, SPH, ROW>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <typename S, typename R>
+static hipError_t raise_all(int bytes) {
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (r != hipSuccess) e = r;
+  };
+  chk(raise_lds_limit<S, R, 1, false, true>(bytes));
+  chk(raise_lds_limit<S, R, 2, false, true>(bytes));
+  chk(raise_lds_limit<S, R, 1, true, true>(bytes));
+  chk(raise_lds_limit<S, R, 2, true, true>(bytes));
+  chk(raise_lds_limit<S, R, 1, false, false>(bytes));
+  chk(raise_lds_limit<S, R, 2, false, false>(bytes));
+  chk(raise_lds_limit<S, R, 3, false, false>(bytes));
+  chk(raise_lds_limit<S, R, 1, true, false>(bytes));
+  chk(raise_lds_limit<S, R, 2, true, false>(bytes));
+  chk(raise_lds_limit<S, R, 3, true, false>(bytes));
+  return e;
 }
 
 int prepare_step_kernels() {
@@ -595,22 +822,9 @@ int prepare_step_kernels() {
   const int want = optin - 1024;
   done = true;
   if (want <= (int)g_max_lds) return FORNAX_OK;
-  hipError_t e = hipSuccess;
-  auto chk = [&](hipError_t r) {
-    if (r != hipSuccess) e = r;
-  };
-  chk(raise_lds_limit<double, double, 1, false>(want));
-  chk(raise_lds_limit<double, double, 2, false>(want));
-  chk(raise_lds_limit<double, double, 3, false>(want));
-  chk(raise_lds_limit<double, double, 1, true>(want));
-  chk(raise_lds_limit<double, double, 2, true>(want));
-  chk(raise_lds_limit<double, double, 3, true>(want));
-  chk(raise_lds_limit<float, float, 1, false>(want));
-  chk(raise_lds_limit<float, float, 2, false>(want));
-  chk(raise_lds_limit<float, float, 3, false>(want));
-  chk(raise_lds_limit<float, float, 1, true>(want));
-  chk(raise_lds_limit<float, float, 2, true>(want));
-  chk(raise_lds_limit<float, float, 3, true>(want));
+  hipError_t e = raise_all<double, double>(want);
+  const hipError_t e2 = raise_all<float, float>(want);
+  if (e == hipSuccess) e = e2;
   if (e == hipSuccess) g_max_lds = (size_t)want;
   (void)hipGetLastError();   // a refused attribute is not an error of later calls
   return FORNAX_OK;
@@ -621,18 +835,30 @@ int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, co
   const bool sph = ctx->desc.coord == FORNAX_SPHERICAL_LOGR;
   const int D = ctx->desc.ndim;
   // dE_matter sums over the groups of a zone inside one block
-  if (tl.nblocks <= 0 || (a.dEm && tl.GB != a.G)) return FORNAX_EUNSUPPORTED;
+  if (tl.nblocks <= 0 || (a.dEm && tl.GB * tl.NW != a.G)) return FORNAX_EUNSUPPORTED;
   dim3 grid(tl.nblocks), block(tl.nthreads);
-#define FM1_LAUNCH(DIMV, SPHV) \
-  hipLaunchKernelGGL((k_step_tiled<S, R, DIMV, SPHV>), grid, block, tl.lds, st, a, geo, tl)
+#define FM1_LAUNCH(DIMV, SPHV, ROWV) \
+  hipLaunchKernelGGL((k_step_tiled<S, R, DIMV, SPHV, ROWV>), grid, block, tl.lds, st, a, geo, tl)
   if (sph) {
-    if (D == 1) FM1_LAUNCH(1, true);
-    else if (D == 2) FM1_LAUNCH(2, true);
-    else FM1_LAUNCH(3, true);
+    if (D == 1) {
+      if (tl.row) FM1_LAUNCH(1, true, true);
+      else FM1_LAUNCH(1, true, false);
+    } else if (D == 2) {
+      if (tl.row) FM1_LAUNCH(2, true, true);
+      else FM1_LAUNCH(2, true, false);
+    } else {
+      FM1_LAUNCH(3, true, false);
+    }
   } else {
-    if (D == 1) FM1_LAUNCH(1, false);
-    else if (D == 2) FM1_LAUNCH(2, false);
-    else FM1_LAUNCH(3, false);
+    if (D == 1) {
+      if (tl.row) FM1_LAUNCH(1, false, true);
+      else FM1_LAUNCH(1, false, false);
+    } else if (D == 2) {
+      if (tl.row) FM1_LAUNCH(2, false, true);
+      else FM1_LAUNCH(2, false, false);
+    } else {
+      FM1_LAUNCH(3, false, false);
+    }
   }
 #undef FM1_LAUNCH
   return hipGetLastError() == hipSuccess ? FORNAX_OK : FORNAX_EDEVICE;

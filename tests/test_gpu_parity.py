@@ -116,8 +116,10 @@ def test_tile_shapes(m1, case):
     changes the work decomposition only: every tiling gives the oracle's result."""
     import os
     if case == "2d":
-        w = wl.blobs2d(n=37, G=6, steps=5)
-        tiles = ["3,1,1,6", "5,1,7,2", "16,1,16,3", "9,1,4,1"]
+        # "TXB,TYB,TM,GB[,NW]": with NW >= 1 a wave holds 64/GB zone columns of GB groups and
+        # a block NW such waves; with NW = 0 a block holds TXB columns of GB groups
+        w = wl.blobs2d(n=70, G=8, steps=5)
+        tiles = ["0,1,1,1", "0,1,7,2,2", "0,1,16,4", "0,1,5,8,1", "0,1,3,1,4", "16,1,8,8,0", "5,1,3,2,0"]
     elif case == "3d":
         w = wl.core3d(n=14, G=6, steps=5)
         tiles = ["4,4,3,6", "6,5,2,2", "5,7,4,3", "8,6,16,1"]
