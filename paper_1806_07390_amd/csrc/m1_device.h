@@ -19,10 +19,11 @@
 
 namespace fm1 {
 
-template <typename R>
-__device__ __forceinline__ R minmod(R a, R b) {
-  return (a * b <= R(0)) ? R(0) : (fabs(a) <= fabs(b) ? a : b);
-}
+// minmod(a, b): 0 when a and b differ in sign, else the one of smaller magnitude; this is the
+// median of a, b and 0 (which differs from the product test a b <= 0 only when the product
+// underflows, below any slope that can change a face state).
+__device__ __forceinline__ double minmod(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
+__device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 
 // 1/x: the hardware estimate (about 25 correct bits) refined by one Newton-Raphson step
 // (double; within about 10 ulp for the normal, finite, non-zero arguments used here), or

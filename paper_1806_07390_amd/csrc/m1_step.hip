@@ -143,16 +143,15 @@ __device__ __forceinline__ int plane_offset(const StepArgsBase& a, int m, bool a
 }
 
 // Apply the sign rules (flip F_c where bit c of lm ^ pm is set) and, on an inflow column,
-// take the prescribed state qin instead.
+// take the prescribed state instead (held in LDS: qin[c * stride], written once).
 template <typename R, int DIM>
-__device__ __forceinline__ void fix_zone(const R raw[4], ColSrc cs, int pm, const R qin[4], R q[4]) {
+__device__ __forceinline__ void fix_zone(const R raw[4], ColSrc cs, int pm, const R* qin, int stride, R q[4]) {
   const int mask = cs.lm ^ pm;
-  q[0] = cs.infl ? qin[0] : raw[0];
-  for (int c = 0; c < DIM; ++c) {
-    const R v = ((mask >> c) & 1) ? -raw[1 + c] : raw[1 + c];
-    q[1 + c] = cs.infl ? qin[1 + c] : v;
-  }
+  q[0] = raw[0];
+  for (int c = 0; c < DIM; ++c) q[1 + c] = ((mask >> c) & 1) ? -raw[1 + c] : raw[1 + c];
   for (int c = DIM; c < 3; ++c) q[1 + c] = R(0);
+  if (cs.infl)
+    for (int c = 0; c <= DIM; ++c) q[c] = qin[c * stride];
 }
 
 // Prescribed inflow state of a column (x ghost): E and covariant F = h F^ with the ghost's own
@@ -181,23 +180,30 @@ __device__ __forceinline__ void unit_sync() {
   }
 }
 
-// LDS bytes of one tile unit (plane values, lower face states, in-plane fluxes)
+// LDS elements of one tile unit: plane values, lower face states, in-plane fluxes, and the
+// prescribed inflow values of each thread (its column's state and up to 3 halo items)
 __host__ __device__ inline size_t unit_lds_elems(int dim, int TXB, int TYB, int GB) {
   const int NC = 1 + dim;
   const int PROWS = (dim == 3) ? TYB + 2 : 1;
-  return ((size_t)(NC + 1) * PROWS * (TXB + 2) + (size_t)NC * TXB * TYB * (dim == 3 ? 4 : 2)) * GB;
+  return ((size_t)(NC + 1) * PROWS * (TXB + 2) + (size_t)NC * TXB * TYB * (dim == 3 ? 4 : 2) +
+          (size_t)(NC + 3) * TXB * TYB) * GB;
 }
 
-template <typename S, typename R, int DIM, bool SPH, bool ROW>
-__global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
+template <typename S, typename R, int DIM, bool SPH, bool ROW, int GBC>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(GBC > 0 && !SPH ? 4 : 1)))
+k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NC = 1 + DIM;   // E, F_1..F_DIM
   constexpr int MD = DIM - 1;   // march direction (DIM >= 2)
   // ROW (1-D / 2-D): a tile unit is one wavefront (one x-row of TXB = 64/GB zone columns);
   // the NW waves of a block march over the same tile with different groups.  Otherwise the
   // unit is the block (TXB x TYB columns of GB groups).
+  // GBC > 0: wave rows of GBC groups known at compile time (constant LDS offsets); 0: runtime
   static_assert(!ROW || DIM < 3, "wave rows are for 1-D and 2-D");
-  const int GB = tl.GB, TXB = tl.TXB, TYB = tl.TYB;
+  static_assert(GBC == 0 || (ROW && 64 % GBC == 0), "compile-time groups per wave row");
+  const int GB = (GBC > 0) ? GBC : tl.GB;
+  const int TXB = (GBC > 0) ? 64 / GBC : tl.TXB;
+  const int TYB = (GBC > 0) ? 1 : tl.TYB;
   const int t = ROW ? (int)(threadIdx.x & 63) : (int)threadIdx.x;   // index in the unit
   const int wv = ROW ? (int)(threadIdx.x >> 6) : 0;                 // unit of the block
   const int gs = t % GB;
@@ -216,6 +222,8 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
   R* LY = LX + (size_t)NC * NCOL * GB;
   R* FX = LY + ((DIM == 3) ? (size_t)NC * NCOL * GB : 0);
   R* FY = FX + (size_t)NC * NCOL * GB;
+  R* QI = FY + ((DIM == 3) ? (size_t)NC * NCOL * GB : 0);   // [NC + 3][NCOL * GB]
+  const int qis = NCOL * GB;                                  // threads of the unit
   size_t dz_off = (ROW ? (size_t)tl.NW : (size_t)1) * unit_elems * sizeof(R);
   dz_off = (dz_off + 15) & ~(size_t)15;
   double* DZ = reinterpret_cast<double*>(smem + dz_off);
@@ -278,14 +286,13 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
   const int nunit = ROW ? 64 : (int)blockDim.x;
   const S* hbase[NITEM];
   int hcb[NITEM], hinfo[NITEM], hlds[NITEM];   // hinfo: v | lm << 3 | inflow << 6 | axis << 7
-  R hvin[NITEM];
   for (int k = 0; k < NITEM; ++k) {
     const int it = t + k * nunit;
     hbase[k] = a.E;   // a harmless in-range load for threads without an item
     hcb[k] = csrc.cb;
     hinfo[k] = 0;
     hlds[k] = -1;
-    hvin[k] = R(0);
+    R hvin = R(0);
     if (it < nitems) {
       const int sl = it / NV, v = it % NV;
       const int g = sl % GB, r = sl / GB;
@@ -315,9 +322,10 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
         R qi[4];
         inflow_state<R, SPH, DIM>(a, geo, min(hxz, n0 + 1) + NG, (DIM == 3) ? min(hyz, n1 + 1) + NG : NG, hg,
                                   qi);
-        hvin[k] = qi[v];
+        hvin = qi[v];
       }
     }
+    QI[(NC + k) * qis + t] = hvin;
   }
   // Values in flight.  Every load of plane data targets one of the "pending" registers below
   // and is consumed, by arithmetic, at the start of the next plane, so that one plane of work
@@ -325,8 +333,12 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
   R Pr[4], Pk = R(0), Ps = R(0), PB = R(0);   // own: raw q, kappa, sigma, B
   R Ph[NITEM];                                 // halo items
   int Ppm = 0;                                 // plane mask of the pending raw values
-  R qin[4] = {R(0), R(0), R(0), R(0)};
-  if (csrc.infl) inflow_state<R, SPH, DIM>(a, geo, ex, eyc, grp, qin);
+  {
+    R qin[4] = {R(0), R(0), R(0), R(0)};
+    if (csrc.infl) inflow_state<R, SPH, DIM>(a, geo, ex, eyc, grp, qin);
+    for (int c = 0; c < NC; ++c) QI[c * qis + t] = qin[c];
+  }
+  const R* qinp = QI + t;
   for (int k = 0; k < 4; ++k) Pr[k] = R(0);
   for (int k = 0; k < NITEM; ++k) Ph[k] = R(0);
   auto load_halo = [&](int m) {
@@ -346,7 +358,7 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
         const int mask = (hinfo[k] >> 3 & 7) ^ pm;
         R val = Ph[k];
         if (v >= 1 && v <= DIM && ((mask >> (v - 1)) & 1)) val = -val;
-        if (hinfo[k] & 64) val = hvin[k];
+        if (hinfo[k] & 64) val = QI[(NC + k) * qis + t];
         PV[hlds[k]] = val;
       }
     }
@@ -368,7 +380,8 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
   // plane ahead with the other plane data)
   double Vcol = 0.0;   // Cartesian and 1-D: the whole volume; else 2-D: x, z factors; 3-D: x, y
   if (want_diag) {
-    if constexpr (DIM == 1 || !SPH) Vcol = geo.Wd[0][ex] * geo.Wd[1][eyc] * geo.Wd[2][NG];
+    if constexpr (!SPH) Vcol = geo.Wd[0][NG] * geo.Wd[1][NG] * geo.Wd[2][NG];   // uniform zones
+    if constexpr (DIM == 1 && SPH) Vcol = geo.Wd[0][ex] * geo.Wd[1][NG] * geo.Wd[2][NG];
     if constexpr (DIM == 2 && SPH) Vcol = geo.Wd[0][ex] * geo.Wd[2][NG];
     if constexpr (DIM == 3 && SPH) Vcol = geo.Wd[0][ex] * geo.Wd[1][eyc];
   }
@@ -392,13 +405,13 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
     if constexpr (DIM >= 2) {
       R qa[4], qb[4], ka, sa;
       int pm = load_own(mbeg - 2, raw, nullptr, nullptr);
-      fix_zone<R, DIM>(raw, csrc, pm, qin, qa);
+      fix_zone<R, DIM>(raw, csrc, pm, qinp, qis, qa);
       pm = load_own(mbeg - 1, raw, &ka, &sa);
-      fix_zone<R, DIM>(raw, csrc, pm, qin, qb);
+      fix_zone<R, DIM>(raw, csrc, pm, qinp, qis, qb);
       pm = load_own(mbeg, raw, &k0, &s0);
-      fix_zone<R, DIM>(raw, csrc, pm, qin, q0);
+      fix_zone<R, DIM>(raw, csrc, pm, qinp, qis, q0);
       pm = load_own(mbeg + 1, raw, nullptr, nullptr);
-      fix_zone<R, DIM>(raw, csrc, pm, qin, q1);
+      fix_zone<R, DIM>(raw, csrc, pm, qinp, qis, q1);
       ks0 = k0 + s0;
       // in flight into the first plane: raw q(mbeg + 2), kappa/sigma(mbeg + 1), B(mbeg)
       Ppm = load_own(mbeg + 2, Pr, nullptr, nullptr);
@@ -425,7 +438,7 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
       }
     } else {
       const int pm = load_own(0, raw, &k0, &s0);
-      fix_zone<R, DIM>(raw, csrc, pm, qin, q0);
+      fix_zone<R, DIM>(raw, csrc, pm, qinp, qis, q0);
       ks0 = k0 + s0;
       PB = loadB(0);
       Pvol = plane_vol(0);
@@ -441,7 +454,7 @@ __global__ void __launch_bounds__(512) k_step_tiled(StepArgs<S> a, Geo<R> geo, T
   for (int m = mbeg; m < mend; ++m) {
     // ---- consume the values loaded one plane ago ----
     R q2[4];
-    fix_zone<R, DIM>(Pr, csrc, Ppm, qin, q2);   // plane m + 2
+    fix_zone<R, DIM>(Pr, csrc, Ppm, qinp, qis, q2);   // plane m + 2
     ks1 = Pk + Ps;                              // plane m + 1
     ck1 = cdt * (double)Pk;
     cks1 = cdt * ((double)Pk + (double)Ps);
@@ -742,7 +755,8 @@ Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB, int NW
 // Default tile.
 //  * 1-D / 2-D: GB = the largest power of two up to 4 dividing G (16 zone columns per wave,
 //    runs of 4 groups), all G / GB group subsets of a tile in one block when they fit in 8
-//    waves; planes per block halved from 32 until the grid has at least 2048 blocks (TM >= 4).
+//    waves; planes per block halved from 32 until the grid has at least 1024 (FP64) or 2048
+//    (MIXED) blocks, TM >= 4.
 //    With all_groups, GB grows until the block holds every group.
 //  * 3-D: a near-square tile of 128-512 threads; with many groups per zone, groups are split
 //    across blocks so that the zone tile stays large enough to amortise its halo, unless all
@@ -757,10 +771,13 @@ Tile choose_tile(const fornax_m1_desc& D, bool all_groups) {
     int NW = std::min(8, G / GB);
     while ((G / GB) % NW != 0) --NW;
     if (all_groups && NW * GB != G) return Tile{};
+    // FP64 waves hold more registers (fewer of them per SIMD): longer marches amortise the
+    // first face of each march better there
+    const int want = (D.precision == FORNAX_FP64) ? 1024 : 2048;
     Tile t{};
     for (int TM = 32; TM >= 4; TM /= 2) {
       t = make_tile(D, 0, 1, TM, GB, NW);
-      if (t.nblocks >= 2048 || D.ndim == 1) break;
+      if (t.nblocks >= want || D.ndim == 1) break;
     }
     return t;
   }
@@ -787,9 +804,9 @@ Tile choose_tile(const fornax_m1_desc& D, bool all_groups) {
   return best;
 }
 
-template <typename S, typename R, int DIM, bool SPH, bool ROW>
+template <typename S, typename R, int DIM, bool SPH, bool ROW, int GBC = 0>
 static hipError_t raise_lds_limit(int bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step_tiled<S, R, DIM, SPH, ROW>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step_tiled<S, R, DIM, SPH, ROW, GBC>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -803,6 +820,8 @@ static hipError_t raise_all(int bytes) {
   chk(raise_lds_limit<S, R, 2, false, true>(bytes));
   chk(raise_lds_limit<S, R, 1, true, true>(bytes));
   chk(raise_lds_limit<S, R, 2, true, true>(bytes));
+  chk(raise_lds_limit<S, R, 2, false, true, 4>(bytes));
+  chk(raise_lds_limit<S, R, 2, true, true, 4>(bytes));
   chk(raise_lds_limit<S, R, 1, false, false>(bytes));
   chk(raise_lds_limit<S, R, 2, false, false>(bytes));
   chk(raise_lds_limit<S, R, 3, false, false>(bytes));
@@ -837,27 +856,29 @@ int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, co
   // dE_matter sums over the groups of a zone inside one block
   if (tl.nblocks <= 0 || (a.dEm && tl.GB * tl.NW != a.G)) return FORNAX_EUNSUPPORTED;
   dim3 grid(tl.nblocks), block(tl.nthreads);
-#define FM1_LAUNCH(DIMV, SPHV, ROWV) \
-  hipLaunchKernelGGL((k_step_tiled<S, R, DIMV, SPHV, ROWV>), grid, block, tl.lds, st, a, geo, tl)
+#define FM1_LAUNCH(DIMV, SPHV, ROWV, GBV) \
+  hipLaunchKernelGGL((k_step_tiled<S, R, DIMV, SPHV, ROWV, GBV>), grid, block, tl.lds, st, a, geo, tl)
   if (sph) {
     if (D == 1) {
-      if (tl.row) FM1_LAUNCH(1, true, true);
-      else FM1_LAUNCH(1, true, false);
+      if (tl.row) FM1_LAUNCH(1, true, true, 0);
+      else FM1_LAUNCH(1, true, false, 0);
     } else if (D == 2) {
-      if (tl.row) FM1_LAUNCH(2, true, true);
-      else FM1_LAUNCH(2, true, false);
+      if (tl.row && tl.GB == 4) FM1_LAUNCH(2, true, true, 4);
+      else if (tl.row) FM1_LAUNCH(2, true, true, 0);
+      else FM1_LAUNCH(2, true, false, 0);
     } else {
-      FM1_LAUNCH(3, true, false);
+      FM1_LAUNCH(3, true, false, 0);
     }
   } else {
     if (D == 1) {
-      if (tl.row) FM1_LAUNCH(1, false, true);
-      else FM1_LAUNCH(1, false, false);
+      if (tl.row) FM1_LAUNCH(1, false, true, 0);
+      else FM1_LAUNCH(1, false, false, 0);
     } else if (D == 2) {
-      if (tl.row) FM1_LAUNCH(2, false, true);
-      else FM1_LAUNCH(2, false, false);
+      if (tl.row && tl.GB == 4) FM1_LAUNCH(2, false, true, 4);
+      else if (tl.row) FM1_LAUNCH(2, false, true, 0);
+      else FM1_LAUNCH(2, false, false, 0);
     } else {
-      FM1_LAUNCH(3, false, false);
+      FM1_LAUNCH(3, false, false, 0);
     }
   }
 #undef FM1_LAUNCH
