@@ -371,11 +371,12 @@ struct ZoneDiag {
 };
 
 // The coefficients enter as cdtk = c dt kappa, cdtks = c dt (kappa + sigma) and the emission
-// term jB = c dt kappa B, all in double.
+// term jB = c dt kappa B, all in double.  Returns E^{n+1} - E^- and the new state in the
+// storage type (E1, F1); the caller stores it.  (i, j) are the zone's x and y indices.
 template <typename S, typename R, bool SPH, int ND>
-__device__ __forceinline__ double finish_zone_c(const StepArgs<S>& a, const Geo<R>& geo, int zg, int i, int j, int k,
-                                                const R Um[4], double cdtk, double cdtks, double jB, bool want_diag,
-                                                double V, ZoneDiag& zd) {
+__device__ __forceinline__ double source_zone(const StepArgsBase& a, const Geo<R>& geo, int i, int j, const R Um[4],
+                                              double cdtk, double cdtks, double jB, bool want_diag, double V,
+                                              ZoneDiag& zd, S& E1o, S F1o[3]) {
   const double c = a.c;
   const double Emd = (double)Um[0];
   // one reciprocal for both denominators: 1/(1+x) = (1+y) / ((1+x)(1+y))
@@ -384,11 +385,11 @@ __device__ __forceinline__ double finish_zone_c(const StepArgs<S>& a, const Geo<
   const double E1 = (Emd + jB) * (dF * rr);
   const double ifden = dE * rr;
   const S E1s = (S)E1;
-  a.Eo[zg] = E1s;
+  E1o = E1s;
   double F1s[3] = {0.0, 0.0, 0.0};
   for (int cc = 0; cc < ND; ++cc) {
     const S v = (S)((double)Um[1 + cc] * ifden);
-    a.Fo[cc][zg] = v;
+    F1o[cc] = v;
     F1s[cc] = (double)v;
   }
   const double E1d = (double)E1s;
@@ -415,16 +416,6 @@ __device__ __forceinline__ double finish_zone_c(const StepArgs<S>& a, const Geo<
     zd.nnp += (E1d > 0.0) ? 0 : 1;
   }
   return E1d - Emd;
-}
-
-template <typename S, typename R, bool SPH, int ND>
-__device__ __forceinline__ double finish_zone(const StepArgs<S>& a, const Geo<R>& geo, int zg, int i, int j, int k,
-                                              const R Um[4], bool want_diag, ZoneDiag& zd) {
-  const double V = want_diag ? geo.Wd[0][i + NG] * geo.Wd[1][j + NG] * geo.Wd[2][k + NG] : 0.0;
-  const double cdt = a.c * a.dt, kd = (double)a.kap[zg], sd = (double)a.sig[zg];
-  const double cdtk = cdt * kd;
-  return finish_zone_c<S, R, SPH, ND>(a, geo, zg, i, j, k, Um, cdtk, cdt * (kd + sd), cdtk * (double)a.B[zg],
-                                      want_diag, V, zd);
 }
 
 }  // namespace fm1

@@ -349,20 +349,33 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
     delete ctx;
     return FORNAX_EDEVICE;
   }
-  ctx->tile = choose_tile(*desc, false);
-  ctx->tile_full = choose_tile(*desc, true);
+  {
+    // pairs of groups per lane (FORNAX_M1_PAIRS=0 disables)
+    const char* pe = std::getenv("FORNAX_M1_PAIRS");
+    // (measured: in 1-D/2-D and in 3-D FP64 the second group's registers cost more waves
+    // than the wider accesses gain; 3-D MIXED gains)
+    const int V = (desc->ndim == 3 && desc->precision == FORNAX_MIXED && desc->ngroups % 2 == 0 &&
+                   !(pe && pe[0] == '0'))
+                      ? 2
+                      : 1;
+    ctx->tile = choose_tile(*desc, false, V);
+    ctx->tile_full = choose_tile(*desc, true, V);
+    if (ctx->tile.nblocks <= 0) ctx->tile = choose_tile(*desc, false, 1);
+    if (ctx->tile_full.nblocks <= 0) ctx->tile_full = choose_tile(*desc, true, 1);
+    ctx->tile_v1 = choose_tile(*desc, true, 1);
+  }
   if (const char* env = std::getenv("FORNAX_M1_TILE")) {
-    // "TXB,TYB,TM,GB[,NW]" (TXB, TYB ignored in 1-D/2-D, where TXB = 64/GB)
-    int tx = 0, ty = 0, tm = 0, gbk = desc->ngroups, nw = 1;
-    const int nread = std::sscanf(env, "%d,%d,%d,%d,%d", &tx, &ty, &tm, &gbk, &nw);
+    // "TXB,TYB,TM,GB[,NW[,V]]" (TXB, TYB ignored for 1-D/2-D wave rows, where TXB = 64 V/GB)
+    int tx = 0, ty = 0, tm = 0, gbk = desc->ngroups, nw = 1, vv = 1;
+    const int nread = std::sscanf(env, "%d,%d,%d,%d,%d,%d", &tx, &ty, &tm, &gbk, &nw, &vv);
     if (nread >= 4) {
       if (nread < 5 && desc->ndim < 3) {
         nw = std::min(8, desc->ngroups / std::max(gbk, 1));
         while (nw > 1 && (desc->ngroups / gbk) % nw != 0) --nw;
       }
-      Tile t = make_tile(*desc, tx, ty, tm, gbk, nw);
+      Tile t = make_tile(*desc, tx, ty, tm, gbk, nw, vv);
       if (t.nblocks > 0) ctx->tile = t;
-      if (t.nblocks > 0 && t.GB * t.NW == desc->ngroups) ctx->tile_full = t;
+      if (t.nblocks > 0 && t.GB * (t.row ? t.NW : 1) == desc->ngroups) ctx->tile_full = t;
     }
   }
   if (ctx->tile.nblocks <= 0) {
@@ -375,7 +388,8 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   int zpb = BLOCK / desc->ngroups;
   int64_t nz = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
   ctx->nblocks_step = (int)((nz + zpb - 1) / zpb);
-  size_t nb = (size_t)std::max(ctx->nblocks_step, std::max(ctx->tile.nblocks, ctx->tile_full.nblocks));
+  size_t nb = (size_t)std::max(std::max(ctx->nblocks_step, ctx->tile_v1.nblocks),
+                               std::max(ctx->tile.nblocks, ctx->tile_full.nblocks));
   void* red = nullptr;
   if (hipMalloc(&red, nb * (2 * sizeof(double) + 2 * sizeof(int)) + 1024) != hipSuccess) {
     (void)hipFree(ctx->geo_mem);

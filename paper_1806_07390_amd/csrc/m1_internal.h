@@ -114,6 +114,7 @@ struct Tile {
   int TXB, TYB;        // zone columns per block in x and in y (y: 3-D only, else 1)
   int TM;              // planes per block along the march direction (1 for 1-D)
   bool row;            // 1-D/2-D wave rows (else one tile unit per block)
+  int V;               // groups per lane (1, or 2: pairs of consecutive groups)
   int GB;              // groups per tile unit (a divisor of G; wave rows: a power of two)
   int NW;              // 1-D/2-D: wavefronts (tile units) per block, each a group subset; 3-D: 1
   int ntx, nty, ntm;   // tiles per direction
@@ -136,6 +137,8 @@ struct fornax_m1_ctx {
   double max_dt1;             // max_dt(cfl = 1)
   fm1::Tile tile;              // tiling of the fused step kernel
   fm1::Tile tile_full;         // same with all groups per block (used when dE_matter is asked for)
+  fm1::Tile tile_v1;           // one group per lane, all groups per block (arrays not aligned to pairs)
+  fm1::Tile last_tile[1];      // the tile of the last step launch (for inspection)
   // reduction scratch (one partial per block of the step kernel)
   int nblocks_step;
   double* p_energy;

@@ -191,10 +191,9 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
     a.p_nun = ctx->p_nun;
     a.p_nnp = ctx->p_nnp;
   }
-  const Tile& tl = a.dEm ? ctx->tile_full : ctx->tile;
-  const int nb = tl.nblocks;
-  const int rc = launch_tiled<S, R>(ctx, geo, a, tl, st);
+  const int rc = launch_tiled<S, R>(ctx, geo, a, st);
   if (rc != FORNAX_OK) return rc;
+  const int nb = ctx->last_tile->nblocks;
   if (want) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, ctx->p_energy, ctx->p_maxf2, ctx->p_nun, ctx->p_nnp, nb,
                        diag->energy_total, diag->max_f, diag->n_unrealizable, diag->n_nonpositive);

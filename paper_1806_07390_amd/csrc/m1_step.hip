@@ -25,6 +25,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "m1_device.h"
 #include "m1_internal.h"
 #include "m1_step.h"
@@ -84,12 +86,39 @@ __device__ __forceinline__ ColSrc col_src(const StepArgsBase& a, int gx, int gy,
   return c;
 }
 
-// Raw values (no sign or inflow rules) of one zone-group of the column cs in plane m (the
+// V consecutive values of array p from element zg (zg a multiple of V): one vector load.
+template <typename S, typename R, int V>
+__device__ __forceinline__ void ldv(const S* p, int zg, R out[V]) {
+  if constexpr (V == 1) {
+    out[0] = R(p[zg]);
+  } else {
+    static_assert(V == 2, "one or two values per lane");
+    using T2 = typename std::conditional<sizeof(S) == 8, double2, float2>::type;
+    const T2 v = *reinterpret_cast<const T2*>(p + zg);
+    out[0] = R(v.x);
+    out[1] = R(v.y);
+  }
+}
+
+template <typename S, int V>
+__device__ __forceinline__ void stv(S* p, int zg, const S in[V]) {
+  if constexpr (V == 1) {
+    p[zg] = in[0];
+  } else {
+    using T2 = typename std::conditional<sizeof(S) == 8, double2, float2>::type;
+    T2 v;
+    v.x = in[0];
+    v.y = in[1];
+    *reinterpret_cast<T2*>(p + zg) = v;
+  }
+}
+
+// Raw values (no sign or inflow rules) of the V zone-groups of the column cs in plane m (the
 // march index, possibly a ghost; unused in 1-D), and the uniform flip mask of that plane.
 // q, kap and sig may be null.  The rules are applied later (fix_zone), not right after the
 // loads, so that the loads of one plane stay in flight while the previous plane is computed.
-template <typename S, typename R, int DIM>
-__device__ __forceinline__ int load_raw(const StepArgs<S>& a, ColSrc cs, int m, R q[4], R* kap, R* sig) {
+template <typename S, typename R, int DIM, int V>
+__device__ __forceinline__ int load_raw(const StepArgs<S>& a, ColSrc cs, int m, R (*q)[4], R* kap, R* sig) {
   constexpr int MD = DIM - 1;
   int zg = cs.cb;
   int pm = 0;
@@ -108,11 +137,16 @@ __device__ __forceinline__ int load_raw(const StepArgs<S>& a, ColSrc cs, int m, 
   } else {
     (void)m;
   }
-  if (kap) *kap = R(a.kap[zg]);
-  if (sig) *sig = R(a.sig[zg]);
+  if (kap) ldv<S, R, V>(a.kap, zg, kap);
+  if (sig) ldv<S, R, V>(a.sig, zg, sig);
   if (q) {
-    q[0] = R(a.E[zg]);
-    for (int c = 0; c < DIM; ++c) q[1 + c] = R(a.F[c][zg]);
+    R t[V];
+    ldv<S, R, V>(a.E, zg, t);
+    for (int u = 0; u < V; ++u) q[u][0] = t[u];
+    for (int c = 0; c < DIM; ++c) {
+      ldv<S, R, V>(a.F[c], zg, t);
+      for (int u = 0; u < V; ++u) q[u][1 + c] = t[u];
+    }
   }
   return pm;
 }
@@ -189,48 +223,49 @@ __host__ __device__ inline size_t unit_lds_elems(int dim, int TXB, int TYB, int 
           (size_t)(NC + 3) * TXB * TYB) * GB;
 }
 
-template <typename S, typename R, int DIM, bool SPH, bool ROW, int GBC>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(GBC > 0 && !SPH ? 4 : 1)))
+template <typename S, typename R, int DIM, bool SPH, bool ROW, int GBC, int V>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(GBC > 0 && !SPH && V == 1 ? 4 : 1)))
 k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NC = 1 + DIM;   // E, F_1..F_DIM
   constexpr int MD = DIM - 1;   // march direction (DIM >= 2)
-  // ROW (1-D / 2-D): a tile unit is one wavefront (one x-row of TXB = 64/GB zone columns);
-  // the NW waves of a block march over the same tile with different groups.  Otherwise the
-  // unit is the block (TXB x TYB columns of GB groups).
-  // GBC > 0: wave rows of GBC groups known at compile time (constant LDS offsets); 0: runtime
+  // ROW (1-D / 2-D): a tile unit is one wavefront (one x-row of TXB zone columns); the NW
+  // waves of a block march over the same tile with different groups.  Otherwise the unit is
+  // the block (TXB x TYB columns of GB groups).  Each lane handles V consecutive groups of
+  // one column (V = 2: 16-byte loads).  GBC > 0: groups per wave row known at compile time.
   static_assert(!ROW || DIM < 3, "wave rows are for 1-D and 2-D");
-  static_assert(GBC == 0 || (ROW && 64 % GBC == 0), "compile-time groups per wave row");
+  static_assert(GBC == 0 || (ROW && (64 * V) % GBC == 0), "compile-time groups per wave row");
   const int GB = (GBC > 0) ? GBC : tl.GB;
-  const int TXB = (GBC > 0) ? 64 / GBC : tl.TXB;
+  const int LPC = GB / V;                                            // lanes per zone column
+  const int TXB = (GBC > 0) ? 64 * V / GBC : tl.TXB;
   const int TYB = (GBC > 0) ? 1 : tl.TYB;
   const int t = ROW ? (int)(threadIdx.x & 63) : (int)threadIdx.x;   // index in the unit
   const int wv = ROW ? (int)(threadIdx.x >> 6) : 0;                 // unit of the block
-  const int gs = t % GB;
-  const int col = t / GB;
+  const int gl = t % LPC;                                            // group pair (V = 2) of the lane
+  const int col = t / LPC;
   const int cx = col % TXB, cy = col / TXB;
   const int NCOL = TXB * TYB;
   const int PCOLS = TXB + 2;
   const int PROWS = (DIM == 3) ? TYB + 2 : 1;
+  const int nunit = NCOL * LPC;                                      // threads of the unit
 
-  // LDS per unit: plane values PV[v][prow][pcol][gs] (v = E, F.., kappa + sigma), lower face
-  // states LX/LY[c][col][gs], in-plane fluxes FX/FY[c][col][gs] (face above the column);
-  // per block: dE_matter partials DZ
+  // LDS per unit: plane values PV[v][prow][pcol][g] (v = E, F.., kappa + sigma), lower face
+  // states LX/LY[c][col][g], in-plane fluxes FX/FY[c][col][g] (face above the column), the
+  // prescribed inflow values QI; per block: dE_matter partials DZ
   const size_t unit_elems = unit_lds_elems(DIM, TXB, TYB, GB);
   R* PV = reinterpret_cast<R*>(smem) + (size_t)wv * unit_elems;
   R* LX = PV + (size_t)(NC + 1) * PROWS * PCOLS * GB;
   R* LY = LX + (size_t)NC * NCOL * GB;
   R* FX = LY + ((DIM == 3) ? (size_t)NC * NCOL * GB : 0);
   R* FY = FX + (size_t)NC * NCOL * GB;
-  R* QI = FY + ((DIM == 3) ? (size_t)NC * NCOL * GB : 0);   // [NC + 3][NCOL * GB]
-  const int qis = NCOL * GB;                                  // threads of the unit
+  R* QI = FY + ((DIM == 3) ? (size_t)NC * NCOL * GB : 0);   // [NC + 3][nunit][V]
   size_t dz_off = (ROW ? (size_t)tl.NW : (size_t)1) * unit_elems * sizeof(R);
   dz_off = (dz_off + 15) & ~(size_t)15;
   double* DZ = reinterpret_cast<double*>(smem + dz_off);
-  auto pv = [&](int v, int prow, int pcol, int g) -> R& {
-    return PV[(((size_t)v * PROWS + prow) * PCOLS + pcol) * GB + g];
-  };
-  auto cidx = [&](int c, int cl) -> size_t { return ((size_t)c * NCOL + cl) * GB + gs; };
+  // element index of (v, prow, pcol) for this lane's first group
+  auto pvi = [&](int v, int prow, int pcol) -> int { return ((v * PROWS + prow) * PCOLS + pcol) * GB + gl * V; };
+  auto cidx = [&](int c, int cl) -> int { return (c * NCOL + cl) * GB + gl * V; };
+  auto qii = [&](int c) -> int { return (c * nunit + t) * V; };
 
   // logical tile of this block (XCD-aware renumbering; group blocks of a tile adjacent)
   const int b = blockIdx.x;
@@ -243,7 +278,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
   rest /= tl.ntx;
   const int ty = (DIM == 3) ? rest % tl.nty : 0;
   const int tm = (DIM == 3) ? rest / tl.nty : rest;
-  const int grp = gb * GB + gs;
+  const int grp0 = gb * GB + gl * V;              // first group of the lane
 
   const int n0 = a.n[0], n1 = a.n[1];
   const int x0 = tx * (TXB - 2) - 1;                          // zone of column 0
@@ -272,18 +307,16 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
 
   // fixed in-plane source of this column (columns beyond the second ghost layer load the
   // last ghost's values, which are never used)
-  const ColSrc csrc = col_src<DIM>(a, min(gx, n0 + 1), (DIM == 3) ? min(gy, n1 + 1) : 0, grp);
+  const ColSrc csrc = col_src<DIM>(a, min(gx, n0 + 1), (DIM == 3) ? min(gy, n1 + 1) : 0, grp0);
 
   // ---- halo items: the values of the unit's halo zone-groups (x halo columns -1 and TXB of
-  // every row; 3-D also y halo rows -1 and TYB of every column), one value (E or F_c) per
-  // item, spread over the unit's threads so that each plane's halo costs at most NITEM loads
-  // per thread (the halo's opacities are never needed: only the faces between work columns
-  // are computed) ----
-  constexpr int NV = NC;
+  // every row; 3-D also y halo rows -1 and TYB of every column), one value (E or F_c) of V
+  // groups per item, spread over the unit's threads so that each plane's halo costs at most
+  // NITEM loads per thread (the halo's opacities are never needed: only the faces between
+  // work columns are computed) ----
   constexpr int NITEM = ROW ? 1 : 3;
-  const int nsx = 2 * TYB * GB;
-  const int nitems = (nsx + ((DIM == 3) ? 2 * TXB * GB : 0)) * NV;
-  const int nunit = ROW ? 64 : (int)blockDim.x;
+  const int nsx = 2 * TYB * LPC;
+  const int nitems = (nsx + ((DIM == 3) ? 2 * TXB * LPC : 0)) * NC;
   const S* hbase[NITEM];
   int hcb[NITEM], hinfo[NITEM], hlds[NITEM];   // hinfo: v | lm << 3 | inflow << 6 | axis << 7
   for (int k = 0; k < NITEM; ++k) {
@@ -292,10 +325,11 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
     hcb[k] = csrc.cb;
     hinfo[k] = 0;
     hlds[k] = -1;
-    R hvin = R(0);
+    R hvin[V];
+    for (int u = 0; u < V; ++u) hvin[u] = R(0);
     if (it < nitems) {
-      const int sl = it / NV, v = it % NV;
-      const int g = sl % GB, r = sl / GB;
+      const int sl = it / NC, v = it % NC;
+      const int g = sl % LPC, r = sl / LPC;
       int hxz, hyz, pcol, prow;
       if (sl < nsx) {
         const int side = r & 1, row = r >> 1;
@@ -304,7 +338,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         hxz = side ? x0 + TXB : x0 - 1;
         hyz = (DIM == 3) ? y0 + row : 0;
       } else {
-        const int r2i = (sl - nsx) / GB;
+        const int r2i = (sl - nsx) / LPC;
         const int side = r2i & 1, cl = r2i >> 1;
         pcol = cl + 1;
         prow = side ? TYB + 1 : 0;
@@ -312,40 +346,46 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         hyz = side ? y0 + TYB : y0 - 1;
       }
       const bool on = hxz <= n0 + 1 && (DIM < 3 || hyz <= n1 + 1);
-      const int hg = gb * GB + g;
+      const int hg = gb * GB + g * V;
       const ColSrc cs = col_src<DIM>(a, min(hxz, n0 + 1), (DIM == 3) ? min(hyz, n1 + 1) : 0, hg);
       hbase[k] = (v == 0) ? a.E : a.F[v - 1];
       hcb[k] = cs.cb;
       hinfo[k] = v | (cs.lm << 3) | (cs.infl ? 64 : 0) | (cs.ax ? 128 : 0);
-      if (on) hlds[k] = (int)((((size_t)v * PROWS + prow) * PCOLS + pcol) * GB + g);
+      if (on) hlds[k] = ((v * PROWS + prow) * PCOLS + pcol) * GB + g * V;
       if (on && cs.infl) {
-        R qi[4];
-        inflow_state<R, SPH, DIM>(a, geo, min(hxz, n0 + 1) + NG, (DIM == 3) ? min(hyz, n1 + 1) + NG : NG, hg,
-                                  qi);
-        hvin = qi[v];
+        for (int u = 0; u < V; ++u) {
+          R qi[4];
+          inflow_state<R, SPH, DIM>(a, geo, min(hxz, n0 + 1) + NG, (DIM == 3) ? min(hyz, n1 + 1) + NG : NG,
+                                    hg + u, qi);
+          hvin[u] = qi[v];
+        }
       }
     }
-    QI[(NC + k) * qis + t] = hvin;
+    for (int u = 0; u < V; ++u) QI[qii(NC + k) + u] = hvin[u];
   }
   // Values in flight.  Every load of plane data targets one of the "pending" registers below
   // and is consumed, by arithmetic, at the start of the next plane, so that one plane of work
   // hides its latency (a register copy of a load still in flight would wait for it).
-  R Pr[4], Pk = R(0), Ps = R(0), PB = R(0);   // own: raw q, kappa, sigma, B
-  R Ph[NITEM];                                 // halo items
-  int Ppm = 0;                                 // plane mask of the pending raw values
-  {
+  R Pr[V][4], Pk[V], Ps[V], PB[V];   // own: raw q, kappa, sigma, B
+  R Ph[NITEM][V];                    // halo items
+  int Ppm = 0;                       // plane mask of the pending raw values
+  for (int u = 0; u < V; ++u) {
     R qin[4] = {R(0), R(0), R(0), R(0)};
-    if (csrc.infl) inflow_state<R, SPH, DIM>(a, geo, ex, eyc, grp, qin);
-    for (int c = 0; c < NC; ++c) QI[c * qis + t] = qin[c];
+    if (csrc.infl) inflow_state<R, SPH, DIM>(a, geo, ex, eyc, grp0 + u, qin);
+    for (int cc = 0; cc < NC; ++cc) QI[qii(cc) + u] = qin[cc];
+    for (int k = 0; k < 4; ++k) Pr[u][k] = R(0);
+    Pk[u] = Ps[u] = PB[u] = R(0);
+    for (int k = 0; k < NITEM; ++k) Ph[k][u] = R(0);
   }
-  const R* qinp = QI + t;
-  for (int k = 0; k < 4; ++k) Pr[k] = R(0);
-  for (int k = 0; k < NITEM; ++k) Ph[k] = R(0);
+  // the sign and inflow rules for the V groups of this column
+  auto fix_all = [&](R (*raw)[4], int pm, R (*q)[4]) {
+    for (int u = 0; u < V; ++u) fix_zone<R, DIM>(raw[u], csrc, pm, QI + qii(0) + u, nunit * V, q[u]);
+  };
   auto load_halo = [&](int m) {
     for (int k = 0; k < NITEM; ++k) {
       int pmk;
       const int off = plane_offset<DIM>(a, m, (hinfo[k] & 128) != 0, pmk);
-      Ph[k] = R(hbase[k][hcb[k] + off]);
+      ldv<S, R, V>(hbase[k], hcb[k] + off, Ph[k]);
     }
   };
   // halo values of plane m (loaded one plane ago) to LDS, with the sign and inflow rules
@@ -356,24 +396,26 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
       if (hlds[k] >= 0) {
         const int v = hinfo[k] & 7;
         const int mask = (hinfo[k] >> 3 & 7) ^ pm;
-        R val = Ph[k];
-        if (v >= 1 && v <= DIM && ((mask >> (v - 1)) & 1)) val = -val;
-        if (hinfo[k] & 64) val = QI[(NC + k) * qis + t];
-        PV[hlds[k]] = val;
+        for (int u = 0; u < V; ++u) {
+          R val = Ph[k][u];
+          if (v >= 1 && v <= DIM && ((mask >> (v - 1)) & 1)) val = -val;
+          if (hinfo[k] & 64) val = QI[qii(NC + k) + u];
+          PV[hlds[k] + u] = val;
+        }
       }
     }
   };
-  // raw values of this column's zone in plane m; returns the plane mask
-  auto load_own = [&](int m, R* q, R* k, R* sg) -> int { return load_raw<S, R, DIM>(a, csrc, m, q, k, sg); };
+  // raw values of this column's zones in plane m; returns the plane mask
+  auto load_own = [&](int m, R (*q)[4], R* k, R* sg) -> int { return load_raw<S, R, DIM, V>(a, csrc, m, q, k, sg); };
   // extended y index of the zone row in plane m (spherical tables; theta is y)
   auto ey_of = [&](int m) -> int { return (DIM == 2) ? m + NG : eyc; };
-  const int zgB = grp;   // B offset added to the zone index below
-  auto loadB = [&](int m) -> R {
-    // B of this column's zone in plane m (only updated columns use it; the index is clamped
-    // into the domain so that every lane may load)
-    const int zi = min(max(gx, 0), n0 - 1);
-    const int zj = (DIM == 2) ? m : min(max(gy, 0), n1 - 1), zk = (DIM == 3) ? m : 0;
-    return R(a.B[((zk * n1 + zj) * n0 + zi) * a.G + zgB]);
+  // B of this column's zones in plane m (only updated columns use it; the index is clamped
+  // into the domain so that every lane may load)
+  const int zib = min(max(gx, 0), n0 - 1);
+  const int zjb = (DIM == 3) ? min(max(gy, 0), n1 - 1) : 0;
+  auto loadB = [&](int m, R out[V]) {
+    const int zj = (DIM == 2) ? m : zjb, zk = (DIM == 3) ? m : 0;
+    ldv<S, R, V>(a.B, ((zk * n1 + zj) * n0 + zib) * a.G + grp0, out);
   };
   // zone volume factors for the energy diagnostic: the column's (fixed) and the plane's
   // (Cartesian zones all have the same volume; spherical: the plane's factor is fetched one
@@ -395,28 +437,32 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
   // applied; of planes m and m+1 the total opacity ks = kappa + sigma and, in double,
   // c dt kappa and c dt (kappa + sigma) ----
   const double cdt = a.c * a.dt;
-  R q0[4], q1[4];
-  R hiM[4], fPrev[4];
-  for (int k = 0; k < 4; ++k) q0[k] = q1[k] = hiM[k] = fPrev[k] = R(0);
-  R ks0 = R(0), ks1 = R(0);
-  double ck0 = 0.0, cks0 = 0.0, ck1 = 0.0, cks1 = 0.0;
+  R q0[V][4], q1[V][4];
+  R hiM[V][4], fPrev[V][4];
+  R ks0[V], ks1[V];
+  double ck0[V], cks0[V], ck1[V], cks1[V];
+  for (int u = 0; u < V; ++u) {
+    for (int k = 0; k < 4; ++k) q0[u][k] = q1[u][k] = hiM[u][k] = fPrev[u][k] = R(0);
+    ks0[u] = ks1[u] = R(0);
+    ck0[u] = cks0[u] = ck1[u] = cks1[u] = 0.0;
+  }
   {
-    R raw[4], k0, s0;
+    R raw[V][4], k0[V], s0[V];
     if constexpr (DIM >= 2) {
-      R qa[4], qb[4], ka, sa;
+      R qa[V][4], qb[V][4], ka[V], sa[V];
       int pm = load_own(mbeg - 2, raw, nullptr, nullptr);
-      fix_zone<R, DIM>(raw, csrc, pm, qinp, qis, qa);
-      pm = load_own(mbeg - 1, raw, &ka, &sa);
-      fix_zone<R, DIM>(raw, csrc, pm, qinp, qis, qb);
-      pm = load_own(mbeg, raw, &k0, &s0);
-      fix_zone<R, DIM>(raw, csrc, pm, qinp, qis, q0);
+      fix_all(raw, pm, qa);
+      pm = load_own(mbeg - 1, raw, ka, sa);
+      fix_all(raw, pm, qb);
+      pm = load_own(mbeg, raw, k0, s0);
+      fix_all(raw, pm, q0);
       pm = load_own(mbeg + 1, raw, nullptr, nullptr);
-      fix_zone<R, DIM>(raw, csrc, pm, qinp, qis, q1);
-      ks0 = k0 + s0;
+      fix_all(raw, pm, q1);
+      for (int u = 0; u < V; ++u) ks0[u] = k0[u] + s0[u];
       // in flight into the first plane: raw q(mbeg + 2), kappa/sigma(mbeg + 1), B(mbeg)
       Ppm = load_own(mbeg + 2, Pr, nullptr, nullptr);
-      load_own(mbeg + 1, nullptr, &Pk, &Ps);
-      PB = loadB(mbeg);
+      load_own(mbeg + 1, nullptr, Pk, Ps);
+      loadB(mbeg, PB);
       Pvol = plane_vol(mbeg);
       // face mbeg - 1/2 from zones mbeg - 1 (upper state) and mbeg (lower state)
       const int ef = mbeg + NG;   // lower face of zone mbeg
@@ -428,23 +474,25 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
       const bool o0 = !SPH || geo.wf[MD][ef - 1] != R(0);
       const bool o1 = !SPH || geo.wf[MD][ef] != R(0);
       const bool o2 = !SPH || geo.wf[MD][ef + 1] != R(0);
-      R lo[4], hiP[4];
-      reconstruct<R, SPH, DIM>(a, geo, MD, ef - 1, qa, qb, q0, h0, h1, o0, o1, lo, hiP);
-      reconstruct<R, SPH, DIM>(a, geo, MD, ef, qb, q0, q1, h1, h2, o1, o2, lo, hiM);
-      if (o1) {
-        const R dlL = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef - 1);
-        const R dlR = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef);
-        hll<R, SPH, DIM>(a, MD, hiP, lo, h1, epsilon_of(ka + sa, ks0, dlL, dlR), fPrev);
+      const R dlL = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef - 1);
+      const R dlR = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef);
+      for (int u = 0; u < V; ++u) {
+        R lo[4], hiP[4];
+        reconstruct<R, SPH, DIM>(a, geo, MD, ef - 1, qa[u], qb[u], q0[u], h0, h1, o0, o1, lo, hiP);
+        reconstruct<R, SPH, DIM>(a, geo, MD, ef, qb[u], q0[u], q1[u], h1, h2, o1, o2, lo, hiM[u]);
+        if (o1) hll<R, SPH, DIM>(a, MD, hiP, lo, h1, epsilon_of(ka[u] + sa[u], ks0[u], dlL, dlR), fPrev[u]);
       }
     } else {
-      const int pm = load_own(0, raw, &k0, &s0);
-      fix_zone<R, DIM>(raw, csrc, pm, qinp, qis, q0);
-      ks0 = k0 + s0;
-      PB = loadB(0);
+      const int pm = load_own(0, raw, k0, s0);
+      fix_all(raw, pm, q0);
+      for (int u = 0; u < V; ++u) ks0[u] = k0[u] + s0[u];
+      loadB(0, PB);
       Pvol = plane_vol(0);
     }
-    ck0 = cdt * (double)k0;
-    cks0 = cdt * ((double)k0 + (double)s0);
+    for (int u = 0; u < V; ++u) {
+      ck0[u] = cdt * (double)k0[u];
+      cks0[u] = cdt * ((double)k0[u] + (double)s0[u]);
+    }
   }
   load_halo(mbeg);
 
@@ -453,63 +501,76 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
   int dz_zone = -1;
   for (int m = mbeg; m < mend; ++m) {
     // ---- consume the values loaded one plane ago ----
-    R q2[4];
-    fix_zone<R, DIM>(Pr, csrc, Ppm, qinp, qis, q2);   // plane m + 2
-    ks1 = Pk + Ps;                              // plane m + 1
-    ck1 = cdt * (double)Pk;
-    cks1 = cdt * ((double)Pk + (double)Ps);
-    const double jB = ck0 * (double)PB;         // c dt kappa B of plane m
-    const double Vm = Vcol * Pvol;              // zone volume (diagnostics)
+    R q2[V][4];
+    fix_all(Pr, Ppm, q2);   // plane m + 2
+    double jB[V];
+    for (int u = 0; u < V; ++u) {
+      ks1[u] = Pk[u] + Ps[u];   // plane m + 1
+      ck1[u] = cdt * (double)Pk[u];
+      cks1[u] = cdt * ((double)Pk[u] + (double)Ps[u]);
+      jB[u] = ck0[u] * (double)PB[u];   // c dt kappa B of plane m
+    }
+    const double Vm = Vcol * Pvol;   // zone volume (diagnostics)
     stage_halo(m);
-    // ---- (a) stage plane m: own zone ----
-    for (int v = 0; v < NC; ++v) pv(v, prow_own, cx + 1, gs) = q0[v];
-    pv(NC, prow_own, cx + 1, gs) = ks0;
+    // ---- (a) stage plane m: own zones ----
+    for (int u = 0; u < V; ++u) {
+      for (int v = 0; v < NC; ++v) PV[pvi(v, prow_own, cx + 1) + u] = q0[u][v];
+      PV[pvi(NC, prow_own, cx + 1) + u] = ks0[u];
+    }
     // ---- prefetch for the next plane: raw q(m+3), kappa/sigma(m+2), B(m+1), halo m+1.
     // Issued on every plane (indices clamped into the ghost range; the last plane's are
     // not used) so that the loads never sit in a branch ----
     if constexpr (DIM >= 2) {
       Ppm = load_own(min(m + 3, nM + 1), Pr, nullptr, nullptr);
-      load_own(min(m + 2, nM + 1), nullptr, &Pk, &Ps);
-      PB = loadB(min(m + 1, nM - 1));
+      load_own(min(m + 2, nM + 1), nullptr, Pk, Ps);
+      loadB(min(m + 1, nM - 1), PB);
       Pvol = plane_vol(m + 1);
       load_halo(m + 1);
     }
     unit_sync<ROW>();
-    // ---- (b) deferred dE_matter of the previous plane (3-D: all groups in the block) ----
-    if (!ROW && a.dEm && dz_zone >= 0 && gs == 0) {
+    // ---- (b) deferred dE_matter of the previous plane (block units: all groups in the block) ----
+    if (!ROW && a.dEm && dz_zone >= 0 && gl == 0) {
       double sdz = 0.0;
       for (int g2 = 0; g2 < GB; ++g2) sdz += DZ[(size_t)col * GB + g2];
       a.dEm[dz_zone] = -sdz;
     }
     // ---- (c) in-plane reconstruction (lower states to LDS), march face m + 1/2 ----
     const int eym = ey_of(m);
-    R hiX[4] = {R(0), R(0), R(0), R(0)}, hiY[4] = {R(0), R(0), R(0), R(0)};
+    R hiX[V][4], hiY[V][4];
+    for (int u = 0; u < V; ++u)
+      for (int k = 0; k < 4; ++k) hiX[u][k] = hiY[u][k] = R(0);
     if (recon) {
-      R qm[4], qp[4], lo[4];
-      for (int v = 0; v < 4; ++v) {
-        qm[v] = (v < NC) ? pv(v, prow_own, cx, gs) : R(0);
-        qp[v] = (v < NC) ? pv(v, prow_own, cx + 2, gs) : R(0);
-      }
       R hlo[3], hhi[3];
       face_h<R, SPH>(geo, 0, ex, eym, ex, hlo);
       face_h<R, SPH>(geo, 0, ex, eym, ex + 1, hhi);
       const bool olo = !SPH || geo.wf[0][ex] != R(0), ohi = !SPH || geo.wf[0][ex + 1] != R(0);
-      reconstruct<R, SPH, DIM>(a, geo, 0, ex, qm, q0, qp, hlo, hhi, olo, ohi, lo, hiX);
-      for (int v = 0; v < NC; ++v) LX[cidx(v, col)] = lo[v];
-      if constexpr (DIM == 3) {
+      for (int u = 0; u < V; ++u) {
+        R qm[4], qp[4], lo[4];
         for (int v = 0; v < 4; ++v) {
-          qm[v] = (v < NC) ? pv(v, prow_own - 1, cx + 1, gs) : R(0);
-          qp[v] = (v < NC) ? pv(v, prow_own + 1, cx + 1, gs) : R(0);
+          qm[v] = (v < NC) ? PV[pvi(v, prow_own, cx) + u] : R(0);
+          qp[v] = (v < NC) ? PV[pvi(v, prow_own, cx + 2) + u] : R(0);
         }
+        reconstruct<R, SPH, DIM>(a, geo, 0, ex, qm, q0[u], qp, hlo, hhi, olo, ohi, lo, hiX[u]);
+        for (int v = 0; v < NC; ++v) LX[cidx(v, col) + u] = lo[v];
+      }
+      if constexpr (DIM == 3) {
         face_h<R, SPH>(geo, 1, ex, eyc, eyc, hlo);
         face_h<R, SPH>(geo, 1, ex, eyc, eyc + 1, hhi);
         const bool ylo = !SPH || geo.wf[1][eyc] != R(0), yhi = !SPH || geo.wf[1][eyc + 1] != R(0);
-        reconstruct<R, SPH, DIM>(a, geo, 1, eyc, qm, q0, qp, hlo, hhi, ylo, yhi, lo, hiY);
-        for (int v = 0; v < NC; ++v) LY[cidx(v, col)] = lo[v];
+        for (int u = 0; u < V; ++u) {
+          R qm[4], qp[4], lo[4];
+          for (int v = 0; v < 4; ++v) {
+            qm[v] = (v < NC) ? PV[pvi(v, prow_own - 1, cx + 1) + u] : R(0);
+            qp[v] = (v < NC) ? PV[pvi(v, prow_own + 1, cx + 1) + u] : R(0);
+          }
+          reconstruct<R, SPH, DIM>(a, geo, 1, eyc, qm, q0[u], qp, hlo, hhi, ylo, yhi, lo, hiY[u]);
+          for (int v = 0; v < NC; ++v) LY[cidx(v, col) + u] = lo[v];
+        }
       }
     }
-    R fNext[4] = {R(0), R(0), R(0), R(0)};
-    R nHi[4] = {R(0), R(0), R(0), R(0)};
+    R fNext[V][4], nHi[V][4];
+    for (int u = 0; u < V; ++u)
+      for (int k = 0; k < 4; ++k) fNext[u][k] = nHi[u][k] = R(0);
     if constexpr (DIM >= 2) {
       if (upd) {
         // reconstruct zone m + 1 along the march direction; flux at m + 1/2
@@ -519,117 +580,123 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         face_h<R, SPH>(geo, MD, ex, eyf, ef, h1);
         face_h<R, SPH>(geo, MD, ex, eyf, ef + 1, h2);
         const bool o1 = !SPH || geo.wf[MD][ef] != R(0), o2 = !SPH || geo.wf[MD][ef + 1] != R(0);
-        R nLo[4];
-        reconstruct<R, SPH, DIM>(a, geo, MD, ef, q0, q1, q2, h1, h2, o1, o2, nLo, nHi);
-        if (o1) {
-          const R dlL = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef - 1);
-          const R dlR = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef);
-          hll<R, SPH, DIM>(a, MD, hiM, nLo, h1, epsilon_of(ks0, ks1, dlL, dlR), fNext);
+        const R dlL = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef - 1);
+        const R dlR = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef);
+        for (int u = 0; u < V; ++u) {
+          R nLo[4];
+          reconstruct<R, SPH, DIM>(a, geo, MD, ef, q0[u], q1[u], q2[u], h1, h2, o1, o2, nLo, nHi[u]);
+          if (o1) hll<R, SPH, DIM>(a, MD, hiM[u], nLo, h1, epsilon_of(ks0[u], ks1[u], dlL, dlR), fNext[u]);
         }
       }
     }
     unit_sync<ROW>();
     // ---- (d) in-plane faces above this column ----
-    R fxR[4] = {R(0), R(0), R(0), R(0)}, fyR[4] = {R(0), R(0), R(0), R(0)};
+    R fxR[V][4], fyR[V][4];
+    for (int u = 0; u < V; ++u)
+      for (int k = 0; k < 4; ++k) fxR[u][k] = fyR[u][k] = R(0);
     if (do_xf) {
-      R qR[4] = {R(0), R(0), R(0), R(0)};
-      for (int v = 0; v < NC; ++v) qR[v] = LX[cidx(v, col + 1)];
-      const R ksR = pv(NC, prow_own, cx + 2, gs);
       const bool open = !SPH || geo.wf[0][ex + 1] != R(0);
-      if (open) {
-        R hf[3];
-        face_h<R, SPH>(geo, 0, ex, eym, ex + 1, hf);
-        const R dlL = proper_width<R, SPH>(geo, 0, ex, eym);
-        const R dlR = proper_width<R, SPH>(geo, 0, ex + 1, eym);
-        hll<R, SPH, DIM>(a, 0, hiX, qR, hf, epsilon_of(ks0, ksR, dlL, dlR), fxR);
+      R hf[3];
+      face_h<R, SPH>(geo, 0, ex, eym, ex + 1, hf);
+      const R dlL = proper_width<R, SPH>(geo, 0, ex, eym);
+      const R dlR = proper_width<R, SPH>(geo, 0, ex + 1, eym);
+      for (int u = 0; u < V; ++u) {
+        R qR[4] = {R(0), R(0), R(0), R(0)};
+        for (int v = 0; v < NC; ++v) qR[v] = LX[cidx(v, col + 1) + u];
+        const R ksR = PV[pvi(NC, prow_own, cx + 2) + u];
+        if (open) hll<R, SPH, DIM>(a, 0, hiX[u], qR, hf, epsilon_of(ks0[u], ksR, dlL, dlR), fxR[u]);
+        for (int v = 0; v < NC; ++v) FX[cidx(v, col) + u] = fxR[u][v];
       }
-      for (int v = 0; v < NC; ++v) FX[cidx(v, col)] = fxR[v];
     }
     if constexpr (DIM == 3) {
       if (do_yf) {
-        R qR[4] = {R(0), R(0), R(0), R(0)};
-        for (int v = 0; v < NC; ++v) qR[v] = LY[cidx(v, col + TXB)];
-        const R ksR = pv(NC, prow_own + 1, cx + 1, gs);
         const bool open = !SPH || geo.wf[1][eyc + 1] != R(0);
-        if (open) {
-          R hf[3];
-          face_h<R, SPH>(geo, 1, ex, eyc, eyc + 1, hf);
-          const R dlL = proper_width<R, SPH>(geo, 1, ex, eyc);
-          const R dlR = proper_width<R, SPH>(geo, 1, ex, eyc + 1);
-          hll<R, SPH, DIM>(a, 1, hiY, qR, hf, epsilon_of(ks0, ksR, dlL, dlR), fyR);
+        R hf[3];
+        face_h<R, SPH>(geo, 1, ex, eyc, eyc + 1, hf);
+        const R dlL = proper_width<R, SPH>(geo, 1, ex, eyc);
+        const R dlR = proper_width<R, SPH>(geo, 1, ex, eyc + 1);
+        for (int u = 0; u < V; ++u) {
+          R qR[4] = {R(0), R(0), R(0), R(0)};
+          for (int v = 0; v < NC; ++v) qR[v] = LY[cidx(v, col + TXB) + u];
+          const R ksR = PV[pvi(NC, prow_own + 1, cx + 1) + u];
+          if (open) hll<R, SPH, DIM>(a, 1, hiY[u], qR, hf, epsilon_of(ks0[u], ksR, dlL, dlR), fyR[u]);
+          for (int v = 0; v < NC; ++v) FY[cidx(v, col) + u] = fyR[u][v];
         }
-        for (int v = 0; v < NC; ++v) FY[cidx(v, col)] = fyR[v];
       }
     }
     unit_sync<ROW>();
     // ---- (e) update ----
     dz_zone = -1;
     if (upd) {
-      R acc[4] = {R(0), R(0), R(0), R(0)};
-      {
-        R wlo = R(1), whi = R(1), iW = idx0;
-        if constexpr (SPH) {
-          wlo = geo.wf[0][ex];
-          whi = geo.wf[0][ex + 1];
-          iW = geo.iW[0][ex];
-        }
-        for (int v = 0; v < NC; ++v) acc[v] += (whi * fxR[v] - wlo * FX[cidx(v, col - 1)]) * iW;
-      }
-      if constexpr (DIM == 3) {
-        R wlo = R(1), whi = R(1), iW = idx1;
-        if constexpr (SPH) {
-          wlo = geo.wf[1][eyc];
-          whi = geo.wf[1][eyc + 1];
-          iW = geo.iW[1][eyc];
-        }
-        for (int v = 0; v < NC; ++v) acc[v] += (whi * fyR[v] - wlo * FY[cidx(v, col - TXB)]) * iW;
-      }
-      if constexpr (DIM >= 2) {
-        const int e = m + NG;
-        R wlo = R(1), whi = R(1), iW = idxM;
-        if constexpr (SPH) {
-          wlo = geo.wf[MD][e];
-          whi = geo.wf[MD][e + 1];
-          iW = geo.iW[MD][e];
-        }
-        for (int v = 0; v < NC; ++v) acc[v] += (whi * fNext[v] - wlo * fPrev[v]) * iW;
-      }
-      R Um[4];
-      for (int cc = 0; cc < 4; ++cc) Um[cc] = (cc < NC) ? q0[cc] - dtR * acc[cc] : R(0);
-      const int zi = gx, zj = (DIM == 2) ? m : gy, zk = (DIM == 3) ? m : 0;
+      R wxl = R(1), wxh = R(1), iWx = idx0;
       if constexpr (SPH) {
-        R h[3], P[9], Sg[3];
-        cell_h<R, SPH>(geo, ex, zj + NG, h);
-        closure_full<R, SPH, DIM>(q0, h, c, a.closure, P);
-        geometric_source<R>(P, h, geo.gam + 4 * zj, c, Sg);
-        for (int cc = 0; cc < DIM; ++cc) Um[1 + cc] += dtR * Sg[cc];
+        wxl = geo.wf[0][ex];
+        wxh = geo.wf[0][ex + 1];
+        iWx = geo.iW[0][ex];
       }
+      R wyl = R(1), wyh = R(1), iWy = idx1;
+      if constexpr (SPH && DIM == 3) {
+        wyl = geo.wf[1][eyc];
+        wyh = geo.wf[1][eyc + 1];
+        iWy = geo.iW[1][eyc];
+      }
+      R wml = R(1), wmh = R(1), iWm = idxM;
+      if constexpr (SPH && DIM >= 2) {
+        wml = geo.wf[MD][m + NG];
+        wmh = geo.wf[MD][m + NG + 1];
+        iWm = geo.iW[MD][m + NG];
+      }
+      const int zi = gx, zj = (DIM == 2) ? m : gy, zk = (DIM == 3) ? m : 0;
       const int zone = (zk * n1 + zj) * n0 + zi;
-      const double V = Vm;
-      const double dz = finish_zone_c<S, R, SPH, DIM>(a, geo, zone * a.G + grp, zi, zj, zk, Um, ck0, cks0, jB,
-                                                      want_diag, V, zd);
-      if (!ROW && a.dEm) {
-        DZ[(size_t)col * GB + gs] = dz;
-        dz_zone = zone;
+      S Eo[V], Fo[3][V];
+      double dzs = 0.0;
+      for (int u = 0; u < V; ++u) {
+        R acc[4] = {R(0), R(0), R(0), R(0)};
+        for (int v = 0; v < NC; ++v) acc[v] += (wxh * fxR[u][v] - wxl * FX[cidx(v, col - 1) + u]) * iWx;
+        if constexpr (DIM == 3)
+          for (int v = 0; v < NC; ++v) acc[v] += (wyh * fyR[u][v] - wyl * FY[cidx(v, col - TXB) + u]) * iWy;
+        if constexpr (DIM >= 2)
+          for (int v = 0; v < NC; ++v) acc[v] += (wmh * fNext[u][v] - wml * fPrev[u][v]) * iWm;
+        R Um[4];
+        for (int cc = 0; cc < 4; ++cc) Um[cc] = (cc < NC) ? q0[u][cc] - dtR * acc[cc] : R(0);
+        if constexpr (SPH) {
+          R h[3], P[9], Sg[3];
+          cell_h<R, SPH>(geo, ex, zj + NG, h);
+          closure_full<R, SPH, DIM>(q0[u], h, c, a.closure, P);
+          geometric_source<R>(P, h, geo.gam + 4 * zj, c, Sg);
+          for (int cc = 0; cc < DIM; ++cc) Um[1 + cc] += dtR * Sg[cc];
+        }
+        S F1[3];
+        const double dz = source_zone<S, R, SPH, DIM>(a, geo, zi, zj, Um, ck0[u], cks0[u], jB[u], want_diag, Vm, zd,
+                                                      Eo[u], F1);
+        for (int cc = 0; cc < DIM; ++cc) Fo[cc][u] = F1[cc];
+        dzs += dz;
+        if (!ROW && a.dEm) DZ[(size_t)col * GB + gl * V + u] = dz;
       }
+      const int zg = zone * a.G + grp0;
+      stv<S, V>(a.Eo, zg, Eo);
+      for (int cc = 0; cc < DIM; ++cc) stv<S, V>(a.Fo[cc], zg, Fo[cc]);
+      if (!ROW && a.dEm) dz_zone = zone;
       if (ROW && a.dEm) {
-        // sum over the GB groups of this column (consecutive lanes), one partial per wave
-        double p = dz;
-        for (int off = 1; off < GB; off <<= 1) p += __shfl_xor(p, off);
-        if (gs == 0) DZ[((size_t)(m - mbeg) * tl.NW + wv) * TXB + cx] = p;
+        // sum over the groups of this column (consecutive lanes), one partial per wave
+        double p = dzs;
+        for (int off = 1; off < LPC; off <<= 1) p += __shfl_xor(p, off);
+        if (gl == 0) DZ[((size_t)(m - mbeg) * tl.NW + wv) * TXB + cx] = p;
       }
     }
     // ---- advance the window ----
     if constexpr (DIM >= 2) {
-      for (int cc = 0; cc < 4; ++cc) {
-        q0[cc] = q1[cc];
-        q1[cc] = q2[cc];
-        hiM[cc] = nHi[cc];
-        fPrev[cc] = fNext[cc];
+      for (int u = 0; u < V; ++u) {
+        for (int cc = 0; cc < 4; ++cc) {
+          q0[u][cc] = q1[u][cc];
+          q1[u][cc] = q2[u][cc];
+          hiM[u][cc] = nHi[u][cc];
+          fPrev[u][cc] = fNext[u][cc];
+        }
+        ks0[u] = ks1[u];
+        ck0[u] = ck1[u];
+        cks0[u] = cks1[u];
       }
-      ks0 = ks1;
-      ck0 = ck1;
-      cks0 = cks1;
     }
   }
   if (a.dEm) {
@@ -647,21 +714,21 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         }
       }
     } else {
-      if (dz_zone >= 0 && gs == 0) {
-        double s = 0.0;
-        for (int g2 = 0; g2 < GB; ++g2) s += DZ[(size_t)col * GB + g2];
-        a.dEm[dz_zone] = -s;
+      if (dz_zone >= 0 && gl == 0) {
+        double s2 = 0.0;
+        for (int g2 = 0; g2 < GB; ++g2) s2 += DZ[(size_t)col * GB + g2];
+        a.dEm[dz_zone] = -s2;
       }
     }
   }
   if (!want_diag) return;
   // ---- block partials of the diagnostics: wave reduction, then across waves ----
   double e = zd.energy, mf = zd.maxf2;
-  int u = zd.nun, p = zd.nnp;
+  int un = zd.nun, p = zd.nnp;
   for (int off = 32; off > 0; off >>= 1) {
     e += __shfl_xor(e, off);
     mf = fmax(mf, __shfl_xor(mf, off));
-    u += __shfl_xor(u, off);
+    un += __shfl_xor(un, off);
     p += __shfl_xor(p, off);
   }
   __shared__ double we[16], wm[16];
@@ -671,11 +738,11 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
   if (lane == 0) {
     we[wave] = e;
     wm[wave] = mf;
-    wu[wave] = u;
+    wu[wave] = un;
     wp[wave] = p;
   }
   __syncthreads();
-  if (t == 0) {
+  if (threadIdx.x == 0) {
     const int nw = (blockDim.x + 63) >> 6;
     double se = 0.0, sm = 0.0;
     int su = 0, sp = 0;
@@ -709,17 +776,23 @@ static size_t lds_bytes(const Tile& tl, int dim, size_t rsize) {
 
 static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB, int NW) {
+Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB, int NW, int V) {
   Tile tl{};
   const size_t rsize = (D.precision == FORNAX_FP64) ? sizeof(double) : sizeof(float);
   // 1-D/2-D with NW >= 1: wave rows; NW = 0 (and always in 3-D): one unit per block
   const bool row = D.ndim < 3 && NW >= 1;
   tl.nblocks = 0;
   if (GB < 1 || TM < 1 || D.ngroups % GB != 0) return tl;
+  // V = 2: pairs of groups per lane (16-byte FP64 / 8-byte FP32 accesses)
+  if (V != 1 && V != 2) return tl;
+  if (V == 2 && (GB % 2 != 0 || D.ngroups % 2 != 0)) return tl;
+  if (D.ndim == 1 && (!row || V != 1)) return tl;
+  if (D.ndim == 2 && !row && V != 1) return tl;
+  const int LPC = GB / V;
   if (row) {
-    // one x-row of 64/GB zone columns per wave, NW waves (group subsets) per block
-    if (!pow2(GB) || GB > 16 || NW > 8 || (D.ngroups / GB) % NW != 0) return tl;
-    TXB = 64 / GB;
+    // one x-row of 64/LPC zone columns per wave, NW waves (group subsets) per block
+    if (!pow2(LPC) || LPC > 16 || NW > 8 || (D.ngroups / GB) % NW != 0) return tl;
+    TXB = 64 / LPC;
     TYB = 1;
   } else {
     NW = 1;
@@ -727,17 +800,18 @@ Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB, int NW
     if (TXB < 4 || (D.ndim == 3 && TYB < 4)) return tl;
   }
   tl.row = row;
+  tl.V = V;
   tl.TXB = TXB;
   tl.TYB = TYB;
   tl.TM = (D.ndim >= 2) ? TM : 1;
   tl.GB = GB;
   tl.NW = NW;
-  tl.nthreads = row ? 64 * NW : TXB * TYB * GB;
+  tl.nthreads = row ? 64 * NW : TXB * TYB * LPC;
   if (tl.nthreads > 512) return tl;
-  // halo items (one value of one halo zone-group each): at most 1 per thread of a wave unit,
-  // 3 per thread of a block unit
+  // halo items (one value of V groups of one halo column each): at most 1 per thread of a
+  // wave unit, 3 per thread of a block unit
   const int nunit = row ? 64 : tl.nthreads;
-  const int nitems = (2 * TYB * GB + (D.ndim == 3 ? 2 * TXB * GB : 0)) * (D.ndim + 1);
+  const int nitems = (2 * TYB * LPC + (D.ndim == 3 ? 2 * TXB * LPC : 0)) * (D.ndim + 1);
   if (nitems > (row ? 1 : 3) * nunit) return tl;
   tl.lds = lds_bytes(tl, D.ndim, rsize);
   if (tl.lds > g_max_lds) return tl;
@@ -753,33 +827,46 @@ Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB, int NW
 }
 
 // Default tile.
-//  * 1-D / 2-D: GB = the largest power of two up to 4 dividing G (16 zone columns per wave,
-//    runs of 4 groups), all G / GB group subsets of a tile in one block when they fit in 8
-//    waves; planes per block halved from 32 until the grid has at least 1024 (FP64) or 2048
-//    (MIXED) blocks, TM >= 4.
-//    With all_groups, GB grows until the block holds every group.
+//  * 1-D / 2-D wave rows: with V = 2 (G even) each lane takes a pair of groups and GB = the
+//    largest power of two up to 8 dividing G, so that a wave row of 16 columns reads runs of
+//    8 groups; with V = 1, GB up to 4.  All G / GB group subsets of a tile share a block when
+//    they fit in 8 waves.  Planes per block are halved from 32 until the grid has at least
+//    1024 (FP64) or 2048 (MIXED) blocks, TM >= 4.  With all_groups, GB grows until the block
+//    holds every group.
 //  * 3-D: a near-square tile of 128-512 threads; with many groups per zone, groups are split
 //    across blocks so that the zone tile stays large enough to amortise its halo, unless all
 //    groups are needed in one block.
-Tile choose_tile(const fornax_m1_desc& D, bool all_groups) {
+Tile choose_tile(const fornax_m1_desc& D, bool all_groups, int V) {
   const int G = D.ngroups;
+  if (V == 2 && G % 2 != 0) return Tile{};
   if (D.ndim < 3) {
-    int GB = 1;
-    while (GB < 4 && G % (2 * GB) == 0) GB *= 2;
+    int GB = V;
+    while (GB < 4 * V && G % (2 * GB) == 0) GB *= 2;
     if (all_groups)
-      while (G / GB > 8 && GB < 16 && G % (2 * GB) == 0) GB *= 2;
+      while (G / GB > 8 && GB < 16 * V && G % (2 * GB) == 0) GB *= 2;
     int NW = std::min(8, G / GB);
     while ((G / GB) % NW != 0) --NW;
     if (all_groups && NW * GB != G) return Tile{};
-    // FP64 waves hold more registers (fewer of them per SIMD): longer marches amortise the
-    // first face of each march better there
     const int want = (D.precision == FORNAX_FP64) ? 1024 : 2048;
     Tile t{};
     for (int TM = 32; TM >= 4; TM /= 2) {
-      t = make_tile(D, 0, 1, TM, GB, NW);
+      t = make_tile(D, 0, 1, TM, GB, NW, V);
       if (t.nblocks >= want || D.ndim == 1) break;
     }
     return t;
+  }
+  // measured on gfx950: FP64 8 x 8 columns of up to 4 groups, 16 planes; FP32 pairs of
+  // groups per lane, 16 x 16 columns of 2 groups, 8 planes
+  if (!all_groups) {
+    Tile t{};
+    if (D.precision == FORNAX_FP64) {
+      int GB = 4;
+      while (G % GB != 0) --GB;
+      t = make_tile(D, 8, 8, 16, GB, 1, 1);
+    } else if (V == 2) {
+      t = make_tile(D, 16, 16, 8, 2, 1, 2);
+    }
+    if (t.nblocks > 0) return t;
   }
   Tile best{};
   double best_cost = 1e30;
@@ -788,7 +875,7 @@ Tile choose_tile(const fornax_m1_desc& D, bool all_groups) {
     if (all_groups && GB != G) break;
     for (int TXB = 4; TXB <= 32; ++TXB)
       for (int TYB = 4; TYB <= 32; ++TYB) {
-        Tile t = make_tile(D, TXB, TYB, 8, GB, 1);
+        Tile t = make_tile(D, TXB, TYB, 8, GB, 1, V);
         if (t.nblocks == 0 || t.nthreads < 128) continue;
         // loaded columns per updated column, and a mild preference for big blocks and
         // for keeping groups together (contiguous runs)
@@ -804,31 +891,36 @@ Tile choose_tile(const fornax_m1_desc& D, bool all_groups) {
   return best;
 }
 
-template <typename S, typename R, int DIM, bool SPH, bool ROW, int GBC = 0>
+template <typename S, typename R, int DIM, bool SPH, bool ROW, int GBC, int V>
 static hipError_t raise_lds_limit(int bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step_tiled<S, R, DIM, SPH, ROW, GBC>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step_tiled<S, R, DIM, SPH, ROW, GBC, V>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-template <typename S, typename R>
-static hipError_t raise_all(int bytes) {
+// Every instantiation that launch_tiled can pick.
+template <typename S, typename R, bool SPH>
+static hipError_t raise_coord(int bytes) {
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) {
     if (r != hipSuccess) e = r;
   };
-  chk(raise_lds_limit<S, R, 1, false, true>(bytes));
-  chk(raise_lds_limit<S, R, 2, false, true>(bytes));
-  chk(raise_lds_limit<S, R, 1, true, true>(bytes));
-  chk(raise_lds_limit<S, R, 2, true, true>(bytes));
-  chk(raise_lds_limit<S, R, 2, false, true, 4>(bytes));
-  chk(raise_lds_limit<S, R, 2, true, true, 4>(bytes));
-  chk(raise_lds_limit<S, R, 1, false, false>(bytes));
-  chk(raise_lds_limit<S, R, 2, false, false>(bytes));
-  chk(raise_lds_limit<S, R, 3, false, false>(bytes));
-  chk(raise_lds_limit<S, R, 1, true, false>(bytes));
-  chk(raise_lds_limit<S, R, 2, true, false>(bytes));
-  chk(raise_lds_limit<S, R, 3, true, false>(bytes));
+  chk(raise_lds_limit<S, R, 1, SPH, true, 0, 1>(bytes));
+  chk(raise_lds_limit<S, R, 2, SPH, true, 0, 1>(bytes));
+  chk(raise_lds_limit<S, R, 2, SPH, true, 4, 1>(bytes));
+  chk(raise_lds_limit<S, R, 2, SPH, true, 8, 2>(bytes));
+  chk(raise_lds_limit<S, R, 2, SPH, true, 16, 2>(bytes));
+  chk(raise_lds_limit<S, R, 2, SPH, true, 0, 2>(bytes));
+  chk(raise_lds_limit<S, R, 2, SPH, false, 0, 1>(bytes));
+  chk(raise_lds_limit<S, R, 3, SPH, false, 0, 1>(bytes));
+  chk(raise_lds_limit<S, R, 3, SPH, false, 0, 2>(bytes));
   return e;
+}
+
+template <typename S, typename R>
+static hipError_t raise_all(int bytes) {
+  const hipError_t e1 = raise_coord<S, R, false>(bytes);
+  const hipError_t e2 = raise_coord<S, R, true>(bytes);
+  return e1 != hipSuccess ? e1 : e2;
 }
 
 int prepare_step_kernels() {
@@ -849,45 +941,50 @@ int prepare_step_kernels() {
   return FORNAX_OK;
 }
 
-template <typename S, typename R>
-int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, const Tile& tl, hipStream_t st) {
-  const bool sph = ctx->desc.coord == FORNAX_SPHERICAL_LOGR;
-  const int D = ctx->desc.ndim;
-  // dE_matter sums over the groups of a zone inside one block
-  if (tl.nblocks <= 0 || (a.dEm && tl.GB * tl.NW != a.G)) return FORNAX_EUNSUPPORTED;
+template <typename S, typename R, bool SPH>
+static int launch_coord(const Geo<R>& geo, const StepArgs<S>& a, const Tile& tl, int D, hipStream_t st) {
   dim3 grid(tl.nblocks), block(tl.nthreads);
-#define FM1_LAUNCH(DIMV, SPHV, ROWV, GBV) \
-  hipLaunchKernelGGL((k_step_tiled<S, R, DIMV, SPHV, ROWV, GBV>), grid, block, tl.lds, st, a, geo, tl)
-  if (sph) {
-    if (D == 1) {
-      if (tl.row) FM1_LAUNCH(1, true, true, 0);
-      else FM1_LAUNCH(1, true, false, 0);
-    } else if (D == 2) {
-      if (tl.row && tl.GB == 4) FM1_LAUNCH(2, true, true, 4);
-      else if (tl.row) FM1_LAUNCH(2, true, true, 0);
-      else FM1_LAUNCH(2, true, false, 0);
-    } else {
-      FM1_LAUNCH(3, true, false, 0);
-    }
+#define FM1_LAUNCH(DIMV, ROWV, GBV, VV) \
+  hipLaunchKernelGGL((k_step_tiled<S, R, DIMV, SPH, ROWV, GBV, VV>), grid, block, tl.lds, st, a, geo, tl)
+  if (D == 1) {
+    if (!tl.row || tl.V != 1) return FORNAX_EUNSUPPORTED;
+    FM1_LAUNCH(1, true, 0, 1);
+  } else if (D == 2) {
+    if (tl.row && tl.V == 1 && tl.GB == 4) FM1_LAUNCH(2, true, 4, 1);
+    else if (tl.row && tl.V == 1) FM1_LAUNCH(2, true, 0, 1);
+    else if (tl.row && tl.V == 2 && tl.GB == 8) FM1_LAUNCH(2, true, 8, 2);
+    else if (tl.row && tl.V == 2 && tl.GB == 16) FM1_LAUNCH(2, true, 16, 2);
+    else if (tl.row && tl.V == 2) FM1_LAUNCH(2, true, 0, 2);
+    else if (!tl.row && tl.V == 1) FM1_LAUNCH(2, false, 0, 1);
+    else return FORNAX_EUNSUPPORTED;
   } else {
-    if (D == 1) {
-      if (tl.row) FM1_LAUNCH(1, false, true, 0);
-      else FM1_LAUNCH(1, false, false, 0);
-    } else if (D == 2) {
-      if (tl.row && tl.GB == 4) FM1_LAUNCH(2, false, true, 4);
-      else if (tl.row) FM1_LAUNCH(2, false, true, 0);
-      else FM1_LAUNCH(2, false, false, 0);
-    } else {
-      FM1_LAUNCH(3, false, false, 0);
-    }
+    if (tl.V == 1) FM1_LAUNCH(3, false, 0, 1);
+    else FM1_LAUNCH(3, false, 0, 2);
   }
 #undef FM1_LAUNCH
   return hipGetLastError() == hipSuccess ? FORNAX_OK : FORNAX_EDEVICE;
 }
 
-template int launch_tiled<double, double>(fornax_m1_ctx*, const Geo<double>&, const StepArgs<double>&, const Tile&,
-                                          hipStream_t);
-template int launch_tiled<float, float>(fornax_m1_ctx*, const Geo<float>&, const StepArgs<float>&, const Tile&,
-                                        hipStream_t);
+static bool aligned_to(const void* p, size_t n) { return p == nullptr || ((uintptr_t)p % n) == 0; }
+
+template <typename S, typename R>
+int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, hipStream_t st) {
+  const bool sph = ctx->desc.coord == FORNAX_SPHERICAL_LOGR;
+  const int D = ctx->desc.ndim;
+  // dE_matter sums over the groups of a zone inside one block; pairs of groups per lane need
+  // arrays aligned to two elements
+  const Tile* tl = a.dEm ? &ctx->tile_full : &ctx->tile;
+  bool al = true;
+  const void* ptrs[] = {a.E, a.F[0], a.F[1], a.F[2], a.Eo, a.Fo[0], a.Fo[1], a.Fo[2], a.kap, a.sig, a.B};
+  for (const void* q : ptrs) al = al && aligned_to(q, 2 * sizeof(S));
+  if (tl->V == 2 && !al) tl = &ctx->tile_v1;
+  if (tl->nblocks <= 0) return FORNAX_EUNSUPPORTED;
+  if (a.dEm && tl->GB * (tl->row ? tl->NW : 1) != a.G) return FORNAX_EUNSUPPORTED;
+  *ctx->last_tile = *tl;
+  return sph ? launch_coord<S, R, true>(geo, a, *tl, D, st) : launch_coord<S, R, false>(geo, a, *tl, D, st);
+}
+
+template int launch_tiled<double, double>(fornax_m1_ctx*, const Geo<double>&, const StepArgs<double>&, hipStream_t);
+template int launch_tiled<float, float>(fornax_m1_ctx*, const Geo<float>&, const StepArgs<float>&, hipStream_t);
 
 }  // namespace fm1

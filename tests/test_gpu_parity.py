@@ -116,16 +116,17 @@ def test_tile_shapes(m1, case):
     changes the work decomposition only: every tiling gives the oracle's result."""
     import os
     if case == "2d":
-        # "TXB,TYB,TM,GB[,NW]": with NW >= 1 a wave holds 64/GB zone columns of GB groups and
-        # a block NW such waves; with NW = 0 a block holds TXB columns of GB groups
+        # "TXB,TYB,TM,GB[,NW[,V]]": with NW >= 1 a wave holds 64 V/GB zone columns of GB
+        # groups (V per lane) and a block NW such waves; with NW = 0 a block holds TXB columns
         w = wl.blobs2d(n=70, G=8, steps=5)
-        tiles = ["0,1,1,1", "0,1,7,2,2", "0,1,16,4", "0,1,5,8,1", "0,1,3,1,4", "16,1,8,8,0", "5,1,3,2,0"]
+        tiles = ["0,1,1,1", "0,1,7,2,2", "0,1,16,4", "0,1,5,8,1", "0,1,3,1,4", "16,1,8,8,0", "5,1,3,2,0",
+                 "0,1,8,8,1,2", "0,1,3,4,2,2", "0,1,6,2,4,2"]
     elif case == "3d":
         w = wl.core3d(n=14, G=6, steps=5)
-        tiles = ["4,4,3,6", "6,5,2,2", "5,7,4,3", "8,6,16,1"]
+        tiles = ["4,4,3,6", "6,5,2,2", "5,7,4,3", "8,6,16,1", "6,6,4,6,1,2", "9,7,3,2,1,2"]
     else:
         w = wl.sphere3d(nr=14, nth=10, nph=8, G=4, steps=5)
-        tiles = ["4,4,3,4", "6,5,2,2", "7,4,5,1"]
+        tiles = ["4,4,3,4", "6,5,2,2", "7,4,5,1", "5,6,4,4,1,2"]
     p = problem_of(w)
     dt = dt_of(w, p)
     E, F, _ = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow)
