@@ -101,7 +101,6 @@ __global__ void __launch_bounds__(512) k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTi
   const int gx = x0 + cx;
   const bool colin = gx >= 0 && gx < n0;            // column inside the domain
   const bool fin = cx < W && gx >= -2 && gx < n0 + 2; // this thread finalises (gx, m)
-  const R c = R(a.c);
   const R dx0 = geo.dx[0];
   const R nux = R(a.dt) * rcp_(dx0);
 

@@ -358,11 +358,9 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
                    !(pe && pe[0] == '0'))
                       ? 2
                       : 1;
-    ctx->tile = choose_tile(*desc, false, V);
-    ctx->tile_full = choose_tile(*desc, true, V);
-    if (ctx->tile.nblocks <= 0) ctx->tile = choose_tile(*desc, false, 1);
-    if (ctx->tile_full.nblocks <= 0) ctx->tile_full = choose_tile(*desc, true, 1);
-    ctx->tile_v1 = choose_tile(*desc, true, 1);
+    ctx->tile = choose_tile(*desc, V);
+    if (ctx->tile.nblocks <= 0) ctx->tile = choose_tile(*desc, 1);
+    ctx->tile_v1 = (ctx->tile.V == 1) ? ctx->tile : choose_tile(*desc, 1);
   }
   if (const char* env = std::getenv("FORNAX_M1_TILE")) {
     // "TXB,TYB,TM,GB[,NW[,V]]" (TXB, TYB ignored for 1-D/2-D wave rows, where TXB = 64 V/GB)
@@ -375,7 +373,7 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
       }
       Tile t = make_tile(*desc, tx, ty, tm, gbk, nw, vv);
       if (t.nblocks > 0) ctx->tile = t;
-      if (t.nblocks > 0 && t.GB * (t.row ? t.NW : 1) == desc->ngroups) ctx->tile_full = t;
+      if (t.nblocks > 0 && t.V == 1) ctx->tile_v1 = t;
     }
   }
   if (ctx->tile.nblocks <= 0) {
@@ -388,10 +386,13 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   int zpb = BLOCK / desc->ngroups;
   int64_t nz = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
   ctx->nblocks_step = (int)((nz + zpb - 1) / zpb);
-  size_t nb = (size_t)std::max(std::max(ctx->nblocks_step, ctx->tile_v1.nblocks),
-                               std::max(ctx->tile.nblocks, ctx->tile_full.nblocks));
+  size_t nb = (size_t)std::max(ctx->nblocks_step, std::max(ctx->tile_v1.nblocks, ctx->tile.nblocks));
+  // dE_matter partials when a tile splits the groups of a zone over several blocks
+  const size_t ngbm = (size_t)std::max(ctx->tile.ngb, ctx->tile_v1.ngb);
+  const size_t dzp_bytes = ngbm > 1 ? ngbm * (size_t)nz * sizeof(double) : 0;
+  const size_t red_bytes = (nb * (2 * sizeof(double) + 2 * sizeof(int)) + 1023) & ~(size_t)255;
   void* red = nullptr;
-  if (hipMalloc(&red, nb * (2 * sizeof(double) + 2 * sizeof(int)) + 1024) != hipSuccess) {
+  if (hipMalloc(&red, red_bytes + dzp_bytes) != hipSuccess) {
     (void)hipFree(ctx->geo_mem);
     delete ctx;
     return FORNAX_ENOMEM;
@@ -400,6 +401,7 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   ctx->p_maxf2 = ctx->p_energy + nb;
   ctx->p_nun = (int*)(ctx->p_maxf2 + nb);
   ctx->p_nnp = ctx->p_nun + nb;
+  ctx->dzp = dzp_bytes ? (double*)((char*)red + red_bytes) : nullptr;
   // adjoint ghost buffers (the adjoint supports 1-D and 2-D Cartesian grids)
   ctx->adj_u1 = nullptr;
   for (int d = 0; d < 3; ++d) {

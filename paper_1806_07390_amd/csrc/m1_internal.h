@@ -100,6 +100,7 @@ struct StepArgs : StepArgsBase {
   const S* sig;
   const S* B;
   double* dEm;               // per zone, nullable
+  double* dzp;               // [group block][zone] partials of dE_matter (tiles with ngb > 1)
   // per-block partial reductions (null: no diagnostics)
   double* p_energy;
   double* p_maxf2;
@@ -136,8 +137,7 @@ struct fornax_m1_ctx {
   size_t geo_bytes;
   double max_dt1;             // max_dt(cfl = 1)
   fm1::Tile tile;              // tiling of the fused step kernel
-  fm1::Tile tile_full;         // same with all groups per block (used when dE_matter is asked for)
-  fm1::Tile tile_v1;           // one group per lane, all groups per block (arrays not aligned to pairs)
+  fm1::Tile tile_v1;           // one group per lane (arrays not aligned to pairs of groups)
   fm1::Tile last_tile[1];      // the tile of the last step launch (for inspection)
   // reduction scratch (one partial per block of the step kernel)
   int nblocks_step;
@@ -145,6 +145,9 @@ struct fornax_m1_ctx {
   double* p_maxf2;
   int* p_nun;
   int* p_nnp;
+  // dE_matter partials of the group blocks of a tile, [ngb][zones] (null when every tile
+  // holds all groups of a zone)
+  double* dzp;
   // adjoint: ghost-zone adjoint buffers per direction, [side][layer][plane][G][1+ndim+1]
   double* adj_gbuf[3];
   int adj_gplane[3];

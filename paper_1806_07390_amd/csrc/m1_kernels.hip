@@ -122,6 +122,17 @@ __global__ void __launch_bounds__(BLOCK) k_source(StepArgs<S> a) {
   }
 }
 
+// dE_matter of every zone from the partial sums of the group blocks of the step tile, in
+// group-block order.
+__global__ void __launch_bounds__(BLOCK) k_dem_sum(const double* __restrict__ part, int nparts, int64_t nz,
+                                                   double* __restrict__ dEm) {
+  const int64_t z = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (z >= nz) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * nz + z];
+  dEm[z] = -s;
+}
+
 __global__ void __launch_bounds__(BLOCK) k_copy(float4* __restrict__ dst, const float4* __restrict__ src, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) dst[i] = src[i];
 }
@@ -165,6 +176,7 @@ void fill_args(const fornax_m1_ctx* ctx, StepArgs<S>& a, const fornax_m1_coeffs*
     a.Fo[k] = nullptr;
   }
   a.dEm = nullptr;
+  a.dzp = nullptr;
   a.p_energy = nullptr;
   a.p_maxf2 = nullptr;
   a.p_nun = nullptr;
@@ -185,6 +197,7 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
   }
   bool want = diag && (diag->energy_total || diag->max_f || diag->n_unrealizable || diag->n_nonpositive);
   if (diag) a.dEm = diag->dE_matter;
+  a.dzp = ctx->dzp;
   if (want) {
     a.p_energy = ctx->p_energy;
     a.p_maxf2 = ctx->p_maxf2;
@@ -194,6 +207,11 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
   const int rc = launch_tiled<S, R>(ctx, geo, a, st);
   if (rc != FORNAX_OK) return rc;
   const int nb = ctx->last_tile->nblocks;
+  if (a.dEm && ctx->last_tile->ngb > 1) {
+    hipLaunchKernelGGL(k_dem_sum, dim3((unsigned)((a.nzones + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, a.dzp,
+                       ctx->last_tile->ngb, a.nzones, a.dEm);
+    if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
+  }
   if (want) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, ctx->p_energy, ctx->p_maxf2, ctx->p_nun, ctx->p_nnp, nb,
                        diag->energy_total, diag->max_f, diag->n_unrealizable, diag->n_nonpositive);

@@ -12,7 +12,7 @@ namespace fm1 {
 // Returns a tile with nblocks = 0 when the combination is invalid (thread count, halo slots,
 // LDS budget).
 Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB, int NW, int V);
-Tile choose_tile(const fornax_m1_desc& D, bool all_groups, int V);
+Tile choose_tile(const fornax_m1_desc& D, int V);
 // Raise the dynamic LDS limit of every step-kernel instantiation (once per process).
 int prepare_step_kernels();
 

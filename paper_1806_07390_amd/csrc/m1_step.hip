@@ -279,6 +279,13 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
   const int ty = (DIM == 3) ? rest % tl.nty : 0;
   const int tm = (DIM == 3) ? rest / tl.nty : rest;
   const int grp0 = gb * GB + gl * V;              // first group of the lane
+  // dE_matter of a zone from the groups of this block: the value itself when the block holds
+  // every group of the zone, else the block's partial (the group blocks are summed after
+  // the launch)
+  auto put_dem = [&](int64_t zone, double s) {
+    if (tl.ngb == 1) a.dEm[zone] = -s;
+    else a.dzp[(int64_t)gbb * a.nzones + zone] = s;
+  };
 
   const int n0 = a.n[0], n1 = a.n[1];
   const int x0 = tx * (TXB - 2) - 1;                          // zone of column 0
@@ -532,7 +539,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
     if (!ROW && a.dEm && dz_zone >= 0 && gl == 0) {
       double sdz = 0.0;
       for (int g2 = 0; g2 < GB; ++g2) sdz += DZ[(size_t)col * GB + g2];
-      a.dEm[dz_zone] = -sdz;
+      put_dem(dz_zone, sdz);
     }
     // ---- (c) in-plane reconstruction (lower states to LDS), march face m + 1/2 ----
     const int eym = ey_of(m);
@@ -710,14 +717,14 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         if (ccx >= 1 && ccx <= TXB - 2 && zx < n0) {
           double sdz = 0.0;
           for (int w2 = 0; w2 < tl.NW; ++w2) sdz += DZ[((size_t)(mm - mbeg) * tl.NW + w2) * TXB + ccx];
-          a.dEm[(size_t)((DIM == 2) ? mm : 0) * n0 + zx] = -sdz;
+          put_dem((int64_t)((DIM == 2) ? mm : 0) * n0 + zx, sdz);
         }
       }
     } else {
       if (dz_zone >= 0 && gl == 0) {
         double s2 = 0.0;
         for (int g2 = 0; g2 < GB; ++g2) s2 += DZ[(size_t)col * GB + g2];
-        a.dEm[dz_zone] = -s2;
+        put_dem(dz_zone, s2);
       }
     }
   }
@@ -831,22 +838,17 @@ Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB, int NW
 //    largest power of two up to 8 dividing G, so that a wave row of 16 columns reads runs of
 //    8 groups; with V = 1, GB up to 4.  All G / GB group subsets of a tile share a block when
 //    they fit in 8 waves.  Planes per block are halved from 32 until the grid has at least
-//    1024 (FP64) or 2048 (MIXED) blocks, TM >= 4.  With all_groups, GB grows until the block
-//    holds every group.
+//    1024 (FP64) or 2048 (MIXED) blocks, TM >= 4.
 //  * 3-D: a near-square tile of 128-512 threads; with many groups per zone, groups are split
-//    across blocks so that the zone tile stays large enough to amortise its halo, unless all
-//    groups are needed in one block.
-Tile choose_tile(const fornax_m1_desc& D, bool all_groups, int V) {
+//    across blocks so that the zone tile stays large enough to amortise its halo.
+Tile choose_tile(const fornax_m1_desc& D, int V) {
   const int G = D.ngroups;
   if (V == 2 && G % 2 != 0) return Tile{};
   if (D.ndim < 3) {
     int GB = V;
     while (GB < 4 * V && G % (2 * GB) == 0) GB *= 2;
-    if (all_groups)
-      while (G / GB > 8 && GB < 16 * V && G % (2 * GB) == 0) GB *= 2;
     int NW = std::min(8, G / GB);
     while ((G / GB) % NW != 0) --NW;
-    if (all_groups && NW * GB != G) return Tile{};
     const int want = (D.precision == FORNAX_FP64) ? 1024 : 2048;
     Tile t{};
     for (int TM = 32; TM >= 4; TM /= 2) {
@@ -857,7 +859,7 @@ Tile choose_tile(const fornax_m1_desc& D, bool all_groups, int V) {
   }
   // measured on gfx950: FP64 8 x 8 columns of up to 4 groups, 16 planes; FP32 pairs of
   // groups per lane, 16 x 16 columns of 2 groups, 8 planes
-  if (!all_groups) {
+  {
     Tile t{};
     if (D.precision == FORNAX_FP64) {
       int GB = 4;
@@ -872,7 +874,6 @@ Tile choose_tile(const fornax_m1_desc& D, bool all_groups, int V) {
   double best_cost = 1e30;
   for (int GB = G; GB >= 1; --GB) {
     if (G % GB != 0) continue;
-    if (all_groups && GB != G) break;
     for (int TXB = 4; TXB <= 32; ++TXB)
       for (int TYB = 4; TYB <= 32; ++TYB) {
         Tile t = make_tile(D, TXB, TYB, 8, GB, 1, V);
@@ -971,15 +972,14 @@ template <typename S, typename R>
 int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, hipStream_t st) {
   const bool sph = ctx->desc.coord == FORNAX_SPHERICAL_LOGR;
   const int D = ctx->desc.ndim;
-  // dE_matter sums over the groups of a zone inside one block; pairs of groups per lane need
-  // arrays aligned to two elements
-  const Tile* tl = a.dEm ? &ctx->tile_full : &ctx->tile;
+  // pairs of groups per lane need arrays aligned to two elements
+  const Tile* tl = &ctx->tile;
   bool al = true;
   const void* ptrs[] = {a.E, a.F[0], a.F[1], a.F[2], a.Eo, a.Fo[0], a.Fo[1], a.Fo[2], a.kap, a.sig, a.B};
   for (const void* q : ptrs) al = al && aligned_to(q, 2 * sizeof(S));
   if (tl->V == 2 && !al) tl = &ctx->tile_v1;
   if (tl->nblocks <= 0) return FORNAX_EUNSUPPORTED;
-  if (a.dEm && tl->GB * (tl->row ? tl->NW : 1) != a.G) return FORNAX_EUNSUPPORTED;
+  if (a.dEm && tl->ngb > 1 && !a.dzp) return FORNAX_EUNSUPPORTED;
   *ctx->last_tile = *tl;
   return sph ? launch_coord<S, R, true>(geo, a, *tl, D, st) : launch_coord<S, R, false>(geo, a, *tl, D, st);
 }

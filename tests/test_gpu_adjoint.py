@@ -101,6 +101,31 @@ def test_one_step_dot_product_options(m1):
         assert abs(lhs - rhs) <= 1e-12 * scale, (lim, clo)
 
 
+@pytest.mark.parametrize("lim", ["minmod", "mc", "none"])
+def test_one_step_dot_product_kappa_only(m1, lim):
+    """Perturb kappa alone: the identity then rests on g_kappa only (the interaction source
+    through U^{n+1}, and epsilon in optically thick faces), not on the state adjoint."""
+    code = {"minmod": m1.LIMITER_MINMOD, "mc": m1.LIMITER_MC, "none": m1.LIMITER_NONE}[lim]
+    w = wl.adjoint2d(n=20, G=3, steps=1)
+    p = problem_of(w, limiter=code)
+    rng = np.random.default_rng(29)
+    dk = rng.standard_normal(w.E.shape) * w.kappa
+    _, _, dE1, dF1 = orc.jvp(p, w.E, w.F, w.kappa, w.sigma, w.B, w.dt, 1, dkappa=dk)
+    lamE = rng.standard_normal(w.E.shape)
+    lamF = [rng.standard_normal(w.E.shape) for _ in w.F]
+    lhs = np.sum(lamE * dE1) + sum(np.sum(a * b) for a, b in zip(lamF, dF1))
+    ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64, limiter=code))
+    t = lambda a: to_dev(a, torch.float64)
+    _, _, gk = ctx.adjoint(t(w.E), [t(f) for f in w.F], t(w.kappa), t(w.sigma), t(w.B), w.dt, t(lamE),
+                           [t(f) for f in lamF])
+    gk = to_host(gk)
+    rhs = np.sum(gk * dk)
+    scale = np.sum(np.abs(gk * dk))
+    say("kappa-only", lim, lhs, rhs, scale)
+    assert scale > 0
+    assert abs(lhs - rhs) <= 1e-12 * scale
+
+
 def test_one_step_dot_product_mixed(m1):
     w = wl.adjoint2d(n=32, G=4, steps=1)
     lhs, rhs, scale = one_step_dot(m1, w, m1.MIXED)

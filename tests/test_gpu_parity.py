@@ -129,7 +129,7 @@ def test_tile_shapes(m1, case):
         tiles = ["4,4,3,4", "6,5,2,2", "7,4,5,1", "5,6,4,4,1,2"]
     p = problem_of(w)
     dt = dt_of(w, p)
-    E, F, _ = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow)
+    E, F, dg, dEm = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow, want_dEm=True)
     for prec, tol in ((m1.FP64, TOL_FP64), (m1.MIXED, TOL_MIXED_RUN)):
         for tile in tiles:
             say(f"case {case} tile {tile} prec {prec}")
@@ -138,10 +138,19 @@ def test_tile_shapes(m1, case):
                 ctx = m1.Context(m1.Config.from_workload(w, precision=prec))
             finally:
                 del os.environ["FORNAX_M1_TILE"]
-            Eg, Fg = gpu_run(ctx, w, dt, w.steps)
+            Eg, Fg, dgg = gpu_run(ctx, w, dt, w.steps, diag=True)
             eE, eF = rel_l1(Eg, Fg, E, F, w.c)
             say("   ", eE, eF)
             assert eE <= tol and eF <= tol, (case, tile, prec)
+            # the group sum of dE_matter spans the blocks of a tile's group subsets.  It is a
+            # difference of nearly equal energies (after and before the interaction update),
+            # so its rounding error scales with E, not with itself
+            if prec == m1.FP64:
+                atol = 1e-12 * np.abs(E).max()
+                assert np.allclose(dgg["dE_matter"], dEm, rtol=1e-10, atol=atol), tile
+                assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-12)
+            else:
+                assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-5)
 
 
 # ------------------------------------------------------------------------------------------
