@@ -129,14 +129,20 @@ int fornax_m1_source(fornax_m1_ctx *ctx, fornax_m1_state *inout, const fornax_m1
 
 /* Adjoint of one step (vector-Jacobian product), for gradients of a loss of U^N:
  *   lam_n = (dU^{n+1}/dU^n)^T lam_np1,   dkappa_accum += (dU^{n+1}/dkappa)^T lam_np1.
- * Un is the state the step started from; lam_np1, lam_n are states of the context's type
- * (lam_n must not alias lam_np1 or Un); dkappa_accum is a zone-group array of the context's
- * type, accumulated into.  Non-smooth points (minmod, realizability fallback, epsilon kink,
- * f clamp) take the derivative of the branch the forward step takes.  Same layout, error and
- * stream rules as fornax_m1_step. */
-int fornax_m1_adjoint(fornax_m1_ctx *ctx, const fornax_m1_state *Un, const fornax_m1_coeffs *cf,
-                      const double *inflow, double dt, const fornax_m1_state *lam_np1,
-                      fornax_m1_state *lam_n, void *dkappa_accum, void *stream);
+ * Un is the state the step started from.  Unp1 is NULL or the state fornax_m1_step produced
+ * from Un with the same coefficients, inflow and dt (the opacity derivative of the
+ * interaction update needs U^{n+1}); when NULL the step is recomputed into scratch owned by
+ * the context (allocated by the first such call).  A Unp1 that is not that step's result
+ * gives a wrong dkappa, with no error.  lam_np1, lam_n are states of the context's type
+ * (lam_n must not alias lam_np1, Un or Unp1); dkappa_accum is a zone-group array of the
+ * context's type, accumulated into.  Non-smooth points (minmod, realizability fallback,
+ * epsilon kink, f clamp) take the derivative of the branch the forward step takes.  Same
+ * layout, error and stream rules as fornax_m1_step; FORNAX_EUNSUPPORTED for spherical grids
+ * and for 3-D. */
+int fornax_m1_adjoint(fornax_m1_ctx *ctx, const fornax_m1_state *Un, const fornax_m1_state *Unp1,
+                      const fornax_m1_coeffs *cf, const double *inflow, double dt,
+                      const fornax_m1_state *lam_np1, fornax_m1_state *lam_n, void *dkappa_accum,
+                      void *stream);
 
 /* Measurement utility (not part of the method): plain device-to-device copy of `nbytes`
  * (multiple of 16, 16-byte aligned pointers) with the library's own kernel, used to scale

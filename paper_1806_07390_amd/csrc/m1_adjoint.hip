@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 
 #include "m1_adjoint_device.h"
 #include "m1_device.h"
@@ -32,7 +34,7 @@ struct AdjArgs : StepArgs<S> {
   const S* lam[3 + 1];    // lambda^{n+1}: E, F_1..F_ND
   S* lamo[3 + 1];         // lambda^n
   S* dk;                  // dkappa accumulator
-  const S* U1[3 + 1];     // U^{n+1} of the step (E, F_1..F_ND), from the forward kernel
+  const S* U1[3 + 1];     // U^{n+1} of the step (E, F_1..F_ND)
   double* gbuf[3];        // ghost adjoints per direction: [side][layer][plane][G][NC+1]
   int gplane[3];          // zones of the plane normal to direction d
 };
@@ -71,7 +73,9 @@ __device__ __forceinline__ void load_mu(const AdjArgs<S>& a, int zg, R mu[4]) {
 }
 
 template <typename S, typename R, int DIM>
-__global__ void __launch_bounds__(512) k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
+// three waves per SIMD (at most 168 VGPRs): measured faster on gfx950 than the unconstrained
+// allocation (two waves) despite a few spilled registers
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NC = 1 + DIM;
   constexpr int NV = 2 * NC + 1;     // state, total opacity, mu
@@ -369,11 +373,12 @@ __global__ void __launch_bounds__(256) k_adj_fold(AdjArgs<S> a, int d) {
 }
 
 // ------------------------------------------------------------------------------------------
-static AdjTile make_adj_tile(const fornax_m1_desc& D, int TM) {
+static AdjTile make_adj_tile(const fornax_m1_desc& D, int TM, int TXB) {
   AdjTile tl;
   const int G = D.ngroups;
-  tl.TXB = std::max(4, 256 / G);
+  tl.TXB = TXB > 0 ? TXB : std::max(4, 256 / G);
   if (tl.TXB * G > 512) tl.TXB = 512 / G;
+  if (tl.TXB < 4) tl.TXB = 4;
   tl.W = tl.TXB - 3;
   tl.TM = TM;
   tl.ntx = (D.n[0] + 4 + tl.W - 1) / tl.W;
@@ -394,16 +399,21 @@ static size_t adj_lds_bytes(const AdjTile& tl, int dim, int G, size_t rsize) {
 
 template <typename S, typename R>
 static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* Un,
-                            const fornax_m1_coeffs* cf, const double* inflow, double dt,
-                            const fornax_m1_state* lam_np1, fornax_m1_state* lam_n, void* dkappa, hipStream_t st) {
+                            const fornax_m1_state* Unp1, const fornax_m1_coeffs* cf, const double* inflow,
+                            double dt, const fornax_m1_state* lam_np1, fornax_m1_state* lam_n, void* dkappa,
+                            hipStream_t st) {
   const fornax_m1_desc& D = ctx->desc;
-  // U^{n+1} of the step, by the forward kernel, into the context's adjoint scratch
+  // U^{n+1} of the step: the caller's, else by the forward kernel into the context's scratch
   fornax_m1_state u1;
-  const size_t nzg = (size_t)D.n[0] * D.n[1] * D.n[2] * D.ngroups;
-  u1.E = ctx->adj_u1;
-  for (int k = 0; k < 3; ++k) u1.F[k] = (k < D.ndim) ? (char*)ctx->adj_u1 + (1 + k) * nzg * sizeof(S) : nullptr;
-  int rc = fm1_launch_step(ctx, Un, &u1, cf, inflow, dt, nullptr, st);
-  if (rc != FORNAX_OK) return rc;
+  if (Unp1) {
+    u1 = *Unp1;
+  } else {
+    const size_t nzg = (size_t)D.n[0] * D.n[1] * D.n[2] * D.ngroups;
+    u1.E = ctx->adj_u1;
+    for (int k = 0; k < 3; ++k) u1.F[k] = (k < D.ndim) ? (char*)ctx->adj_u1 + (1 + k) * nzg * sizeof(S) : nullptr;
+    const int rc = fm1_launch_step(ctx, Un, &u1, cf, inflow, dt, nullptr, st);
+    if (rc != FORNAX_OK) return rc;
+  }
   AdjArgs<S> a;
   for (int d = 0; d < 3; ++d) {
     a.n[d] = D.n[d];
@@ -446,7 +456,17 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
     a.gbuf[d] = ctx->adj_gbuf[d];
     a.gplane[d] = ctx->adj_gplane[d];
   }
-  AdjTile tl = make_adj_tile(D, 8);
+  // tiling: FORNAX_M1_ADJ_TILE="TXB,TM" overrides the default (256 threads, 8 planes)
+  int txb = 0, tm = 8;
+  if (const char* env = std::getenv("FORNAX_M1_ADJ_TILE")) {
+    int x = 0, y = 0;
+    if (std::sscanf(env, "%d,%d", &x, &y) == 2 && x >= 4 && y >= 1) {
+      txb = x;
+      tm = y;
+    }
+  }
+  AdjTile tl = make_adj_tile(D, tm, txb);
+  if (tl.TXB * D.ngroups > 512) return FORNAX_EUNSUPPORTED;
   const size_t lds = adj_lds_bytes(tl, D.ndim, D.ngroups, sizeof(R));
   if (lds > 65536) return FORNAX_EUNSUPPORTED;
   if (D.ndim == 1)
@@ -469,13 +489,13 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
 
 using namespace fm1;
 
-int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const fornax_m1_coeffs* cf,
-                       const double* inflow, double dt, const fornax_m1_state* lam_np1, fornax_m1_state* lam_n,
-                       void* dkappa, hipStream_t stream) {
+int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const fornax_m1_state* Unp1,
+                       const fornax_m1_coeffs* cf, const double* inflow, double dt, const fornax_m1_state* lam_np1,
+                       fornax_m1_state* lam_n, void* dkappa, hipStream_t stream) {
   const fornax_m1_desc& D = ctx->desc;
   if (D.coord != FORNAX_CARTESIAN || D.ndim > 2 || D.ngroups > 128) return FORNAX_EUNSUPPORTED;
   if (!ctx->adj_gbuf[0]) return FORNAX_ENOMEM;
-  if (!ctx->adj_u1) {
+  if (!Unp1 && !ctx->adj_u1) {
     // first adjoint call on this context: scratch for U^{n+1}
     const size_t es = D.precision == FORNAX_FP64 ? sizeof(double) : sizeof(float);
     const size_t bytes = (size_t)(1 + D.ndim) * D.n[0] * D.n[1] * D.n[2] * D.ngroups * es;
@@ -485,6 +505,7 @@ int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const forn
     }
   }
   if (D.precision == FORNAX_FP64)
-    return launch_adjoint_t<double, double>(ctx, ctx->geo_d, Un, cf, inflow, dt, lam_np1, lam_n, dkappa, stream);
-  return launch_adjoint_t<float, float>(ctx, ctx->geo_f, Un, cf, inflow, dt, lam_np1, lam_n, dkappa, stream);
+    return launch_adjoint_t<double, double>(ctx, ctx->geo_d, Un, Unp1, cf, inflow, dt, lam_np1, lam_n, dkappa,
+                                            stream);
+  return launch_adjoint_t<float, float>(ctx, ctx->geo_f, Un, Unp1, cf, inflow, dt, lam_np1, lam_n, dkappa, stream);
 }

@@ -366,8 +366,10 @@ __device__ __forceinline__ void geometric_source(const R P[9], const R h[3], con
 // contributions: V E^{n+1}, f^2 = (|F^|/cE)^2, realizability and positivity counts.  Returns
 // E^{n+1} - E^- (energy handed to matter, with the sign reversed).
 struct ZoneDiag {
-  double energy = 0.0, maxf2 = 0.0;
+  double energy = 0.0;
+  double fnum = 0.0, fden = 1.0;   // the largest f^2 seen, kept as the ratio fnum / fden
   int nun = 0, nnp = 0;
+  __device__ double maxf2() const { return fnum / fden; }
 };
 
 // The coefficients enter as cdtk = c dt kappa, cdtks = c dt (kappa + sigma) and the emission
@@ -406,10 +408,11 @@ __device__ __forceinline__ double source_zone(const StepArgsBase& a, const Geo<R
       F2 += fk * fk;
     }
     const double cE = c * E1d;
-    if (E1d > 0.0) {
-      const double icE = rcp_(cE);
-      zd.maxf2 = fmax(zd.maxf2, F2 * (icE * icE));
-    }
+    // f^2 = F2 / (cE)^2 compared by cross-multiplication (one division per thread at the end)
+    const double cE2 = cE * cE;
+    const bool up = E1d > 0.0 && F2 * zd.fden > zd.fnum * cE2;
+    zd.fnum = up ? F2 : zd.fnum;
+    zd.fden = up ? cE2 : zd.fden;
     const double u = (sizeof(S) == 8) ? 0x1p-53 : 0x1p-24;
     const double lim = cE * (1.0 + 8.0 * u);
     zd.nun += (F2 > lim * lim) ? 1 : 0;

@@ -503,18 +503,20 @@ int fornax_m1_source(fornax_m1_ctx* ctx, fornax_m1_state* inout, const fornax_m1
   return fm1_launch_source(ctx, inout, cf, dt, dE_matter, (hipStream_t)stream);
 }
 
-int fornax_m1_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const fornax_m1_coeffs* cf,
-                      const double* inflow, double dt, const fornax_m1_state* lam_np1, fornax_m1_state* lam_n,
-                      void* dkappa_accum, void* stream) {
+int fornax_m1_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const fornax_m1_state* Unp1,
+                      const fornax_m1_coeffs* cf, const double* inflow, double dt, const fornax_m1_state* lam_np1,
+                      fornax_m1_state* lam_n, void* dkappa_accum, void* stream) {
   if (!ctx || !dkappa_accum) return FORNAX_EINVAL;
   int rc;
   if ((rc = check_state(ctx, Un)) || (rc = check_state(ctx, lam_np1)) || (rc = check_state(ctx, lam_n)) ||
       (rc = check_coeffs(ctx, cf)))
     return rc;
+  if (Unp1 && (rc = check_state(ctx, Unp1))) return rc;
   if (overlaps(ctx, lam_n, lam_np1) || overlaps(ctx, lam_n, Un)) return FORNAX_EINVAL;
+  if (Unp1 && overlaps(ctx, lam_n, Unp1)) return FORNAX_EINVAL;
   if (needs_inflow(ctx->desc) != (inflow != nullptr)) return FORNAX_EINVAL;
   if (!(dt > 0.0) || dt > ctx->max_dt1 * (1.0 + 1e-12)) return FORNAX_ECFL;
-  return fm1_launch_adjoint(ctx, Un, cf, inflow, dt, lam_np1, lam_n, dkappa_accum, (hipStream_t)stream);
+  return fm1_launch_adjoint(ctx, Un, Unp1, cf, inflow, dt, lam_np1, lam_n, dkappa_accum, (hipStream_t)stream);
 }
 
 int fornax_m1_copy_probe(void* dst, const void* src, int64_t nbytes, void* stream) {

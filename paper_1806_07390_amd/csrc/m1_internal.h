@@ -162,7 +162,8 @@ int fm1_launch_flux(fornax_m1_ctx* ctx, const fornax_m1_state* in, const fornax_
                     const double* inflow, void* face_flux[3], hipStream_t stream);
 int fm1_launch_source(fornax_m1_ctx* ctx, fornax_m1_state* inout, const fornax_m1_coeffs* cf,
                       double dt, double* dEm, hipStream_t stream);
-int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const fornax_m1_coeffs* cf,
+int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const fornax_m1_state* Unp1,
+                       const fornax_m1_coeffs* cf,
                        const double* inflow, double dt, const fornax_m1_state* lam_np1,
                        fornax_m1_state* lam_n, void* dkappa, hipStream_t stream);
 int fm1_launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t stream);

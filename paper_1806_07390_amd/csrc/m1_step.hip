@@ -730,7 +730,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
   }
   if (!want_diag) return;
   // ---- block partials of the diagnostics: wave reduction, then across waves ----
-  double e = zd.energy, mf = zd.maxf2;
+  double e = zd.energy, mf = zd.maxf2();
   int un = zd.nun, p = zd.nnp;
   for (int off = 32; off > 0; off >>= 1) {
     e += __shfl_xor(e, off);

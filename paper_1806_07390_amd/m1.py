@@ -76,7 +76,8 @@ _lib.fornax_m1_max_dt.restype = ctypes.c_double
 _lib.fornax_m1_step.argtypes = [_vp, _P(State), _P(State), _P(Coeffs), _vp, ctypes.c_double, _P(Diag), _vp]
 _lib.fornax_m1_flux.argtypes = [_vp, _P(State), _P(Coeffs), _vp, _vp * 3, _vp]
 _lib.fornax_m1_source.argtypes = [_vp, _P(State), _P(Coeffs), ctypes.c_double, _vp, _vp]
-_lib.fornax_m1_adjoint.argtypes = [_vp, _P(State), _P(Coeffs), _vp, ctypes.c_double, _P(State), _P(State), _vp, _vp]
+_lib.fornax_m1_adjoint.argtypes = [_vp, _P(State), _P(State), _P(Coeffs), _vp, ctypes.c_double, _P(State), _P(State),
+                                    _vp, _vp]
 _lib.fornax_m1_copy_probe.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
 _lib.fornax_m1_strerror.argtypes = [ctypes.c_int]
 _lib.fornax_m1_strerror.restype = ctypes.c_char_p
@@ -261,9 +262,12 @@ class Context:
         _check(_lib.fornax_m1_source(self._h, ctypes.byref(s), ctypes.byref(cf), dt, _ptr(dE_matter),
                                      _stream(stream)), "fornax_m1_source")
 
-    def adjoint(self, E, F, kappa, sigma, B, dt, lamE, lamF, out=None, dkappa=None, inflow=None, stream=None):
-        """lam_n = J^T lam_{n+1}; dkappa += (dU^{n+1}/dkappa)^T lam_{n+1}. Returns (lamE_n, [lamF_n], dkappa)."""
+    def adjoint(self, E, F, kappa, sigma, B, dt, lamE, lamF, out=None, dkappa=None, inflow=None, stream=None,
+                U1=None):
+        """lam_n = J^T lam_{n+1}; dkappa += (dU^{n+1}/dkappa)^T lam_{n+1}. Returns (lamE_n, [lamF_n], dkappa).
+        U1: optional (E, [F]) of the step's result from (E, F) (recomputed when None)."""
         su = self._state(E, F, "Un")
+        s1 = None if U1 is None else self._state(U1[0], U1[1], "Unp1")
         sl = self._state(lamE, lamF, "lam_np1")
         if out is None:
             out = self.empty_state()
@@ -272,7 +276,8 @@ class Context:
             dkappa = torch.zeros(self.shape, dtype=self.dtype, device=self.device)
         self._check_arr(dkappa, "dkappa")
         cf = self._coeffs(kappa, sigma, B)
-        _check(_lib.fornax_m1_adjoint(self._h, ctypes.byref(su), ctypes.byref(cf), self._inflow(inflow), dt,
+        _check(_lib.fornax_m1_adjoint(self._h, ctypes.byref(su), ctypes.byref(s1) if s1 is not None else None,
+                                      ctypes.byref(cf), self._inflow(inflow), dt,
                                       ctypes.byref(sl), ctypes.byref(so), ctypes.c_void_p(dkappa.data_ptr()),
                                       _stream(stream)), "fornax_m1_adjoint")
         return out[0], out[1], dkappa
@@ -333,18 +338,20 @@ class Context:
         call._keep = (sa, sb, cf)
         return call
 
-    def adjointer(self, U, kappa, sigma, B, dt, lam_in, lam_out, dkappa, inflow=None, stream=None):
+    def adjointer(self, U, kappa, sigma, B, dt, lam_in, lam_out, dkappa, inflow=None, stream=None, U1=None):
         """Pre-bound fornax_m1_adjoint call (arguments built once): returns a function that
-        computes lam_out = J^T lam_in and accumulates into dkappa for the state U."""
+        computes lam_out = J^T lam_in and accumulates into dkappa for the state U (U1: the
+        step's result from U, when the caller holds it)."""
         su = self._state(U[0], U[1], "Un")
+        s1 = None if U1 is None else self._state(U1[0], U1[1], "Unp1")
         sl = self._state(lam_in[0], lam_in[1], "lam_np1")
         so = self._state(lam_out[0], lam_out[1], "lam_n")
         self._check_arr(dkappa, "dkappa")
         cf = self._coeffs(kappa, sigma, B)
         infl = self._inflow(inflow)
         st = _stream(stream)
-        args = (self._h, ctypes.byref(su), ctypes.byref(cf), infl, dt, ctypes.byref(sl), ctypes.byref(so),
-                ctypes.c_void_p(dkappa.data_ptr()), st)
+        args = (self._h, ctypes.byref(su), ctypes.byref(s1) if s1 is not None else None, ctypes.byref(cf), infl, dt,
+                ctypes.byref(sl), ctypes.byref(so), ctypes.c_void_p(dkappa.data_ptr()), st)
         fn = _lib.fornax_m1_adjoint
 
         def call():
@@ -352,7 +359,7 @@ class Context:
             if rc != FORNAX_OK:
                 raise FornaxError(rc, "fornax_m1_adjoint")
 
-        call._keep = (su, sl, so, cf)
+        call._keep = (su, s1, sl, so, cf)
         return call
 
     def run(self, E, F, kappa, sigma, B, dt, nsteps, inflow=None, diag=None):
@@ -396,13 +403,15 @@ class M1Steps(torch.autograd.Function):
                 ckpts.append((s, cur[0].clone(), [f.clone() for f in cur[1]]))
             step()
         out = current()
-        fctx.m1 = (ctx, dt, nsteps, ckpt_every, inflow, ckpts)
+        res = (out[0].clone(),) + tuple(f.clone() for f in out[1])
+        # the final state closes the last segment of the replay
+        fctx.m1 = (ctx, dt, nsteps, ckpt_every, inflow, ckpts, (out[0].clone(), [f.clone() for f in out[1]]))
         fctx.save_for_backward(kappa, sigma, B)
-        return (out[0].clone(),) + tuple(f.clone() for f in out[1])
+        return res
 
     @staticmethod
     def backward(fctx, gE, *gF):
-        ctx, dt, nsteps, ckpt_every, inflow, ckpts = fctx.m1
+        ctx, dt, nsteps, ckpt_every, inflow, ckpts, final = fctx.m1
         kappa, sigma, B = fctx.saved_tensors
         kappa, sigma, B = kappa.detach(), sigma.detach(), B.detach()
         zeros = lambda: torch.zeros(ctx.shape, dtype=ctx.dtype, device=ctx.device)
@@ -411,17 +420,23 @@ class M1Steps(torch.autograd.Function):
                ctx.empty_state()]
         dk = zeros()
         K = min(ckpt_every, nsteps)
-        seg = [ctx.empty_state() for _ in range(K)]
+        # seg[i]: state i of the segment being replayed; seg[n_in] holds the state that ends
+        # it (the next checkpoint, or the final state), so that every adjoint step gets both
+        # U^n and U^{n+1} and none recomputes the step
+        seg = [ctx.empty_state() for _ in range(K + 1)]
         # every C call of the replay is bound once: K-1 steps, K adjoint steps per lambda parity
         steps = [ctx.bound_step(seg[i], seg[i + 1], kappa, sigma, B, dt, inflow=inflow) for i in range(K - 1)]
-        adj = [[ctx.adjointer(seg[i], kappa, sigma, B, dt, lam[p], lam[1 - p], dk, inflow=inflow)
+        adj = [[ctx.adjointer(seg[i], kappa, sigma, B, dt, lam[p], lam[1 - p], dk, inflow=inflow, U1=seg[i + 1])
                 for p in range(2)] for i in range(K)]
+        ends = [(c[1], c[2]) for c in ckpts[1:]] + [final]
         p = 0
-        for (s0, E, F) in reversed(ckpts):
+        for j in reversed(range(len(ckpts))):
+            s0, E, F = ckpts[j]
             n_in = min(s0 + ckpt_every, nsteps) - s0
-            seg[0][0].copy_(E)
-            for k in range(len(F)):
-                seg[0][1][k].copy_(F[k])
+            for dst, src in ((seg[0], (E, F)), (seg[n_in], ends[j])):
+                dst[0].copy_(src[0])
+                for k in range(len(src[1])):
+                    dst[1][k].copy_(src[1][k])
             for i in range(n_in - 1):
                 steps[i]()
             for i in reversed(range(n_in)):

@@ -126,6 +126,32 @@ def test_one_step_dot_product_kappa_only(m1, lim):
     assert abs(lhs - rhs) <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adjoint_with_given_next_state(m1, precision):
+    """Supplying U^{n+1} (as the checkpointed backward does) gives bit for bit the result of
+    the call that recomputes the step itself; a wrong U^{n+1} changes only dkappa."""
+    prec = m1.FP64 if precision == "fp64" else m1.MIXED
+    w = wl.adjoint2d(n=40, G=4, steps=1)
+    ctx = m1.Context(m1.Config.from_workload(w, precision=prec))
+    dtp = ctx.dtype
+    rng = np.random.default_rng(5)
+    E = to_dev(w.E, dtp)
+    F = [to_dev(f, dtp) for f in w.F]
+    k, s, B = (to_dev(x, dtp) for x in (w.kappa, w.sigma, w.B))
+    lamE = to_dev(rng.standard_normal(w.E.shape), dtp)
+    lamF = [to_dev(rng.standard_normal(w.E.shape), dtp) for _ in w.F]
+    U1 = ctx.step(E, F, k, s, B, w.dt)
+    a = ctx.adjoint(E, F, k, s, B, w.dt, lamE, lamF)
+    b = ctx.adjoint(E, F, k, s, B, w.dt, lamE, lamF, U1=U1)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and all(torch.equal(x, y) for x, y in zip(a[1], b[1]))
+    assert torch.equal(a[2], b[2])
+    wrong = (U1[0] * 1.5, U1[1])
+    c = ctx.adjoint(E, F, k, s, B, w.dt, lamE, lamF, U1=wrong)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], c[0]) and not torch.equal(a[2], c[2])
+
+
 def test_one_step_dot_product_mixed(m1):
     w = wl.adjoint2d(n=32, G=4, steps=1)
     lhs, rhs, scale = one_step_dot(m1, w, m1.MIXED)
