@@ -150,11 +150,14 @@ __device__ __forceinline__ bool realizable(const R q[4], const R h[3], R c) {
 
 // Linear reconstruction of one zone along d (extended index e): face states at its lower
 // and upper faces, with the piecewise-constant fallback when either is not realizable.
-template <typename R, bool SPH, int ND>
+// LIM: the limiter when known at compile time (a FORNAX_LIMITER_* value), -1 to read it from
+// the arguments.
+template <typename R, bool SPH, int ND, int LIM = -1>
 __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>& geo, int d, int e, const R qm[4],
                                             const R q0[4], const R qp[4], const R hlo[3], const R hhi[3],
                                             bool lo_open, bool hi_open, R lo[4], R hi[4]) {
   const R c = R(a.c);
+  const int limiter = (LIM >= 0) ? LIM : a.limiter;
   R s[4];
   R dl = R(-0.5), dh = R(0.5);
   if constexpr (SPH) {
@@ -164,9 +167,9 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
     dh = geo.dhi[d][e];
     for (int cp = 0; cp <= ND; ++cp) {
       const R sa = (q0[cp] - qm[cp]) * idm, sb = (qp[cp] - q0[cp]) * idp;
-      if (a.limiter == FORNAX_LIMITER_MINMOD) {
+      if (limiter == FORNAX_LIMITER_MINMOD) {
         s[cp] = minmod(sa, sb);
-      } else if (a.limiter == FORNAX_LIMITER_MC) {
+      } else if (limiter == FORNAX_LIMITER_MC) {
         s[cp] = minmod(R(2) * sa, minmod(R(2) * sb, (qp[cp] - qm[cp]) * geo.idc[d][e]));
       } else {
         s[cp] = R(0);
@@ -179,9 +182,9 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
     (void)e;
     for (int cp = 0; cp <= ND; ++cp) {
       const R dm = q0[cp] - qm[cp], dp = qp[cp] - q0[cp];
-      if (a.limiter == FORNAX_LIMITER_MINMOD) {
+      if (limiter == FORNAX_LIMITER_MINMOD) {
         s[cp] = minmod(dm, dp);
-      } else if (a.limiter == FORNAX_LIMITER_MC) {
+      } else if (limiter == FORNAX_LIMITER_MC) {
         s[cp] = minmod(R(2) * dm, minmod(R(2) * dp, R(0.5) * (dm + dp)));
       } else {
         s[cp] = R(0);
@@ -235,8 +238,9 @@ __device__ __forceinline__ void closure_full(const R q[4], const R h[3], R c, in
   P[8] += iso;
 }
 
-// Row d of the closure, P^^{dk} for k < ND.  In the MIXED path (R = float) the closure is
-// evaluated in double where f^2 >= f2_fp64.
+// Row d of the closure, P^^{dk} for k < ND.  In double, from E and F directly (one square
+// root, one reciprocal); in the MIXED path (R = float) from f = F/(cE), in double where
+// f^2 >= f2_fp64.
 template <typename R, bool SPH, int ND>
 __device__ __forceinline__ void closure_row(const R q[4], const R h[3], int d, R c, int eddington, double f2_fp64,
                                             R P[3]) {
@@ -244,6 +248,30 @@ __device__ __forceinline__ void closure_row(const R q[4], const R h[3], int d, R
   for (int k = 0; k < 3; ++k) P[k] = R(0);
   if (eddington || !(E > R(0))) {
     P[d] = E * R(1.0 / 3.0);
+    return;
+  }
+  if constexpr (sizeof(R) == 8) {
+    // double: from E and F directly, with S = cE s = sqrt(4 (cE)^2 - 3 |F|^2),
+    //   P = (S - cE)/(3c) delta + 3 F F / (c (2 cE + S)),
+    // one square root and one reciprocal (the squares stay far inside the double range)
+    R Fh[3] = {R(0), R(0), R(0)};
+    R F2 = R(0);
+    for (int k = 0; k < ND; ++k) {
+      Fh[k] = SPH ? q[1 + k] * rcp_(h[k]) : q[1 + k];
+      F2 += Fh[k] * Fh[k];
+    }
+    const R cE = c * E;
+    const R A = cE * cE;
+    if (F2 > A) {
+      // |f| > 1: the direction of F with |f| = 1
+      const R sc = cE * rcp_(sqrt_(F2));
+      for (int k = 0; k < ND; ++k) Fh[k] *= sc;
+      F2 = A;
+    }
+    const R S = sqrt_(R(4) * A - R(3) * F2);
+    const R iso = (S - cE) * rcp_(R(3) * c);   // c is uniform: hoisted
+    const R af = R(3) * rcp_(c * (R(2) * cE + S)) * Fh[d];
+    for (int k = 0; k < ND; ++k) P[k] = af * Fh[k] + (k == d ? iso : R(0));
     return;
   }
   R f[3] = {R(0), R(0), R(0)};

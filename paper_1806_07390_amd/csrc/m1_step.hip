@@ -223,8 +223,11 @@ __host__ __device__ inline size_t unit_lds_elems(int dim, int TXB, int TYB, int 
           (size_t)(NC + 3) * TXB * TYB) * GB;
 }
 
-template <typename S, typename R, int DIM, bool SPH, bool ROW, int GBC, int V>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(GBC > 0 && !SPH && V == 1 ? 4 : 1)))
+// Waves per SIMD for the compile-time wave-row kernels (measured on gfx950): 3 in double
+// (at most 168 VGPRs, no spills), 5 in float (at most 96 VGPRs).  LIM: the limiter when
+// known at compile time, -1 to read it from the arguments.
+template <typename S, typename R, int DIM, bool SPH, bool ROW, int GBC, int V, int LIM>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(GBC > 0 && !SPH && V == 1 ? (sizeof(R) == 8 ? 3 : 5) : 1)))
 k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NC = 1 + DIM;   // E, F_1..F_DIM
@@ -485,8 +488,8 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
       const R dlR = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef);
       for (int u = 0; u < V; ++u) {
         R lo[4], hiP[4];
-        reconstruct<R, SPH, DIM>(a, geo, MD, ef - 1, qa[u], qb[u], q0[u], h0, h1, o0, o1, lo, hiP);
-        reconstruct<R, SPH, DIM>(a, geo, MD, ef, qb[u], q0[u], q1[u], h1, h2, o1, o2, lo, hiM[u]);
+        reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef - 1, qa[u], qb[u], q0[u], h0, h1, o0, o1, lo, hiP);
+        reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef, qb[u], q0[u], q1[u], h1, h2, o1, o2, lo, hiM[u]);
         if (o1) hll<R, SPH, DIM>(a, MD, hiP, lo, h1, epsilon_of(ka[u] + sa[u], ks0[u], dlL, dlR), fPrev[u]);
       }
     } else {
@@ -557,7 +560,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
           qm[v] = (v < NC) ? PV[pvi(v, prow_own, cx) + u] : R(0);
           qp[v] = (v < NC) ? PV[pvi(v, prow_own, cx + 2) + u] : R(0);
         }
-        reconstruct<R, SPH, DIM>(a, geo, 0, ex, qm, q0[u], qp, hlo, hhi, olo, ohi, lo, hiX[u]);
+        reconstruct<R, SPH, DIM, LIM>(a, geo, 0, ex, qm, q0[u], qp, hlo, hhi, olo, ohi, lo, hiX[u]);
         for (int v = 0; v < NC; ++v) LX[cidx(v, col) + u] = lo[v];
       }
       if constexpr (DIM == 3) {
@@ -570,7 +573,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
             qm[v] = (v < NC) ? PV[pvi(v, prow_own - 1, cx + 1) + u] : R(0);
             qp[v] = (v < NC) ? PV[pvi(v, prow_own + 1, cx + 1) + u] : R(0);
           }
-          reconstruct<R, SPH, DIM>(a, geo, 1, eyc, qm, q0[u], qp, hlo, hhi, ylo, yhi, lo, hiY[u]);
+          reconstruct<R, SPH, DIM, LIM>(a, geo, 1, eyc, qm, q0[u], qp, hlo, hhi, ylo, yhi, lo, hiY[u]);
           for (int v = 0; v < NC; ++v) LY[cidx(v, col) + u] = lo[v];
         }
       }
@@ -591,7 +594,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         const R dlR = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef);
         for (int u = 0; u < V; ++u) {
           R nLo[4];
-          reconstruct<R, SPH, DIM>(a, geo, MD, ef, q0[u], q1[u], q2[u], h1, h2, o1, o2, nLo, nHi[u]);
+          reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef, q0[u], q1[u], q2[u], h1, h2, o1, o2, nLo, nHi[u]);
           if (o1) hll<R, SPH, DIM>(a, MD, hiM[u], nLo, h1, epsilon_of(ks0[u], ks1[u], dlL, dlR), fNext[u]);
         }
       }
@@ -894,8 +897,12 @@ Tile choose_tile(const fornax_m1_desc& D, int V) {
 
 template <typename S, typename R, int DIM, bool SPH, bool ROW, int GBC, int V>
 static hipError_t raise_lds_limit(int bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step_tiled<S, R, DIM, SPH, ROW, GBC, V>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const hipError_t e1 = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&k_step_tiled<S, R, DIM, SPH, ROW, GBC, V, FORNAX_LIMITER_MINMOD>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step_tiled<S, R, DIM, SPH, ROW, GBC, V, -1>),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return e1 != hipSuccess ? e1 : e2;
 }
 
 // Every instantiation that launch_tiled can pick.
@@ -945,8 +952,16 @@ int prepare_step_kernels() {
 template <typename S, typename R, bool SPH>
 static int launch_coord(const Geo<R>& geo, const StepArgs<S>& a, const Tile& tl, int D, hipStream_t st) {
   dim3 grid(tl.nblocks), block(tl.nthreads);
-#define FM1_LAUNCH(DIMV, ROWV, GBV, VV) \
-  hipLaunchKernelGGL((k_step_tiled<S, R, DIMV, SPH, ROWV, GBV, VV>), grid, block, tl.lds, st, a, geo, tl)
+  // the method's default limiter is a compile-time constant of its own instantiation
+  const bool mm = a.limiter == FORNAX_LIMITER_MINMOD;
+#define FM1_LAUNCH(DIMV, ROWV, GBV, VV)                                                                          \
+  do {                                                                                                          \
+    if (mm)                                                                                                     \
+      hipLaunchKernelGGL((k_step_tiled<S, R, DIMV, SPH, ROWV, GBV, VV, FORNAX_LIMITER_MINMOD>), grid, block,     \
+                         tl.lds, st, a, geo, tl);                                                                \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_step_tiled<S, R, DIMV, SPH, ROWV, GBV, VV, -1>), grid, block, tl.lds, st, a, geo, tl); \
+  } while (0)
   if (D == 1) {
     if (!tl.row || tl.V != 1) return FORNAX_EUNSUPPORTED;
     FM1_LAUNCH(1, true, 0, 1);
