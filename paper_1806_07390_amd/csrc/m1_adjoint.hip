@@ -72,10 +72,12 @@ __device__ __forceinline__ void load_mu(const AdjArgs<S>& a, int zg, R mu[4]) {
   for (int k = 0; k < 4; ++k) mu[k] = (R)m[k];
 }
 
-template <typename S, typename R, int DIM>
-// three waves per SIMD (at most 168 VGPRs): measured faster on gfx950 than the unconstrained
-// allocation (two waves) despite a few spilled registers
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
+// Three waves per SIMD (at most 168 VGPRs): measured faster on gfx950 than the unconstrained
+// allocation (two waves) despite a few spilled registers.  LIM: the limiter when known at
+// compile time, -1 to read it from the arguments.
+template <typename S, typename R, int DIM, int LIM>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
+k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NC = 1 + DIM;
   constexpr int NV = 2 * NC + 1;     // state, total opacity, mu
@@ -144,7 +146,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k
     if (f < 0 || f > nM) return;
     R nu[4] = {R(0), R(0), R(0), R(0)};
     for (int v = 0; v < NC; ++v) nu[v] = nuy * (wmu[2][v] - wmu[1][v]);
-    face_vjp_cart<R, DIM>(a, MD < 0 ? 0 : MD, geo.dx[MD < 0 ? 0 : MD], wq, wks[1], wks[2], nu, fl, C, dkL, dkR);
+    face_vjp_cart<R, DIM, LIM>(a, MD < 0 ? 0 : MD, geo.dx[MD < 0 ? 0 : MD], wq, wks[1], wks[2], nu, fl, C, dkL, dkR);
   };
   if constexpr (DIM >= 2) {
     if (colin) {
@@ -248,7 +250,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k
         }
         R nu[4] = {R(0), R(0), R(0), R(0)};
         for (int v = 0; v < NC; ++v) nu[v] = nux * (pv(NC + 1 + v, cx + 2) - pv(NC + 1 + v, cx + 1));
-        face_vjp_cart<R, DIM>(a, 0, dx0, q, pv(NC, cx + 1), pv(NC, cx + 2), nu, fl, C, dkL, dkR);
+        face_vjp_cart<R, DIM, LIM>(a, 0, dx0, q, pv(NC, cx + 1), pv(NC, cx + 2), nu, fl, C, dkL, dkR);
       }
       for (int p = 0; p < 4; ++p)
         for (int v = 0; v < NC; ++v) cxr(p, v, cx) = C[p][v];
@@ -313,26 +315,17 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k
   }
 }
 
-// Fold the ghost-zone adjoints of direction d into the zones they copy.  One thread per
-// (candidate destination zone along d, plane, group); the four ghost entries are visited in
-// a fixed order.
+// Ghost-zone adjoints of direction d that fold into zone dst along d (plane index pidx in the
+// plane normal to d): the four ghost entries visited in a fixed order through the boundary
+// rule.  Returns whether any ghost copies dst.
 template <typename S, int ND>
-__global__ void __launch_bounds__(256) k_adj_fold(AdjArgs<S> a, int d) {
+__device__ bool fold_sum(const AdjArgs<S>& a, int d, int dst, int pidx, int grp, double acc[4], double& dka) {
   constexpr int NC = 1 + ND;
   const int G = a.G;
   const int np = a.gplane[d];
-  const int id = blockIdx.x * 256 + threadIdx.x;
-  if (id >= 4 * np * G) return;
-  const int grp = id % G;
-  const int pidx = (id / G) % np;
-  const int cand = id / (G * np);
   const int nd = a.n[d];
-  const int cands[4] = {0, 1, nd - 2, nd - 1};
-  const int dst = cands[cand];
-  if (dst < 0 || dst >= nd) return;
-  for (int c2 = 0; c2 < cand; ++c2)
-    if (cands[c2] == dst) return;   // duplicate candidate (small n)
-  double acc[4] = {0, 0, 0, 0}, dka = 0.0;
+  for (int v = 0; v < 4; ++v) acc[v] = 0.0;
+  dka = 0.0;
   bool any = false;
   for (int side = 0; side < 2; ++side) {
     const int bc = side ? a.bc_hi[d] : a.bc_lo[d];
@@ -360,14 +353,57 @@ __global__ void __launch_bounds__(256) k_adj_fold(AdjArgs<S> a, int d) {
       any = true;
     }
   }
-  if (!any) return;
-  // zone-group index of (dst along d, pidx in the normal plane)
-  int zg;
-  if (ND == 1) {
-    zg = dst * G + grp;
-  } else {   // 2-D: d = 0 -> plane index is the row; d = 1 -> plane index is the column
-    zg = (d == 0) ? ((pidx * a.n[0] + dst) * G + grp) : ((dst * a.n[0] + pidx) * G + grp);
+  return any;
+}
+
+// k-th distinct zone index within two of either end of an axis of n zones (k < 4), or -1
+__device__ __forceinline__ int edge_zone(int k, int n) {
+  const int cands[4] = {0, 1, n - 2, n - 1};
+  const int z = cands[k];
+  if (z < 0 || z >= n) return -1;
+  for (int k2 = 0; k2 < k; ++k2)
+    if (cands[k2] == z) return -1;
+  return z;
+}
+
+__device__ __forceinline__ bool near_edge(int z, int n) { return z < 2 || z >= n - 2; }
+
+// Fold the ghost-zone adjoints into the zones they copy, both directions in one launch.  One
+// thread per (edge zone along d, plane, group): threads of direction 0 take the zones away
+// from the y edges; a thread of direction 1 whose zone is also near an x edge applies the x
+// fold first, then its own, so that every zone sees the same additions, in the same order,
+// as with one launch per direction.
+template <typename S, int ND>
+__global__ void __launch_bounds__(256) k_adj_fold(AdjArgs<S> a) {
+  constexpr int NC = 1 + ND;
+  const int G = a.G;
+  const int n0 = a.n[0];
+  const int n1 = (ND >= 2) ? a.n[1] : 1;
+  const int nx = 4 * a.gplane[0] * G;
+  int id = blockIdx.x * 256 + threadIdx.x;
+  int d = 0;
+  if (id >= nx) {
+    if (ND < 2) return;
+    id -= nx;
+    d = 1;
+    if (id >= 4 * a.gplane[1] * G) return;
   }
+  const int np = a.gplane[d];
+  const int grp = id % G;
+  const int pidx = (id / G) % np;
+  const int dst = edge_zone(id / (G * np), a.n[d]);
+  if (dst < 0) return;
+  // zone (x, y) of this thread
+  const int x = (d == 0) ? dst : pidx;
+  const int y = (ND < 2) ? 0 : ((d == 0) ? pidx : dst);
+  if (ND >= 2 && d == 0 && near_edge(y, n1)) return;   // folded by the direction-1 thread
+  const int zg = (y * n0 + x) * G + grp;
+  double acc[4], dka;
+  if (ND >= 2 && d == 1 && near_edge(x, n0) && fold_sum<S, ND>(a, 0, x, y, grp, acc, dka)) {
+    for (int v = 0; v < NC; ++v) a.lamo[v][zg] = (S)((double)a.lamo[v][zg] + acc[v]);
+    a.dk[zg] = (S)((double)a.dk[zg] + dka);
+  }
+  if (!fold_sum<S, ND>(a, d, dst, pidx, grp, acc, dka)) return;
   for (int v = 0; v < NC; ++v) a.lamo[v][zg] = (S)((double)a.lamo[v][zg] + acc[v]);
   a.dk[zg] = (S)((double)a.dk[zg] + dka);
 }
@@ -469,17 +505,26 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
   if (tl.TXB * D.ngroups > 512) return FORNAX_EUNSUPPORTED;
   const size_t lds = adj_lds_bytes(tl, D.ndim, D.ngroups, sizeof(R));
   if (lds > 65536) return FORNAX_EUNSUPPORTED;
-  if (D.ndim == 1)
-    hipLaunchKernelGGL((k_adjoint<S, R, 1>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a, geo, tl);
+  // the method's default limiter is a compile-time constant of its own instantiation
+  const bool mm = D.limiter == FORNAX_LIMITER_MINMOD;
+  if (D.ndim == 1 && mm)
+    hipLaunchKernelGGL((k_adjoint<S, R, 1, FORNAX_LIMITER_MINMOD>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a,
+                       geo, tl);
+  else if (D.ndim == 1)
+    hipLaunchKernelGGL((k_adjoint<S, R, 1, -1>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a, geo, tl);
+  else if (mm)
+    hipLaunchKernelGGL((k_adjoint<S, R, 2, FORNAX_LIMITER_MINMOD>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a,
+                       geo, tl);
   else
-    hipLaunchKernelGGL((k_adjoint<S, R, 2>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a, geo, tl);
+    hipLaunchKernelGGL((k_adjoint<S, R, 2, -1>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a, geo, tl);
   if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
-  for (int d = 0; d < D.ndim; ++d) {
-    const int nt = 4 * a.gplane[d] * a.G;
+  {
+    int nt = 4 * a.gplane[0] * a.G;
+    if (D.ndim >= 2) nt += 4 * a.gplane[1] * a.G;
     if (D.ndim == 1)
-      hipLaunchKernelGGL((k_adj_fold<S, 1>), dim3((nt + 255) / 256), dim3(256), 0, st, a, d);
+      hipLaunchKernelGGL((k_adj_fold<S, 1>), dim3((nt + 255) / 256), dim3(256), 0, st, a);
     else
-      hipLaunchKernelGGL((k_adj_fold<S, 2>), dim3((nt + 255) / 256), dim3(256), 0, st, a, d);
+      hipLaunchKernelGGL((k_adj_fold<S, 2>), dim3((nt + 255) / 256), dim3(256), 0, st, a);
     if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
   }
   return FORNAX_OK;

@@ -24,32 +24,30 @@ struct ReconRec {
 
 template <typename R>
 __device__ __forceinline__ void minmod_sel(R a, R b, R& s, signed char& which) {
-  if (a * b <= R(0)) {
-    s = R(0);
-    which = 0;
-  } else if (fabs(a) <= fabs(b)) {
-    s = a;
-    which = 1;
-  } else {
-    s = b;
-    which = 2;
-  }
+  // selects, not branches: the choice differs from lane to lane
+  const bool same = a * b > R(0);
+  const bool first = fabs(a) <= fabs(b);
+  s = same ? (first ? a : b) : R(0);
+  which = same ? (first ? 1 : 2) : 0;
 }
 
-template <typename R, int ND>
+// LIM: the limiter when known at compile time (a FORNAX_LIMITER_* value), -1 to read it from
+// the arguments.
+template <typename R, int ND, int LIM = -1>
 __device__ __forceinline__ void reconstruct_rec(const StepArgsBase& a, const R qm[4], const R q0[4], const R qp[4],
                                                 bool lo_open, bool hi_open, ReconRec<R, ND>& rr) {
   const R c = R(a.c);
+  const int limiter = (LIM >= 0) ? LIM : a.limiter;
   const R one[3] = {R(1), R(1), R(1)};
   R s[4];
   for (int cp = 0; cp <= ND; ++cp) {
     const R dm = q0[cp] - qm[cp], dp = qp[cp] - q0[cp];
     rr.fac[cp] = R(1);
-    if (a.limiter == FORNAX_LIMITER_MINMOD) {
+    if (limiter == FORNAX_LIMITER_MINMOD) {
       signed char w;
       minmod_sel(dm, dp, s[cp], w);
       rr.sel[cp] = w;
-    } else if (a.limiter == FORNAX_LIMITER_MC) {
+    } else if (limiter == FORNAX_LIMITER_MC) {
       // minmod(2 dm, minmod(2 dp, (dm + dp)/2))
       R inner;
       signed char wi, wo;
@@ -169,13 +167,13 @@ __device__ __forceinline__ void closure_row_vjp(const R q[4], int d, R c, int ed
 // total opacities of zones f-1, f, face adjoint nu (the adjoint of the face flux).  Outputs
 // the forward flux, the contributions C[p] to the adjoints of the four stencil zones and the
 // adjoint contributions to kappa of zones f-1 (dkL) and f (dkR) through epsilon.
-template <typename R, int ND>
+template <typename R, int ND, int LIM = -1>
 __device__ __forceinline__ void face_vjp_cart(const StepArgsBase& a, int d, R dx, const R q[4][4], R ksL, R ksR,
                                               const R nu[4], R flux[4], R C[4][4], R& dkL, R& dkR) {
   const R c = R(a.c);
   ReconRec<R, ND> rl, rr;
-  reconstruct_rec<R, ND>(a, q[0], q[1], q[2], true, true, rl);
-  reconstruct_rec<R, ND>(a, q[1], q[2], q[3], true, true, rr);
+  reconstruct_rec<R, ND, LIM>(a, q[0], q[1], q[2], true, true, rl);
+  reconstruct_rec<R, ND, LIM>(a, q[1], q[2], q[3], true, true, rr);
   const R* qL = rl.hi;
   const R* qR = rr.lo;
   // epsilon
