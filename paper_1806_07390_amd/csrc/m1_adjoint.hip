@@ -47,28 +47,25 @@ struct AdjTile {
   int nthreads;
 };
 
-// mu = (dS/dU^-)^T lam and the source part of dkappa, for an in-domain zone-group, in double
+// mu = (dS/dU^-)^T lam for an in-domain zone-group, in double: the interaction update divides
+// E by 1 + c dt kappa and F by 1 + c dt (kappa + sigma)
 template <typename S, int ND>
-__device__ __forceinline__ void source_adjoint(const AdjArgs<S>& a, int zg, const double lam[4], double mu[4],
-                                               const double* U1, double& dk_src) {
-  const double kd = (double)a.kap[zg], sd = (double)a.sig[zg], Bd = (double)a.B[zg];
+__device__ __forceinline__ void source_adjoint(const AdjArgs<S>& a, int zg, const double lam[4], double mu[4]) {
+  const double kd = (double)a.kap[zg], sd = (double)a.sig[zg];
   const double cdt = a.c * a.dt;
-  const double aE = rcp_(1.0 + cdt * kd), aF = rcp_(1.0 + cdt * (kd + sd));
-  mu[0] = lam[0] * aE;
-  for (int k = 0; k < ND; ++k) mu[1 + k] = lam[1 + k] * aF;
-  if (U1) {
-    double s = cdt * aE * lam[0] * (Bd - U1[0]);
-    for (int k = 0; k < ND; ++k) s -= cdt * aF * lam[1 + k] * U1[1 + k];
-    dk_src = s;
-  }
+  // one reciprocal for both denominators
+  const double dE = 1.0 + cdt * kd, dF = 1.0 + cdt * (kd + sd);
+  const double rr = rcp_(dE * dF);
+  mu[0] = lam[0] * (dF * rr);
+  for (int k = 0; k < ND; ++k) mu[1 + k] = lam[1 + k] * (dE * rr);
 }
 
 template <typename S, typename R, int DIM>
 __device__ __forceinline__ void load_mu(const AdjArgs<S>& a, int zg, R mu[4]) {
-  double lam[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0}, dummy = 0.0;
+  double lam[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0};
   lam[0] = (double)a.lam[0][zg];
   for (int k = 0; k < DIM; ++k) lam[1 + k] = (double)a.lam[1 + k][zg];
-  source_adjoint<S, DIM>(a, zg, lam, m, nullptr, dummy);
+  source_adjoint<S, DIM>(a, zg, lam, m);
   for (int k = 0; k < 4; ++k) mu[k] = (R)m[k];
 }
 
@@ -274,14 +271,15 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
         }
       }
       if (colin && rowin) {
-        // U^{n+1} of this zone (written by the forward step) for the source derivative
+        // mu of this zone (staged in LDS) and U^{n+1} for the source derivative:
+        //   dkappa_src = c dt [mu_E (B - E^{n+1}) - sum_k mu_Fk F_k^{n+1}]
+        // (mu_E = lam_E / (1 + c dt kappa), mu_F = lam_F / (1 + c dt (kappa + sigma)))
         const int zg = zgi(gx, m);
-        double U1[4] = {0, 0, 0, 0};
-        for (int v = 0; v < NC; ++v) U1[v] = (double)a.U1[v][zg];
-        double lam[4] = {0, 0, 0, 0}, mu[4] = {0, 0, 0, 0}, dk_src = 0.0;
-        lam[0] = (double)a.lam[0][zg];
-        for (int k = 0; k < DIM; ++k) lam[1 + k] = (double)a.lam[1 + k][zg];
-        source_adjoint<S, DIM>(a, zg, lam, mu, U1, dk_src);
+        double mu[4] = {0, 0, 0, 0};
+        for (int v = 0; v < NC; ++v) mu[v] = (double)pv(NC + 1 + v, cx + 3);
+        double sdk = mu[0] * ((double)a.B[zg] - (double)a.U1[0][zg]);
+        for (int k = 0; k < DIM; ++k) sdk -= mu[1 + k] * (double)a.U1[1 + k][zg];
+        const double dk_src = (a.c * a.dt) * sdk;
         for (int v = 0; v < NC; ++v) a.lamo[v][zg] = (S)(mu[v] + (double)gsum[v]);
         a.dk[zg] = (S)((double)a.dk[zg] + dk_src + (double)dks);
       } else if (colin != rowin) {

@@ -86,27 +86,18 @@ __device__ __forceinline__ void reconstruct_rec(const StepArgsBase& a, const R q
 template <typename R, int ND>
 __device__ __forceinline__ void reconstruct_vjp(const ReconRec<R, ND>& rr, const R glo[4], const R ghi[4], R gm[4],
                                                 R g0[4], R gp[4]) {
+  // with selects, not branches (the selector differs from lane to lane):
+  //   sel 1: s = fac (q0 - qm);  sel 2: s = fac (qp - q0);  sel 3: s = (qp - qm)/2
   for (int cp = 0; cp <= ND; ++cp) {
-    g0[cp] += glo[cp] + ghi[cp];
-    if (!rr.ok) continue;
-    const R gs = R(0.5) * (ghi[cp] - glo[cp]);   // lo = q0 - s/2, hi = q0 + s/2
+    const R gs = rr.ok ? R(0.5) * (ghi[cp] - glo[cp]) : R(0);   // lo = q0 - s/2, hi = q0 + s/2
     const R gf = gs * rr.fac[cp];
-    switch (rr.sel[cp]) {
-      case 1:  // s = fac (q0 - qm)
-        g0[cp] += gf;
-        gm[cp] -= gf;
-        break;
-      case 2:  // s = fac (qp - q0)
-        gp[cp] += gf;
-        g0[cp] -= gf;
-        break;
-      case 3:  // s = (qp - qm)/2
-        gp[cp] += R(0.5) * gs;
-        gm[cp] -= R(0.5) * gs;
-        break;
-      default:
-        break;
-    }
+    const int sel = rr.sel[cp];
+    const R hm = (sel == 1) ? -gf : ((sel == 3) ? R(-0.5) * gs : R(0));
+    const R h0 = (sel == 1) ? gf : ((sel == 2) ? -gf : R(0));
+    const R hp = (sel == 2) ? gf : ((sel == 3) ? R(0.5) * gs : R(0));
+    g0[cp] += (glo[cp] + ghi[cp]) + h0;
+    gm[cp] += hm;
+    gp[cp] += hp;
   }
 }
 
@@ -148,7 +139,10 @@ __device__ __forceinline__ void closure_row_vjp(const R q[4], int d, R c, int ed
     return;
   }
   const R s = sqrt_(R(4) - R(3) * f2);
-  const R i1s = rcp_(R(1) + s), i2s = rcp_(R(2) + s), is = rcp_(s);
+  // 1/s, 1/(1 + s), 1/(2 + s) from one reciprocal of s (1 + s)(2 + s)
+  const R s1 = R(1) + s, s2 = R(2) + s;
+  const R rall = rcp_(s * s1 * s2);
+  const R i1s = s * s2 * rall, i2s = s * s1 * rall, is = s1 * s2 * rall;
   const R A = (R(1) - f2) * i1s;
   const R Bc = R(3) * i2s;
   const R Ap = -i1s + (R(1) - f2) * (R(1.5) * is) * (i1s * i1s);
