@@ -34,7 +34,7 @@ def log(*a):
 # WRITE_SIZE counters scaled by the copy-kernel calibration (see the file); it applies only
 # while the kernel sources are the ones it was measured on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_blobs2d_512x512x16_fp64_traffic.json")
-KERNEL_SOURCES = ["m1_step.hip", "m1_device.h", "m1_internal.h"]
+KERNEL_SOURCES = ["m1_step_rows.hip", "m1_device.h", "m1_internal.h"]
 
 
 def kernel_source_digest():
@@ -292,7 +292,7 @@ def main():
                    "zone_groups": w.zone_groups, "dt": w.dt},
         "roofline": {"bound": "hbm", "achieved": round(h["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(h["achieved"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "k_step_tiled<double, double, 2, false, true, 4>", "bytes_per_zone_group": h["bpz"],
+                     "kernel": "k_step_rows<double, 0, 1>", "bytes_per_zone_group": h["bpz"],
                      "kernel_ms": round(h["ms_kernel"], 5)},
         "extra": extra,
     }

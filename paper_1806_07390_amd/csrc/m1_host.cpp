@@ -376,6 +376,14 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
       if (t.nblocks > 0 && t.V == 1) ctx->tile_v1 = t;
     }
   }
+  // the whole-zone kernel where the grid qualifies (FORNAX_M1_ROWS="0" disables it,
+  // "NWX,TM" picks its tiling)
+  ctx->rows = choose_rows_tile(*desc);
+  if (const char* env = std::getenv("FORNAX_M1_ROWS")) {
+    int nwx = 0, tm = 0;
+    if (env[0] == '0' && env[1] == 0) ctx->rows = fm1::RowsTile{};
+    else if (std::sscanf(env, "%d,%d", &nwx, &tm) == 2) ctx->rows = make_rows_tile(*desc, nwx, tm);
+  }
   if (ctx->tile.nblocks <= 0) {
     (void)hipFree(ctx->geo_mem);
     delete ctx;
@@ -386,7 +394,8 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   int zpb = BLOCK / desc->ngroups;
   int64_t nz = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
   ctx->nblocks_step = (int)((nz + zpb - 1) / zpb);
-  size_t nb = (size_t)std::max(ctx->nblocks_step, std::max(ctx->tile_v1.nblocks, ctx->tile.nblocks));
+  size_t nb = (size_t)std::max(std::max(ctx->nblocks_step, ctx->rows.nblocks),
+                               std::max(ctx->tile_v1.nblocks, ctx->tile.nblocks));
   // dE_matter partials when a tile splits the groups of a zone over several blocks
   const size_t ngbm = (size_t)std::max(ctx->tile.ngb, ctx->tile_v1.ngb);
   const size_t dzp_bytes = ngbm > 1 ? ngbm * (size_t)nz * sizeof(double) : 0;

@@ -125,6 +125,15 @@ struct Tile {
   int nthreads;        // 64 NW (1-D/2-D) or TXB * TYB * GB (3-D)
   size_t lds;          // dynamic LDS bytes per block (with the dE_matter buffer)
 };
+// Tiling of the 2-D, 16-group step kernel that streams whole zones through LDS
+// (m1_step_rows.hip): NWX wave rows of 16 zone columns (4 NWX waves), TM planes per block.
+struct RowsTile {
+  int NWX, TXB, TM;
+  int ntx, ntm, nblocks;
+  int xq, xr;
+  int nthreads;
+  size_t lds;          // static LDS bytes per block
+};
 }  // namespace fm1
 
 struct fornax_m1_ctx {
@@ -138,6 +147,7 @@ struct fornax_m1_ctx {
   double max_dt1;             // max_dt(cfl = 1)
   fm1::Tile tile;              // tiling of the fused step kernel
   fm1::Tile tile_v1;           // one group per lane (arrays not aligned to pairs of groups)
+  fm1::RowsTile rows;          // the whole-zone LDS kernel when nblocks > 0 (2-D, 16 groups)
   fm1::Tile last_tile[1];      // the tile of the last step launch (for inspection)
   // reduction scratch (one partial per block of the step kernel)
   int nblocks_step;

@@ -24,40 +24,51 @@
 
 namespace fm1 {
 
-// second stage of the diagnostics reduction: fixed order, one block
-__global__ void __launch_bounds__(BLOCK) k_finalize(const double* p_energy, const double* p_maxf2, const int* p_nun,
-                                                     const int* p_nnp, int nb, double* energy, double* maxf,
-                                                     int* nun, int* nnp) {
-  __shared__ double sa[BLOCK], sb[BLOCK];
-  __shared__ int su[BLOCK], sp[BLOCK];
+// second stage of the diagnostics reduction: one block of 1024 threads, each summing a fixed
+// stride of the block partials (independent loads in flight), then the waves in order
+// (deterministic, no atomics)
+constexpr int FIN_THREADS = 1024;
+__global__ void __launch_bounds__(FIN_THREADS) k_finalize(const double* p_energy, const double* p_maxf2,
+                                                           const int* p_nun, const int* p_nnp, int nb, double* energy,
+                                                           double* maxf, int* nun, int* nnp) {
+  __shared__ double sa[FIN_THREADS / 64], sb[FIN_THREADS / 64];
+  __shared__ int su[FIN_THREADS / 64], sp[FIN_THREADS / 64];
   const int t = threadIdx.x;
   double ea = 0.0, mb = 0.0;
   int ua = 0, pa = 0;
-  for (int b = t; b < nb; b += BLOCK) {
+#pragma unroll 4
+  for (int b = t; b < nb; b += FIN_THREADS) {
     ea += p_energy[b];
     mb = fmax(mb, p_maxf2[b]);
     ua += p_nun[b];
     pa += p_nnp[b];
   }
-  sa[t] = ea;
-  sb[t] = mb;
-  su[t] = ua;
-  sp[t] = pa;
-  __syncthreads();
-  for (int s = BLOCK / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      sa[t] += sa[t + s];
-      sb[t] = fmax(sb[t], sb[t + s]);
-      su[t] += su[t + s];
-      sp[t] += sp[t + s];
-    }
-    __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) {
+    ea += __shfl_xor(ea, off);
+    mb = fmax(mb, __shfl_xor(mb, off));
+    ua += __shfl_xor(ua, off);
+    pa += __shfl_xor(pa, off);
   }
+  if ((t & 63) == 0) {
+    sa[t >> 6] = ea;
+    sb[t >> 6] = mb;
+    su[t >> 6] = ua;
+    sp[t >> 6] = pa;
+  }
+  __syncthreads();
   if (t == 0) {
-    if (energy) *energy = sa[0];
-    if (maxf) *maxf = sqrt(sb[0]);
-    if (nun) *nun = su[0];
-    if (nnp) *nnp = sp[0];
+    double e = 0.0, m = 0.0;
+    int u = 0, p = 0;
+    for (int k = 0; k < FIN_THREADS / 64; ++k) {
+      e += sa[k];
+      m = fmax(m, sb[k]);
+      u += su[k];
+      p += sp[k];
+    }
+    if (energy) *energy = e;
+    if (maxf) *maxf = sqrt(m);
+    if (nun) *nun = u;
+    if (nnp) *nnp = p;
   }
 }
 
@@ -213,7 +224,8 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
     if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
   }
   if (want) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, ctx->p_energy, ctx->p_maxf2, ctx->p_nun, ctx->p_nnp, nb,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, st, ctx->p_energy, ctx->p_maxf2, ctx->p_nun,
+                       ctx->p_nnp, nb,
                        diag->energy_total, diag->max_f, diag->n_unrealizable, diag->n_nonpositive);
     if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
   }

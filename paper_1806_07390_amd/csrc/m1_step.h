@@ -16,10 +16,18 @@ Tile choose_tile(const fornax_m1_desc& D, int V);
 // Raise the dynamic LDS limit of every step-kernel instantiation (once per process).
 int prepare_step_kernels();
 
-// Launch the step kernel with the context's tile for these arguments (all groups per block
-// when dE_matter is asked for; single groups per lane when an array is not aligned to two
+// Launch the step kernel with the context's tile for these arguments (the whole-zone kernel
+// when the context has one; single groups per lane when an array is not aligned to two
 // elements).
 template <typename S, typename R>
 int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, hipStream_t st);
+
+// The 2-D, 16-group kernel with whole-zone transfers through LDS (m1_step_rows.hip): a tile
+// with nblocks = 0 when the grid does not qualify (2-D Cartesian, 16 groups, arrays under
+// 2 GiB; NWX in {1, 2}; TM a multiple of 3).
+RowsTile make_rows_tile(const fornax_m1_desc& D, int NWX, int TM);
+RowsTile choose_rows_tile(const fornax_m1_desc& D);
+template <typename S>
+int launch_rows(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipStream_t st);
 
 }  // namespace fm1

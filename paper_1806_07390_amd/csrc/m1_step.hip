@@ -985,6 +985,8 @@ static bool aligned_to(const void* p, size_t n) { return p == nullptr || ((uintp
 
 template <typename S, typename R>
 int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, hipStream_t st) {
+  if constexpr (std::is_same<S, R>::value)
+    if (ctx->rows.nblocks > 0) return launch_rows<S>(ctx, geo, a, st);
   const bool sph = ctx->desc.coord == FORNAX_SPHERICAL_LOGR;
   const int D = ctx->desc.ndim;
   // pairs of groups per lane need arrays aligned to two elements

@@ -153,6 +153,69 @@ def test_tile_shapes(m1, case):
                 assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-5)
 
 
+def _rows_case(bc, n0=70, n1=40, G=16, steps=4):
+    """A 2-D, 16-group grid of the whole-zone kernel's kind: 70 columns (three tiles of 30 with a
+    ragged tail) by 40 rows (planes per block not dividing it)."""
+    w = wl.blobs2d(n=n0, G=G, steps=steps)
+    w.E = np.ascontiguousarray(w.E[:, :n1])
+    w.F = [np.ascontiguousarray(f[:, :n1]) for f in w.F]
+    w.kappa = np.ascontiguousarray(w.kappa[:, :n1])
+    w.sigma = np.ascontiguousarray(w.sigma[:, :n1])
+    w.B = np.ascontiguousarray(w.B[:, :n1])
+    w.n = (n0, n1, 1)
+    if bc == "outflow_reflect":
+        w.bc_lo = (wl.BC_REFLECT, wl.BC_OUTFLOW, 0)
+        w.bc_hi = (wl.BC_OUTFLOW, wl.BC_REFLECT, 0)
+    elif bc == "inflow":
+        w.bc_lo = (wl.BC_INFLOW, wl.BC_REFLECT, 0)
+        w.bc_hi = (wl.BC_OUTFLOW, wl.BC_OUTFLOW, 0)
+        rng = np.random.default_rng(7)
+        w.inflow = np.zeros((G, 3))
+        w.inflow[:, 0] = rng.uniform(0.2, 1.0, G)
+        w.inflow[:, 1] = 0.6 * w.c * w.inflow[:, 0]
+        w.inflow[:, 2] = -0.2 * w.c * w.inflow[:, 0]
+    return w
+
+
+@pytest.mark.parametrize("bc", ["periodic", "outflow_reflect", "inflow"])
+@pytest.mark.parametrize("lim", ["minmod", "mc"])
+def test_whole_zone_kernel(m1, bc, lim):
+    """The 2-D, 16-group kernel that moves whole zones through LDS gives the oracle's result and
+    that of the tiled kernel (FORNAX_M1_ROWS selects either: "NWX,TM" the whole-zone kernel,
+    "0" the tiled one), in both precisions: the same arithmetic in the same order, up to where
+    the compiler fuses a multiply and an add."""
+    import os
+    code = {"minmod": m1.LIMITER_MINMOD, "mc": m1.LIMITER_MC}[lim]
+    w = _rows_case(bc)
+    p = problem_of(w, limiter=code)
+    dt = dt_of(w, p)
+    E, F, dg, dEm = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow, want_dEm=True)
+    for prec, tol in ((m1.FP64, TOL_FP64), (m1.MIXED, TOL_MIXED_RUN)):
+        say(f"whole-zone kernel bc={bc} lim={lim} prec={prec}")
+        ctxs = []
+        for rows in ("1,9", "0"):
+            os.environ["FORNAX_M1_ROWS"] = rows
+            try:
+                ctxs.append(m1.Context(m1.Config.from_workload(w, precision=prec, limiter=code)))
+            finally:
+                del os.environ["FORNAX_M1_ROWS"]
+        ctx, ctx_t = ctxs
+        Eg, Fg, dgg = gpu_run(ctx, w, dt, w.steps, diag=True)
+        Et, Ft, dgt = gpu_run(ctx_t, w, dt, w.steps, diag=True)
+        eE, eF = rel_l1(Eg, Fg, E, F, w.c)
+        say("   ", eE, eF)
+        assert eE <= tol and eF <= tol
+        tE, tF = rel_l1(Eg, Fg, Et, Ft, w.c)
+        say("    vs tiled", tE, tF)
+        close = 1e-14 if prec == m1.FP64 else 1e-6
+        assert tE <= close and tF <= close
+        assert np.allclose(dgg["dE_matter"], dgt["dE_matter"], rtol=0, atol=close * np.abs(Et).max())
+        assert dgg["energy_total"][0] == pytest.approx(dgt["energy_total"][0], rel=close)
+        assert dgg["max_f"][0] == pytest.approx(dgt["max_f"][0], rel=close)
+        if prec == m1.FP64:
+            assert np.allclose(dgg["dE_matter"], dEm, rtol=1e-10, atol=1e-12 * np.abs(E).max())
+
+
 # ------------------------------------------------------------------------------------------
 def test_flux_and_source_entry_points(m1):
     w = wl.sphere3d(nr=12, nth=8, nph=8, G=3, steps=1)
