@@ -42,7 +42,8 @@ struct RowsLds {
   static constexpr int EPC = 16 / (int)sizeof(S);      // elements per 16-byte chunk
   static constexpr int CPZ = RG / EPC;                 // chunks per zone
   static constexpr int SLOT = RNA * NCOL * RG;         // elements per slot
-  static constexpr int GS = RG + EPC;                  // padded group stride of the exchange arrays
+  static constexpr int ROT = 4 / EPC > 0 ? 4 / EPC : 1; // chunks of a zone that one wave row reads
+  static constexpr int GS = RG + 4;                    // padded group stride of the exchange arrays
   static constexpr int XCH = RNC * TXB * GS;           // elements per exchange array
 };
 
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(64 * 4 * NWX) __attribute__((amdgpu_waves_per_
 k_step_rows(StepArgs<S> a, Geo<S> geo, RowsTile tl) {
   using R = S;
   using L = RowsLds<S, NWX>;
-  constexpr int TXB = L::TXB, NCOL = L::NCOL, EPC = L::EPC, CPZ = L::CPZ, GS = L::GS;
+  constexpr int TXB = L::TXB, NCOL = L::NCOL, EPC = L::EPC, CPZ = L::CPZ, GS = L::GS, ROT = L::ROT;
   constexpr int NW = 4 * NWX;                      // waves
   constexpr int NT = 64 * NW;                      // threads
   constexpr int NI = (NCOL * CPZ + 63) / 64;      // wave loads of 64 16-byte chunks per array
@@ -135,10 +136,12 @@ k_step_rows(StepArgs<S> a, Geo<S> geo, RowsTile tl) {
   if ((xf_m | xf_o | xf_p) & 2)
     for (int k = 0; k < 3; ++k) qin[k] = R(a.inflow[g * 3 + k]);
 
-  // element of (array, LDS column, group) in a slot: each zone's chunks are rotated by its
-  // column so that the lanes of a wave (16 columns) spread over the LDS banks
+  // element of (array, LDS column, group) in a slot: each zone's chunks are rotated by ROT
+  // per pair of columns, so that the chunks a wave row reads from 8 consecutive columns fall
+  // on distinct banks of gfx950's 64 (measured: a third of the conflicts of a rotation per
+  // column)
   auto ridx = [&](int arr, int jc, int gg) -> int {
-    return ((arr * NCOL + jc) * CPZ + ((gg / EPC + jc) % CPZ)) * EPC + gg % EPC;
+    return ((arr * NCOL + jc) * CPZ + ((gg / EPC + ROT * (jc >> 1)) % CPZ)) * EPC + gg % EPC;
   };
   auto slot_ptr = [&](int s) -> S* { return s == 0 ? ring0 : (s == 1 ? ring1 : ring2); };
   auto arr_ptr = [&](int arr) -> const S* {
@@ -164,7 +167,7 @@ k_step_rows(StepArgs<S> a, Geo<S> geo, RowsTile tl) {
     xv[k] = J < RNA * NI && r < NCOL * CPZ;
     const int rr = xv[k] ? r : 0;
     const int jc = rr / CPZ;
-    const int part = (rr - jc * CPZ - jc % CPZ + 2 * CPZ) % CPZ;   // inverse of the rotation
+    const int part = (rr - jc * CPZ + CPZ * ROT * NCOL - ROT * (jc >> 1)) % CPZ;   // inverse of the rotation
     int xsrc, xfl;
     x_rule(a, min(x0 - 1 + jc, n0 + 1), xsrc, xfl);
     (void)xfl;
@@ -436,9 +439,9 @@ k_step_rows(StepArgs<S> a, Geo<S> geo, RowsTile tl) {
 // ------------------------------------------------------------------------------------------
 size_t rows_lds_bytes(const fornax_m1_desc& D, int NWX) {
   const size_t s = (D.precision == FORNAX_FP64) ? 8 : 4;
-  const size_t epc = 16 / s, txb = 16 * (size_t)NWX;
+  const size_t txb = 16 * (size_t)NWX;
   const size_t slot = RNA * (txb + 2) * RG * s;
-  const size_t xch = RNC * txb * (RG + epc) * s;
+  const size_t xch = RNC * txb * (RG + 4) * s;
   return 3 * slot + 2 * xch + 4 * txb * 8 + 16 * 24;
 }
 
