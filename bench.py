@@ -33,7 +33,7 @@ def log(*a):
 # HBM traffic of the step kernel on the headline workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counters scaled by the copy-kernel calibration (see the file); it applies only
 # while the kernel sources are the ones it was measured on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_blobs2d_512x512x16_fp64_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_rows_blobs2d_512x512x16_fp64_traffic.json")
 KERNEL_SOURCES = ["m1_step_rows.hip", "m1_device.h", "m1_internal.h"]
 
 
@@ -199,7 +199,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", default=None, help="profiling: run only this workload's timed loop")
+    ap.add_argument("--only", default=None,
+                    help="profiling: run only this workload's timed loop (blobs2d, core3d, sphere3d, adjoint, "
+                         "extras = the three after blobs2d, copy = the copy probe alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU path; "
@@ -234,7 +236,7 @@ def main():
     extra = {}
     if not args.no_extra:
         # ---- 3-D 192^3 x 12: FP64 vs MIXED -------------------------------------------------
-        if args.only in (None, "core3d"):
+        if args.only in (None, "extras", "core3d"):
             w3 = wl.core3d()
             for prec, name, dt_, el in ((m1.FP64, "fp64", torch.float64, 8), (m1.MIXED, "mixed", torch.float32, 4)):
                 ctx = m1.Context(m1.Config.from_workload(w3, precision=prec))
@@ -249,7 +251,7 @@ def main():
                 torch.cuda.empty_cache()
             del w3
         # ---- spherical 256x64x128 x 20 MIXED -----------------------------------------------
-        if args.only in (None, "sphere3d"):
+        if args.only in (None, "extras", "sphere3d"):
             w4 = wl.sphere3d()
             for prec, name, dt_, el in ((m1.MIXED, "mixed", torch.float32, 4), (m1.FP64, "fp64", torch.float64, 8)):
                 ctx = m1.Context(m1.Config.from_workload(w4, precision=prec))
@@ -264,7 +266,7 @@ def main():
                 del ctx, inp
                 torch.cuda.empty_cache()
             del w4
-        if args.only in (None, "adjoint"):
+        if args.only in (None, "extras", "adjoint"):
             extra["adjoint"] = adjoint_ratios()
             log("  adjoint:", extra["adjoint"])
         copy_gbs, copy_ms = copy_bandwidth()

@@ -86,6 +86,21 @@ def test_core3d_reduced_fp64_and_mixed(m1):
     assert eEn <= TOL_MIXED_RUN and eFn <= TOL_MIXED_RUN
 
 
+@pytest.mark.parametrize("case", ["blobs2d", "core3d", "sphere3d"])
+def test_mixed_after_100_steps(m1, case):
+    """FP32 bulk with FP64 where the error concentrates stays within 1e-4 (rel-L1) of the FP64
+    oracle after 100 steps, at reduced sizes of the three workloads."""
+    if case == "blobs2d":
+        w = wl.blobs2d(n=48, G=16, steps=100)
+    elif case == "core3d":
+        w = wl.core3d(n=20, G=12, steps=100)
+    else:
+        w = wl.sphere3d(nr=24, nth=16, nph=16, G=4, steps=100)
+    eE, eF = run_pair(m1, w, m1.MIXED, 100)
+    say(f"{case} mixed after 100 steps", eE, eF)
+    assert eE <= TOL_MIXED_RUN and eF <= TOL_MIXED_RUN
+
+
 def test_sphere_reduced_fp64_and_mixed(m1):
     w = wl.sphere3d(nr=24, nth=16, nph=16, G=4, steps=20)
     eE, eF = run_pair(m1, w, m1.FP64, w.steps)
