@@ -74,8 +74,10 @@ struct OrcDesc {
   int32_t eps_mode;   // 0 = eq:epsilon as in the paper; 1 = epsilon forced to 1 (plain HLL)
   double c;           // (reduced) speed of light
   int32_t nthreads;   // OpenMP threads (0 = runtime default)
+  int32_t integrator; // OI_EULER (default): one forward-Euler push; OI_SSPRK2: Shu-Osher RK2
 };
 }
+enum { OI_EULER = 0, OI_SSPRK2 = 1 };
 
 static const int NG = 2;  // ghost layers required by linear reconstruction
 
@@ -550,16 +552,62 @@ static void implicit_source(T E_m, const T F_m[3], T kap, double sig, double B, 
     F1[k] = (k < ndim) ? F_m[k] / (T(1.0) + T(c * dt) * (kap + T(sig))) : T(0.0);
 }
 
+// The interaction update of one zone-group from its explicitly updated state U^-.
 template <class T>
-static void zone_step(const Ctx<T>& C, const int idx[3], int g, T Un1[4], T* Em_out) {
-  T Um[4];
-  explicit_update(C, idx, g, Um);
+static void source_of(const Ctx<T>& C, const int idx[3], int g, const T Um[4], T Un1[4]) {
   size_t zg = C.zone(idx) * C.G + g;
   T Fm[3] = {Um[1], Um[2], Um[3]}, F1[3];
   T E1;
   implicit_source(Um[0], Fm, C.kap[zg], C.sig[zg], C.B[zg], C.c, C.dt, C.ndim, E1, F1);
   Un1[0] = E1;
   for (int k = 0; k < 3; ++k) Un1[1 + k] = F1[k];
+}
+
+// One step of one zone-group with the forward-Euler push: U^- = U^n + dt L(U^n), then the
+// interaction update.
+template <class T>
+static void zone_step(const Ctx<T>& C, const int idx[3], int g, T Un1[4], T* Em_out) {
+  T Um[4];
+  explicit_update(C, idx, g, Um);
+  source_of(C, idx, g, Um, Un1);
+  if (Em_out) *Em_out = Um[0];
+}
+
+// The explicit part with Shu & Osher's second-order TVD Runge-Kutta scheme (Numerical
+// Discretization: the paper's explicit integrator; Algorithmic Steps: the Euler push is its
+// first-order case), written as
+//   U* = U^n + dt L(U^n),   U^- = (U^n + (U* + dt L(U*))) / 2,
+// with the stiff interaction update applied once, to U^-, as in the Euler push.
+// Stage 1 over every zone-group: U* into Es, Fs (boundary rules then apply to U* as to U^n).
+template <class T>
+static void rk2_stage1(const Ctx<T>& C, std::vector<T>& Es, std::vector<std::vector<T>>& Fs) {
+  long nz = (long)C.n[0] * C.n[1] * C.n[2];
+  Es.assign((size_t)nz * C.G, T(0.0));
+  Fs.assign(3, std::vector<T>());
+  for (int k = 0; k < C.ndim; ++k) Fs[k].assign((size_t)nz * C.G, T(0.0));
+#pragma omp parallel for schedule(static)
+  for (long z = 0; z < nz; ++z) {
+    int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
+    for (int g = 0; g < C.G; ++g) {
+      T Us[4];
+      explicit_update(C, idx, g, Us);
+      size_t zg = (size_t)z * C.G + g;
+      Es[zg] = Us[0];
+      for (int k = 0; k < C.ndim; ++k) Fs[k][zg] = Us[1 + k];
+    }
+  }
+}
+
+// Stage 2 of one zone-group from the stage-1 context C1 (state U*): U^- as above, then the
+// interaction update.  C holds U^n.
+template <class T>
+static void rk2_zone(const Ctx<T>& C, const Ctx<T>& C1, const int idx[3], int g, T Un1[4], T* Em_out) {
+  T Uss[4], Um[4];
+  explicit_update(C1, idx, g, Uss);
+  size_t zg = C.zone(idx) * C.G + g;
+  Um[0] = T(0.5) * (C.E[zg] + Uss[0]);
+  for (int k = 0; k < 3; ++k) Um[1 + k] = (k < C.ndim) ? T(0.5) * (C.F[k][zg] + Uss[1 + k]) : T(0.0);
+  source_of(C, idx, g, Um, Un1);
   if (Em_out) *Em_out = Um[0];
 }
 
@@ -603,12 +651,24 @@ static void full_step(const OrcDesc* D, const Geom& geo, const T* E, const T* co
   long nz = (long)C.n[0] * C.n[1] * C.n[2];
   std::vector<double> Em_all(nz * C.G);
   set_threads(D);
+  const bool rk2 = D->integrator == OI_SSPRK2;
+  std::vector<T> Es;
+  std::vector<std::vector<T>> Fs;
+  Ctx<T> C1 = C;
+  if (rk2) {
+    rk2_stage1(C, Es, Fs);
+    C1.E = Es.data();
+    for (int k = 0; k < D->ndim; ++k) C1.F[k] = Fs[k].data();
+  }
 #pragma omp parallel for schedule(static)
   for (long z = 0; z < nz; ++z) {
     int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
     for (int g = 0; g < C.G; ++g) {
       T U1[4], Em;
-      zone_step(C, idx, g, U1, &Em);
+      if (rk2)
+        rk2_zone(C, C1, idx, g, U1, &Em);
+      else
+        zone_step(C, idx, g, U1, &Em);
       size_t zg = (size_t)z * C.G + g;
       Eo[zg] = U1[0];
       for (int k = 0; k < D->ndim; ++k) Fo[k][zg] = U1[1 + k];
@@ -730,13 +790,26 @@ int orc_step_zones(const OrcDesc* D, const double* E, const double* const* F, co
   C.B = B;
   C.inflow = inflow;
   set_threads(D);
+  // SSP-RK2: stage 1 everywhere (the stencil of a zone's stage 2 reaches two zones out)
+  const bool rk2 = D->integrator == OI_SSPRK2;
+  std::vector<double> Es;
+  std::vector<std::vector<double>> Fs;
+  Ctx<double> C1 = C;
+  if (rk2) {
+    rk2_stage1(C, Es, Fs);
+    C1.E = Es.data();
+    for (int k = 0; k < D->ndim; ++k) C1.F[k] = Fs[k].data();
+  }
 #pragma omp parallel for schedule(dynamic, 16)
   for (int s = 0; s < nsel; ++s) {
     long z = (long)zones[s];
     int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
     for (int g = 0; g < C.G; ++g) {
       double U1[4], Em;
-      zone_step(C, idx, g, U1, &Em);
+      if (rk2)
+        rk2_zone(C, C1, idx, g, U1, &Em);
+      else
+        zone_step(C, idx, g, U1, &Em);
       Eo[(size_t)s * C.G + g] = U1[0];
       for (int k = 0; k < D->ndim; ++k) Fo[k][(size_t)s * C.G + g] = U1[1 + k];
       if (Em_out) Em_out[(size_t)s * C.G + g] = Em;

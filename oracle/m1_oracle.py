@@ -22,6 +22,7 @@ _LIB = os.path.join(_HERE, "libm1_oracle.so")
 CART, SPH_LOGR = 0, 1
 OUTFLOW, PERIODIC, REFLECT, INFLOW, AXIS = 0, 1, 2, 3, 4
 MINMOD, MC, CONST = 0, 1, 2
+EULER, SSPRK2 = 0, 1
 
 
 def build(force: bool = False) -> str:
@@ -48,6 +49,7 @@ class OrcDesc(ctypes.Structure):
         ("eps_mode", ctypes.c_int32),
         ("c", ctypes.c_double),
         ("nthreads", ctypes.c_int32),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -99,6 +101,7 @@ class Problem:
     eps_mode: int = 0
     c: float = 1.0
     nthreads: int = 0
+    integrator: int = EULER
     extra: dict = field(default_factory=dict)
 
     def desc(self) -> OrcDesc:
@@ -117,6 +120,7 @@ class Problem:
         d.eps_mode = self.eps_mode
         d.c = self.c
         d.nthreads = self.nthreads
+        d.integrator = self.integrator
         return d
 
     @property

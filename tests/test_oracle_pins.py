@@ -370,6 +370,76 @@ def test_fourier_mode_follows_amplification_matrix():
     assert np.allclose(F[0].ravel(), np.real(am[1] * np.exp(1j * kk * x)), rtol=0, atol=1e-13)
 
 
+def test_fourier_mode_follows_ssprk2_polynomial():
+    """Shu-Osher RK2 on the same linear scheme: U* = A U, U^- = (U + A U*)/2, i.e. the
+    amplification matrix I + M + M^2/2 with M = A - I (the Taylor polynomial of exp(M) to second
+    order); with no interaction the step is that matrix."""
+    n, c, m = 32, 1.3, 11
+    p = orc.Problem(ndim=1, n=(n,), G=1, c=c, limiter=orc.CONST, closure=1, integrator=orc.SSPRK2,
+                    bc_lo=(orc.PERIODIC,) * 3, bc_hi=(orc.PERIODIC,) * 3)
+    dx = 1.0 / n
+    dt = 0.35 * dx / c
+    kk = 2 * math.pi * 5
+    x = (np.arange(n) + 0.5) * dx
+    a0 = np.array([0.4 - 0.7j, -0.2 + 0.3j])
+    E0 = np.real(a0[0] * np.exp(1j * kk * x))
+    F0 = np.real(a0[1] * np.exp(1j * kk * x))
+    z = np.zeros((1, 1, n, 1))
+    E, F, _ = orc.run(p, E0.reshape(z.shape), [F0.reshape(z.shape)], z, z, z, dt, m)
+    th = kk * dx
+    lam = dt / dx
+    M = -lam * np.array([[c * (1 - math.cos(th)), 1j * math.sin(th)],
+                         [1j * math.sin(th) * c * c / 3, c * (1 - math.cos(th))]])
+    A2 = np.eye(2) + M + M @ M / 2
+    am = np.linalg.matrix_power(A2, m) @ a0
+    assert np.allclose(E.ravel(), np.real(am[0] * np.exp(1j * kk * x)), rtol=0, atol=1e-13)
+    assert np.allclose(F[0].ravel(), np.real(am[1] * np.exp(1j * kk * x)), rtol=0, atol=1e-13)
+    # and it differs from the Euler push by the M^2/2 term
+    p.integrator = orc.EULER
+    Ee, _, _ = orc.run(p, E0.reshape(z.shape), [F0.reshape(z.shape)], z, z, z, dt, m)
+    assert np.max(np.abs(Ee - E)) > 1e-3
+
+
+def test_ssprk2_reduces_to_the_interaction_update_without_gradients():
+    """A uniform state has no flux divergence: both stages leave it unchanged and the step is the
+    backward-Euler interaction update alone, bit for bit the Euler push."""
+    w = wl.blobs2d(n=8, G=3, steps=1)
+    E = np.full(w.E.shape, 0.7)
+    F = [np.full(w.E.shape, 0.2), np.full(w.E.shape, -0.1)]
+    kap = np.full(w.E.shape, 3.0)
+    sig = np.full(w.E.shape, 1.5)
+    B = np.full(w.E.shape, 0.4)
+    outs = []
+    for integ in (orc.EULER, orc.SSPRK2):
+        p = problem_of(w, integrator=integ)
+        outs.append(orc.run(p, E, F, kap, sig, B, w.dt, 3))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert all(np.array_equal(a, b) for a, b in zip(outs[0][1], outs[1][1]))
+
+
+def test_ssprk2_time_error_is_second_order():
+    """Halving dt (same end time) on a smooth free-streaming problem with piecewise-constant
+    space: the gap to a much finer-in-time run shrinks by about 4 for RK2 and 2 for Euler."""
+    n, c = 64, 1.0
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    E0 = (1.0 + 0.5 * np.sin(2 * math.pi * x)).reshape(1, 1, n, 1)
+    F0 = (0.3 * np.cos(2 * math.pi * x)).reshape(1, 1, n, 1)
+    z = np.zeros_like(E0)
+    T = 0.25
+    def run(integ, nst):
+        p = orc.Problem(ndim=1, n=(n,), G=1, c=c, limiter=orc.CONST, integrator=integ,
+                        bc_lo=(orc.PERIODIC,) * 3, bc_hi=(orc.PERIODIC,) * 3)
+        E, F, _ = orc.run(p, E0, [F0], z, z, z, T / nst, nst)
+        return E.ravel()
+    for integ, order in ((orc.SSPRK2, 2), (orc.EULER, 1)):
+        ref = run(orc.SSPRK2, 2048)
+        e1 = np.max(np.abs(run(integ, 64) - ref))
+        e2 = np.max(np.abs(run(integ, 128) - ref))
+        ratio = e1 / e2
+        assert 2 ** order * 0.8 < ratio < 2 ** order * 1.25, (integ, ratio)
+
+
 # --------------------------------------------------------------------------------------
 # Geometry and spherical pins
 # --------------------------------------------------------------------------------------
