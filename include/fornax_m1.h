@@ -67,6 +67,14 @@ enum { FORNAX_FP64 = 0, FORNAX_MIXED = 1 };
 enum { FORNAX_LIMITER_MINMOD = 0, FORNAX_LIMITER_MC = 1, FORNAX_LIMITER_NONE = 2 };
 enum { FORNAX_CLOSURE_M1 = 0, FORNAX_CLOSURE_EDDINGTON = 1 };
 
+/* Explicit integrator of the transport (Numerical Discretization: the paper integrates the
+ * explicit terms with Shu & Osher's second-order TVD Runge-Kutta scheme; Algorithmic Steps
+ * describe its first-order case, the Euler push).  EULER: U^- = U^n + dt L(U^n).  SSPRK2:
+ * U* = U^n + dt L(U^n), U^- = (U^n + U* + dt L(U*)) / 2 (two launches of the step kernel,
+ * U* in context scratch).  Either way the implicit interaction update then maps U^- to
+ * U^{n+1} once per step, and dE_matter is taken against that U^-. */
+enum { FORNAX_EULER = 0, FORNAX_SSPRK2 = 1 };
+
 typedef struct {
   int32_t ndim;             /* active directions, 1..3 */
   int32_t n[3];             /* zones per direction; n[d] = 1 for d >= ndim */
@@ -79,6 +87,7 @@ typedef struct {
   int32_t precision;        /* FORNAX_FP64 or FORNAX_MIXED */
   double c;                 /* (reduced) speed of light, > 0 */
   double f_fp64;            /* MIXED only: closure evaluated in double where f >= f_fp64 */
+  int32_t integrator;       /* FORNAX_EULER (the configurations' default) or FORNAX_SSPRK2 */
 } fornax_m1_desc;
 
 typedef struct fornax_m1_ctx fornax_m1_ctx;   /* opaque; owns geometry tables and scratch */

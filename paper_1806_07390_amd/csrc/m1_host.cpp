@@ -83,6 +83,7 @@ int validate(const fornax_m1_desc* d) {
   if (d->precision != FORNAX_FP64 && d->precision != FORNAX_MIXED) return FORNAX_EINVAL;
   if (d->limiter < 0 || d->limiter > 2) return FORNAX_EINVAL;
   if (d->closure < 0 || d->closure > 1) return FORNAX_EINVAL;
+  if (d->integrator != FORNAX_EULER && d->integrator != FORNAX_SSPRK2) return FORNAX_EINVAL;
   if (!(d->c > 0.0) || !std::isfinite(d->c)) return FORNAX_EINVAL;
   int64_t nz = 1;
   for (int k = 0; k < 3; ++k) {
@@ -352,10 +353,10 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   {
     // pairs of groups per lane (FORNAX_M1_PAIRS=0 disables)
     const char* pe = std::getenv("FORNAX_M1_PAIRS");
-    // (measured: in 1-D/2-D and in 3-D FP64 the second group's registers cost more waves
-    // than the wider accesses gain; 3-D MIXED gains)
-    const int V = (desc->ndim == 3 && desc->precision == FORNAX_MIXED && desc->ngroups % 2 == 0 &&
-                   !(pe && pe[0] == '0'))
+    // (measured: in 1-D/2-D, in 3-D FP64 and on spherical grids the second group's registers
+    // cost more waves, or spill, than the wider accesses gain; 3-D Cartesian MIXED gains)
+    const int V = (desc->ndim == 3 && desc->precision == FORNAX_MIXED && desc->coord == FORNAX_CARTESIAN &&
+                   desc->ngroups % 2 == 0 && !(pe && pe[0] == '0'))
                       ? 2
                       : 1;
     ctx->tile = choose_tile(*desc, V);
@@ -411,6 +412,17 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   ctx->p_nun = (int*)(ctx->p_maxf2 + nb);
   ctx->p_nnp = ctx->p_nun + nb;
   ctx->dzp = dzp_bytes ? (double*)((char*)red + red_bytes) : nullptr;
+  // SSP-RK2: storage of the first stage's state
+  ctx->stage_mem = nullptr;
+  if (desc->integrator == FORNAX_SSPRK2) {
+    const size_t es = desc->precision == FORNAX_FP64 ? sizeof(double) : sizeof(float);
+    if (hipMalloc(&ctx->stage_mem, (size_t)(1 + desc->ndim) * nz * desc->ngroups * es) != hipSuccess) {
+      (void)hipFree(red);
+      (void)hipFree(ctx->geo_mem);
+      delete ctx;
+      return FORNAX_ENOMEM;
+    }
+  }
   // adjoint ghost buffers (the adjoint supports 1-D and 2-D Cartesian grids)
   ctx->adj_u1 = nullptr;
   for (int d = 0; d < 3; ++d) {
@@ -422,6 +434,7 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
       size_t bytes = (size_t)4 * ctx->adj_gplane[d] * desc->ngroups * (desc->ndim + 2) * sizeof(double);
       if (hipMalloc((void**)&ctx->adj_gbuf[d], bytes) != hipSuccess) {
         for (int e = 0; e < d; ++e) (void)hipFree(ctx->adj_gbuf[e]);
+        if (ctx->stage_mem) (void)hipFree(ctx->stage_mem);
         (void)hipFree(red);
         (void)hipFree(ctx->geo_mem);
         delete ctx;
@@ -440,6 +453,7 @@ int fornax_m1_destroy(fornax_m1_ctx* ctx) {
   for (int d = 0; d < 3; ++d)
     if (ctx->adj_gbuf[d]) (void)hipFree(ctx->adj_gbuf[d]);
   if (ctx->adj_u1) (void)hipFree(ctx->adj_u1);
+  if (ctx->stage_mem) (void)hipFree(ctx->stage_mem);
   delete ctx;
   return FORNAX_OK;
 }

@@ -101,6 +101,11 @@ struct StepArgs : StepArgsBase {
   const S* B;
   double* dEm;               // per zone, nullable
   double* dzp;               // [group block][zone] partials of dE_matter (tiles with ngb > 1)
+  // Runge-Kutta stages: src = 0 writes U^- itself (no interaction update); Ea, Fa (nullable)
+  // replace U^- by (Ua + U^-) / 2 before the interaction update
+  int src;
+  const S* Ea;
+  const S* Fa[3];
   // per-block partial reductions (null: no diagnostics)
   double* p_energy;
   double* p_maxf2;
@@ -158,6 +163,8 @@ struct fornax_m1_ctx {
   // dE_matter partials of the group blocks of a tile, [ngb][zones] (null when every tile
   // holds all groups of a zone)
   double* dzp;
+  // SSP-RK2: the first stage's state U* (E, F_1..F_ndim), null for the Euler push
+  void* stage_mem;
   // adjoint: ghost-zone adjoint buffers per direction, [side][layer][plane][G][1+ndim+1]
   double* adj_gbuf[3];
   int adj_gplane[3];

@@ -188,6 +188,9 @@ void fill_args(const fornax_m1_ctx* ctx, StepArgs<S>& a, const fornax_m1_coeffs*
   }
   a.dEm = nullptr;
   a.dzp = nullptr;
+  a.src = 1;
+  a.Ea = nullptr;
+  for (int k = 0; k < 3; ++k) a.Fa[k] = nullptr;
   a.p_energy = nullptr;
   a.p_maxf2 = nullptr;
   a.p_nun = nullptr;
@@ -214,6 +217,25 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
     a.p_maxf2 = ctx->p_maxf2;
     a.p_nun = ctx->p_nun;
     a.p_nnp = ctx->p_nnp;
+  }
+  if (ctx->desc.integrator == FORNAX_SSPRK2) {
+    // stage 1: U* = U^n + dt L(U^n) into the context's stage storage, no interaction update
+    StepArgs<S> a1 = a;
+    const size_t nzg = (size_t)a.nzones * a.G;
+    S* st_E = (S*)ctx->stage_mem;
+    a1.Eo = st_E;
+    for (int k = 0; k < 3; ++k) a1.Fo[k] = (k < ctx->desc.ndim) ? st_E + (1 + k) * nzg : nullptr;
+    a1.src = 0;
+    a1.dEm = nullptr;
+    a1.p_energy = a1.p_maxf2 = nullptr;
+    a1.p_nun = a1.p_nnp = nullptr;
+    const int rc1 = launch_tiled<S, R>(ctx, geo, a1, st);
+    if (rc1 != FORNAX_OK) return rc1;
+    // stage 2 reads U* and averages with U^n: U^- = (U^n + U* + dt L(U*)) / 2
+    a.Ea = a.E;
+    for (int k = 0; k < 3; ++k) a.Fa[k] = a.F[k];
+    a.E = a1.Eo;
+    for (int k = 0; k < 3; ++k) a.F[k] = a1.Fo[k];
   }
   const int rc = launch_tiled<S, R>(ctx, geo, a, st);
   if (rc != FORNAX_OK) return rc;

@@ -676,9 +676,20 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
           geometric_source<R>(P, h, geo.gam + 4 * zj, c, Sg);
           for (int cc = 0; cc < DIM; ++cc) Um[1 + cc] += dtR * Sg[cc];
         }
+        if (a.Ea) {
+          // second Runge-Kutta stage: the average with U^n
+          const int zgu = zone * a.G + grp0 + u;
+          Um[0] = R(0.5) * (R(a.Ea[zgu]) + Um[0]);
+          for (int cc = 0; cc < DIM; ++cc) Um[1 + cc] = R(0.5) * (R(a.Fa[cc][zgu]) + Um[1 + cc]);
+        }
         S F1[3];
-        const double dz = source_zone<S, R, SPH, DIM>(a, geo, zi, zj, Um, ck0[u], cks0[u], jB[u], want_diag, Vm, zd,
-                                                      Eo[u], F1);
+        double dz = 0.0;
+        if (a.src) {
+          dz = source_zone<S, R, SPH, DIM>(a, geo, zi, zj, Um, ck0[u], cks0[u], jB[u], want_diag, Vm, zd, Eo[u], F1);
+        } else {
+          Eo[u] = S(Um[0]);
+          for (int cc = 0; cc < DIM; ++cc) F1[cc] = S(Um[1 + cc]);
+        }
         for (int cc = 0; cc < DIM; ++cc) Fo[cc][u] = F1[cc];
         dzs += dz;
         if (!ROW && a.dEm) DZ[(size_t)col * GB + gl * V + u] = dz;
@@ -985,14 +996,16 @@ static bool aligned_to(const void* p, size_t n) { return p == nullptr || ((uintp
 
 template <typename S, typename R>
 int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, hipStream_t st) {
+  // the whole-zone kernel does the Euler push; Runge-Kutta stages run on the tiled kernel
   if constexpr (std::is_same<S, R>::value)
-    if (ctx->rows.nblocks > 0) return launch_rows<S>(ctx, geo, a, st);
+    if (ctx->rows.nblocks > 0 && a.src && !a.Ea) return launch_rows<S>(ctx, geo, a, st);
   const bool sph = ctx->desc.coord == FORNAX_SPHERICAL_LOGR;
   const int D = ctx->desc.ndim;
   // pairs of groups per lane need arrays aligned to two elements
   const Tile* tl = &ctx->tile;
   bool al = true;
-  const void* ptrs[] = {a.E, a.F[0], a.F[1], a.F[2], a.Eo, a.Fo[0], a.Fo[1], a.Fo[2], a.kap, a.sig, a.B};
+  const void* ptrs[] = {a.E,   a.F[0], a.F[1], a.F[2],  a.Eo,    a.Fo[0], a.Fo[1],
+                        a.Fo[2], a.kap, a.sig,  a.B,    a.Ea,    a.Fa[0], a.Fa[1], a.Fa[2]};
   for (const void* q : ptrs) al = al && aligned_to(q, 2 * sizeof(S));
   if (tl->V == 2 && !al) tl = &ctx->tile_v1;
   if (tl->nblocks <= 0) return FORNAX_EUNSUPPORTED;

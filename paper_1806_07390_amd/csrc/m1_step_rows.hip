@@ -18,7 +18,7 @@
 //     (a fixed number per wave; chunks outside the domain fall beyond the buffer and are
 //     dropped), so that the wait for the next plane's loads can count the stores exactly.
 // Four block barriers per plane: loads of the next plane arrived, lower states written,
-// fluxes written, outputs staged.
+// fluxes written, outputs staged.  The Euler push only (Runge-Kutta stages use k_step_tiled).
 
 #include <hip/hip_runtime.h>
 

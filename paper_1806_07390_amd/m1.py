@@ -30,6 +30,7 @@ BC_OUTFLOW, BC_PERIODIC, BC_REFLECT, BC_INFLOW, BC_AXIS = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 LIMITER_MINMOD, LIMITER_MC, LIMITER_NONE = 0, 1, 2
 CLOSURE_M1, CLOSURE_EDDINGTON = 0, 1
+EULER, SSPRK2 = 0, 1
 
 EXPORTED = ["fornax_m1_create", "fornax_m1_destroy", "fornax_m1_max_dt", "fornax_m1_step", "fornax_m1_flux",
             "fornax_m1_source", "fornax_m1_adjoint", "fornax_m1_copy_probe", "fornax_m1_strerror"]
@@ -50,6 +51,7 @@ class Desc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("c", ctypes.c_double),
         ("f_fp64", ctypes.c_double),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -118,6 +120,7 @@ class Config:
     precision: int = FP64
     c: float = 1.0
     f_fp64: float = 0.9
+    integrator: int = EULER
 
     @classmethod
     def from_workload(cls, w, precision=FP64, **kw):
@@ -145,6 +148,7 @@ class Context:
         d.precision = cfg.precision
         d.c = cfg.c
         d.f_fp64 = cfg.f_fp64
+        d.integrator = cfg.integrator
         self.desc = d
         self.shape = (n[2], n[1], n[0], cfg.G)
         self.nzones = n[0] * n[1] * n[2]

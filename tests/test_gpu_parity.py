@@ -231,6 +231,45 @@ def test_whole_zone_kernel(m1, bc, lim):
             assert np.allclose(dgg["dE_matter"], dEm, rtol=1e-10, atol=1e-12 * np.abs(E).max())
 
 
+@pytest.mark.parametrize("case", ["blobs2d", "reflect2d", "core3d", "sphere3d"])
+def test_ssprk2_matches_oracle(m1, case):
+    """Shu-Osher SSP-RK2 for the transport (two launches of the step kernel, U* in context
+    scratch), the interaction update once per step: the oracle's result in FP64 and MIXED, and
+    dE_matter against the averaged U^-."""
+    if case == "blobs2d":
+        w = wl.blobs2d(n=40, G=16, steps=5)
+    elif case == "reflect2d":
+        w = _rows_case("outflow_reflect", steps=5)
+    elif case == "core3d":
+        w = wl.core3d(n=14, G=6, steps=5)
+    else:
+        w = wl.sphere3d(nr=14, nth=10, nph=8, G=4, steps=5)
+    p = problem_of(w, integrator=orc.SSPRK2)
+    dt = dt_of(w, p)
+    E, F, dg, dEm = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow, want_dEm=True)
+    Ee, Fe, _ = orc.run(problem_of(w), w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow)
+    assert rel_l1(Ee, Fe, E, F, w.c)[0] > 1e-9      # the integrators differ
+    for prec, tol in ((m1.FP64, TOL_FP64), (m1.MIXED, TOL_MIXED_RUN)):
+        ctx = m1.Context(m1.Config.from_workload(w, precision=prec, integrator=m1.SSPRK2))
+        Eg, Fg, dgg = gpu_run(ctx, w, dt, w.steps, diag=True)
+        eE, eF = rel_l1(Eg, Fg, E, F, w.c)
+        say(f"ssprk2 {case} prec={prec}", eE, eF)
+        assert eE <= tol and eF <= tol
+        if prec == m1.FP64:
+            assert np.allclose(dgg["dE_matter"], dEm, rtol=1e-10, atol=1e-12 * np.abs(E).max())
+            assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-12)
+
+
+def test_adjoint_refuses_ssprk2(m1):
+    w = wl.adjoint2d(n=16, G=2, steps=1)
+    ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64, integrator=m1.SSPRK2))
+    t = lambda a: to_dev(a, torch.float64)
+    z = [torch.zeros_like(t(w.E)) for _ in w.F]
+    with pytest.raises(m1.FornaxError) as ei:
+        ctx.adjoint(t(w.E), [t(f) for f in w.F], t(w.kappa), t(w.sigma), t(w.B), w.dt, t(w.E), z)
+    assert ei.value.code == m1.FORNAX_EUNSUPPORTED
+
+
 # ------------------------------------------------------------------------------------------
 def test_flux_and_source_entry_points(m1):
     w = wl.sphere3d(nr=12, nth=8, nph=8, G=3, steps=1)
