@@ -177,7 +177,7 @@ __device__ __forceinline__ void face_vjp_cart(const StepArgsBase& a, int d, R dx
   const R eps = itau;
   // forward flux
   const R one[3] = {R(1), R(1), R(1)};
-  hll<R, false, ND>(a, d, qL, qR, one, eps, flux);
+  hll<R, false, ND>(a, d, qL, qR, one, one, eps, flux);
   // adjoint of the HLL flux
   R gL[4] = {R(0), R(0), R(0), R(0)}, gR[4] = {R(0), R(0), R(0), R(0)};
   const R half = R(0.5);

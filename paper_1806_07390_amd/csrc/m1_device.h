@@ -76,6 +76,34 @@ __device__ __forceinline__ void face_h(const Geo<R>& geo, int d, int ei, int ej,
   }
 }
 
+// inverse cell-centred scale factors 1/h (spherical tables of 1/sqrt(<r^2>), 1/sqrt(<sin^2>))
+template <typename R, bool SPH>
+__device__ __forceinline__ void cell_ih(const Geo<R>& geo, int ei, int ej, R ih[3]) {
+  if constexpr (SPH) {
+    const R ir = geo.ihr[ei];
+    ih[0] = ir;
+    ih[1] = ir;
+    ih[2] = ir * geo.ihs[ej];
+  } else {
+    ih[0] = ih[1] = ih[2] = R(1);
+  }
+}
+
+// inverse scale factors at the centre of a d-face (tables of 1/r and 1/|sin theta|; 0 on a
+// polar-axis face, which is closed and never used)
+template <typename R, bool SPH>
+__device__ __forceinline__ void face_ih(const Geo<R>& geo, int d, int ei, int ej, int ef, R ih[3]) {
+  if constexpr (SPH) {
+    const R ir = (d == 0) ? geo.irf[ef] : geo.irc[ei];
+    const R is = (d == 1) ? geo.isf[ef] : geo.isc[ej];
+    ih[0] = ir;
+    ih[1] = ir;
+    ih[2] = ir * is;
+  } else {
+    ih[0] = ih[1] = ih[2] = R(1);
+  }
+}
+
 // Proper width h_d Delta x^d of the zone with extended indices (ei, ej) along d.
 template <typename R, bool SPH>
 __device__ __forceinline__ R proper_width(const Geo<R>& geo, int d, int ei, int ej) {
@@ -136,12 +164,12 @@ __device__ __forceinline__ void fetch(const StepArgs<S>& a, const Geo<R>& geo, i
   for (int c = ND; c < 3; ++c) q[1 + c] = R(0);
 }
 
-// E > 0 and |F^| <= cE with F^_k = F_k / h_k
+// E > 0 and |F^| <= cE with F^_k = F_k / h_k (ih = 1/h)
 template <typename R, bool SPH, int ND>
-__device__ __forceinline__ bool realizable(const R q[4], const R h[3], R c) {
+__device__ __forceinline__ bool realizable(const R q[4], const R ih[3], R c) {
   R F2 = R(0);
   for (int k = 0; k < ND; ++k) {
-    R fk = SPH ? q[1 + k] * rcp_(h[k]) : q[1 + k];
+    R fk = SPH ? q[1 + k] * ih[k] : q[1 + k];
     F2 += fk * fk;
   }
   R cE = c * q[0];
@@ -154,7 +182,7 @@ __device__ __forceinline__ bool realizable(const R q[4], const R h[3], R c) {
 // the arguments.
 template <typename R, bool SPH, int ND, int LIM = -1>
 __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>& geo, int d, int e, const R qm[4],
-                                            const R q0[4], const R qp[4], const R hlo[3], const R hhi[3],
+                                            const R q0[4], const R qp[4], const R ihlo[3], const R ihhi[3],
                                             bool lo_open, bool hi_open, R lo[4], R hi[4]) {
   const R c = R(a.c);
   const int limiter = (LIM >= 0) ? LIM : a.limiter;
@@ -195,7 +223,8 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
     lo[cp] = q0[cp] + s[cp] * dl;
     hi[cp] = q0[cp] + s[cp] * dh;
   }
-  const bool ok = (!lo_open || realizable<R, SPH, ND>(lo, hlo, c)) && (!hi_open || realizable<R, SPH, ND>(hi, hhi, c));
+  const bool ok =
+      (!lo_open || realizable<R, SPH, ND>(lo, ihlo, c)) && (!hi_open || realizable<R, SPH, ND>(hi, ihhi, c));
   for (int cp = 0; cp <= ND; ++cp) {
     lo[cp] = ok ? lo[cp] : q0[cp];
     hi[cp] = ok ? hi[cp] : q0[cp];
@@ -208,7 +237,7 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
 // cancellation as f -> 1).  Physical components.  Full tensor (row-major 3x3) for the
 // geometric sources.
 template <typename R, bool SPH, int ND>
-__device__ __forceinline__ void closure_full(const R q[4], const R h[3], R c, int eddington, R P[9]) {
+__device__ __forceinline__ void closure_full(const R q[4], const R ih[3], R c, int eddington, R P[9]) {
   const R E = q[0];
   for (int t = 0; t < 9; ++t) P[t] = R(0);
   if (eddington || !(E > R(0))) {
@@ -219,7 +248,7 @@ __device__ __forceinline__ void closure_full(const R q[4], const R h[3], R c, in
   const R icE = rcp_(c * E);
   R f2 = R(0);
   for (int k = 0; k < ND; ++k) {
-    f[k] = (SPH ? q[1 + k] * rcp_(h[k]) : q[1 + k]) * icE;
+    f[k] = (SPH ? q[1 + k] * ih[k] : q[1 + k]) * icE;
     f2 += f[k] * f[k];
   }
   if (f2 > R(1)) {
@@ -242,7 +271,7 @@ __device__ __forceinline__ void closure_full(const R q[4], const R h[3], R c, in
 // root, one reciprocal); in the MIXED path (R = float) from f = F/(cE), in double where
 // f^2 >= f2_fp64.
 template <typename R, bool SPH, int ND>
-__device__ __forceinline__ void closure_row(const R q[4], const R h[3], int d, R c, int eddington, double f2_fp64,
+__device__ __forceinline__ void closure_row(const R q[4], const R ih[3], int d, R c, int eddington, double f2_fp64,
                                             R P[3]) {
   const R E = q[0];
   for (int k = 0; k < 3; ++k) P[k] = R(0);
@@ -257,7 +286,7 @@ __device__ __forceinline__ void closure_row(const R q[4], const R h[3], int d, R
     R Fh[3] = {R(0), R(0), R(0)};
     R F2 = R(0);
     for (int k = 0; k < ND; ++k) {
-      Fh[k] = SPH ? q[1 + k] * rcp_(h[k]) : q[1 + k];
+      Fh[k] = SPH ? q[1 + k] * ih[k] : q[1 + k];
       F2 += Fh[k] * Fh[k];
     }
     const R cE = c * E;
@@ -278,7 +307,7 @@ __device__ __forceinline__ void closure_row(const R q[4], const R h[3], int d, R
   const R icE = rcp_(c * E);
   R f2 = R(0);
   for (int k = 0; k < ND; ++k) {
-    f[k] = (SPH ? q[1 + k] * rcp_(h[k]) : q[1 + k]) * icE;
+    f[k] = (SPH ? q[1 + k] * ih[k] : q[1 + k]) * icE;
     f2 += f[k] * f[k];
   }
   if constexpr (sizeof(R) == 4) {
@@ -286,7 +315,7 @@ __device__ __forceinline__ void closure_row(const R q[4], const R h[3], int d, R
       double fd[3] = {0.0, 0.0, 0.0}, f2d = 0.0;
       const double icEd = rcp_((double)c * (double)E);
       for (int k = 0; k < ND; ++k) {
-        fd[k] = (SPH ? (double)q[1 + k] * rcp_((double)h[k]) : (double)q[1 + k]) * icEd;
+        fd[k] = (SPH ? (double)q[1 + k] * (double)ih[k] : (double)q[1 + k]) * icEd;
         f2d += fd[k] * fd[k];
       }
       if (f2d > 1.0) {
@@ -318,18 +347,18 @@ __device__ __forceinline__ void closure_row(const R q[4], const R h[3], int d, R
   for (int k = 0; k < ND; ++k) P[k] = af * f[k] + (k == d ? iso : R(0));
 }
 
-// HLL flux (coordinate components) across a d-face with face scale factors h, left/right
-// states qL, qR and the correction factor eps of the energy flux.
+// HLL flux (coordinate components) across a d-face with face scale factors h and their
+// inverses ih, left/right states qL, qR and the correction factor eps of the energy flux.
 template <typename R, bool SPH, int ND>
-__device__ __forceinline__ void hll(const StepArgsBase& a, int d, const R qL[4], const R qR[4], const R h[3], R eps,
-                                    R flux[4]) {
+__device__ __forceinline__ void hll(const StepArgsBase& a, int d, const R qL[4], const R qR[4], const R h[3],
+                                    const R ih[3], R eps, R flux[4]) {
   const R c = R(a.c);
   R PL[3], PR[3];
-  closure_row<R, SPH, ND>(qL, h, d, c, a.closure, a.f2_fp64, PL);
-  closure_row<R, SPH, ND>(qR, h, d, c, a.closure, a.f2_fp64, PR);
+  closure_row<R, SPH, ND>(qL, ih, d, c, a.closure, a.f2_fp64, PL);
+  closure_row<R, SPH, ND>(qR, ih, d, c, a.closure, a.f2_fp64, PR);
   R ihd = R(1), S = c;
   if constexpr (SPH) {
-    ihd = rcp_(h[d]);
+    ihd = ih[d];
     S = c * ihd;
   }
   const R half = R(0.5);
@@ -358,31 +387,33 @@ __device__ __forceinline__ void face_flux(const StepArgs<S>& a, const Geo<R>& ge
   for (int c = 0; c < 4; ++c) flux[c] = R(0);
   if (SPH && geo.wf[d][ef] == R(0)) return;
   const int ei = i + NG, ej = j + NG;
-  R h0[3], h1[3], h2[3];
-  face_h<R, SPH>(geo, d, ei, ej, ef - 1, h0);
+  R ih0[3], h1[3], ih1[3], ih2[3];
+  face_ih<R, SPH>(geo, d, ei, ej, ef - 1, ih0);
   face_h<R, SPH>(geo, d, ei, ej, ef, h1);
-  face_h<R, SPH>(geo, d, ei, ej, ef + 1, h2);
+  face_ih<R, SPH>(geo, d, ei, ej, ef, ih1);
+  face_ih<R, SPH>(geo, d, ei, ej, ef + 1, ih2);
   const bool o0 = !SPH || geo.wf[d][ef - 1] != R(0), o2 = !SPH || geo.wf[d][ef + 1] != R(0);
   R Llo[4], Lhi[4], Rlo[4], Rhi[4];
-  reconstruct<R, SPH, ND>(a, geo, d, ef - 1, q[0], q[1], q[2], h0, h1, o0, true, Llo, Lhi);
-  reconstruct<R, SPH, ND>(a, geo, d, ef, q[1], q[2], q[3], h1, h2, true, o2, Rlo, Rhi);
+  reconstruct<R, SPH, ND>(a, geo, d, ef - 1, q[0], q[1], q[2], ih0, ih1, o0, true, Llo, Lhi);
+  reconstruct<R, SPH, ND>(a, geo, d, ef, q[1], q[2], q[3], ih1, ih2, true, o2, Rlo, Rhi);
   const int eL = ef - 1;
   const R dlL = proper_width<R, SPH>(geo, d, d == 0 ? eL : ei, d == 1 ? eL : ej);
   const R dlR = proper_width<R, SPH>(geo, d, d == 0 ? ef : ei, d == 1 ? ef : ej);
   const R eps = epsilon_of(ksL, ksR, dlL, dlR);
-  hll<R, SPH, ND>(a, d, Lhi, Rlo, h1, eps, flux);
+  hll<R, SPH, ND>(a, d, Lhi, Rlo, h1, ih1, eps, flux);
 }
 
 // geometric source c^2 sum_{l,m} <Gamma^l_{km}> P^m_l for the covariant flux components of a
 // spherical (ln r, theta, phi) zone, P^m_l = P^^{ml} h_l / h_m with cell-centred h
 template <typename R>
-__device__ __forceinline__ void geometric_source(const R P[9], const R h[3], const R* gam, R c, R Sg[3]) {
+__device__ __forceinline__ void geometric_source(const R P[9], const R h[3], const R ih[3], const R* gam, R c,
+                                                 R Sg[3]) {
   const R G323 = gam[0], G133 = gam[1], G233 = gam[2], G222 = gam[3];
   const R c2 = c * c;
   // F_1: Gamma^1_11 = Gamma^2_12 = Gamma^3_13 = 1
   Sg[0] = c2 * (P[0] + P[4] + P[8]);
   // F_2: Gamma^1_22 = -1, Gamma^2_21 = 1, <Gamma^2_22>, <Gamma^3_23>
-  const R ih0 = rcp_(h[0]), ih1 = rcp_(h[1]), ih2 = rcp_(h[2]);
+  const R ih0 = ih[0], ih1 = ih[1], ih2 = ih[2];
   Sg[1] = c2 * (-P[3] * (h[0] * ih1) + P[1] * (h[1] * ih0) + G222 * P[4] + G323 * P[8]);
   // F_3: <Gamma^1_33>, <Gamma^2_33>, Gamma^3_31 = 1, <Gamma^3_32>
   Sg[2] = c2 * (G133 * P[6] * (h[0] * ih2) + G233 * P[7] * (h[1] * ih2) + P[2] * (h[2] * ih0) +

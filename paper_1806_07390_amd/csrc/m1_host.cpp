@@ -224,6 +224,17 @@ void build_geometry(const fornax_m1_desc& D, HostGeo& H) {
       H.gam[4 * j + 2] = -s2 * cot;                  // <Gamma^2_33> = -<g33>/<g22> <Gamma^3_23>
       H.gam[4 * j + 3] = (H.wf[1][e + 1] - H.wf[1][e]) * H.iW[1][e] - cot;   // eq:grad2P
     }
+    auto inv = [](const std::vector<double>& v) {
+      std::vector<double> r(v.size());
+      for (size_t i = 0; i < v.size(); ++i) r[i] = v[i] != 0.0 ? 1.0 / v[i] : 0.0;
+      return r;
+    };
+    H.irc = inv(H.rc);
+    H.irf = inv(H.rf);
+    H.isc = inv(H.sc);
+    H.isf = inv(H.sf);
+    H.ihr = inv(H.hr);
+    H.ihs = inv(H.hs);
   }
 }
 
@@ -231,10 +242,11 @@ template <typename R>
 size_t table_bytes(const HostGeo& H, bool sph) {
   size_t n = 0;
   for (int d = 0; d < 3; ++d) n += 7 * H.idm[d].size() + H.wf[d].size();
-  if (sph) n += H.rc.size() + H.rf.size() + H.hr.size() + H.sc.size() + H.sf.size() + H.hs.size() + H.gam.size();
+  if (sph)
+    n += 2 * (H.rc.size() + H.rf.size() + H.hr.size() + H.sc.size() + H.sf.size() + H.hs.size()) + H.gam.size();
   size_t b = n * sizeof(R);
   for (int d = 0; d < 3; ++d) b += H.W[d].size() * sizeof(double);
-  return b + 256 * 48;   // 256-byte alignment of each of the (at most 31) tables
+  return b + 256 * 48;   // 256-byte alignment of each of the (at most 37) tables
 }
 
 struct Packer {
@@ -267,7 +279,14 @@ void pack(const HostGeo& H, bool sph, Packer& P, Geo<R>& G) {
     G.idx[d] = (R)(1.0 / H.dx[d]);
   }
   G.rc = G.rf = G.hr = G.sc = G.sf = G.hs = G.gam = nullptr;
+  G.irc = G.irf = G.isc = G.isf = G.ihr = G.ihs = nullptr;
   if (sph) {
+    G.irc = P.put<R>(H.irc);
+    G.irf = P.put<R>(H.irf);
+    G.isc = P.put<R>(H.isc);
+    G.isf = P.put<R>(H.isf);
+    G.ihr = P.put<R>(H.ihr);
+    G.ihs = P.put<R>(H.ihs);
     G.rc = P.put<R>(H.rc);
     G.rf = P.put<R>(H.rf);
     G.hr = P.put<R>(H.hr);

@@ -34,6 +34,12 @@ struct Geo {
   const R* sf;       // axis 1: |sin theta| at face e
   const R* hs;       // axis 1: sqrt(<sin^2 theta>)  (h_3 = hr * hs)
   const R* gam;      // axis 1, active zones j: <Gamma^3_23>, <Gamma^1_33>, <Gamma^2_33>, <Gamma^2_22>
+  const R* irc;      // 1 / rc, 1 / rf, 1 / sc, 1 / sf (0 where sf = 0), 1 / hr, 1 / hs
+  const R* irf;
+  const R* isc;
+  const R* isf;
+  const R* ihr;
+  const R* ihs;
   R dx[3];           // coordinate spacing
   R idx[3];          // 1 / dx
 };
@@ -43,6 +49,7 @@ struct HostGeo {
   int n[3];
   std::vector<double> idm[3], idp[3], dlo[3], dhi[3], iW[3], W[3], wf[3], idc[3];
   std::vector<double> rc, rf, hr, sc, sf, hs, gam;
+  std::vector<double> irc, irf, isc, isf, ihr, ihs;   // inverses (0 for a zero entry)
   double dx[3];
 };
 

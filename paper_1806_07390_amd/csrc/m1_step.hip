@@ -477,10 +477,11 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
       // face mbeg - 1/2 from zones mbeg - 1 (upper state) and mbeg (lower state)
       const int ef = mbeg + NG;   // lower face of zone mbeg
       const int eyf = (DIM == 3) ? eyc : ef;
-      R h0[3], h1[3], h2[3];
-      face_h<R, SPH>(geo, MD, ex, eyf, ef - 1, h0);
+      R ih0[3], h1[3], ih1[3], ih2[3];
+      face_ih<R, SPH>(geo, MD, ex, eyf, ef - 1, ih0);
       face_h<R, SPH>(geo, MD, ex, eyf, ef, h1);
-      face_h<R, SPH>(geo, MD, ex, eyf, ef + 1, h2);
+      face_ih<R, SPH>(geo, MD, ex, eyf, ef, ih1);
+      face_ih<R, SPH>(geo, MD, ex, eyf, ef + 1, ih2);
       const bool o0 = !SPH || geo.wf[MD][ef - 1] != R(0);
       const bool o1 = !SPH || geo.wf[MD][ef] != R(0);
       const bool o2 = !SPH || geo.wf[MD][ef + 1] != R(0);
@@ -488,9 +489,9 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
       const R dlR = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef);
       for (int u = 0; u < V; ++u) {
         R lo[4], hiP[4];
-        reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef - 1, qa[u], qb[u], q0[u], h0, h1, o0, o1, lo, hiP);
-        reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef, qb[u], q0[u], q1[u], h1, h2, o1, o2, lo, hiM[u]);
-        if (o1) hll<R, SPH, DIM>(a, MD, hiP, lo, h1, epsilon_of(ka[u] + sa[u], ks0[u], dlL, dlR), fPrev[u]);
+        reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef - 1, qa[u], qb[u], q0[u], ih0, ih1, o0, o1, lo, hiP);
+        reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef, qb[u], q0[u], q1[u], ih1, ih2, o1, o2, lo, hiM[u]);
+        if (o1) hll<R, SPH, DIM>(a, MD, hiP, lo, h1, ih1, epsilon_of(ka[u] + sa[u], ks0[u], dlL, dlR), fPrev[u]);
       }
     } else {
       const int pm = load_own(0, raw, k0, s0);
@@ -551,8 +552,8 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
       for (int k = 0; k < 4; ++k) hiX[u][k] = hiY[u][k] = R(0);
     if (recon) {
       R hlo[3], hhi[3];
-      face_h<R, SPH>(geo, 0, ex, eym, ex, hlo);
-      face_h<R, SPH>(geo, 0, ex, eym, ex + 1, hhi);
+      face_ih<R, SPH>(geo, 0, ex, eym, ex, hlo);
+      face_ih<R, SPH>(geo, 0, ex, eym, ex + 1, hhi);
       const bool olo = !SPH || geo.wf[0][ex] != R(0), ohi = !SPH || geo.wf[0][ex + 1] != R(0);
       for (int u = 0; u < V; ++u) {
         R qm[4], qp[4], lo[4];
@@ -564,8 +565,8 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         for (int v = 0; v < NC; ++v) LX[cidx(v, col) + u] = lo[v];
       }
       if constexpr (DIM == 3) {
-        face_h<R, SPH>(geo, 1, ex, eyc, eyc, hlo);
-        face_h<R, SPH>(geo, 1, ex, eyc, eyc + 1, hhi);
+        face_ih<R, SPH>(geo, 1, ex, eyc, eyc, hlo);
+        face_ih<R, SPH>(geo, 1, ex, eyc, eyc + 1, hhi);
         const bool ylo = !SPH || geo.wf[1][eyc] != R(0), yhi = !SPH || geo.wf[1][eyc + 1] != R(0);
         for (int u = 0; u < V; ++u) {
           R qm[4], qp[4], lo[4];
@@ -586,16 +587,17 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         // reconstruct zone m + 1 along the march direction; flux at m + 1/2
         const int ef = m + 1 + NG;   // lower face of zone m + 1
         const int eyf = (DIM == 3) ? eyc : ef;
-        R h1[3], h2[3];
+        R h1[3], ih1[3], ih2[3];
         face_h<R, SPH>(geo, MD, ex, eyf, ef, h1);
-        face_h<R, SPH>(geo, MD, ex, eyf, ef + 1, h2);
+        face_ih<R, SPH>(geo, MD, ex, eyf, ef, ih1);
+        face_ih<R, SPH>(geo, MD, ex, eyf, ef + 1, ih2);
         const bool o1 = !SPH || geo.wf[MD][ef] != R(0), o2 = !SPH || geo.wf[MD][ef + 1] != R(0);
         const R dlL = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef - 1);
         const R dlR = proper_width<R, SPH>(geo, MD, ex, (DIM == 3) ? eyc : ef);
         for (int u = 0; u < V; ++u) {
           R nLo[4];
-          reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef, q0[u], q1[u], q2[u], h1, h2, o1, o2, nLo, nHi[u]);
-          if (o1) hll<R, SPH, DIM>(a, MD, hiM[u], nLo, h1, epsilon_of(ks0[u], ks1[u], dlL, dlR), fNext[u]);
+          reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef, q0[u], q1[u], q2[u], ih1, ih2, o1, o2, nLo, nHi[u]);
+          if (o1) hll<R, SPH, DIM>(a, MD, hiM[u], nLo, h1, ih1, epsilon_of(ks0[u], ks1[u], dlL, dlR), fNext[u]);
         }
       }
     }
@@ -606,30 +608,32 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
       for (int k = 0; k < 4; ++k) fxR[u][k] = fyR[u][k] = R(0);
     if (do_xf) {
       const bool open = !SPH || geo.wf[0][ex + 1] != R(0);
-      R hf[3];
+      R hf[3], ihf[3];
       face_h<R, SPH>(geo, 0, ex, eym, ex + 1, hf);
+      face_ih<R, SPH>(geo, 0, ex, eym, ex + 1, ihf);
       const R dlL = proper_width<R, SPH>(geo, 0, ex, eym);
       const R dlR = proper_width<R, SPH>(geo, 0, ex + 1, eym);
       for (int u = 0; u < V; ++u) {
         R qR[4] = {R(0), R(0), R(0), R(0)};
         for (int v = 0; v < NC; ++v) qR[v] = LX[cidx(v, col + 1) + u];
         const R ksR = PV[pvi(NC, prow_own, cx + 2) + u];
-        if (open) hll<R, SPH, DIM>(a, 0, hiX[u], qR, hf, epsilon_of(ks0[u], ksR, dlL, dlR), fxR[u]);
+        if (open) hll<R, SPH, DIM>(a, 0, hiX[u], qR, hf, ihf, epsilon_of(ks0[u], ksR, dlL, dlR), fxR[u]);
         for (int v = 0; v < NC; ++v) FX[cidx(v, col) + u] = fxR[u][v];
       }
     }
     if constexpr (DIM == 3) {
       if (do_yf) {
         const bool open = !SPH || geo.wf[1][eyc + 1] != R(0);
-        R hf[3];
+        R hf[3], ihf[3];
         face_h<R, SPH>(geo, 1, ex, eyc, eyc + 1, hf);
+        face_ih<R, SPH>(geo, 1, ex, eyc, eyc + 1, ihf);
         const R dlL = proper_width<R, SPH>(geo, 1, ex, eyc);
         const R dlR = proper_width<R, SPH>(geo, 1, ex, eyc + 1);
         for (int u = 0; u < V; ++u) {
           R qR[4] = {R(0), R(0), R(0), R(0)};
           for (int v = 0; v < NC; ++v) qR[v] = LY[cidx(v, col + TXB) + u];
           const R ksR = PV[pvi(NC, prow_own + 1, cx + 1) + u];
-          if (open) hll<R, SPH, DIM>(a, 1, hiY[u], qR, hf, epsilon_of(ks0[u], ksR, dlL, dlR), fyR[u]);
+          if (open) hll<R, SPH, DIM>(a, 1, hiY[u], qR, hf, ihf, epsilon_of(ks0[u], ksR, dlL, dlR), fyR[u]);
           for (int v = 0; v < NC; ++v) FY[cidx(v, col) + u] = fyR[u][v];
         }
       }
@@ -670,10 +674,11 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         R Um[4];
         for (int cc = 0; cc < 4; ++cc) Um[cc] = (cc < NC) ? q0[u][cc] - dtR * acc[cc] : R(0);
         if constexpr (SPH) {
-          R h[3], P[9], Sg[3];
+          R h[3], ih[3], P[9], Sg[3];
           cell_h<R, SPH>(geo, ex, zj + NG, h);
-          closure_full<R, SPH, DIM>(q0[u], h, c, a.closure, P);
-          geometric_source<R>(P, h, geo.gam + 4 * zj, c, Sg);
+          cell_ih<R, SPH>(geo, ex, zj + NG, ih);
+          closure_full<R, SPH, DIM>(q0[u], ih, c, a.closure, P);
+          geometric_source<R>(P, h, ih, geo.gam + 4 * zj, c, Sg);
           for (int cc = 0; cc < DIM; ++cc) Um[1 + cc] += dtR * Sg[cc];
         }
         if (a.Ea) {

@@ -300,7 +300,7 @@ k_step_rows(StepArgs<S> a, Geo<S> geo, RowsTile tl) {
     R lo[4], hiP[4];
     reconstruct<R, false, 2, LIM>(a, geo, 1, mbeg - 1 + NG, qa, qb, q0, hone, hone, true, true, lo, hiP);
     reconstruct<R, false, 2, LIM>(a, geo, 1, mbeg + NG, qb, q0, q1, hone, hone, true, true, lo, hiM);
-    hll<R, false, 2>(a, 1, hiP, lo, hone, epsilon_of(ksb, ks0, dx1, dx1), fPrev);
+    hll<R, false, 2>(a, 1, hiP, lo, hone, hone, epsilon_of(ksb, ks0, dx1, dx1), fPrev);
   }
 
   // ---- one plane; SP = slot of plane m (the slots of m + 1, m + 2 follow cyclically) ----
@@ -342,7 +342,7 @@ k_step_rows(StepArgs<S> a, Geo<S> geo, RowsTile tl) {
     if (upd) {
       R nLo[4];
       reconstruct<R, false, 2, LIM>(a, geo, 1, m + 1 + NG, q0, q1, q2, hone, hone, true, true, nLo, nHi);
-      hll<R, false, 2>(a, 1, hiM, nLo, hone, epsilon_of(ks0, ks1, dx1, dx1), fNext);
+      hll<R, false, 2>(a, 1, hiM, nLo, hone, hone, epsilon_of(ks0, ks1, dx1, dx1), fNext);
     }
     barrier();
     // x face above the own column
@@ -351,7 +351,7 @@ k_step_rows(StepArgs<S> a, Geo<S> geo, RowsTile tl) {
       R qR[4] = {R(0), R(0), R(0), R(0)};
       for (int v = 0; v < RNC; ++v) qR[v] = LX[(v * TXB + c + 1) * GS + g];
       const R ksR = R(P0[ridx(3, c + 2, g)]) + R(P0[ridx(4, c + 2, g)]);
-      hll<R, false, 2>(a, 0, hiX, qR, hone, epsilon_of(ks0, ksR, dx0, dx0), fx);
+      hll<R, false, 2>(a, 0, hiX, qR, hone, hone, epsilon_of(ks0, ksR, dx0, dx0), fx);
       for (int v = 0; v < RNC; ++v) FX[(v * TXB + c) * GS + g] = fx[v];
     }
     barrier();
