@@ -294,7 +294,7 @@ def main():
                    "zone_groups": w.zone_groups, "dt": w.dt},
         "roofline": {"bound": "hbm", "achieved": round(h["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(h["achieved"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "k_step_rows<double, 0, 1>", "bytes_per_zone_group": h["bpz"],
+                     "kernel": "k_step_rows<double, 0>", "bytes_per_zone_group": h["bpz"],
                      "kernel_ms": round(h["ms_kernel"], 5)},
         "extra": extra,
     }

@@ -225,9 +225,12 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
   }
   const bool ok =
       (!lo_open || realizable<R, SPH, ND>(lo, ihlo, c)) && (!hi_open || realizable<R, SPH, ND>(hi, ihhi, c));
-  for (int cp = 0; cp <= ND; ++cp) {
-    lo[cp] = ok ? lo[cp] : q0[cp];
-    hi[cp] = ok ? hi[cp] : q0[cp];
+  // the fallback is rare: the selects only run in a wave where some lane needs it
+  if (__builtin_amdgcn_ballot_w64(!ok)) {
+    for (int cp = 0; cp <= ND; ++cp) {
+      lo[cp] = ok ? lo[cp] : q0[cp];
+      hi[cp] = ok ? hi[cp] : q0[cp];
+    }
   }
   for (int cp = ND + 1; cp < 4; ++cp) lo[cp] = hi[cp] = R(0);
 }
@@ -375,7 +378,10 @@ __device__ __forceinline__ void hll(const StepArgsBase& a, int d, const R qL[4],
 template <typename R>
 __device__ __forceinline__ R epsilon_of(R ksL, R ksR, R dlL, R dlR) {
   const R tau = R(0.5) * (ksL + ksR) * (R(0.5) * (dlL + dlR));
-  return (tau > R(1)) ? rcp_(tau) : R(1);
+  // the reciprocal only in a wave where some face is optically thick
+  R eps = R(1);
+  if (__builtin_amdgcn_ballot_w64(tau > R(1))) eps = (tau > R(1)) ? rcp_(tau) : R(1);
+  return eps;
 }
 
 // Flux through the d-face with index f (face f-1/2 of zone f along d) of the row (i, j), from

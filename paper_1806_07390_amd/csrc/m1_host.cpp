@@ -398,7 +398,9 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   }
   // the whole-zone kernel where the grid qualifies (FORNAX_M1_ROWS="0" disables it,
   // "NWX,TM" picks its tiling)
-  ctx->rows = choose_rows_tile(*desc);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) cus = 0;
+  ctx->rows = choose_rows_tile(*desc, cus);
   if (const char* env = std::getenv("FORNAX_M1_ROWS")) {
     int nwx = 0, tm = 0;
     if (env[0] == '0' && env[1] == 0) ctx->rows = fm1::RowsTile{};

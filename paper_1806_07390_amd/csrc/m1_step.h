@@ -24,9 +24,9 @@ int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, hi
 
 // The 2-D, 16-group kernel with whole-zone transfers through LDS (m1_step_rows.hip): a tile
 // with nblocks = 0 when the grid does not qualify (2-D Cartesian, 16 groups, arrays under
-// 2 GiB; NWX in {1, 2}; TM a multiple of 3).
+// 2 GiB; NWX = 1; TM >= 3).
 RowsTile make_rows_tile(const fornax_m1_desc& D, int NWX, int TM);
-RowsTile choose_rows_tile(const fornax_m1_desc& D);
+RowsTile choose_rows_tile(const fornax_m1_desc& D, int cus);
 template <typename S>
 int launch_rows(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipStream_t st);
 
