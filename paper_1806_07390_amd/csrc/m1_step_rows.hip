@@ -414,9 +414,8 @@ k_step_rows(StepArgs<S> a, Geo<S> geo, RowsTile tl) {
       __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
       barrier();
     }
-    // the slot plane m - 1 has left: plane m + 3 (past the last plane used, the last one
-    // again, so that every plane issues the same loads)
-    issue(min(m + 3, mend + 1), std::integral_constant<int, s3>{});
+    // the slot plane m - 1 has left: plane m + 3, when it is used (up to mend + 1)
+    if (m + 3 <= mend + 1) issue(m + 3, std::integral_constant<int, s3>{});
     // the outputs of plane m - 1
     if (m > mbeg) {
       store_out(rsE, off_o, Eo_o);
