@@ -977,3 +977,266 @@ int orc_closure(const OrcDesc* D, double E, const double* Fphys, double* P) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------------------
+// Explicit transport alone (Algorithmic Steps, Step 1 for a static medium): U^- = U^n +
+// dt L(U^n) for every zone-group, without the interaction update.
+// ------------------------------------------------------------------------------------
+extern "C" int orc_explicit(const OrcDesc* D, const double* E, const double* const* F, const double* kap,
+                            const double* sig, const double* inflow, double dt, double* Eo, double* const* Fo) {
+  Geom geo;
+  geo.build(*D);
+  Ctx<double> C;
+  C.D = D;
+  C.geo = &geo;
+  for (int d = 0; d < 3; ++d) C.n[d] = D->n[d];
+  C.G = D->G;
+  C.ndim = D->ndim;
+  C.c = D->c;
+  C.dt = dt;
+  C.E = E;
+  for (int k = 0; k < 3; ++k) C.F[k] = (k < D->ndim) ? F[k] : nullptr;
+  C.kap = kap;
+  C.sig = sig;
+  C.B = nullptr;
+  C.inflow = inflow;
+  set_threads(D);
+  long nz = (long)C.n[0] * C.n[1] * C.n[2];
+#pragma omp parallel for schedule(static)
+  for (long z = 0; z < nz; ++z) {
+    int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
+    for (int g = 0; g < C.G; ++g) {
+      double Um[4];
+      explicit_update(C, idx, g, Um);
+      size_t zg = (size_t)z * C.G + g;
+      Eo[zg] = Um[0];
+      for (int k = 0; k < D->ndim; ++k) Fo[k][zg] = Um[1 + k];
+    }
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------
+// Radiation-matter energy exchange with the matter temperature as unknown (Interaction
+// Terms subsection, photon case: one outer equation; Algorithmic Steps, Steps 3 and 4).
+//
+// Matter model (Reading: the paper leaves the equation of state and the opacities to the
+// application; this follows its multigroup pulse test):
+//   internal energy density u = cv T (ideal gas, cv per zone);
+//   absorption kappa_g(T) = kappa0 kg_g T^(-1/2) (1 - exp(-nu_g / T)) (the pulse test's
+//     frequency- and temperature-dependent opacity at the group's frequency nu_g, with
+//     kg_g holding the normalisation and the nu^-3 factor; units with h = k_B = 1);
+//   emission j_g = c kappa_g B_g(T), B_g(T) = a_R T^4 (15/pi^4) int_{x_g}^{x_{g+1}}
+//     x^3 / (e^x - 1) dx, x = nu / T, over the group's frequency edges (Kirchhoff's law
+//     with the group-integrated Planck function; edges 0 and infinity allowed);
+//   scattering sigma_g per zone-group, independent of T.
+// ------------------------------------------------------------------------------------
+static const double ORC_PI4_15 = 6.4939394022668291;   // pi^4 / 15 = int_0^inf x^3/(e^x-1) dx
+
+// int_0^x t^3 / (e^t - 1) dt for 0 <= x < 2 pi: the series from t/(e^t - 1) = sum_k B_k t^k / k!
+// (Bernoulli numbers), integrated term by term.
+static double orc_planck_head_(double x) {
+  // B_k / k! for k = 0 .. 24 (odd k > 1 vanish)
+  static const double bk[25] = {1.0,
+                                -0.5,
+                                1.0 / 12.0,
+                                0.0,
+                                -1.0 / 720.0,
+                                0.0,
+                                1.0 / 30240.0,
+                                0.0,
+                                -1.0 / 1209600.0,
+                                0.0,
+                                1.0 / 47900160.0,
+                                0.0,
+                                -691.0 / 1307674368000.0,
+                                0.0,
+                                1.0 / 74724249600.0,
+                                0.0,
+                                -3617.0 / 10670622842880000.0,
+                                0.0,
+                                43867.0 / 5109094217170944000.0,
+                                0.0,
+                                -174611.0 / 802857662698291200000.0,
+                                0.0,
+                                77683.0 / 14101100039391805440000.0,
+                                0.0,
+                                -236364091.0 / 1693824136731743669452800000.0};
+  double head = 0.0, p = x * x * x;
+  for (int k = 0; k < 25; ++k) {
+    head += bk[k] * p / (double)(k + 3);
+    p *= x;
+  }
+  return head;
+}
+
+// int_x^inf t^3 / (e^t - 1) dt for x >= 1.5 (infinity gives 0): 1/(e^t - 1) = sum_n e^(-n t)
+// and t^3 e^(-n t) integrated in closed form.
+static double orc_planck_exp_tail_(double x) {
+  if (!(x < INFINITY)) return 0.0;
+  double s = 0.0;
+  for (int n = 1; n <= 60; ++n) {
+    double e = std::exp(-n * x);
+    if (e < 1e-300) break;
+    double dn = (double)n;
+    s += e * (x * x * x / dn + 3.0 * x * x / (dn * dn) + 6.0 * x / (dn * dn * dn) + 6.0 / (dn * dn * dn * dn));
+    if (e < 1e-18 * s) break;
+  }
+  return s;
+}
+
+static const double ORC_PLANCK_SPLIT = 1.5;   // the head series below, the exponential series above
+
+// int_x^inf t^3 / (e^t - 1) dt for x >= 0
+static double orc_planck_tail_(double x) {
+  return x < ORC_PLANCK_SPLIT ? ORC_PI4_15 - orc_planck_head_(x) : orc_planck_exp_tail_(x);
+}
+
+// int_a^b t^3 / (e^t - 1) dt for 0 <= a <= b <= infinity, without subtracting two large
+// integrals where the interval is small: heads below the split, tails above it
+static double orc_planck_between_(double a, double b) {
+  if (b <= ORC_PLANCK_SPLIT) return orc_planck_head_(b) - orc_planck_head_(a);
+  if (a >= ORC_PLANCK_SPLIT) return orc_planck_exp_tail_(a) - orc_planck_exp_tail_(b);
+  return (orc_planck_head_(ORC_PLANCK_SPLIT) - orc_planck_head_(a)) +
+         (orc_planck_exp_tail_(ORC_PLANCK_SPLIT) - orc_planck_exp_tail_(b));
+}
+
+struct OrcMatterModel {
+  int G;
+  const double* nu_edge;   // [G + 1] group frequency edges (0 and infinity allowed)
+  const double* nu_c;      // [G] frequency of the group's opacity
+  const double* kg;        // [G] opacity factor of the group
+  double a_rad;            // radiation constant
+  double c;                // speed of light
+  double tol;              // relative change of T that ends the Newton iteration
+  int max_newton;          // Newton iterations before bisection takes over
+};
+
+static double orc_group_B(const OrcMatterModel& M, int g, double T) {
+  const double part = orc_planck_between_(M.nu_edge[g] / T, M.nu_edge[g + 1] / T);
+  return M.a_rad * T * T * T * T * part / ORC_PI4_15;
+}
+
+static double orc_group_kappa(const OrcMatterModel& M, int g, double kappa0, double T) {
+  return kappa0 * M.kg[g] / std::sqrt(T) * (1.0 - std::exp(-M.nu_c[g] / T));
+}
+
+// Inner update of every group at temperature T (eq:be_update), and the outer residual
+// r(T) = u(T) - u^- + sum_g (E_g(T) - E_g^-) (Interaction Terms: r_E with Delta E^k).
+static double orc_residual(const OrcMatterModel& M, double dt, double cv, double kappa0, double Tm, const double* Em,
+                           double T, double* Eout) {
+  double dE = 0.0;
+  for (int g = 0; g < M.G; ++g) {
+    double kap = orc_group_kappa(M, g, kappa0, T);
+    double j = M.c * kap * orc_group_B(M, g, T);
+    double E = (Em[g] + dt * j) / (1.0 + M.c * dt * kap);
+    if (Eout) Eout[g] = E;
+    dE += E - Em[g];
+  }
+  return cv * (T - Tm) + dE;
+}
+
+// Outer update of one zone: Newton-Raphson on r(T) = 0 from T^- with a forward-difference
+// derivative and a backtracking line search (halving the step until |r| decreases), ended
+// when the relative change of T is below tol; bisection between 0 and the temperature that
+// holds all the radiation's energy when Newton fails (r is increasing in T and negative at
+// 0: the root is bracketed).  Reading: the paper gives the method (finite-difference
+// Jacobian, backtracking, bisection fallback, tolerance on the relative change of T,
+// typically 1e-6) but not its constants; those here are: derivative step 1e-7 T, at most 10
+// halvings, bisection until the bracket is 1e-13 of its upper end.  Returns the number of
+// Newton iterations, or -(bisection steps) when bisection decided T.
+static int orc_solve_T(const OrcMatterModel& M, double dt, double cv, double kappa0, double Tm, const double* Em,
+                       double* Tout) {
+  double T = Tm;
+  double r = orc_residual(M, dt, cv, kappa0, Tm, Em, T, nullptr);
+  for (int it = 0; it < M.max_newton; ++it) {
+    double h = 1e-7 * T;
+    double J = (orc_residual(M, dt, cv, kappa0, Tm, Em, T + h, nullptr) - r) / h;
+    if (!(J > 0.0)) break;
+    double d = -r / J;
+    if (std::fabs(d) <= M.tol * T) {
+      *Tout = T + d;
+      return it + 1;
+    }
+    double lam = 1.0, Tn = T, rn = r;
+    bool ok = false;
+    for (int ls = 0; ls <= 10; ++ls) {
+      Tn = T + lam * d;
+      if (Tn > 0.0) {
+        rn = orc_residual(M, dt, cv, kappa0, Tm, Em, Tn, nullptr);
+        if (std::fabs(rn) < std::fabs(r)) {
+          ok = true;
+          break;
+        }
+      }
+      lam *= 0.5;
+    }
+    if (!ok) break;
+    bool conv = std::fabs(Tn - T) <= M.tol * Tn;
+    T = Tn;
+    r = rn;
+    if (conv) {
+      *Tout = T;
+      return it + 1;
+    }
+  }
+  double esum = 0.0;
+  for (int g = 0; g < M.G; ++g) esum += std::max(Em[g], 0.0);
+  double lo = 0.0, hi = Tm + esum / cv;
+  int steps = 0;
+  while (hi - lo > 1e-13 * hi && steps < 400) {
+    double mid = 0.5 * (lo + hi);
+    if (orc_residual(M, dt, cv, kappa0, Tm, Em, mid, nullptr) > 0.0)
+      hi = mid;
+    else
+      lo = mid;
+    ++steps;
+  }
+  *Tout = 0.5 * (lo + hi);
+  return -steps;
+}
+
+extern "C" {
+
+double orc_planck_tail(double x) { return orc_planck_tail_(x); }
+
+// kappa_g(T) and B_g(T) of every zone-group: kap, B [nz][G].
+int orc_matter_coeffs(int G, const double* nu_edge, const double* nu_c, const double* kg, double a_rad, long nz,
+                      const double* kappa0, const double* T, double* kap, double* B) {
+  OrcMatterModel M{G, nu_edge, nu_c, kg, a_rad, 1.0, 0.0, 0};
+  for (long z = 0; z < nz; ++z)
+    for (int g = 0; g < G; ++g) {
+      kap[z * G + g] = orc_group_kappa(M, g, kappa0[z], T[z]);
+      B[z * G + g] = orc_group_B(M, g, T[z]);
+    }
+  return 0;
+}
+
+// The interaction update with the matter energy equation, in place on E, F[k] (ndim arrays)
+// and T, per zone: the outer solve for T^{n+1}, the groups' inner update at T^{n+1}, then the
+// flux update F^{n+1} = F^- / (1 + c dt (kappa_g(T^{n+1}) + sigma_g)).  dEm (nullable):
+// u^{n+1} - u^- per zone; iters (nullable): the solve's return value per zone.
+int orc_matter_source(int G, const double* nu_edge, const double* nu_c, const double* kg, double a_rad, double c,
+                      double tol, int max_newton, int ndim, long nz, double* E, double* const* F, const double* sig,
+                      const double* cv, const double* kappa0, double* T, double dt, double* dEm, int* iters) {
+  OrcMatterModel M{G, nu_edge, nu_c, kg, a_rad, c, tol, max_newton};
+#pragma omp parallel for schedule(dynamic, 64)
+  for (long z = 0; z < nz; ++z) {
+    double* Ez = E + z * G;
+    std::vector<double> Em(Ez, Ez + G), E1(G);
+    double T1 = T[z];
+    int it = orc_solve_T(M, dt, cv[z], kappa0[z], T[z], Em.data(), &T1);
+    orc_residual(M, dt, cv[z], kappa0[z], T[z], Em.data(), T1, E1.data());
+    for (int g = 0; g < G; ++g) {
+      Ez[g] = E1[g];
+      double kap = orc_group_kappa(M, g, kappa0[z], T1);
+      for (int k = 0; k < ndim; ++k) F[k][z * G + g] /= (1.0 + c * dt * (kap + sig[z * G + g]));
+    }
+    if (dEm) dEm[z] = cv[z] * (T1 - T[z]);
+    if (iters) iters[z] = it;
+    T[z] = T1;
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -81,6 +81,12 @@ def lib():
         _lib.orc_jvp.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, vp, vp, vp, d, ctypes.c_int, vp, vp, vp, vp]
         _lib.orc_geometry.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_closure.argtypes = [P(OrcDesc), d, vp, vp]
+        _lib.orc_explicit.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, d, vp, vp]
+        _lib.orc_planck_tail.restype = d
+        _lib.orc_planck_tail.argtypes = [d]
+        _lib.orc_matter_coeffs.argtypes = [ctypes.c_int, vp, vp, vp, d, ctypes.c_long, vp, vp, vp, vp]
+        _lib.orc_matter_source.argtypes = [ctypes.c_int, vp, vp, vp, d, d, d, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_long, vp, vp, vp, vp, vp, vp, d, vp, vp]
     return _lib
 
 
@@ -268,3 +274,81 @@ def closure(E, Fphys, c=1.0, eddington=False):
     P = np.empty(9)
     lib().orc_closure(ctypes.byref(desc), float(E), _ptr(F), _ptr(P))
     return P.reshape(3, 3)
+
+
+def explicit(p: Problem, E, F, kappa, sigma, dt, inflow=None):
+    """The explicit transport update alone (U^- = U^n + dt L(U^n)). Returns (E, [F_k])."""
+    d = p.desc()
+    E = _c(E)
+    F = [_c(f) for f in F]
+    kappa, sigma = _c(kappa), _c(sigma)
+    inflow = None if inflow is None else _c(inflow)
+    Eo = np.empty_like(E)
+    Fo = [np.empty_like(E) for _ in range(p.ndim)]
+    lib().orc_explicit(ctypes.byref(d), E.ctypes.data, _ptrs(F), kappa.ctypes.data, sigma.ctypes.data,
+                       None if inflow is None else inflow.ctypes.data, dt, Eo.ctypes.data, _ptrs(Fo))
+    return Eo, Fo
+
+
+# ---- radiation-matter energy exchange (photon case: one outer equation for T) ----
+
+def planck_tail(x: float) -> float:
+    """int_x^inf t^3/(e^t - 1) dt."""
+    return lib().orc_planck_tail(float(x))
+
+
+@dataclass
+class MatterModel:
+    """Group tables of the matter model: frequency edges nu_edge [G+1] (0 and inf allowed),
+    opacity frequency nu_c [G] and factor kg [G], radiation constant a_rad, light speed c;
+    Newton tolerance on the relative change of T and the Newton iterations before bisection."""
+
+    nu_edge: np.ndarray
+    nu_c: np.ndarray
+    kg: np.ndarray
+    a_rad: float = 1.0
+    c: float = 1.0
+    tol: float = 1e-6
+    max_newton: int = 30
+
+    @property
+    def G(self):
+        return len(self.nu_c)
+
+
+def matter_coeffs(m: MatterModel, kappa0, T):
+    """kappa_g(T) and B_g(T) per zone-group ([..., G])."""
+    kappa0, T = _c(kappa0), _c(T)
+    nz = T.size
+    kap = np.empty(T.shape + (m.G,))
+    B = np.empty_like(kap)
+    ne, nc, kg = _c(m.nu_edge), _c(m.nu_c), _c(m.kg)
+    lib().orc_matter_coeffs(m.G, ne.ctypes.data, nc.ctypes.data, kg.ctypes.data, m.a_rad, nz, kappa0.ctypes.data,
+                            T.ctypes.data, kap.ctypes.data, B.ctypes.data)
+    return kap, B
+
+
+def matter_source(m: MatterModel, E, F, sigma, cv, kappa0, T, dt):
+    """Interaction update with the matter energy equation (zone arrays cv, kappa0, T shaped like
+    E without its group axis). Returns (E, [F_k], T, dE_matter = u^{n+1} - u^-, iterations)."""
+    E = _c(E).copy()
+    F = [_c(f).copy() for f in F]
+    sigma, cv, kappa0 = _c(sigma), _c(cv), _c(kappa0)
+    T = _c(T).copy()
+    nz = T.size
+    dEm = np.empty(T.shape)
+    it = np.empty(T.shape, dtype=np.int32)
+    ne, nc, kg = _c(m.nu_edge), _c(m.nu_c), _c(m.kg)
+    lib().orc_matter_source(m.G, ne.ctypes.data, nc.ctypes.data, kg.ctypes.data, m.a_rad, m.c, m.tol, m.max_newton,
+                            len(F), nz, E.ctypes.data, _ptrs(F), sigma.ctypes.data, cv.ctypes.data,
+                            kappa0.ctypes.data, T.ctypes.data, dt, dEm.ctypes.data, it.ctypes.data)
+    return E, F, T, dEm, it
+
+
+def matter_step(p: Problem, m: MatterModel, E, F, sigma, cv, kappa0, T, dt, inflow=None):
+    """One step with the matter coupled (Algorithmic Steps 1, 3, 4 for a static medium):
+    explicit transport with the opacities at T^n, then the interaction update with the outer
+    solve for T^{n+1}. Returns (E, [F_k], T, dE_matter, iterations)."""
+    kap, _ = matter_coeffs(m, kappa0, T)
+    Em, Fm = explicit(p, E, F, kap, sigma, dt, inflow=inflow)
+    return matter_source(m, Em, Fm, sigma, cv, kappa0, T, dt)

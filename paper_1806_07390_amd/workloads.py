@@ -12,6 +12,8 @@ Workloads (sizes overridable for reduced parity cases):
   * ``core3d``   3-D 192^3, 12 groups, opaque core in a thin halo, Planck group weights (50 steps)
   * ``sphere3d`` spherical (ln r, theta, phi) 256x64x128, 20 groups, inner inflow (100 steps)
   * ``adjoint2d`` 2-D periodic 256^2, 16 groups, lognormal per zone-group opacity (40 steps)
+  * ``matter2d`` the ``blobs2d`` radiation with a matter temperature, heat capacity and
+    opacity scale per zone (the radiation-matter energy exchange)
 """
 from __future__ import annotations
 
@@ -206,3 +208,43 @@ def adjoint2d(n=256, G=16, steps=40, seed=0, window=32):
                   dt=0.2 / n)
     wl.extra = dict(window=(ix, iy, window), ckpt_every=8)
     return wl
+
+
+@dataclass
+class MatterGroups:
+    """Group tables of the matter model: frequency edges [G+1] (first 0, last inf), the
+    frequency at which a group's opacity is taken [G] and the group's opacity factor [G]."""
+
+    nu_edge: np.ndarray
+    nu_c: np.ndarray
+    kg: np.ndarray
+    a_rad: float = 1.0
+
+
+def matter_groups(G=16, lo=0.1, hi=30.0, T1=1.0):
+    """Edges 0, G - 1 log-spaced on [lo, hi] (units of k_B T1 / h), inf; opacity frequency the
+    geometric mean of a group's edges (lo/2 and 2 hi for the two open groups); opacity factor
+    (nu_c / nu_1)^-3 T1^(1/2) with nu_1 = 2.821 T1, the normalisation of the paper's pulse test."""
+    inner = np.geomspace(lo, hi, G - 1)
+    edges = np.concatenate([[0.0], inner, [np.inf]])
+    nu_c = np.empty(G)
+    nu_c[0] = 0.5 * inner[0]
+    nu_c[1:G - 1] = np.sqrt(inner[:-1] * inner[1:])
+    nu_c[G - 1] = 2.0 * inner[-1]
+    kg = (nu_c / (2.821 * T1)) ** -3 * math.sqrt(T1)
+    return MatterGroups(edges, nu_c, kg)
+
+
+def matter2d(n=512, G=16, steps=100, seed=0, kappa_scale=1.0):
+    """The blobs2d radiation with matter: temperature T = exp(0.3 z1) per zone (z1 ~ N(0,1)),
+    heat capacity cv = exp(0.5 z2), opacity scale kappa0 = kappa_scale exp(z3) (the opacity of
+    the groups follows from T through the matter model), sigma as in blobs2d."""
+    w = blobs2d(n=n, G=G, steps=steps, seed=seed)
+    rng = np.random.default_rng(seed + 101)
+    z = rng.standard_normal((3, 1, n, n))
+    w.name = "matter2d"
+    w.T = np.exp(0.3 * z[0])
+    w.cv = np.exp(0.5 * z[1])
+    w.kappa0 = kappa_scale * np.exp(z[2])
+    w.groups = matter_groups(G)
+    return w
