@@ -12,7 +12,8 @@
  *     geometric source terms of the covariant form (Appendix: covariant form, connection
  *     coefficients, eq:angmom, eq:grad2P);
  *   - operator-split backward-Euler interaction update (Interaction Terms, eq:be_update and
- *     the flux update that follows it), Algorithmic Steps 1, 3 and 4 with matter held fixed.
+ *     the flux update that follows it), Algorithmic Steps 1, 3 and 4 with matter held fixed,
+ *     or with the matter temperature solved for (the outer update; photons, ideal gas).
  *
  * Conventions
  *   - Every array pointer is a DEVICE pointer (hipMalloc'd or a torch CUDA tensor's data).
@@ -152,6 +153,61 @@ int fornax_m1_adjoint(fornax_m1_ctx *ctx, const fornax_m1_state *Un, const forna
                       const fornax_m1_coeffs *cf, const double *inflow, double dt,
                       const fornax_m1_state *lam_np1, fornax_m1_state *lam_n, void *dkappa_accum,
                       void *stream);
+
+/* Explicit transport alone (Algorithmic Steps, step 1 with v = 0): out = U^- = U^n + dt L(U^n)
+ * (with the SSPRK2 integrator, U^- = (U^n + U* + dt L(U*)) / 2), without the interaction
+ * update.  cf->B is not read and may be NULL.  Same rules and errors as fornax_m1_step. */
+int fornax_m1_transport(fornax_m1_ctx *ctx, const fornax_m1_state *in, fornax_m1_state *out,
+                        const fornax_m1_coeffs *cf, const double *inflow, double dt, void *stream);
+
+/* ---- Radiation-matter energy exchange (Interaction Terms: the outer update; photons, one
+ * equation for the matter temperature T) ----
+ * Matter model: internal energy density u = cv T (ideal gas); absorption
+ *   kappa_g(T) = kappa0 * kg[g] * T^(-1/2) * (1 - exp(-nu_c[g] / T))
+ * (the frequency- and temperature-dependent opacity of the paper's multigroup pulse test, at
+ * the group's frequency nu_c[g]; units with h = k_B = 1); emission j_g = c kappa_g B_g(T) with
+ *   B_g(T) = a_rad T^4 (15/pi^4) int_{nu_edge[g]/T}^{nu_edge[g+1]/T} x^3/(e^x - 1) dx
+ * (Kirchhoff's law with the group-integrated Planck function); scattering sigma_g per
+ * zone-group, independent of T. */
+typedef struct {
+  int32_t ngroups;          /* must equal the context's ngroups (<= 64) */
+  const double *nu_edge;    /* HOST array [ngroups + 1], increasing, >= 0; the last may be +inf */
+  const double *nu_c;       /* HOST array [ngroups], > 0 */
+  const double *kg;         /* HOST array [ngroups], >= 0 */
+  double a_rad;             /* radiation constant, > 0 */
+  double tol;               /* Newton ends when |T^{k+1} - T^k| <= tol T^{k+1} (the paper: 1e-6) */
+  int32_t max_newton;       /* Newton iterations before bisection decides T (0: bisection only) */
+} fornax_m1_matter_model;
+
+typedef struct {
+  const double *cv;         /* [nzones] heat capacity per volume, > 0 */
+  const double *kappa0;     /* [nzones] opacity scale, >= 0 */
+  double *T;                /* [nzones] matter temperature, > 0; in: T^-, out: T^{n+1} */
+} fornax_m1_matter;         /* device arrays of doubles */
+
+/* Copies the model's tables into the context (host call; synchronous with the null stream).
+ * EINVAL for a bad table, EUNSUPPORTED for ngroups > 64. */
+int fornax_m1_set_matter_model(fornax_m1_ctx *ctx, const fornax_m1_matter_model *model);
+
+/* kappa_g(T) and B_g(T) of every zone-group into kappa_out and B_out (zone-group arrays of the
+ * context's type), for the transport with the opacities at T^n.  EINVAL without a model. */
+int fornax_m1_matter_coeffs(fornax_m1_ctx *ctx, const fornax_m1_matter *m, void *kappa_out, void *B_out,
+                            void *stream);
+
+/* The interaction update with the matter energy equation, in place, per zone (all groups of a
+ * zone together): the outer solve of r(T) = cv (T - T^-) + sum_g (E_g(T) - E_g^-) = 0 by
+ * Newton-Raphson from T^- (forward-difference derivative with step 1e-7 T, backtracking by
+ * halving until |r| decreases, at most 10 halvings), bisection on (0, T^- + sum_g max(E_g^-, 0)
+ * / cv] until the bracket is 1e-13 of its upper end when Newton fails or runs out of
+ * iterations; each group's inner backward-Euler update E_g(T) = (E_g^- + dt c kappa_g B_g)
+ * / (1 + c dt kappa_g) (eq:be_update) at the converged T; then F^{n+1} = F^- / (1 + c dt
+ * (kappa_g(T^{n+1}) + sigma_g)).  Always computed in double (float states are read and
+ * written as float).  dE_matter (nullable): u^{n+1} - u^- per zone; iters (nullable, int32):
+ * Newton iterations, or -(bisection steps) where bisection decided T.  EINVAL without a model
+ * or for bad pointers. */
+int fornax_m1_matter_source(fornax_m1_ctx *ctx, fornax_m1_state *inout, const void *sigma,
+                            const fornax_m1_matter *m, double dt, double *dE_matter, int32_t *iters,
+                            void *stream);
 
 /* Measurement utility (not part of the method): plain device-to-device copy of `nbytes`
  * (multiple of 16, 16-byte aligned pointers) with the library's own kernel, used to scale

@@ -475,6 +475,7 @@ int fornax_m1_destroy(fornax_m1_ctx* ctx) {
     if (ctx->adj_gbuf[d]) (void)hipFree(ctx->adj_gbuf[d]);
   if (ctx->adj_u1) (void)hipFree(ctx->adj_u1);
   if (ctx->stage_mem) (void)hipFree(ctx->stage_mem);
+  if (ctx->mat_tab) (void)hipFree(ctx->mat_tab);
   delete ctx;
   return FORNAX_OK;
 }
@@ -561,6 +562,81 @@ int fornax_m1_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const forna
   if (needs_inflow(ctx->desc) != (inflow != nullptr)) return FORNAX_EINVAL;
   if (!(dt > 0.0) || dt > ctx->max_dt1 * (1.0 + 1e-12)) return FORNAX_ECFL;
   return fm1_launch_adjoint(ctx, Un, Unp1, cf, inflow, dt, lam_np1, lam_n, dkappa_accum, (hipStream_t)stream);
+}
+
+int fornax_m1_transport(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
+                        const fornax_m1_coeffs* cf, const double* inflow, double dt, void* stream) {
+  if (!ctx || !cf || !cf->kappa || !cf->sigma) return FORNAX_EINVAL;
+  int rc;
+  if ((rc = check_state(ctx, in)) || (rc = check_state(ctx, out))) return rc;
+  const size_t al = ctx->desc.precision == FORNAX_FP64 ? 8 : 4;
+  if (!aligned(cf->kappa, al) || !aligned(cf->sigma, al) || (cf->B && !aligned(cf->B, al))) return FORNAX_EINVAL;
+  if (overlaps(ctx, in, out)) return FORNAX_EINVAL;
+  if (needs_inflow(ctx->desc) != (inflow != nullptr)) return FORNAX_EINVAL;
+  if (!(dt > 0.0) || dt > ctx->max_dt1 * (1.0 + 1e-12)) return FORNAX_ECFL;
+  return fm1_launch_transport(ctx, in, out, cf, inflow, dt, (hipStream_t)stream);
+}
+
+int fornax_m1_set_matter_model(fornax_m1_ctx* ctx, const fornax_m1_matter_model* mm) {
+  if (!ctx || !mm || !mm->nu_edge || !mm->nu_c || !mm->kg) return FORNAX_EINVAL;
+  const int G = ctx->desc.ngroups;
+  if (mm->ngroups != G) return FORNAX_EINVAL;
+  if (G > 64) return FORNAX_EUNSUPPORTED;
+  if (!(mm->a_rad > 0.0) || !std::isfinite(mm->a_rad) || !(mm->tol > 0.0) || !(mm->tol < 1.0) ||
+      mm->max_newton < 0)
+    return FORNAX_EINVAL;
+  if (!(mm->nu_edge[0] >= 0.0) || !std::isfinite(mm->nu_edge[0])) return FORNAX_EINVAL;
+  for (int g = 0; g < G; ++g) {
+    if (!(mm->nu_edge[g + 1] > mm->nu_edge[g])) return FORNAX_EINVAL;
+    if (g + 1 < G && !std::isfinite(mm->nu_edge[g + 1])) return FORNAX_EINVAL;
+    if (!(mm->nu_c[g] > 0.0) || !std::isfinite(mm->nu_c[g]) || !(mm->kg[g] >= 0.0) || !std::isfinite(mm->kg[g]))
+      return FORNAX_EINVAL;
+  }
+  std::vector<double> tab((size_t)3 * G + 1);
+  for (int g = 0; g <= G; ++g) tab[g] = mm->nu_edge[g];
+  for (int g = 0; g < G; ++g) {
+    tab[G + 1 + g] = mm->nu_c[g];
+    tab[2 * G + 1 + g] = mm->kg[g];
+  }
+  if (!ctx->mat_tab && hipMalloc((void**)&ctx->mat_tab, tab.size() * sizeof(double)) != hipSuccess) {
+    ctx->mat_tab = nullptr;
+    return FORNAX_ENOMEM;
+  }
+  if (hipMemcpy(ctx->mat_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return FORNAX_EDEVICE;
+  ctx->mat_a = mm->a_rad;
+  ctx->mat_tol = mm->tol;
+  ctx->mat_maxn = mm->max_newton;
+  return FORNAX_OK;
+}
+
+static int check_matter(const fornax_m1_ctx* ctx, const fornax_m1_matter* m) {
+  if (!ctx->mat_tab) return FORNAX_EINVAL;
+  if (!m || !m->cv || !m->kappa0 || !m->T) return FORNAX_EINVAL;
+  if (!aligned(m->cv, 8) || !aligned(m->kappa0, 8) || !aligned(m->T, 8)) return FORNAX_EINVAL;
+  return FORNAX_OK;
+}
+
+int fornax_m1_matter_coeffs(fornax_m1_ctx* ctx, const fornax_m1_matter* m, void* kappa_out, void* B_out,
+                            void* stream) {
+  if (!ctx || !kappa_out || !B_out) return FORNAX_EINVAL;
+  int rc;
+  if ((rc = check_matter(ctx, m))) return rc;
+  const size_t al = ctx->desc.precision == FORNAX_FP64 ? 8 : 4;
+  if (!aligned(kappa_out, al) || !aligned(B_out, al) || kappa_out == B_out) return FORNAX_EINVAL;
+  return fm1_launch_matter_coeffs(ctx, m, kappa_out, B_out, (hipStream_t)stream);
+}
+
+int fornax_m1_matter_source(fornax_m1_ctx* ctx, fornax_m1_state* inout, const void* sigma,
+                            const fornax_m1_matter* m, double dt, double* dE_matter, int32_t* iters, void* stream) {
+  if (!ctx || !sigma) return FORNAX_EINVAL;
+  int rc;
+  if ((rc = check_state(ctx, inout)) || (rc = check_matter(ctx, m))) return rc;
+  const size_t al = ctx->desc.precision == FORNAX_FP64 ? 8 : 4;
+  if (!aligned(sigma, al) || (dE_matter && !aligned(dE_matter, 8)) || (iters && !aligned(iters, 4)))
+    return FORNAX_EINVAL;
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return FORNAX_EINVAL;
+  return fm1_launch_matter_source(ctx, inout, sigma, m, dt, dE_matter, iters, (hipStream_t)stream);
 }
 
 int fornax_m1_copy_probe(void* dst, const void* src, int64_t nbytes, void* stream) {

@@ -176,6 +176,10 @@ struct fornax_m1_ctx {
   double* adj_gbuf[3];
   int adj_gplane[3];
   void* adj_u1;               // U^{n+1} scratch of the adjoint (allocated by its first call)
+  // matter model (fornax_m1_set_matter_model): device tables nu_edge [G+1], nu_c [G], kg [G]
+  double* mat_tab;
+  double mat_a, mat_tol;
+  int mat_maxn;
 };
 
 // kernel launchers (m1_kernels.hip)
@@ -191,3 +195,11 @@ int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const forn
                        const double* inflow, double dt, const fornax_m1_state* lam_np1,
                        fornax_m1_state* lam_n, void* dkappa, hipStream_t stream);
 int fm1_launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t stream);
+int fm1_launch_transport(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
+                         const fornax_m1_coeffs* cf, const double* inflow, double dt, hipStream_t stream);
+// m1_matter.hip
+int fm1_launch_matter_coeffs(fornax_m1_ctx* ctx, const fornax_m1_matter* m, void* kap, void* B,
+                             hipStream_t stream);
+int fm1_launch_matter_source(fornax_m1_ctx* ctx, fornax_m1_state* io, const void* sigma,
+                             const fornax_m1_matter* m, double dt, double* dEm, int* iters,
+                             hipStream_t stream);

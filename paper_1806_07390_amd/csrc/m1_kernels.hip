@@ -254,6 +254,39 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
   return FORNAX_OK;
 }
 
+// The explicit transport alone: the step kernel without the interaction update (the state
+// the interaction update would start from, U^-).  B is not used; the kernels still load it,
+// so a missing B reads the opacity array instead.
+template <typename S, typename R>
+int launch_transport_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* in, fornax_m1_state* out,
+                       const fornax_m1_coeffs* cf, const double* inflow, double dt, hipStream_t st) {
+  fornax_m1_coeffs c2 = *cf;
+  if (!c2.B) c2.B = c2.kappa;
+  StepArgs<S> a;
+  fill_args<S>(ctx, a, &c2, inflow, dt);
+  a.src = 0;
+  a.E = (const S*)in->E;
+  a.Eo = (S*)out->E;
+  for (int k = 0; k < ctx->desc.ndim; ++k) {
+    a.F[k] = (const S*)in->F[k];
+    a.Fo[k] = (S*)out->F[k];
+  }
+  if (ctx->desc.integrator == FORNAX_SSPRK2) {
+    StepArgs<S> a1 = a;
+    const size_t nzg = (size_t)a.nzones * a.G;
+    S* st_E = (S*)ctx->stage_mem;
+    a1.Eo = st_E;
+    for (int k = 0; k < 3; ++k) a1.Fo[k] = (k < ctx->desc.ndim) ? st_E + (1 + k) * nzg : nullptr;
+    const int rc1 = launch_tiled<S, R>(ctx, geo, a1, st);
+    if (rc1 != FORNAX_OK) return rc1;
+    a.Ea = a.E;
+    for (int k = 0; k < 3; ++k) a.Fa[k] = a.F[k];
+    a.E = a1.Eo;
+    for (int k = 0; k < 3; ++k) a.F[k] = a1.Fo[k];
+  }
+  return launch_tiled<S, R>(ctx, geo, a, st);
+}
+
 template <typename S, typename R>
 int launch_flux_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* in, const fornax_m1_coeffs* cf,
                   const double* inflow, void* face_flux[3], hipStream_t st) {
@@ -308,6 +341,13 @@ int fm1_launch_step(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_sta
   if (ctx->desc.precision == FORNAX_FP64)
     return launch_step_t<double, double>(ctx, ctx->geo_d, in, out, cf, inflow, dt, diag, stream);
   return launch_step_t<float, float>(ctx, ctx->geo_f, in, out, cf, inflow, dt, diag, stream);
+}
+
+int fm1_launch_transport(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
+                         const fornax_m1_coeffs* cf, const double* inflow, double dt, hipStream_t stream) {
+  if (ctx->desc.precision == FORNAX_FP64)
+    return launch_transport_t<double, double>(ctx, ctx->geo_d, in, out, cf, inflow, dt, stream);
+  return launch_transport_t<float, float>(ctx, ctx->geo_f, in, out, cf, inflow, dt, stream);
 }
 
 int fm1_launch_flux(fornax_m1_ctx* ctx, const fornax_m1_state* in, const fornax_m1_coeffs* cf, const double* inflow,

@@ -33,7 +33,9 @@ CLOSURE_M1, CLOSURE_EDDINGTON = 0, 1
 EULER, SSPRK2 = 0, 1
 
 EXPORTED = ["fornax_m1_create", "fornax_m1_destroy", "fornax_m1_max_dt", "fornax_m1_step", "fornax_m1_flux",
-            "fornax_m1_source", "fornax_m1_adjoint", "fornax_m1_copy_probe", "fornax_m1_strerror"]
+            "fornax_m1_source", "fornax_m1_adjoint", "fornax_m1_copy_probe", "fornax_m1_strerror",
+            "fornax_m1_transport", "fornax_m1_set_matter_model", "fornax_m1_matter_coeffs",
+            "fornax_m1_matter_source"]
 
 
 class Desc(ctypes.Structure):
@@ -63,6 +65,16 @@ class Coeffs(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("B", ctypes.c_void_p)]
 
 
+class MatterModel(ctypes.Structure):
+    _fields_ = [("ngroups", ctypes.c_int32), ("nu_edge", ctypes.c_void_p), ("nu_c", ctypes.c_void_p),
+                ("kg", ctypes.c_void_p), ("a_rad", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_newton", ctypes.c_int32)]
+
+
+class Matter(ctypes.Structure):
+    _fields_ = [("cv", ctypes.c_void_p), ("kappa0", ctypes.c_void_p), ("T", ctypes.c_void_p)]
+
+
 class Diag(ctypes.Structure):
     _fields_ = [("energy_total", ctypes.c_void_p), ("dE_matter", ctypes.c_void_p), ("max_f", ctypes.c_void_p),
                 ("n_unrealizable", ctypes.c_void_p), ("n_nonpositive", ctypes.c_void_p)]
@@ -81,6 +93,10 @@ _lib.fornax_m1_source.argtypes = [_vp, _P(State), _P(Coeffs), ctypes.c_double, _
 _lib.fornax_m1_adjoint.argtypes = [_vp, _P(State), _P(State), _P(Coeffs), _vp, ctypes.c_double, _P(State), _P(State),
                                     _vp, _vp]
 _lib.fornax_m1_copy_probe.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
+_lib.fornax_m1_transport.argtypes = [_vp, _P(State), _P(State), _P(Coeffs), _vp, ctypes.c_double, _vp]
+_lib.fornax_m1_set_matter_model.argtypes = [_vp, _P(MatterModel)]
+_lib.fornax_m1_matter_coeffs.argtypes = [_vp, _P(Matter), _vp, _vp, _vp]
+_lib.fornax_m1_matter_source.argtypes = [_vp, _P(State), _vp, _P(Matter), ctypes.c_double, _vp, _vp, _vp]
 _lib.fornax_m1_strerror.argtypes = [ctypes.c_int]
 _lib.fornax_m1_strerror.restype = ctypes.c_char_p
 
@@ -265,6 +281,71 @@ class Context:
         cf = self._coeffs(kappa, sigma, B)
         _check(_lib.fornax_m1_source(self._h, ctypes.byref(s), ctypes.byref(cf), dt, _ptr(dE_matter),
                                      _stream(stream)), "fornax_m1_source")
+
+    def transport(self, E, F, kappa, sigma, dt, out=None, inflow=None, stream=None):
+        """The explicit transport alone: returns (E^-, [F^-]) = U^n + dt L(U^n)."""
+        sin = self._state(E, F, "in")
+        if out is None:
+            out = self.empty_state()
+        sout = self._state(out[0], out[1], "out")
+        for t, nm in ((kappa, "kappa"), (sigma, "sigma")):
+            self._check_arr(t, nm)
+        cf = Coeffs()
+        cf.kappa, cf.sigma, cf.B = kappa.data_ptr(), sigma.data_ptr(), None
+        _check(_lib.fornax_m1_transport(self._h, ctypes.byref(sin), ctypes.byref(sout), ctypes.byref(cf),
+                                        self._inflow(inflow), dt, _stream(stream)), "fornax_m1_transport")
+        return out
+
+    # -- radiation-matter energy exchange ------------------------------------------------------
+    def set_matter_model(self, nu_edge, nu_c, kg, a_rad=1.0, tol=1e-6, max_newton=30):
+        """Group tables of the matter model (host arrays; copied into the context)."""
+        import numpy as np
+        ne = np.ascontiguousarray(nu_edge, dtype=np.float64)
+        nc = np.ascontiguousarray(nu_c, dtype=np.float64)
+        k = np.ascontiguousarray(kg, dtype=np.float64)
+        mm = MatterModel()
+        mm.ngroups = len(nc)
+        mm.nu_edge, mm.nu_c, mm.kg = ne.ctypes.data, nc.ctypes.data, k.ctypes.data
+        mm.a_rad, mm.tol, mm.max_newton = a_rad, tol, max_newton
+        _check(_lib.fornax_m1_set_matter_model(self._h, ctypes.byref(mm)), "fornax_m1_set_matter_model")
+
+    def _matter(self, cv, kappa0, T):
+        zshape = self.shape[:3]
+        for t, nm in ((cv, "cv"), (kappa0, "kappa0"), (T, "T")):
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64 \
+                    or tuple(t.shape) != zshape or not t.is_contiguous():
+                raise ValueError(f"{nm} must be a contiguous float64 CUDA tensor of shape {zshape}")
+        m = Matter()
+        m.cv, m.kappa0, m.T = cv.data_ptr(), kappa0.data_ptr(), T.data_ptr()
+        return m
+
+    def matter_coeffs(self, cv, kappa0, T, stream=None):
+        """kappa_g(T), B_g(T) per zone-group (tensors of the context's type)."""
+        m = self._matter(cv, kappa0, T)
+        kap = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        B = torch.empty_like(kap)
+        _check(_lib.fornax_m1_matter_coeffs(self._h, ctypes.byref(m), ctypes.c_void_p(kap.data_ptr()),
+                                            ctypes.c_void_p(B.data_ptr()), _stream(stream)), "fornax_m1_matter_coeffs")
+        return kap, B
+
+    def matter_source(self, E, F, sigma, cv, kappa0, T, dt, dE_matter=None, iters=None, stream=None):
+        """Interaction update with the matter temperature solved for, in place on E, F and T."""
+        s = self._state(E, F, "inout")
+        self._check_arr(sigma, "sigma")
+        m = self._matter(cv, kappa0, T)
+        _check(_lib.fornax_m1_matter_source(self._h, ctypes.byref(s), ctypes.c_void_p(sigma.data_ptr()),
+                                            ctypes.byref(m), dt, _ptr(dE_matter), _ptr(iters), _stream(stream)),
+               "fornax_m1_matter_source")
+
+    def matter_step(self, E, F, sigma, cv, kappa0, T, dt, out=None, inflow=None, dE_matter=None, iters=None,
+                    stream=None):
+        """One step with the matter coupled (Algorithmic Steps 1, 3 and 4, static medium): the
+        opacities at T^n, the explicit transport, then the interaction update with the outer
+        solve for T^{n+1} (T updated in place). Returns (E^{n+1}, [F^{n+1}])."""
+        kap, _ = self.matter_coeffs(cv, kappa0, T, stream=stream)
+        out = self.transport(E, F, kap, sigma, dt, out=out, inflow=inflow, stream=stream)
+        self.matter_source(out[0], out[1], sigma, cv, kappa0, T, dt, dE_matter=dE_matter, iters=iters, stream=stream)
+        return out
 
     def adjoint(self, E, F, kappa, sigma, B, dt, lamE, lamF, out=None, dkappa=None, inflow=None, stream=None,
                 U1=None):
