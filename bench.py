@@ -192,6 +192,67 @@ def cpu_baseline(w, dt, target_s=20.0):
                        f"{ncores} OpenMP threads, {t1 - t0:.1f} s")
 
 
+def matter_timings(reps=10, steps=10):
+    """The radiation-matter energy exchange on the 512^2 x 16 blob radiation with random matter
+    (matter2d): the interaction update with the outer solve for T alone (each repetition from
+    the same state, HIP events around the call only) and the coupled step (matter
+    coefficients at T^n, explicit transport, interaction update) over `steps` steps."""
+    import torch
+    from paper_1806_07390_amd import m1, workloads as wl
+    w = wl.matter2d()
+    g = w.groups
+    out = {"workload": "2-D periodic 512x512 x 16 groups, blob radiation, random matter T, cv, kappa0 (seed 0)"}
+    for prec, name, dtp, el in ((m1.FP64, "fp64", torch.float64, 8), (m1.MIXED, "mixed", torch.float32, 4)):
+        ctx = m1.Context(m1.Config.from_workload(w, precision=prec))
+        ctx.set_matter_model(g.nu_edge, g.nu_c, g.kg, a_rad=g.a_rad)
+        E0, F0 = (torch.from_numpy(w.E).to("cuda", dtp), [torch.from_numpy(f).to("cuda", dtp) for f in w.F])
+        sig = torch.from_numpy(w.sigma).to("cuda", dtp)
+        cv, k0, T0 = (torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (w.cv, w.kappa0, w.T))
+        E, F, T = E0.clone(), [f.clone() for f in F0], T0.clone()
+        it = torch.zeros(ctx.nzones, dtype=torch.int32, device="cuda")
+        st = torch.cuda.current_stream()
+        tot = 0.0
+        for r in range(reps + 2):
+            E.copy_(E0)
+            for f, f0 in zip(F, F0):
+                f.copy_(f0)
+            T.copy_(T0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            ctx.matter_source(E, F, sig, cv, k0, T, w.dt, iters=it)
+            e1.record(st)
+            torch.cuda.synchronize()
+            if r >= 2:
+                tot += e0.elapsed_time(e1)
+        ms_src = tot / reps
+        iters = it.abs().double().mean().item()
+        # coupled steps from the initial state
+        E, F, T = E0.clone(), [f.clone() for f in F0], T0.clone()
+        Eb, Fb = ctx.empty_state()
+        for _ in range(2):
+            ctx.matter_step(E, F, sig, cv, k0, T, w.dt, out=(Eb, Fb))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        a, b = (E, F), (Eb, Fb)
+        for _ in range(steps):
+            ctx.matter_step(a[0], a[1], sig, cv, k0, T, w.dt, out=b)
+            a, b = b, a
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms_step = e0.elapsed_time(e1) / steps
+        bytes_src = w.zone_groups * (7 * el) + w.n[0] * w.n[1] * 5 * 8
+        out[name] = dict(interaction_update_ms=round(ms_src, 5),
+                         interaction_update_zgu_per_s=w.zone_groups / (ms_src * 1e-3),
+                         interaction_update_algorithmic_GBps=round(bytes_src / (ms_src * 1e-3) / 1e9, 1),
+                         mean_newton_iterations=round(iters, 3),
+                         coupled_step_ms=round(ms_step, 5),
+                         coupled_step_zgu_per_s=w.zone_groups / (ms_step * 1e-3))
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,8 +261,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default=None,
-                    help="profiling: run only this workload's timed loop (blobs2d, core3d, sphere3d, adjoint, "
-                         "extras = the three after blobs2d, copy = the copy probe alone)")
+                    help="profiling: run only this workload's timed loop (blobs2d, core3d, sphere3d, matter, "
+                         "adjoint, extras = all after blobs2d, copy = the copy probe alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU path; "
@@ -266,6 +327,9 @@ def main():
                 del ctx, inp
                 torch.cuda.empty_cache()
             del w4
+        if args.only in (None, "extras", "matter"):
+            extra["matter"] = matter_timings()
+            log("  matter:", extra["matter"])
         if args.only in (None, "extras", "adjoint"):
             extra["adjoint"] = adjoint_ratios()
             log("  adjoint:", extra["adjoint"])

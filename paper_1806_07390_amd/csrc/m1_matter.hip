@@ -62,6 +62,15 @@ __device__ __forceinline__ double planck_low(double x) {
   return x * y * (1.0 / 3.0 - x * 0.125 + y * p);
 }
 
+// 1/n for the terms of the exponential series
+__constant__ double c_recip[64] = {
+    1.0,        1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,  1.0 / 7,  1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
+    1.0 / 12,   1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17, 1.0 / 18, 1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22,
+    1.0 / 23,   1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27, 1.0 / 28, 1.0 / 29, 1.0 / 30, 1.0 / 31, 1.0 / 32, 1.0 / 33,
+    1.0 / 34,   1.0 / 35, 1.0 / 36, 1.0 / 37, 1.0 / 38, 1.0 / 39, 1.0 / 40, 1.0 / 41, 1.0 / 42, 1.0 / 43, 1.0 / 44,
+    1.0 / 45,   1.0 / 46, 1.0 / 47, 1.0 / 48, 1.0 / 49, 1.0 / 50, 1.0 / 51, 1.0 / 52, 1.0 / 53, 1.0 / 54, 1.0 / 55,
+    1.0 / 56,   1.0 / 57, 1.0 / 58, 1.0 / 59, 1.0 / 60, 1.0 / 61, 1.0 / 62, 1.0 / 63, 1.0 / 64};
+
 // x^3 / (e^x - 1) integrated from x to infinity (x at or above the split; +inf gives 0):
 // sum over n of the closed-form integral of x^3 e^(-n x), the powers e^(-n x) by products.
 __device__ __forceinline__ double planck_high(double x) {
@@ -69,9 +78,9 @@ __device__ __forceinline__ double planck_high(double x) {
   const double q = exp(-x);
   const double x2 = x * x, x3 = x2 * x;
   double qn = 1.0, s = 0.0;
-  for (int n = 1; n <= 64; ++n) {
+  for (int n = 0; n < 64; ++n) {
     qn *= q;
-    const double r = 1.0 / (double)n;
+    const double r = c_recip[n];
     const double term = qn * r * (x3 + r * (3.0 * x2 + r * (6.0 * x + 6.0 * r)));
     s += term;
     if (term <= 1e-18 * s) break;
@@ -81,12 +90,29 @@ __device__ __forceinline__ double planck_high(double x) {
 
 constexpr double PLANCK_SPLIT = 1.5;
 
-// integral of x^3 / (e^x - 1) over [a, b], 0 <= a <= b <= inf, hs = planck_low(split),
+// one edge's value in the form the group integrals need: the integral from 0 below the
+// split, the integral to infinity from the split on
+__device__ __forceinline__ double planck_edge(double x) { return x < PLANCK_SPLIT ? planck_low(x) : planck_high(x); }
+
+// integral of x^3 / (e^x - 1) over [a, b] (0 <= a <= b <= inf) from the edge values va, vb
+// (planck_edge), without subtracting two nearly equal integrals; hs = planck_low(split),
 // hh = planck_high(split)
+__device__ __forceinline__ double planck_part_v(double a, double b, double va, double vb, double hs, double hh) {
+  if (b < PLANCK_SPLIT) return vb - va;
+  if (a >= PLANCK_SPLIT) return va - vb;
+  return (hs - va) + (hh - vb);
+}
+
 __device__ __forceinline__ double planck_part(double a, double b, double hs, double hh) {
-  if (b <= PLANCK_SPLIT) return planck_low(b) - planck_low(a);
-  if (a >= PLANCK_SPLIT) return planck_high(a) - planck_high(b);
-  return (hs - planck_low(a)) + (hh - planck_high(b));
+  return planck_part_v(a, b, planck_edge(a), planck_edge(b), hs, hh);
+}
+
+// the value v of the lane whose byte address (4 x lane) is addr
+__device__ __forceinline__ double lane_value(int addr, double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // sum of v over the 2^lg lanes of a zone
@@ -123,23 +149,36 @@ __global__ void __launch_bounds__(MBLOCK) k_matter_source(MatterArgs<S> a) {
   const double Em = on ? (double)a.E[zg] : 0.0;
   const double cv = a.cv[z], k0 = a.kappa0[z], Tm = a.T[z];
   const double kq = on ? k0 * a.tab.kg[gg] : 0.0;
-  const double nuc = a.tab.nu_c[gg], nlo = a.tab.nu_edge[gg], nhi = a.tab.nu_edge[gg + 1];
+  const double nuc = a.tab.nu_c[gg], nhi = a.tab.nu_edge[gg + 1];
   const double cdt = a.c * a.dt;
   const double hs = planck_low(PLANCK_SPLIT), hh = planck_high(PLANCK_SPLIT);
   const double pnorm = a.tab.a_rad * 15.0 / (M_PI * M_PI * M_PI * M_PI);
 
-  // the group's opacity and inner update at temperature T; r(T) summed over the zone
-  auto kappa_at = [&](double T) { return kq / sqrt(T) * -expm1(-nuc / T); };
+  // the group's opacity and inner update at temperature T; r(T) summed over the zone.  A lane
+  // evaluates the Planck integral at its group's lower edge and takes the upper edge's value
+  // from the next lane (the zone's last lane evaluates its upper edge itself; lanes past the
+  // last group evaluate the top edge)
+  const int lpz = 1 << a.lg;
+  const double nedge = a.tab.nu_edge[g < a.G ? g : a.G];
+  const double ntop = a.tab.nu_edge[a.G];
+  const int up = (((int)threadIdx.x + 1) & 63) << 2;   // byte address of the next lane (a zone's
+                                                          // last lane does not use it)
   auto inner = [&](double T, double& kap) {
-    kap = kappa_at(T);
+    const double iT = 1.0 / T;
+    kap = kq * sqrt(iT) * -expm1(-nuc * iT);
+    const double xa = nedge * iT;
+    const double va = planck_edge(xa);
+    const double vn = lane_value(up, va);
+    const double xb = nhi * iT;
+    const double vb = (g == lpz - 1) ? planck_edge(ntop * iT) : vn;
     const double T2 = T * T;
-    const double B = pnorm * T2 * T2 * planck_part(nlo / T, nhi / T, hs, hh);
+    const double B = pnorm * T2 * T2 * planck_part_v(xa, xb, va, vb, hs, hh);
     return (Em + cdt * kap * B) / (1.0 + cdt * kap);
   };
   auto residual = [&](double T) {
     double kap;
-    const double d = on ? inner(T, kap) - Em : 0.0;
-    return cv * (T - Tm) + zone_sum(d, a.lg);
+    const double E = inner(T, kap);
+    return cv * (T - Tm) + zone_sum(on ? E - Em : 0.0, a.lg);
   };
 
   // outer solve: Newton with a forward-difference derivative and backtracking, then bisection
