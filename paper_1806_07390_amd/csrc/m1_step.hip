@@ -226,9 +226,14 @@ __host__ __device__ inline size_t unit_lds_elems(int dim, int TXB, int TYB, int 
 // Waves per SIMD for the compile-time wave-row kernels (measured on gfx950): 3 in double
 // (at most 168 VGPRs, no spills), 5 in float (at most 96 VGPRs).  LIM: the limiter when
 // known at compile time, -1 to read it from the arguments.
+// The spherical 3-D step in double needs more than the 256 registers of a wave that shares its
+// SIMD: its blocks are limited to 256 threads (one wave per SIMD) and the empty asm statement
+// at its start, which names an accumulation register, keeps that bank available to the
+// register allocator, which then holds there what it would otherwise spill to scratch memory.
 template <typename S, typename R, int DIM, bool SPH, bool ROW, int GBC, int V, int LIM>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(GBC > 0 && !SPH && V == 1 ? (sizeof(R) == 8 ? 3 : 5) : 1)))
+__global__ void __launch_bounds__((DIM == 3 && SPH && sizeof(R) == 8) ? 256 : 512) __attribute__((amdgpu_waves_per_eu(GBC > 0 && !SPH && V == 1 ? (sizeof(R) == 8 ? 3 : 5) : 1)))
 k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
+  if constexpr (DIM == 3 && SPH && sizeof(R) == 8) asm volatile("" ::: "a0");
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NC = 1 + DIM;   // E, F_1..F_DIM
   constexpr int MD = DIM - 1;   // march direction (DIM >= 2)
@@ -834,6 +839,8 @@ Tile make_tile(const fornax_m1_desc& D, int TXB, int TYB, int TM, int GB, int NW
   tl.NW = NW;
   tl.nthreads = row ? 64 * NW : TXB * TYB * LPC;
   if (tl.nthreads > 512) return tl;
+  // the spherical 3-D double kernel takes at most 256 threads per block
+  if (D.ndim == 3 && D.coord == FORNAX_SPHERICAL_LOGR && D.precision == FORNAX_FP64 && tl.nthreads > 256) return tl;
   // halo items (one value of V groups of one halo column each): at most 1 per thread of a
   // wave unit, 3 per thread of a block unit
   const int nunit = row ? 64 : tl.nthreads;
@@ -876,16 +883,23 @@ Tile choose_tile(const fornax_m1_desc& D, int V) {
     }
     return t;
   }
-  // measured on gfx950: FP64 8 x 8 columns of up to 4 groups, 16 planes; FP32 pairs of
-  // groups per lane, 16 x 16 columns of 2 groups, 8 planes
+  // measured on gfx950 (192^3 x 12 and 256 x 64 x 128 x 20): Cartesian FP64 8 x 8 columns of
+  // up to 4 groups, 16 planes; Cartesian FP32 pairs of groups per lane, 16 x 16 columns of 2
+  // groups, 8 planes; spherical FP64 16 x 16 columns of 2 groups, 16 planes; spherical FP32
+  // 16 x 8 columns of up to 4 groups, 16 planes
   {
     Tile t{};
+    const bool sph = D.coord == FORNAX_SPHERICAL_LOGR;
     if (D.precision == FORNAX_FP64) {
-      int GB = 4;
+      int GB = sph ? 2 : 4;
       while (G % GB != 0) --GB;
-      t = make_tile(D, 8, 8, 16, GB, 1, 1);
+      t = sph ? make_tile(D, 16, 8, 16, GB, 1, 1) : make_tile(D, 8, 8, 16, GB, 1, 1);
     } else if (V == 2) {
       t = make_tile(D, 16, 16, 8, 2, 1, 2);
+    } else if (sph) {
+      int GB = 4;
+      while (G % GB != 0) --GB;
+      t = make_tile(D, 16, 8, 16, GB, 1, 1);
     }
     if (t.nblocks > 0) return t;
   }
