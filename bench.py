@@ -3,7 +3,8 @@
 Headline (`value`): zone-group updates per second of the full step (explicit transport +
 implicit interaction update + energy/realizability diagnostics) on the 2-D periodic
 512 x 512 zone, 16 group FP64 workload, inputs resident in HBM, timed with HIP events over
-K steps after W warmup steps.  Extra workloads (3-D 192^3 x 12 FP64 vs MIXED, spherical
+K steps after W warmup steps (default 300, about 30 ms: a GPU that has been idle runs its first
+few milliseconds of work at lower clocks, which a 10-step warm-up still times).  Extra workloads (3-D 192^3 x 12 FP64 vs MIXED, spherical
 256 x 64 x 128 x 20 MIXED) and the adjoint/forward ratio are reported beside it, plus the
 roofline of the dominant kernel and the CPU oracle's rate on this host (a baseline only).
 
@@ -257,7 +258,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default=None,

@@ -476,6 +476,9 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
   a.B = (const S*)cf->B;
   a.dEm = nullptr;
   a.p_energy = a.p_maxf2 = nullptr;
+  a.p_ticket = nullptr;
+  a.o_energy = a.o_maxf = nullptr;
+  a.o_nun = a.o_nnp = nullptr;
   a.p_nun = a.p_nnp = nullptr;
   a.lam[0] = (const S*)lam_np1->E;
   a.lamo[0] = (S*)lam_n->E;

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -421,7 +422,7 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   // dE_matter partials when a tile splits the groups of a zone over several blocks
   const size_t ngbm = (size_t)std::max(ctx->tile.ngb, ctx->tile_v1.ngb);
   const size_t dzp_bytes = ngbm > 1 ? ngbm * (size_t)nz * sizeof(double) : 0;
-  const size_t red_bytes = (nb * (2 * sizeof(double) + 2 * sizeof(int)) + 1023) & ~(size_t)255;
+  const size_t red_bytes = (nb * (2 * sizeof(double) + 2 * sizeof(int)) + 256 + 1023) & ~(size_t)255;
   void* red = nullptr;
   if (hipMalloc(&red, red_bytes + dzp_bytes) != hipSuccess) {
     (void)hipFree(ctx->geo_mem);
@@ -432,6 +433,14 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   ctx->p_maxf2 = ctx->p_energy + nb;
   ctx->p_nun = (int*)(ctx->p_maxf2 + nb);
   ctx->p_nnp = ctx->p_nun + nb;
+  ctx->ticket = (unsigned*)((((uintptr_t)(ctx->p_nnp + nb)) + 255) & ~(uintptr_t)255);
+  ctx->last_fused_fin = false;
+  if (hipMemset(ctx->ticket, 0, sizeof(unsigned)) != hipSuccess) {
+    (void)hipFree(red);
+    (void)hipFree(ctx->geo_mem);
+    delete ctx;
+    return FORNAX_EDEVICE;
+  }
   ctx->dzp = dzp_bytes ? (double*)((char*)red + red_bytes) : nullptr;
   // SSP-RK2: storage of the first stage's state
   ctx->stage_mem = nullptr;

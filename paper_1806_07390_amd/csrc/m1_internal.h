@@ -118,6 +118,13 @@ struct StepArgs : StepArgsBase {
   double* p_maxf2;
   int* p_nun;
   int* p_nnp;
+  // kernels that finish the reduction themselves: the last block to arrive (ticket counter,
+  // zero between launches) sums the partials into the caller's outputs (each nullable)
+  unsigned* p_ticket;
+  double* o_energy;
+  double* o_maxf;
+  int* o_nun;
+  int* o_nnp;
 };
 
 }  // namespace fm1
@@ -167,6 +174,8 @@ struct fornax_m1_ctx {
   double* p_maxf2;
   int* p_nun;
   int* p_nnp;
+  unsigned* ticket;            // arrival counter of the kernels that finish the reduction
+  bool last_fused_fin;         // the last step launch finished the diagnostics itself
   // dE_matter partials of the group blocks of a tile, [ngb][zones] (null when every tile
   // holds all groups of a zone)
   double* dzp;

@@ -195,6 +195,9 @@ void fill_args(const fornax_m1_ctx* ctx, StepArgs<S>& a, const fornax_m1_coeffs*
   a.p_maxf2 = nullptr;
   a.p_nun = nullptr;
   a.p_nnp = nullptr;
+  a.p_ticket = nullptr;
+  a.o_energy = a.o_maxf = nullptr;
+  a.o_nun = a.o_nnp = nullptr;
 }
 
 template <typename S, typename R>
@@ -217,6 +220,11 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
     a.p_maxf2 = ctx->p_maxf2;
     a.p_nun = ctx->p_nun;
     a.p_nnp = ctx->p_nnp;
+    a.p_ticket = ctx->ticket;
+    a.o_energy = diag->energy_total;
+    a.o_maxf = diag->max_f;
+    a.o_nun = diag->n_unrealizable;
+    a.o_nnp = diag->n_nonpositive;
   }
   if (ctx->desc.integrator == FORNAX_SSPRK2) {
     // stage 1: U* = U^n + dt L(U^n) into the context's stage storage, no interaction update
@@ -229,6 +237,7 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
     a1.dEm = nullptr;
     a1.p_energy = a1.p_maxf2 = nullptr;
     a1.p_nun = a1.p_nnp = nullptr;
+    a1.p_ticket = nullptr;
     const int rc1 = launch_tiled<S, R>(ctx, geo, a1, st);
     if (rc1 != FORNAX_OK) return rc1;
     // stage 2 reads U* and averages with U^n: U^- = (U^n + U* + dt L(U*)) / 2
@@ -245,7 +254,7 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
                        ctx->last_tile->ngb, a.nzones, a.dEm);
     if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
   }
-  if (want) {
+  if (want && !ctx->last_fused_fin) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, st, ctx->p_energy, ctx->p_maxf2, ctx->p_nun,
                        ctx->p_nnp, nb,
                        diag->energy_total, diag->max_f, diag->n_unrealizable, diag->n_nonpositive);

@@ -1030,6 +1030,7 @@ int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, hi
   if (tl->nblocks <= 0) return FORNAX_EUNSUPPORTED;
   if (a.dEm && tl->ngb > 1 && !a.dzp) return FORNAX_EUNSUPPORTED;
   *ctx->last_tile = *tl;
+  ctx->last_fused_fin = false;
   return sph ? launch_coord<S, R, true>(geo, a, *tl, D, st) : launch_coord<S, R, false>(geo, a, *tl, D, st);
 }
 

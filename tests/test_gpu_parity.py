@@ -234,6 +234,49 @@ def test_whole_zone_kernel(m1, bc, lim):
                 assert np.allclose(dgg["dE_matter"], dEm, rtol=1e-10, atol=1e-12 * np.abs(E).max())
 
 
+def test_whole_zone_kernel_finishes_diagnostics_each_step(m1):
+    """The whole-zone kernel's last block to finish sums every block's diagnostics partials (no
+    separate reduction launch).  Each of several steps on one context reports the totals of its
+    own output -- the volume sum of E, the largest f = |F|/(cE), the realizability and
+    positivity counts -- also when the state changes by a large factor between calls and when
+    steps without diagnostics come in between, so neither a partial of an earlier launch nor
+    the block arrival counter carries over."""
+    import os
+    w = _rows_case("periodic")
+    p = problem_of(w)
+    dt = dt_of(w, p)
+    V = orc.geometry(p)["vol"].reshape(-1)
+    os.environ["FORNAX_M1_ROWS"] = "1,9"
+    try:
+        ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64))
+    finally:
+        del os.environ["FORNAX_M1_ROWS"]
+    E0 = to_dev(w.E, torch.float64)
+    F0 = [to_dev(f, torch.float64) for f in w.F]
+    k, s, B0 = (to_dev(x, torch.float64) for x in (w.kappa, w.sigma, w.B))
+    u = 2.0 ** -53
+    for scale, plain_before in ((1.0, False), (3.0, True), (0.25, False), (1e3, True)):
+        E, F, B = E0 * scale, [f * scale for f in F0], B0 * scale
+        if plain_before:
+            ctx.step(E, F, k, s, B, dt)
+        dg = ctx.new_diag()
+        Eo, Fo = ctx.step(E, F, k, s, B, dt, diag=dg)
+        torch.cuda.synchronize()
+        say(f"fused diagnostics scale={scale}")
+        Eh = to_host(Eo).reshape(len(V), -1)
+        Fh = [to_host(f).reshape(len(V), -1) for f in Fo[:2]]
+        e_ref = float(np.sum(V[:, None] * Eh))
+        assert dg["energy_total"].item() == pytest.approx(e_ref, rel=1e-13)
+        F2 = Fh[0] ** 2 + Fh[1] ** 2
+        cE = w.c * Eh
+        pos = Eh > 0
+        f_ref = float(np.sqrt((F2[pos] / cE[pos] ** 2).max()))
+        assert dg["max_f"].item() == pytest.approx(f_ref, rel=1e-13)
+        n_un = int(np.count_nonzero(F2 > (cE * (1 + 8 * u)) ** 2))
+        assert int(dg["n_unrealizable"].item()) == n_un
+        assert int(dg["n_nonpositive"].item()) == int(np.count_nonzero(~pos))
+
+
 @pytest.mark.parametrize("case", ["blobs2d", "reflect2d", "core3d", "sphere3d"])
 def test_ssprk2_matches_oracle(m1, case):
     """Shu-Osher SSP-RK2 for the transport (two launches of the step kernel, U* in context
