@@ -401,6 +401,7 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   // "NWX,TM" picks its tiling)
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) cus = 0;
+  ctx->cus = cus;
   ctx->rows = choose_rows_tile(*desc, cus);
   if (const char* env = std::getenv("FORNAX_M1_ROWS")) {
     int nwx = 0, tm = 0;

@@ -167,6 +167,7 @@ struct fornax_m1_ctx {
   fm1::Tile tile;              // tiling of the fused step kernel
   fm1::Tile tile_v1;           // one group per lane (arrays not aligned to pairs of groups)
   fm1::RowsTile rows;          // the whole-zone LDS kernel when nblocks > 0 (2-D, 16 groups)
+  int cus;                     // compute units of the device (0 if unknown)
   fm1::Tile last_tile[1];      // the tile of the last step launch (for inspection)
   // reduction scratch (one partial per block of the step kernel)
   int nblocks_step;

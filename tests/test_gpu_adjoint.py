@@ -152,6 +152,46 @@ def test_adjoint_with_given_next_state(m1, precision):
     assert torch.equal(a[0], c[0]) and not torch.equal(a[2], c[2])
 
 
+@pytest.mark.parametrize("bc", ["periodic", "reflect"])
+def test_adjoint_independent_of_tiling(m1, bc):
+    """The adjoint kernel's blocks of TXB zone columns by TM planes (FORNAX_M1_ADJ_TILE="TXB,TM";
+    the default takes TM from the CU count): one plane per block, the fewest columns, tiles
+    that do not divide the grid, all give the default tiling's result -- each zone sums the
+    same face contributions in the same order whichever block computes them."""
+    import os
+    w = wl.adjoint2d(n=40, G=4, steps=1)
+    cut = lambda a: np.ascontiguousarray(a[..., :37, :])   # 37 zones along x
+    w.E, w.kappa, w.sigma, w.B = cut(w.E), cut(w.kappa), cut(w.sigma), cut(w.B)
+    w.F = [cut(f) for f in w.F]
+    w.n = (37, 40, 1)
+    if bc == "reflect":
+        w.bc_lo = (wl.BC_REFLECT, wl.BC_OUTFLOW, 0)
+        w.bc_hi = (wl.BC_OUTFLOW, wl.BC_REFLECT, 0)
+    ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64))
+    dtp = ctx.dtype
+    rng = np.random.default_rng(9)
+    E = to_dev(w.E, dtp)
+    F = [to_dev(f, dtp) for f in w.F]
+    k, s, B = (to_dev(x, dtp) for x in (w.kappa, w.sigma, w.B))
+    lamE = to_dev(rng.standard_normal(w.E.shape), dtp)
+    lamF = [to_dev(rng.standard_normal(w.E.shape), dtp) for _ in w.F]
+    ref = ctx.adjoint(E, F, k, s, B, w.dt, lamE, lamF)
+    torch.cuda.synchronize()
+    ref = [to_host(ref[0])] + [to_host(f) for f in ref[1]] + [to_host(ref[2])]
+    for tile in ("16,1", "16,2", "16,3", "4,5", "7,7", "64,9", "9,40"):
+        os.environ["FORNAX_M1_ADJ_TILE"] = tile
+        try:
+            got = ctx.adjoint(E, F, k, s, B, w.dt, lamE, lamF)
+            torch.cuda.synchronize()
+        finally:
+            del os.environ["FORNAX_M1_ADJ_TILE"]
+        got = [to_host(got[0])] + [to_host(f) for f in got[1]] + [to_host(got[2])]
+        for a, b in zip(got, ref):
+            err = np.abs(a - b).max() / np.abs(b).max()
+            say("adjoint tile", bc, tile, err)
+            assert err <= 1e-14
+
+
 def test_one_step_dot_product_mixed(m1):
     w = wl.adjoint2d(n=32, G=4, steps=1)
     lhs, rhs, scale = one_step_dot(m1, w, m1.MIXED)
