@@ -75,9 +75,11 @@ struct OrcDesc {
   double c;           // (reduced) speed of light
   int32_t nthreads;   // OpenMP threads (0 = runtime default)
   int32_t integrator; // OI_EULER (default): one forward-Euler push; OI_SSPRK2: Shu-Osher RK2
+  int32_t wavespeed;  // OW_LIGHT (default): S_L = -c, S_R = +c; OW_M1: HLLE with the M1 speeds
 };
 }
 enum { OI_EULER = 0, OI_SSPRK2 = 1 };
+enum { OW_LIGHT = 0, OW_M1 = 1 };
 
 static const int NG = 2;  // ghost layers required by linear reconstruction
 
@@ -444,6 +446,46 @@ static void closure(const Ctx<T>& C, const T q[4], const double h[3], T P[3][3])
   }
 }
 
+// Characteristic speeds (physical units) of the M1 system along direction d at a face state,
+// the reading of the HLLE speed bounds ("wavespeed estimates for the fastest left- and
+// right-going waves", not given in the paper): the eigenvalues of the flux Jacobian of the
+// one-dimensional system U = (E, F), flux (F, c^2 chi(f) E), f = F / (c E), taken with the
+// state's normal reduced flux f = F^_d / (c E):
+//   dFlux/dU = [[0, 1], [c^2 (chi - f chi'), c chi']],
+//   lambda = (c / 2) (chi' -+ sqrt(chi'^2 + 4 (chi - f chi'))).
+// With the Levermore factor chi = (5 - 2 s) / 3, s = sqrt(4 - 3 f^2), chi' = 2 f / s, the
+// discriminant is 16 (s - 1)^2 / (3 s^2), so
+//   lambda = (c / s) (f -+ 2 (s - 1) / sqrt(3)),   s - 1 = 3 (1 - f^2) / (1 + s),
+// which keeps full accuracy as |f| -> 1 (both speeds -> c f).  |f| is clamped to 1; the
+// Eddington closure (chi = 1/3) and a state with E <= 0 give -+c/sqrt(3) and -+c.
+template <class T>
+static void m1_speeds(const Ctx<T>& C, const T q[4], const double h[3], int d, T& lmin, T& lmax) {
+  const T E = q[0];
+  const double c = C.c;
+  if (!(val(E) > 0.0)) {
+    lmin = T(-c);
+    lmax = T(c);
+    return;
+  }
+  if (C.D->closure == 1) {
+    lmin = T(-c / std::sqrt(3.0));
+    lmax = T(c / std::sqrt(3.0));
+    return;
+  }
+  T f = q[1 + d] / T(h[d] != 0.0 ? h[d] : 1.0) / (T(c) * E);
+  if (val(f) > 1.0) f = T(1.0);
+  if (val(f) < -1.0) f = T(-1.0);
+  const T s = sqrt(T(4.0) - T(3.0) * f * f);
+  const T w = T(2.0 * std::sqrt(3.0)) * (T(1.0) - f * f) / (T(1.0) + s);   // 2 (s - 1) / sqrt(3)
+  lmin = T(c) * (f - w) / s;
+  lmax = T(c) * (f + w) / s;
+}
+
+template <class T>
+static T tmin(T a, T b) { return val(b) < val(a) ? b : a; }
+template <class T>
+static T tmax(T a, T b) { return val(b) > val(a) ? b : a; }
+
 // Numerical flux across the d-face at face index f (between zones f-1 and f along d) of
 // the row idx.  Riemann Solvers subsection: HLL fluxes for the radiation subsystem, the
 // energy flux corrected as in eq:hll with epsilon = min(1, 1/tau_cell) (eq:epsilon).
@@ -451,7 +493,9 @@ static void closure(const Ctx<T>& C, const T q[4], const double h[3], T P[3][3])
 //   E   : flux F^d = F^_d / h_d,
 //   F_k : flux c^2 P^d_k = c^2 P^^{dk} h_k / h_d      (mixed components of the pressure).
 // Reading (wavespeeds, not given in the paper): S_R = +c, S_L = -c physical, i.e. +-c/h_d
-// in the coordinate x^d.  Reading (tau_cell): arithmetic mean of (kappa + sigma) of the two
+// in the coordinate x^d; or, as an option, HLLE bounds from the M1 characteristic speeds of
+// both face states, S_L = min(0, lambda_-(L), lambda_-(R)), S_R = max(0, lambda_+(L),
+// lambda_+(R)) (m1_speeds), also divided by h_d.  Reading (tau_cell): arithmetic mean of (kappa + sigma) of the two
 // zones times the mean proper zone width h_d Delta x^d of the two.  Reading: epsilon enters
 // the energy flux only ("a correction to the energy fluxes").
 // A face of zero area returns a zero flux.
@@ -477,7 +521,14 @@ static void face_flux(const Ctx<T>& C, int d, const int row[3], int f, int g, T 
   closure(C, qL, h, PL);
   closure(C, qR, h, PR);
   // wavespeeds in the coordinate x^d
-  double SR = C.c / h[d], SL = -C.c / h[d];
+  T SR = T(C.c / h[d]), SL = T(-C.c / h[d]);
+  if (C.D->wavespeed == OW_M1) {
+    T aL, bL, aR, bR;
+    m1_speeds(C, qL, h, d, aL, bL);
+    m1_speeds(C, qR, h, d, aR, bR);
+    SL = tmin(T(0.0), tmin(aL, aR)) / T(h[d]);
+    SR = tmax(T(0.0), tmax(bL, bR)) / T(h[d]);
+  }
   // epsilon (eq:epsilon)
   T ksa, ksb, tmp[4];
   zone_state(C, ia, g, tmp, &ksa);
@@ -489,13 +540,13 @@ static void face_flux(const Ctx<T>& C, int d, const int row[3], int f, int g, T 
   // energy: F^d_{L,R} = F^_d / h_d = F_d / h_d^2 (coordinate contravariant component)
   T FdL = qL[1 + d] / T(h[d] * h[d]);
   T FdR = qR[1 + d] / T(h[d] * h[d]);
-  flux[0] = (T(SR) * FdL - T(SL) * FdR + eps * T(SR * SL) * (qR[0] - qL[0])) / T(SR - SL);
+  flux[0] = (SR * FdL - SL * FdR + eps * (SR * SL) * (qR[0] - qL[0])) / (SR - SL);
   // flux components: conserved F_k, flux c^2 P^d_k, plain HLL
   for (int k = 0; k < C.ndim; ++k) {
     double hk = h[k] != 0.0 ? h[k] : 1.0;
     T PdkL = T(C.c * C.c) * PL[d][k] * T(hk / h[d]);
     T PdkR = T(C.c * C.c) * PR[d][k] * T(hk / h[d]);
-    flux[1 + k] = (T(SR) * PdkL - T(SL) * PdkR + T(SR * SL) * (qR[1 + k] - qL[1 + k])) / T(SR - SL);
+    flux[1 + k] = (SR * PdkL - SL * PdkR + (SR * SL) * (qR[1 + k] - qL[1 + k])) / (SR - SL);
   }
 }
 
@@ -973,6 +1024,17 @@ int orc_closure(const OrcDesc* D, double E, const double* Fphys, double* P) {
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) P[3 * a + b] = Pm[a][b];
   (void)geo;
+  return 0;
+}
+
+// The M1 characteristic speeds of one state along x (Cartesian): F_x = Fn (physical).
+int orc_m1_speeds(const OrcDesc* D, double E, double Fn, double* lmin, double* lmax) {
+  Ctx<double> C;
+  C.D = D;
+  C.c = D->c;
+  C.ndim = 3;
+  double q[4] = {E, Fn, 0.0, 0.0}, h[3] = {1.0, 1.0, 1.0};
+  m1_speeds(C, q, h, 0, *lmin, *lmax);
   return 0;
 }
 

@@ -50,6 +50,7 @@ class OrcDesc(ctypes.Structure):
         ("c", ctypes.c_double),
         ("nthreads", ctypes.c_int32),
         ("integrator", ctypes.c_int32),
+        ("wavespeed", ctypes.c_int32),
     ]
 
 
@@ -81,6 +82,7 @@ def lib():
         _lib.orc_jvp.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, vp, vp, vp, d, ctypes.c_int, vp, vp, vp, vp]
         _lib.orc_geometry.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_closure.argtypes = [P(OrcDesc), d, vp, vp]
+        _lib.orc_m1_speeds.argtypes = [P(OrcDesc), d, d, P(d), P(d)]
         _lib.orc_explicit.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, d, vp, vp]
         _lib.orc_planck_tail.restype = d
         _lib.orc_planck_tail.argtypes = [d]
@@ -108,6 +110,7 @@ class Problem:
     c: float = 1.0
     nthreads: int = 0
     integrator: int = EULER
+    wavespeed: int = 0          # 0: S = -+c; 1: HLLE bounds from the M1 characteristic speeds
     extra: dict = field(default_factory=dict)
 
     def desc(self) -> OrcDesc:
@@ -127,6 +130,7 @@ class Problem:
         d.c = self.c
         d.nthreads = self.nthreads
         d.integrator = self.integrator
+        d.wavespeed = self.wavespeed
         return d
 
     @property
@@ -274,6 +278,16 @@ def closure(E, Fphys, c=1.0, eddington=False):
     P = np.empty(9)
     lib().orc_closure(ctypes.byref(desc), float(E), _ptr(F), _ptr(P))
     return P.reshape(3, 3)
+
+
+def m1_speeds(E, Fn, c=1.0, eddington=False):
+    """(lambda_-, lambda_+): the oracle's M1 characteristic speeds of one state with physical
+    normal flux Fn (the HLLE wavespeed option)."""
+    p = Problem(ndim=3, n=(1, 1, 1), G=1, c=c, closure=1 if eddington else 0)
+    desc = p.desc()
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().orc_m1_speeds(ctypes.byref(desc), float(E), float(Fn), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def explicit(p: Problem, E, F, kappa, sigma, dt, inflow=None):
