@@ -76,6 +76,17 @@ enum { FORNAX_CLOSURE_M1 = 0, FORNAX_CLOSURE_EDDINGTON = 1 };
  * U^{n+1} once per step, and dE_matter is taken against that U^-. */
 enum { FORNAX_EULER = 0, FORNAX_SSPRK2 = 1 };
 
+/* Wavespeed bounds of the HLL fluxes (Riemann Solvers subsection, eq:hll: the paper names the
+ * fastest left- and right-going wave speeds S_L, S_R without giving them).  LIGHT: S_L = -c,
+ * S_R = +c, the bound of every M1 characteristic speed (the method's default here).  M1:
+ * HLLE bounds S_L = min(0, l-(L), l-(R)), S_R = max(0, l+(L), l+(R)) from the eigenvalues of the
+ * flux Jacobian of the one-dimensional M1 system at each face state, taken with the state's
+ * normal reduced flux f = F^_d / (cE): l-+ = (c / s)(f -+ 2 (s - 1) / sqrt(3)),
+ * s = sqrt(4 - 3 f^2) (+-c/sqrt(3) at f = 0, both c f at |f| = 1; +-c/sqrt(3) for the
+ * Eddington closure; +-c where E <= 0).  Less numerical diffusion where the radiation is close
+ * to isotropic.  fornax_m1_adjoint supports LIGHT only. */
+enum { FORNAX_WAVESPEED_LIGHT = 0, FORNAX_WAVESPEED_M1 = 1 };
+
 typedef struct {
   int32_t ndim;             /* active directions, 1..3 */
   int32_t n[3];             /* zones per direction; n[d] = 1 for d >= ndim */
@@ -89,6 +100,7 @@ typedef struct {
   double c;                 /* (reduced) speed of light, > 0 */
   double f_fp64;            /* MIXED only: closure evaluated in double where f >= f_fp64 */
   int32_t integrator;       /* FORNAX_EULER (the configurations' default) or FORNAX_SSPRK2 */
+  int32_t wavespeed;        /* FORNAX_WAVESPEED_LIGHT (default) or FORNAX_WAVESPEED_M1 */
 } fornax_m1_desc;
 
 typedef struct fornax_m1_ctx fornax_m1_ctx;   /* opaque; owns geometry tables and scratch */

@@ -487,6 +487,7 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
   a.ndim = D.ndim;
   a.limiter = D.limiter;
   a.closure = D.closure;
+  a.wavespeed = D.wavespeed;
   a.zones_per_block = 0;
   a.nzones = (int64_t)D.n[0] * D.n[1] * D.n[2];
   a.c = D.c;
@@ -571,6 +572,7 @@ int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const forn
   const fornax_m1_desc& D = ctx->desc;
   if (D.coord != FORNAX_CARTESIAN || D.ndim > 2 || D.ngroups > 128) return FORNAX_EUNSUPPORTED;
   if (D.integrator != FORNAX_EULER) return FORNAX_EUNSUPPORTED;   // the adjoint is of the Euler push
+  if (D.wavespeed != FORNAX_WAVESPEED_LIGHT) return FORNAX_EUNSUPPORTED;
   if (!ctx->adj_gbuf[0]) return FORNAX_ENOMEM;
   if (!Unp1 && !ctx->adj_u1) {
     // first adjoint call on this context: scratch for U^{n+1}

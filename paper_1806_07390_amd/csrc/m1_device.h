@@ -350,9 +350,38 @@ __device__ __forceinline__ void closure_row(const R q[4], const R ih[3], int d, 
   for (int k = 0; k < ND; ++k) P[k] = af * f[k] + (k == d ? iso : R(0));
 }
 
+// Characteristic speeds (physical) of the one-dimensional M1 system at a face state with
+// energy E and normal physical flux Fn: the eigenvalues of its flux Jacobian, which for the
+// Levermore factor reduce to l-+ = c (f (1 + s) -+ 2 sqrt(3) (1 - f^2)) / (s (1 + s)),
+// f = Fn / (cE) clamped to [-1, 1], s = sqrt(4 - 3 f^2) -- free of cancellation as |f| -> 1.
+// Eddington closure: -+c/sqrt(3); E <= 0: -+c.
+template <typename R>
+__device__ __forceinline__ void m1_speeds(R E, R Fn, R c, int closure, R& lo, R& hi) {
+  if (!(E > R(0))) {
+    lo = -c;
+    hi = c;
+    return;
+  }
+  if (closure == FORNAX_CLOSURE_EDDINGTON) {
+    hi = c * R(0.57735026918962576451);
+    lo = -hi;
+    return;
+  }
+  R f = Fn * rcp_(c * E);
+  f = f > R(1) ? R(1) : (f < R(-1) ? R(-1) : f);
+  const R g = R(1) - f * f;
+  const R s = sqrt_(R(4) - R(3) * f * f);
+  const R r = c * rcp_(s * (R(1) + s));
+  const R u = f * (R(1) + s), v = R(3.46410161513775458705) * g;
+  lo = (u - v) * r;
+  hi = (u + v) * r;
+}
+
 // HLL flux (coordinate components) across a d-face with face scale factors h and their
 // inverses ih, left/right states qL, qR and the correction factor eps of the energy flux.
-template <typename R, bool SPH, int ND>
+// S_R = -S_L = c; with WS, a launch whose wavespeed option asks for them takes the HLLE bounds
+// from the M1 characteristic speeds of both states instead.
+template <typename R, bool SPH, int ND, bool WS = false>
 __device__ __forceinline__ void hll(const StepArgsBase& a, int d, const R qL[4], const R qR[4], const R h[3],
                                     const R ih[3], R eps, R flux[4]) {
   const R c = R(a.c);
@@ -363,6 +392,22 @@ __device__ __forceinline__ void hll(const StepArgsBase& a, int d, const R qL[4],
   if constexpr (SPH) {
     ihd = ih[d];
     S = c * ihd;
+  }
+  if constexpr (WS) {
+    if (a.wavespeed == FORNAX_WAVESPEED_M1) {
+      R lL, hL, lR, hR;
+      m1_speeds<R>(qL[0], SPH ? qL[1 + d] * ihd : qL[1 + d], c, a.closure, lL, hL);
+      m1_speeds<R>(qR[0], SPH ? qR[1 + d] * ihd : qR[1 + d], c, a.closure, lR, hR);
+      const R SL = fmin(R(0), fmin(lL, lR)) * ihd, SR = fmax(R(0), fmax(hL, hR)) * ihd;
+      const R SLR = SR * SL, id = rcp_(SR - SL);
+      flux[0] = (SR * (qL[1 + d] * (ihd * ihd)) - SL * (qR[1 + d] * (ihd * ihd)) + eps * SLR * (qR[0] - qL[0])) * id;
+      for (int k = 0; k < ND; ++k) {
+        const R hk = SPH ? h[k] * ihd : R(1);
+        flux[1 + k] = (SR * (c * c * PL[k] * hk) - SL * (c * c * PR[k] * hk) + SLR * (qR[1 + k] - qL[1 + k])) * id;
+      }
+      for (int k = ND; k < 3; ++k) flux[1 + k] = R(0);
+      return;
+    }
   }
   const R half = R(0.5);
   // energy: F^d = F_d / h_d^2; S_R = -S_L = S
@@ -406,7 +451,7 @@ __device__ __forceinline__ void face_flux(const StepArgs<S>& a, const Geo<R>& ge
   const R dlL = proper_width<R, SPH>(geo, d, d == 0 ? eL : ei, d == 1 ? eL : ej);
   const R dlR = proper_width<R, SPH>(geo, d, d == 0 ? ef : ei, d == 1 ? ef : ej);
   const R eps = epsilon_of(ksL, ksR, dlL, dlR);
-  hll<R, SPH, ND>(a, d, Lhi, Rlo, h1, ih1, eps, flux);
+  hll<R, SPH, ND, true>(a, d, Lhi, Rlo, h1, ih1, eps, flux);
 }
 
 // geometric source c^2 sum_{l,m} <Gamma^l_{km}> P^m_l for the covariant flux components of a

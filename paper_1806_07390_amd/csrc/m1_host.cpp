@@ -85,6 +85,7 @@ int validate(const fornax_m1_desc* d) {
   if (d->limiter < 0 || d->limiter > 2) return FORNAX_EINVAL;
   if (d->closure < 0 || d->closure > 1) return FORNAX_EINVAL;
   if (d->integrator != FORNAX_EULER && d->integrator != FORNAX_SSPRK2) return FORNAX_EINVAL;
+  if (d->wavespeed != FORNAX_WAVESPEED_LIGHT && d->wavespeed != FORNAX_WAVESPEED_M1) return FORNAX_EINVAL;
   if (!(d->c > 0.0) || !std::isfinite(d->c)) return FORNAX_EINVAL;
   int64_t nz = 1;
   for (int k = 0; k < 3; ++k) {

@@ -61,6 +61,7 @@ struct StepArgsBase {
   // flags (bit 0: flip the normal flux, bit 1: inflow state, bit 2: polar-axis copy)
   int gsrc[3][4], gfl[3][4];
   int limiter, closure;
+  int wavespeed;             // FORNAX_WAVESPEED_*
   int zones_per_block;
   int64_t nzones;
   double c, dt;

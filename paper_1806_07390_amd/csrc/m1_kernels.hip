@@ -171,6 +171,7 @@ void fill_args(const fornax_m1_ctx* ctx, StepArgs<S>& a, const fornax_m1_coeffs*
   a.ndim = D.ndim;
   a.limiter = D.limiter;
   a.closure = D.closure;
+  a.wavespeed = D.wavespeed;
   a.zones_per_block = BLOCK / D.ngroups;
   a.nzones = (int64_t)D.n[0] * D.n[1] * D.n[2];
   a.c = D.c;

@@ -225,7 +225,8 @@ __host__ __device__ inline size_t unit_lds_elems(int dim, int TXB, int TYB, int 
 
 // Waves per SIMD for the compile-time wave-row kernels (measured on gfx950): 3 in double
 // (at most 168 VGPRs, no spills), 5 in float (at most 96 VGPRs).  LIM: the limiter when
-// known at compile time, -1 to read it from the arguments.
+// known at compile time, -1 to read it from the arguments (that instantiation also takes the
+// wavespeed option from the arguments; the others use S = -+c).
 // The spherical 3-D step in double needs more than the 256 registers of a wave that shares its
 // SIMD: its blocks are limited to 256 threads (one wave per SIMD) and the empty asm statement
 // at its start, which names an accumulation register, keeps that bank available to the
@@ -496,7 +497,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         R lo[4], hiP[4];
         reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef - 1, qa[u], qb[u], q0[u], ih0, ih1, o0, o1, lo, hiP);
         reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef, qb[u], q0[u], q1[u], ih1, ih2, o1, o2, lo, hiM[u]);
-        if (o1) hll<R, SPH, DIM>(a, MD, hiP, lo, h1, ih1, epsilon_of(ka[u] + sa[u], ks0[u], dlL, dlR), fPrev[u]);
+        if (o1) hll<R, SPH, DIM, (LIM < 0)>(a, MD, hiP, lo, h1, ih1, epsilon_of(ka[u] + sa[u], ks0[u], dlL, dlR), fPrev[u]);
       }
     } else {
       const int pm = load_own(0, raw, k0, s0);
@@ -602,7 +603,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         for (int u = 0; u < V; ++u) {
           R nLo[4];
           reconstruct<R, SPH, DIM, LIM>(a, geo, MD, ef, q0[u], q1[u], q2[u], ih1, ih2, o1, o2, nLo, nHi[u]);
-          if (o1) hll<R, SPH, DIM>(a, MD, hiM[u], nLo, h1, ih1, epsilon_of(ks0[u], ks1[u], dlL, dlR), fNext[u]);
+          if (o1) hll<R, SPH, DIM, (LIM < 0)>(a, MD, hiM[u], nLo, h1, ih1, epsilon_of(ks0[u], ks1[u], dlL, dlR), fNext[u]);
         }
       }
     }
@@ -622,7 +623,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
         R qR[4] = {R(0), R(0), R(0), R(0)};
         for (int v = 0; v < NC; ++v) qR[v] = LX[cidx(v, col + 1) + u];
         const R ksR = PV[pvi(NC, prow_own, cx + 2) + u];
-        if (open) hll<R, SPH, DIM>(a, 0, hiX[u], qR, hf, ihf, epsilon_of(ks0[u], ksR, dlL, dlR), fxR[u]);
+        if (open) hll<R, SPH, DIM, (LIM < 0)>(a, 0, hiX[u], qR, hf, ihf, epsilon_of(ks0[u], ksR, dlL, dlR), fxR[u]);
         for (int v = 0; v < NC; ++v) FX[cidx(v, col) + u] = fxR[u][v];
       }
     }
@@ -638,7 +639,7 @@ k_step_tiled(StepArgs<S> a, Geo<R> geo, Tile tl) {
           R qR[4] = {R(0), R(0), R(0), R(0)};
           for (int v = 0; v < NC; ++v) qR[v] = LY[cidx(v, col + TXB) + u];
           const R ksR = PV[pvi(NC, prow_own + 1, cx + 1) + u];
-          if (open) hll<R, SPH, DIM>(a, 1, hiY[u], qR, hf, ihf, epsilon_of(ks0[u], ksR, dlL, dlR), fyR[u]);
+          if (open) hll<R, SPH, DIM, (LIM < 0)>(a, 1, hiY[u], qR, hf, ihf, epsilon_of(ks0[u], ksR, dlL, dlR), fyR[u]);
           for (int v = 0; v < NC; ++v) FY[cidx(v, col) + u] = fyR[u][v];
         }
       }
@@ -982,8 +983,10 @@ int prepare_step_kernels() {
 template <typename S, typename R, bool SPH>
 static int launch_coord(const Geo<R>& geo, const StepArgs<S>& a, const Tile& tl, int D, hipStream_t st) {
   dim3 grid(tl.nblocks), block(tl.nthreads);
-  // the method's default limiter is a compile-time constant of its own instantiation
-  const bool mm = a.limiter == FORNAX_LIMITER_MINMOD;
+  // the method's default limiter (with the -+c wavespeed bounds) is a compile-time constant of
+  // its own instantiation; the instantiation that reads the limiter at run time also takes the
+  // M1-speed bounds
+  const bool mm = a.limiter == FORNAX_LIMITER_MINMOD && a.wavespeed == FORNAX_WAVESPEED_LIGHT;
 #define FM1_LAUNCH(DIMV, ROWV, GBV, VV)                                                                          \
   do {                                                                                                          \
     if (mm)                                                                                                     \

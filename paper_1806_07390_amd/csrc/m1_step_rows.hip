@@ -615,6 +615,7 @@ RowsTile make_rows_tile(const fornax_m1_desc& D, int NWX, int TM) {
   RowsTile tl{};
   tl.nblocks = 0;
   if (D.ndim != 2 || D.coord != FORNAX_CARTESIAN || D.ngroups != RG) return tl;
+  if (D.wavespeed != FORNAX_WAVESPEED_LIGHT) return tl;   // -+c bounds only
   if (NWX != 1) return tl;
   if (TM < 3) return tl;
   const size_t s = (D.precision == FORNAX_FP64) ? 8 : 4;
@@ -634,8 +635,9 @@ RowsTile make_rows_tile(const fornax_m1_desc& D, int NWX, int TM) {
 }
 
 RowsTile choose_rows_tile(const fornax_m1_desc& D, int cus) {
-  // in float (half the bytes per zone) the tiled kernel is faster (measured on gfx950)
-  if (D.precision != FORNAX_FP64) return RowsTile{};
+  // in float (half the bytes per zone) the tiled kernel is faster (measured on gfx950); the
+  // M1-speed bounds are in the tiled kernel only
+  if (D.precision != FORNAX_FP64 || D.wavespeed != FORNAX_WAVESPEED_LIGHT) return RowsTile{};
   // planes per block: every block loads TM + 3 planes (two below, two above, one repeated) and
   // holds its CU's LDS share (three blocks per CU); take the TM whose blocks fill whole rounds
   // of the CUs' block slots (at least 90 %) at the least TM + 3 per round, measured best on

@@ -31,6 +31,7 @@ FP64, MIXED = 0, 1
 LIMITER_MINMOD, LIMITER_MC, LIMITER_NONE = 0, 1, 2
 CLOSURE_M1, CLOSURE_EDDINGTON = 0, 1
 EULER, SSPRK2 = 0, 1
+WAVESPEED_LIGHT, WAVESPEED_M1 = 0, 1
 
 EXPORTED = ["fornax_m1_create", "fornax_m1_destroy", "fornax_m1_max_dt", "fornax_m1_step", "fornax_m1_flux",
             "fornax_m1_source", "fornax_m1_adjoint", "fornax_m1_copy_probe", "fornax_m1_strerror",
@@ -54,6 +55,7 @@ class Desc(ctypes.Structure):
         ("c", ctypes.c_double),
         ("f_fp64", ctypes.c_double),
         ("integrator", ctypes.c_int32),
+        ("wavespeed", ctypes.c_int32),
     ]
 
 
@@ -137,6 +139,7 @@ class Config:
     c: float = 1.0
     f_fp64: float = 0.9
     integrator: int = EULER
+    wavespeed: int = WAVESPEED_LIGHT
 
     @classmethod
     def from_workload(cls, w, precision=FP64, **kw):
@@ -165,6 +168,7 @@ class Context:
         d.c = cfg.c
         d.f_fp64 = cfg.f_fp64
         d.integrator = cfg.integrator
+        d.wavespeed = cfg.wavespeed
         self.desc = d
         self.shape = (n[2], n[1], n[0], cfg.G)
         self.nzones = n[0] * n[1] * n[2]

@@ -1,0 +1,122 @@
+"""GPU parity of the HLLE wavespeed option (S_L, S_R from the M1 characteristic speeds of both
+face states, FORNAX_WAVESPEED_M1) against the CPU oracle on the same seeded inputs: the step
+in every geometry the tiled kernel covers, both precisions, both closures, the face-flux entry
+point, and the entry points that refuse the option."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import m1_oracle as orc
+from paper_1806_07390_amd import workloads as wl
+from tests.parity_util import TOL_FP64, TOL_MIXED_RUN, gpu_run, problem_of, rel_l1, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m1():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1806_07390_amd import m1 as mod
+    return mod
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _case(name):
+    if name == "slab1d":
+        return wl.slab1d(steps=40)
+    if name == "blobs2d":
+        return wl.blobs2d(n=40, G=16, steps=6)
+    if name == "reflect2d":
+        w = wl.blobs2d(n=36, G=5, steps=6)
+        w.bc_lo = (wl.BC_REFLECT, wl.BC_OUTFLOW, 0)
+        w.bc_hi = (wl.BC_OUTFLOW, wl.BC_REFLECT, 0)
+        return w
+    if name == "core3d":
+        return wl.core3d(n=14, G=6, steps=5)
+    return wl.sphere3d(nr=14, nth=10, nph=8, G=4, steps=5)
+
+
+# (the Eddington closure's speeds, -+c/sqrt(3), do not bound the beams of the slab and of the
+# reflecting box, whose states then leave the realizable set: those pairs are left out)
+@pytest.mark.parametrize("name,closure", [("slab1d", "m1"), ("blobs2d", "m1"), ("reflect2d", "m1"),
+                                          ("core3d", "m1"), ("sphere3d", "m1"), ("blobs2d", "eddington"),
+                                          ("core3d", "eddington"), ("sphere3d", "eddington")])
+def test_m1_speed_bounds_match_oracle(m1, name, closure):
+    w = _case(name)
+    cl = 0 if closure == "m1" else 1
+    p = problem_of(w, wavespeed=1, closure=cl)
+    dt = w.dt if w.dt is not None else orc.max_dt(p, w.cfl)
+    E, F, dg = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow)
+    E0, F0, _ = orc.run(problem_of(w, closure=cl), w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow)
+    assert rel_l1(E0, F0, E, F, w.c)[0] > 1e-10      # the option changes the result
+    for prec, tol in ((m1.FP64, TOL_FP64), (m1.MIXED, TOL_MIXED_RUN)):
+        ctx = m1.Context(m1.Config.from_workload(w, precision=prec, closure=cl, wavespeed=m1.WAVESPEED_M1))
+        Eg, Fg, dgg = gpu_run(ctx, w, dt, w.steps, diag=True)
+        eE, eF = rel_l1(Eg, Fg, E, F, w.c)
+        say(f"M1 speeds {name} closure={closure} prec={prec}", eE, eF)
+        assert eE <= tol and eF <= tol
+        assert int(dgg["n_unrealizable"][0]) == dg["n_unrealizable"]
+        if prec == m1.FP64:
+            assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-12)
+
+
+def test_whole_zone_grid_falls_back_to_the_tiled_kernel(m1):
+    """A 2-D 16-group FP64 grid (the whole-zone kernel's kind, which has -+c bounds only) with
+    the M1 speeds runs on the tiled kernel, also when the whole-zone tiling is asked for."""
+    w = wl.blobs2d(n=70, G=16, steps=3)
+    p = problem_of(w, wavespeed=1)
+    E, F, _ = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, w.dt, w.steps)
+    for rows in (None, "1,9"):
+        if rows:
+            os.environ["FORNAX_M1_ROWS"] = rows
+        try:
+            ctx = m1.Context(m1.Config.from_workload(w, wavespeed=m1.WAVESPEED_M1))
+        finally:
+            os.environ.pop("FORNAX_M1_ROWS", None)
+        Eg, Fg = gpu_run(ctx, w, w.dt, w.steps)
+        eE, eF = rel_l1(Eg, Fg, E, F, w.c)
+        say("M1 speeds on a whole-zone grid", rows, eE, eF)
+        assert eE <= TOL_FP64 and eF <= TOL_FP64
+
+
+def test_flux_entry_point_with_m1_speeds(m1):
+    w = wl.sphere3d(nr=12, nth=8, nph=8, G=3, steps=1)
+    rng = np.random.default_rng(4)
+    w.E = w.B * (1 + rng.random(w.E.shape))
+    w.F = [0.6 * w.E * rng.uniform(-1, 1, w.E.shape) for _ in range(3)]
+    p = problem_of(w, wavespeed=1)
+    ctx = m1.Context(m1.Config.from_workload(w, wavespeed=m1.WAVESPEED_M1))
+    E = to_dev(w.E, torch.float64)
+    F = [to_dev(f, torch.float64) for f in w.F]
+    k, s, B = (to_dev(x, torch.float64) for x in (w.kappa, w.sigma, w.B))
+    fl = ctx.flux(E, F, k, s, B, inflow=to_dev(w.inflow, torch.float64))
+    for d in range(3):
+        ref = orc.flux(p, w.E, w.F, w.kappa, w.sigma, w.B, d, inflow=w.inflow)
+        ref0 = orc.flux(problem_of(w), w.E, w.F, w.kappa, w.sigma, w.B, d, inflow=w.inflow)
+        scale = np.abs(ref).max()
+        assert np.max(np.abs(ref - ref0)) > 1e-6 * scale
+        assert np.max(np.abs(to_host(fl[d]) - ref)) <= 1e-13 * scale, d
+
+
+def test_adjoint_refuses_m1_speeds(m1):
+    w = wl.adjoint2d(n=16, G=2, steps=1)
+    ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64, wavespeed=m1.WAVESPEED_M1))
+    t = lambda a: to_dev(a, torch.float64)
+    z = [torch.zeros_like(t(w.E)) for _ in w.F]
+    with pytest.raises(m1.FornaxError) as ei:
+        ctx.adjoint(t(w.E), [t(f) for f in w.F], t(w.kappa), t(w.sigma), t(w.B), w.dt, t(w.E), z)
+    assert ei.value.code == m1.FORNAX_EUNSUPPORTED
+
+
+def test_invalid_wavespeed_is_rejected(m1):
+    w = wl.blobs2d(n=8, G=2, steps=1)
+    with pytest.raises(m1.FornaxError) as ei:
+        m1.Context(m1.Config.from_workload(w, wavespeed=7))
+    assert ei.value.code == m1.FORNAX_EINVAL
