@@ -59,7 +59,7 @@ static inline double der(const Dual& a) { return a.d; }
 // ------------------------------------------------------------------------------------
 enum { OC_CART = 0, OC_SPH_LOGR = 1 };
 enum { OB_OUTFLOW = 0, OB_PERIODIC = 1, OB_REFLECT = 2, OB_INFLOW = 3, OB_AXIS = 4 };
-enum { OL_MINMOD = 0, OL_MC = 1, OL_CONST = 2 };
+enum { OL_MINMOD = 0, OL_MC = 1, OL_CONST = 2, OL_PPM = 3 };
 
 extern "C" {
 struct OrcDesc {
@@ -69,7 +69,7 @@ struct OrcDesc {
   int32_t coord;      // OC_CART, or OC_SPH_LOGR: x1 = ln r, x2 = theta, x3 = phi
   double lo[3], hi[3];
   int32_t bc_lo[3], bc_hi[3];
-  int32_t limiter;    // OL_MINMOD (default), OL_MC, OL_CONST (piecewise constant)
+  int32_t limiter;    // OL_MINMOD (default), OL_MC, OL_CONST (piecewise constant), OL_PPM (parabolic)
   int32_t closure;    // 0 = M1 (Levermore), 1 = Eddington (P = E/3 I)
   int32_t eps_mode;   // 0 = eq:epsilon as in the paper; 1 = epsilon forced to 1 (plain HLL)
   double c;           // (reduced) speed of light
@@ -128,6 +128,9 @@ struct Geom {
   std::vector<double> W[3];    // integral of w_d over the zone
   std::vector<double> X[3];    // volume centroid <x^d> of the zone
   std::vector<double> wf[3];   // w_d at face i-1/2 (exactly 0 on a polar-axis boundary face)
+  // parabolic reconstruction: volume averages <u>, <u^2> of u = x - xc_i over zones i-1, i,
+  // i+1 (index 3 (i+NG) + k, k = 0, 1, 2), for every zone with both neighbours in the table
+  std::vector<double> pu1[3], pu2[3];
   std::vector<double> r2;      // <r^2> over the zone (axis 0), spherical only
   std::vector<double> s2;      // <sin^2 theta> over the zone (axis 1), spherical only
   // volume-averaged connection coefficients that depend on theta (axis 1):
@@ -165,6 +168,17 @@ struct Geom {
         X[d][e] = romberg([&](double x) { return x * w(d, x); }, a, b) / W[d][e];
       }
       for (int e = 0; e <= m; ++e) wf[d][e] = w(d, xf[d][e]);
+      pu1[d].assign(3 * m, 0.0);
+      pu2[d].assign(3 * m, 0.0);
+      if (D.limiter == OL_PPM) {
+        for (int e = 1; e + 1 < m; ++e)
+          for (int k = 0; k < 3; ++k) {
+            const int z = e - 1 + k;
+            const double a = xf[d][z], b = xf[d][z + 1], u0 = xc[d][e];
+            pu1[d][3 * e + k] = romberg([&](double x) { return (x - u0) * w(d, x); }, a, b) / W[d][z];
+            pu2[d][3 * e + k] = romberg([&](double x) { return (x - u0) * (x - u0) * w(d, x); }, a, b) / W[d][z];
+          }
+      }
       // Reading: a face on the polar axis has zero area (sin theta = 0 there); the
       // floating-point sin(pi) is not exactly 0, so the axis faces are set to 0 exactly.
       if (sph() && d == 1) {
@@ -365,13 +379,111 @@ static bool realizable(const Ctx<T>& C, const T q[4], const double h[3]) {
   return f2 <= cE * cE;
 }
 
+// Solution of A c = r for a 3x3 matrix of geometry (Cramer's rule).
+template <class T>
+static void solve3(const double A[3][3], const T r[3], T c[3]) {
+  auto det3 = [](const double M[3][3]) {
+    return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+           M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+  };
+  const double det = det3(A);
+  for (int j = 0; j < 3; ++j) {
+    // column j replaced by r: expand along that column
+    double cof[3];
+    for (int i = 0; i < 3; ++i) {
+      double M[2][2];
+      int a = 0;
+      for (int ii = 0; ii < 3; ++ii) {
+        if (ii == i) continue;
+        int b = 0;
+        for (int jj = 0; jj < 3; ++jj) {
+          if (jj == j) continue;
+          M[a][b++] = A[ii][jj];
+        }
+        ++a;
+      }
+      cof[i] = (((i + j) & 1) ? -1.0 : 1.0) * (M[0][0] * M[1][1] - M[0][1] * M[1][0]);
+    }
+    c[j] = (r[0] * T(cof[0]) + r[1] * T(cof[1]) + r[2] * T(cof[2])) / T(det);
+  }
+}
+
+// Parabolic reconstruction of one component along d (Reconstruction subsection, n = 2), in
+// the local coordinate u = x - x_i (x_i the zone's coordinate centre, x_{i-+1/2} = x_i -+ dx/2):
+//  1. if q_i is a local extremum of (q_{i-1}, q_i, q_{i+1}) the zone is piecewise constant;
+//  2. else the parabola p(u) = c0 + c1 u + c2 u^2 with the three zones' volume averages
+//     (eq:recon_system1, <u^j> over each zone with the volume element) gives the face states
+//     p(u_{i-1/2}) and p(u_{i+1/2});
+//  3. if p has its extremum between the centres of zones i-1 and i, the lower face state is
+//     reset to make the profile monotone there with zero slope at the centre of zone i-1:
+//     the parabola through (x_{i-1}, q_{i-1}) and (x_i, q_i) with zero slope at x_{i-1},
+//     evaluated at the face; likewise the upper face state with zones i and i+1 and zero
+//     slope at x_{i+1};
+//  4. the parabola through the two face states and the zone's average (eq:recon_system2);
+//     if its extremum lies inside the zone, the face state nearer to it (the upper one when
+//     the extremum is at the centre) is reset so that the parabola through the other face
+//     state and the average has zero slope at that face.
+// Readings: the extremum test of step 1 is (q_i - q_{i-1})(q_{i+1} - q_i) <= 0; steps 3 and 4
+// take the paper's "zero slope" conditions at the places it names, with the neighbours'
+// averages as the values at their centres in step 3; "nearest" in step 4 is by position.
+template <class T>
+static void parabolic_faces(const Geom& G, int d, int e, T qm, T q0, T qp, T& vl, T& vh) {
+  vl = vh = q0;
+  if (!(val((q0 - qm) * (qp - q0)) > 0.0)) return;
+  const double ulo = G.xf[d][e] - G.xc[d][e], uhi = G.xf[d][e + 1] - G.xc[d][e];
+  const double um = G.xc[d][e - 1] - G.xc[d][e], up = G.xc[d][e + 1] - G.xc[d][e];
+  const double* m1 = &G.pu1[d][3 * e];
+  const double* m2 = &G.pu2[d][3 * e];
+  // step 2 (eq:recon_system1)
+  const double A1[3][3] = {{1.0, m1[0], m2[0]}, {1.0, m1[1], m2[1]}, {1.0, m1[2], m2[2]}};
+  const T r1[3] = {qm, q0, qp};
+  T c[3];
+  solve3(A1, r1, c);
+  vl = c[0] + c[1] * T(ulo) + c[2] * T(ulo * ulo);
+  vh = c[0] + c[1] * T(uhi) + c[2] * T(uhi * uhi);
+  // step 3
+  if (val(c[2]) != 0.0) {
+    const double us = -val(c[1]) / (2.0 * val(c[2]));
+    if (us > um && us < 0.0) {
+      const double t = (ulo - um) / (0.0 - um);
+      vl = qm + (q0 - qm) * T(t * t);
+    } else if (us > 0.0 && us < up) {
+      const double t = (uhi - up) / (0.0 - up);
+      vh = qp + (q0 - qp) * T(t * t);
+    }
+  }
+  // step 4 (eq:recon_system2)
+  const double A2[3][3] = {{1.0, ulo, ulo * ulo}, {1.0, m1[1], m2[1]}, {1.0, uhi, uhi * uhi}};
+  const T r2[3] = {vl, q0, vh};
+  solve3(A2, r2, c);
+  if (val(c[2]) != 0.0) {
+    const double us = -val(c[1]) / (2.0 * val(c[2]));
+    if (us > ulo && us < uhi) {
+      if (us - ulo < uhi - us) {
+        // zero slope at the lower face, through the upper face state and the average
+        const double A3[3][3] = {{0.0, 1.0, 2.0 * ulo}, {1.0, m1[1], m2[1]}, {1.0, uhi, uhi * uhi}};
+        const T r3[3] = {T(0.0), q0, vh};
+        solve3(A3, r3, c);
+        vl = c[0] + c[1] * T(ulo) + c[2] * T(ulo * ulo);
+      } else {
+        const double A3[3][3] = {{1.0, ulo, ulo * ulo}, {1.0, m1[1], m2[1]}, {0.0, 1.0, 2.0 * uhi}};
+        const T r3[3] = {vl, q0, T(0.0)};
+        solve3(A3, r3, c);
+        vh = c[0] + c[1] * T(uhi) + c[2] * T(uhi * uhi);
+      }
+    }
+  }
+}
+
 // Linear reconstruction along d in the volume coordinate (Reconstruction subsection,
 // eq:recon_constraints with n = 1; the paper reconstructs radiation with linear profiles):
 // p(x) = q_i + s (x - <x>_i) has the zone's volume average, and the slope s is the minmod
 // of the one-sided differences taken between volume centroids.  Face states are
 // p(x_{i-1/2}) and p(x_{i+1/2}).
 // Reading (non-realizable face states): if either face state of the zone fails the
-// realizability test, the zone falls back to piecewise-constant in direction d.
+// realizability test, the zone falls back to piecewise-constant in direction d.  With the
+// parabolic option (OL_PPM) the face states come from parabolic_faces instead, with the same
+// fallback.
 template <class T>
 static void reconstruct(const Ctx<T>& C, int d, const int idx[3], int g, T lo[4], T hi[4]) {
   const Geom& G = *C.geo;
@@ -385,6 +497,14 @@ static void reconstruct(const Ctx<T>& C, int d, const int idx[3], int g, T lo[4]
   double Xm = G.X[d][im[d] + NG], X0 = G.X[d][idx[d] + NG], Xp = G.X[d][ip[d] + NG];
   double xlo = G.xf[d][idx[d] + NG], xhi = G.xf[d][idx[d] + NG + 1];
   for (int cpt = 0; cpt < 4; ++cpt) {
+    if (C.D->limiter == OL_PPM) {
+      if (cpt <= C.ndim) {
+        parabolic_faces(G, d, idx[d] + NG, qm[cpt], q0[cpt], qp[cpt], lo[cpt], hi[cpt]);
+      } else {
+        lo[cpt] = hi[cpt] = q0[cpt];
+      }
+      continue;
+    }
     T s = T(0.0);
     if (cpt <= C.ndim) {
       if (C.D->limiter == OL_MINMOD) {
@@ -903,6 +1023,42 @@ int orc_flux(const OrcDesc* D, const double* E, const double* const* F, const do
       double fl[4];
       face_flux(C, d, row, idx[d], g, fl);
       for (int k = 0; k < nc; ++k) out[((size_t)f * D->G + g) * nc + k] = fl[k];
+    }
+  }
+  return 0;
+}
+
+// Face states of every zone along d (the reconstruction step, with its realizability
+// fallback): out[((zone * G + g) * 2 + side) * (1 + ndim) + k], side 0 = lower face.
+int orc_faces(const OrcDesc* D, const double* E, const double* const* F, const double* inflow, int d, double* out) {
+  Geom geo;
+  geo.build(*D);
+  Ctx<double> C;
+  C.D = D;
+  C.geo = &geo;
+  for (int e = 0; e < 3; ++e) C.n[e] = D->n[e];
+  C.G = D->G;
+  C.ndim = D->ndim;
+  C.c = D->c;
+  C.dt = 0.0;
+  C.E = E;
+  for (int k = 0; k < 3; ++k) C.F[k] = (k < D->ndim) ? F[k] : nullptr;
+  std::vector<double> zero((size_t)D->n[0] * D->n[1] * D->n[2] * D->G, 0.0);
+  C.kap = zero.data();
+  C.sig = zero.data();
+  C.B = zero.data();
+  C.inflow = inflow;
+  const long nz = (long)D->n[0] * D->n[1] * D->n[2];
+  const int nc = 1 + D->ndim;
+  for (long z = 0; z < nz; ++z) {
+    int idx[3] = {(int)(z % D->n[0]), (int)((z / D->n[0]) % D->n[1]), (int)(z / ((long)D->n[0] * D->n[1]))};
+    for (int g = 0; g < D->G; ++g) {
+      double lo[4], hi[4];
+      reconstruct(C, d, idx, g, lo, hi);
+      for (int k = 0; k < nc; ++k) {
+        out[((z * D->G + g) * 2 + 0) * nc + k] = lo[k];
+        out[((z * D->G + g) * 2 + 1) * nc + k] = hi[k];
+      }
     }
   }
   return 0;

@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "libm1_oracle.so")
 
 CART, SPH_LOGR = 0, 1
 OUTFLOW, PERIODIC, REFLECT, INFLOW, AXIS = 0, 1, 2, 3, 4
-MINMOD, MC, CONST = 0, 1, 2
+MINMOD, MC, CONST, PPM = 0, 1, 2, 3
 EULER, SSPRK2 = 0, 1
 
 
@@ -83,6 +83,7 @@ def lib():
         _lib.orc_geometry.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_closure.argtypes = [P(OrcDesc), d, vp, vp]
         _lib.orc_m1_speeds.argtypes = [P(OrcDesc), d, d, P(d), P(d)]
+        _lib.orc_faces.argtypes = [P(OrcDesc), vp, vp, vp, ctypes.c_int, vp]
         _lib.orc_explicit.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, d, vp, vp]
         _lib.orc_planck_tail.restype = d
         _lib.orc_planck_tail.argtypes = [d]
@@ -214,6 +215,18 @@ def flux(p: Problem, E, F, kappa, sigma, B, d, inflow=None):
     out = np.empty(tuple(s) + (p.G, 1 + p.ndim))
     lib().orc_flux(ctypes.byref(desc), _ptr(E), _ptrs(F), _ptr(kappa), _ptr(sigma), _ptr(B), _ptr(inflow), d,
                    _ptr(out))
+    return out
+
+
+def faces(p: Problem, E, F, d, inflow=None):
+    """Face states of every zone along d (after the realizability fallback): array
+    [zones..., G, 2, 1+ndim], index 0 of the 2 the lower face."""
+    desc = p.desc()
+    E = _c(E)
+    F = [_c(f) for f in F]
+    inflow = None if inflow is None else _c(inflow)
+    out = np.empty(tuple(p.shape[:3]) + (p.G, 2, 1 + p.ndim))
+    lib().orc_faces(ctypes.byref(desc), _ptr(E), _ptrs(F), _ptr(inflow), d, _ptr(out))
     return out
 
 
