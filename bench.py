@@ -262,8 +262,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default=None,
-                    help="profiling: run only this workload's timed loop (blobs2d, core3d, sphere3d, matter, "
-                         "adjoint, extras = all after blobs2d, copy = the copy probe alone)")
+                    help="profiling: run only this workload's timed loop (blobs2d, core3d, sphere3d, options, "
+                         "matter, adjoint, extras = all after blobs2d, copy = the copy probe alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU path; "
@@ -328,6 +328,28 @@ def main():
                 del ctx, inp
                 torch.cuda.empty_cache()
             del w4
+        # ---- the reconstruction and wavespeed options on the headline grid -----------------
+        if args.only in (None, "extras", "options"):
+            wo = wl.blobs2d()
+            inp = device_inputs(wo, torch.float64)
+            opts = {"ppm": dict(limiter=m1.LIMITER_PPM), "m1_speeds": dict(wavespeed=m1.WAVESPEED_M1),
+                    "minmod_tiled": dict(limiter=m1.LIMITER_MINMOD)}
+            for name, kw in opts.items():
+                if name == "minmod_tiled":
+                    os.environ["FORNAX_M1_ROWS"] = "0"
+                try:
+                    ctx = m1.Context(m1.Config.from_workload(wo, precision=m1.FP64, **kw))
+                finally:
+                    os.environ.pop("FORNAX_M1_ROWS", None)
+                mso, _ = time_steps(ctx, inp, wo.dt, 50, 20, with_diag=True)
+                gbs = wo.zone_groups * algorithmic_bytes(2, 8) / (mso * 1e-3) / 1e9
+                extra[f"blobs2d_512^2x16_fp64_{name}"] = dict(ms_per_step=round(mso, 5),
+                                                              zgu_per_s=wo.zone_groups / (mso * 1e-3),
+                                                              algorithmic_GBps=round(gbs, 1))
+                log(f"  blobs2d fp64 {name}: {mso:.4f} ms/step, {gbs:.0f} GB/s")
+                del ctx
+            del inp, wo
+            torch.cuda.empty_cache()
         if args.only in (None, "extras", "matter"):
             extra["matter"] = matter_timings()
             log("  matter:", extra["matter"])

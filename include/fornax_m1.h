@@ -65,7 +65,17 @@ enum { FORNAX_BC_OUTFLOW = 0, FORNAX_BC_PERIODIC = 1, FORNAX_BC_REFLECT = 2, FOR
  * all accumulations (energy, dE_matter) in double. */
 enum { FORNAX_FP64 = 0, FORNAX_MIXED = 1 };
 
-enum { FORNAX_LIMITER_MINMOD = 0, FORNAX_LIMITER_MC = 1, FORNAX_LIMITER_NONE = 2 };
+/* Reconstruction (Reconstruction subsection).  MINMOD (the method's default here), MC: linear
+ * profiles in the volume coordinate with limited slopes (eq:recon_constraints, n = 1); NONE:
+ * piecewise constant; PPM: the paper's piecewise-parabolic reconstruction (n = 2): constant at
+ * a local extremum of the data, else the parabola with the three zones' averages
+ * (eq:recon_system1), each face state reset where that parabola turns between the zone's and
+ * its neighbour's centres (monotone there, zero slope at the neighbour's centre), and the face
+ * state nearer to an extremum of the parabola through both face states and the average
+ * (eq:recon_system2) reset to give that parabola zero slope at its face.  PPM is available on
+ * Cartesian grids (fornax_m1_create returns FORNAX_EUNSUPPORTED on spherical ones) and not in
+ * fornax_m1_adjoint. */
+enum { FORNAX_LIMITER_MINMOD = 0, FORNAX_LIMITER_MC = 1, FORNAX_LIMITER_NONE = 2, FORNAX_LIMITER_PPM = 3 };
 enum { FORNAX_CLOSURE_M1 = 0, FORNAX_CLOSURE_EDDINGTON = 1 };
 
 /* Explicit integrator of the transport (Numerical Discretization: the paper integrates the

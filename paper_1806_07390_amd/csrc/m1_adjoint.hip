@@ -572,7 +572,7 @@ int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const forn
   const fornax_m1_desc& D = ctx->desc;
   if (D.coord != FORNAX_CARTESIAN || D.ndim > 2 || D.ngroups > 128) return FORNAX_EUNSUPPORTED;
   if (D.integrator != FORNAX_EULER) return FORNAX_EUNSUPPORTED;   // the adjoint is of the Euler push
-  if (D.wavespeed != FORNAX_WAVESPEED_LIGHT) return FORNAX_EUNSUPPORTED;
+  if (D.wavespeed != FORNAX_WAVESPEED_LIGHT || D.limiter == FORNAX_LIMITER_PPM) return FORNAX_EUNSUPPORTED;
   if (!ctx->adj_gbuf[0]) return FORNAX_ENOMEM;
   if (!Unp1 && !ctx->adj_u1) {
     // first adjoint call on this context: scratch for U^{n+1}

@@ -176,8 +176,9 @@ __device__ __forceinline__ bool realizable(const R q[4], const R ih[3], R c) {
   return (q[0] > R(0)) && (F2 <= cE * cE);
 }
 
-// Linear reconstruction of one zone along d (extended index e): face states at its lower
-// and upper faces, with the piecewise-constant fallback when either is not realizable.
+// Linear reconstruction of one zone along d (extended index e), or parabolic on Cartesian
+// grids with the PPM option: face states at its lower and upper faces, with the
+// piecewise-constant fallback when either is not realizable.
 // LIM: the limiter when known at compile time (a FORNAX_LIMITER_* value), -1 to read it from
 // the arguments.
 template <typename R, bool SPH, int ND, int LIM = -1>
@@ -203,6 +204,37 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
         s[cp] = R(0);
       }
     }
+  } else if (limiter == FORNAX_LIMITER_PPM) {
+    // uniform Cartesian zones, parabolic: in u = (x - x_i)/dx the parabola with the three
+    // averages is p0 - c2/12 + c1 u + c2 u^2, c1 = (qp - qm)/2, c2 = (qm - 2 q0 + qp)/2
+    (void)geo;
+    (void)d;
+    (void)e;
+    for (int cp = 0; cp <= ND; ++cp) {
+      const R pm = qm[cp], p0 = q0[cp], pp = qp[cp];
+      R vl = p0, vh = p0;
+      if ((p0 - pm) * (pp - p0) > R(0)) {
+        vl = (R(2) * pm + R(5) * p0 - pp) * R(1.0 / 6.0);
+        vh = (R(5) * p0 + R(2) * pp - pm) * R(1.0 / 6.0);
+        // turning point -c1/(2 c2) between the centres of zones i-1 and i (c1 c2 > 0) or of
+        // zones i and i+1 (c1 c2 < 0): that face from the parabola with zero slope at the
+        // neighbour's centre through both averages, i.e. q_n + (q_i - q_n)/4
+        const R c1 = R(0.5) * (pp - pm), c2 = R(0.5) * (pm - R(2) * p0 + pp);
+        if (fabs(c1) < R(2) * fabs(c2)) {
+          if (c1 * c2 > R(0)) vl = pm + R(0.25) * (p0 - pm);
+          else vh = pp + R(0.25) * (p0 - pp);
+        }
+        // the parabola through vl, the average and vh: turning point -d1/(2 d2) inside the
+        // zone (|d1| < |d2|) resets the nearer face so that the slope vanishes there
+        const R d1 = vh - vl, d2 = R(3) * (vl + vh - R(2) * p0);
+        if (fabs(d1) < fabs(d2)) {
+          if (d1 * d2 > R(0)) vl = R(1.5) * p0 - R(0.5) * vh;
+          else vh = R(1.5) * p0 - R(0.5) * vl;
+        }
+      }
+      lo[cp] = vl;
+      hi[cp] = vh;
+    }
   } else {
     // uniform Cartesian zones: centroid = centre, faces at -+ dx/2 (slope times dx)
     (void)geo;
@@ -219,9 +251,11 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
       }
     }
   }
-  for (int cp = 0; cp <= ND; ++cp) {
-    lo[cp] = q0[cp] + s[cp] * dl;
-    hi[cp] = q0[cp] + s[cp] * dh;
+  if (SPH || limiter != FORNAX_LIMITER_PPM) {
+    for (int cp = 0; cp <= ND; ++cp) {
+      lo[cp] = q0[cp] + s[cp] * dl;
+      hi[cp] = q0[cp] + s[cp] * dh;
+    }
   }
   const bool ok =
       (!lo_open || realizable<R, SPH, ND>(lo, ihlo, c)) && (!hi_open || realizable<R, SPH, ND>(hi, ihhi, c));

@@ -82,7 +82,8 @@ int validate(const fornax_m1_desc* d) {
   if (d->ngroups > BLOCK) return FORNAX_EUNSUPPORTED;
   if (d->coord != FORNAX_CARTESIAN && d->coord != FORNAX_SPHERICAL_LOGR) return FORNAX_EINVAL;
   if (d->precision != FORNAX_FP64 && d->precision != FORNAX_MIXED) return FORNAX_EINVAL;
-  if (d->limiter < 0 || d->limiter > 2) return FORNAX_EINVAL;
+  if (d->limiter < 0 || d->limiter > 3) return FORNAX_EINVAL;
+  if (d->limiter == FORNAX_LIMITER_PPM && d->coord != FORNAX_CARTESIAN) return FORNAX_EUNSUPPORTED;
   if (d->closure < 0 || d->closure > 1) return FORNAX_EINVAL;
   if (d->integrator != FORNAX_EULER && d->integrator != FORNAX_SSPRK2) return FORNAX_EINVAL;
   if (d->wavespeed != FORNAX_WAVESPEED_LIGHT && d->wavespeed != FORNAX_WAVESPEED_M1) return FORNAX_EINVAL;

@@ -28,7 +28,7 @@ FORNAX_OK, FORNAX_EINVAL, FORNAX_ECFL, FORNAX_EDEVICE, FORNAX_ENOMEM, FORNAX_EUN
 CARTESIAN, SPHERICAL_LOGR = 0, 1
 BC_OUTFLOW, BC_PERIODIC, BC_REFLECT, BC_INFLOW, BC_AXIS = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
-LIMITER_MINMOD, LIMITER_MC, LIMITER_NONE = 0, 1, 2
+LIMITER_MINMOD, LIMITER_MC, LIMITER_NONE, LIMITER_PPM = 0, 1, 2, 3
 CLOSURE_M1, CLOSURE_EDDINGTON = 0, 1
 EULER, SSPRK2 = 0, 1
 WAVESPEED_LIGHT, WAVESPEED_M1 = 0, 1

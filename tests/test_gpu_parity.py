@@ -193,7 +193,7 @@ def _rows_case(bc, n0=70, n1=40, G=16, steps=4):
 
 
 @pytest.mark.parametrize("bc", ["periodic", "outflow_reflect", "inflow"])
-@pytest.mark.parametrize("lim", ["minmod", "mc"])
+@pytest.mark.parametrize("lim", ["minmod", "mc", "ppm"])
 def test_whole_zone_kernel(m1, bc, lim):
     """The 2-D, 16-group kernel that moves whole zones through LDS gives the oracle's result and
     that of the tiled kernel (FORNAX_M1_ROWS selects either: "NWX,TM" the whole-zone kernel,
@@ -201,7 +201,7 @@ def test_whole_zone_kernel(m1, bc, lim):
     the compiler fuses a multiply and an add.  Blocks of 9 planes (the last one 4) and of 3
     (the last one 1: a single plane after the prologue)."""
     import os
-    code = {"minmod": m1.LIMITER_MINMOD, "mc": m1.LIMITER_MC}[lim]
+    code = {"minmod": m1.LIMITER_MINMOD, "mc": m1.LIMITER_MC, "ppm": m1.LIMITER_PPM}[lim]
     w = _rows_case(bc)
     p = problem_of(w, limiter=code)
     dt = dt_of(w, p)
