@@ -170,11 +170,33 @@ def adjoint_ratios(steps=20):
                 end_to_end_backward_over_forward=round((t2 - t1) / (t1 - t0), 3))
 
 
-def cpu_baseline(w, dt, target_s=20.0):
-    """The CPU oracle on a bounded sample of the same workload: whole steps on the first rows."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, dt, target_s=20.0, single_s=8.0):
+    """The CPU oracle on a bounded sample of the same workload: whole steps with OpenMP over
+    the host's cores (the reported value), and whole steps on one thread."""
     from oracle import m1_oracle as orc
     ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     ncores = min(ncores, 16)
+    p1 = orc.Problem(ndim=w.ndim, n=w.n, G=w.G, coord=w.coord, lo=w.lo, hi=w.hi, bc_lo=w.bc_lo, bc_hi=w.bc_hi,
+                     c=w.c, nthreads=1)
+    t0 = time.perf_counter()
+    orc.run(p1, w.E, w.F, w.kappa, w.sigma, w.B, dt, 1)
+    t1 = time.perf_counter()
+    n1 = max(1, min(50, int(single_s / max(t1 - t0, 1e-3))))
+    t0 = time.perf_counter()
+    orc.run(p1, w.E, w.F, w.kappa, w.sigma, w.B, dt, n1)
+    t1 = time.perf_counter()
+    single = dict(value=w.zone_groups * n1 / (t1 - t0), sample=f"{n1} full steps on 1 thread, {t1 - t0:.1f} s")
     p = orc.Problem(ndim=w.ndim, n=w.n, G=w.G, coord=w.coord, lo=w.lo, hi=w.hi, bc_lo=w.bc_lo, bc_hi=w.bc_hi,
                     c=w.c, nthreads=ncores)
     # probe on a small strip, then size the sample to ~target_s seconds
@@ -190,7 +212,8 @@ def cpu_baseline(w, dt, target_s=20.0):
     zgu = w.zone_groups * nsteps / (t1 - t0)
     return dict(value=zgu, unit="zone-group updates/s", cores=ncores, kind="oracle",
                 sample=f"{nsteps} full steps of the {w.n[0]}x{w.n[1]} x {w.G}-group workload, "
-                       f"{ncores} OpenMP threads, {t1 - t0:.1f} s")
+                       f"{ncores} OpenMP threads, {t1 - t0:.1f} s",
+                single_thread=single, cpu_model=cpu_model())
 
 
 def matter_timings(reps=10, steps=10):
@@ -358,6 +381,8 @@ def main():
             log("  adjoint:", extra["adjoint"])
         copy_gbs, copy_ms = copy_bandwidth()
         extra["copy_probe_GBps"] = round(copy_gbs, 1)
+        if "headline" in res:
+            res["headline"]["frac_of_copy"] = res["headline"]["achieved"] / copy_gbs
         log(f"  copy probe: {copy_gbs:.0f} GB/s")
     if "headline" not in res:
         print(json.dumps(dict(extra=extra)))
@@ -382,7 +407,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(h["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(h["achieved"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_step_rows<double, 0>", "bytes_per_zone_group": h["bpz"],
-                     "kernel_ms": round(h["ms_kernel"], 5)},
+                     "kernel_ms": round(h["ms_kernel"], 5),
+                     "frac_of_copy_probe": (round(h["frac_of_copy"], 4) if "frac_of_copy" in h else None)},
         "extra": extra,
     }
     if not args.no_cpu:
