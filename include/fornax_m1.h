@@ -72,9 +72,9 @@ enum { FORNAX_FP64 = 0, FORNAX_MIXED = 1 };
  * (eq:recon_system1), each face state reset where that parabola turns between the zone's and
  * its neighbour's centres (monotone there, zero slope at the neighbour's centre), and the face
  * state nearer to an extremum of the parabola through both face states and the average
- * (eq:recon_system2) reset to give that parabola zero slope at its face.  PPM is available on
- * Cartesian grids (fornax_m1_create returns FORNAX_EUNSUPPORTED on spherical ones) and not in
- * fornax_m1_adjoint. */
+ * (eq:recon_system2) reset to give that parabola zero slope at its face; in the volume
+ * coordinate on spherical grids (moments of each zone from the volume element).  PPM is not
+ * available in fornax_m1_adjoint. */
 enum { FORNAX_LIMITER_MINMOD = 0, FORNAX_LIMITER_MC = 1, FORNAX_LIMITER_NONE = 2, FORNAX_LIMITER_PPM = 3 };
 enum { FORNAX_CLOSURE_M1 = 0, FORNAX_CLOSURE_EDDINGTON = 1 };
 

@@ -176,9 +176,9 @@ __device__ __forceinline__ bool realizable(const R q[4], const R ih[3], R c) {
   return (q[0] > R(0)) && (F2 <= cE * cE);
 }
 
-// Linear reconstruction of one zone along d (extended index e), or parabolic on Cartesian
-// grids with the PPM option: face states at its lower and upper faces, with the
-// piecewise-constant fallback when either is not realizable.
+// Linear reconstruction of one zone along d (extended index e), or parabolic with the PPM
+// option: face states at its lower and upper faces, with the piecewise-constant fallback when
+// either is not realizable.
 // LIM: the limiter when known at compile time (a FORNAX_LIMITER_* value), -1 to read it from
 // the arguments.
 template <typename R, bool SPH, int ND, int LIM = -1>
@@ -190,6 +190,31 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
   R s[4];
   R dl = R(-0.5), dh = R(0.5);
   if constexpr (SPH) {
+    if (limiter == FORNAX_LIMITER_PPM) {
+      // parabolic, from the zone's weights in u = (x - x_i)/dx (volume-weighted moments); the
+      // same decisions as the uniform Cartesian closed forms below
+      const R* T = geo.ppm[d] + (size_t)PPM_TAB * e;
+      for (int cp = 0; cp <= ND; ++cp) {
+        const R pm = qm[cp], p0 = q0[cp], pp = qp[cp];
+        R vl = p0, vh = p0;
+        if ((p0 - pm) * (pp - p0) > R(0)) {
+          vl = T[0] * pm + T[1] * p0 + T[2] * pp;
+          vh = T[3] * pm + T[4] * p0 + T[5] * pp;
+          const R c1 = T[6] * pm + T[7] * p0 + T[8] * pp, c2 = T[9] * pm + T[10] * p0 + T[11] * pp;
+          if (fabs(c1) < R(2) * fabs(c2)) {
+            if (c1 * c2 > R(0)) vl = pm + R(0.25) * (p0 - pm);
+            else vh = pp + R(0.25) * (p0 - pp);
+          }
+          const R d1 = T[12] * vl + T[13] * p0 + T[14] * vh, d2 = T[15] * vl + T[16] * p0 + T[17] * vh;
+          if (fabs(d1) < fabs(d2)) {
+            if (d1 * d2 > R(0)) vl = T[18] * p0 + T[19] * vh;
+            else vh = T[20] * vl + T[21] * p0;
+          }
+        }
+        lo[cp] = vl;
+        hi[cp] = vh;
+      }
+    }
     // slopes between volume centroids, face offsets from the centroid
     const R idm = geo.idm[d][e], idp = geo.idp[d][e];
     dl = geo.dlo[d][e];
@@ -251,7 +276,7 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
       }
     }
   }
-  if (SPH || limiter != FORNAX_LIMITER_PPM) {
+  if (limiter != FORNAX_LIMITER_PPM) {
     for (int cp = 0; cp <= ND; ++cp) {
       lo[cp] = q0[cp] + s[cp] * dl;
       hi[cp] = q0[cp] + s[cp] * dh;

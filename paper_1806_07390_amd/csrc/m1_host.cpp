@@ -83,7 +83,6 @@ int validate(const fornax_m1_desc* d) {
   if (d->coord != FORNAX_CARTESIAN && d->coord != FORNAX_SPHERICAL_LOGR) return FORNAX_EINVAL;
   if (d->precision != FORNAX_FP64 && d->precision != FORNAX_MIXED) return FORNAX_EINVAL;
   if (d->limiter < 0 || d->limiter > 3) return FORNAX_EINVAL;
-  if (d->limiter == FORNAX_LIMITER_PPM && d->coord != FORNAX_CARTESIAN) return FORNAX_EUNSUPPORTED;
   if (d->closure < 0 || d->closure > 1) return FORNAX_EINVAL;
   if (d->integrator != FORNAX_EULER && d->integrator != FORNAX_SSPRK2) return FORNAX_EINVAL;
   if (d->wavespeed != FORNAX_WAVESPEED_LIGHT && d->wavespeed != FORNAX_WAVESPEED_M1) return FORNAX_EINVAL;
@@ -122,6 +121,53 @@ int validate(const fornax_m1_desc* d) {
   if (std::max(nz, nf) * (int64_t)d->ngroups * (1 + d->ndim) >= ((int64_t)1 << 31)) return FORNAX_EUNSUPPORTED;
   if (d->precision == FORNAX_MIXED && !(d->f_fp64 >= 0.0)) return FORNAX_EINVAL;
   return FORNAX_OK;
+}
+
+// Inverse of a 3x3 matrix (cofactors), for the parabolic reconstruction's weights.
+static void inv3(const double A[3][3], double B[3][3]) {
+  const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                     A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                     A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      // cofactor of A[j][i]
+      const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+      B[i][j] = (A[r0][c0] * A[r1][c1] - A[r0][c1] * A[r1][c0]) / det;
+    }
+}
+
+// Parabolic reconstruction weights of one zone (spherical grids; the Reconstruction
+// subsection's n = 2 case in the volume coordinate).  u = (x - x_i)/dx is the zone's own
+// coordinate (its faces at -+1/2, the neighbours' centres at -+1), mu1[k], mu2[k] the volume
+// averages of u and u^2 over zones i-1, i, i+1.  Layout as PPM_TAB describes.
+static void ppm_weights(const double mu1[3], const double mu2[3], double* T) {
+  const double ulo = -0.5, uhi = 0.5;
+  const double A1[3][3] = {{1.0, mu1[0], mu2[0]}, {1.0, mu1[1], mu2[1]}, {1.0, mu1[2], mu2[2]}};
+  double B1[3][3];
+  inv3(A1, B1);
+  for (int k = 0; k < 3; ++k) {
+    T[k] = B1[0][k] + ulo * B1[1][k] + ulo * ulo * B1[2][k];
+    T[3 + k] = B1[0][k] + uhi * B1[1][k] + uhi * uhi * B1[2][k];
+    T[6 + k] = B1[1][k];
+    T[9 + k] = B1[2][k];
+  }
+  const double A2[3][3] = {{1.0, ulo, ulo * ulo}, {1.0, mu1[1], mu2[1]}, {1.0, uhi, uhi * uhi}};
+  double B2[3][3];
+  inv3(A2, B2);
+  for (int k = 0; k < 3; ++k) {
+    T[12 + k] = B2[1][k];
+    T[15 + k] = B2[2][k];
+  }
+  // zero slope at the lower face through (average, upper face state): rows p'(ulo) = 0,
+  // <p> = q_i, p(uhi) = v_hi; the lower face state p(ulo) on (q_i, v_hi)
+  const double A3[3][3] = {{0.0, 1.0, 2.0 * ulo}, {1.0, mu1[1], mu2[1]}, {1.0, uhi, uhi * uhi}};
+  double B3[3][3];
+  inv3(A3, B3);
+  for (int k = 1; k < 3; ++k) T[18 + k - 1] = B3[0][k] + ulo * B3[1][k] + ulo * ulo * B3[2][k];
+  const double A4[3][3] = {{1.0, ulo, ulo * ulo}, {1.0, mu1[1], mu2[1]}, {0.0, 1.0, 2.0 * uhi}};
+  double B4[3][3];
+  inv3(A4, B4);
+  for (int k = 0; k < 2; ++k) T[20 + k] = B4[0][k] + uhi * B4[1][k] + uhi * uhi * B4[2][k];
 }
 
 void build_geometry(const fornax_m1_desc& D, HostGeo& H) {
@@ -177,6 +223,29 @@ void build_geometry(const fornax_m1_desc& D, HostGeo& H) {
       H.dhi[d][e] = (a[e + 1] + dx) - X0;
       H.W[d][e] = W[e + 1];
       H.iW[d][e] = 1.0 / W[e + 1];
+    }
+    // parabolic reconstruction on spherical grids: the moments of u = (x - x_e)/dx over zones
+    // e - 1, e, e + 1 with the axis's volume element, by Gauss-Legendre quadrature
+    H.ppm[d].clear();
+    if (sph && D.limiter == FORNAX_LIMITER_PPM) {
+      H.ppm[d].resize((size_t)PPM_TAB * m);
+      for (int e = 0; e < m; ++e) {
+        const double xc = a[e + 1] + 0.5 * dx;
+        double mu1[3], mu2[3];
+        for (int k = 0; k < 3; ++k) {
+          const double lo = a[e + k];   // zone e - 1 + k
+          auto wt = [&](double t) {
+            if (d == 0) return std::exp(3.0 * (lo + t - xc));
+            if (d == 1) return std::fabs(std::sin(lo + t));
+            return 1.0;
+          };
+          const double den = Q.offset_integral(wt, lo, lo + dx);
+          mu1[k] = Q.offset_integral([&](double t) { return (lo + t - xc) / dx * wt(t); }, lo, lo + dx) / den;
+          mu2[k] = Q.offset_integral([&](double t) { const double u = (lo + t - xc) / dx; return u * u * wt(t); },
+                                     lo, lo + dx) / den;
+        }
+        ppm_weights(mu1, mu2, &H.ppm[d][(size_t)PPM_TAB * e]);
+      }
     }
     for (int e = 0; e <= m; ++e) {
       double xf = D.lo[d] + (e - NG) * dx;
@@ -244,12 +313,12 @@ void build_geometry(const fornax_m1_desc& D, HostGeo& H) {
 template <typename R>
 size_t table_bytes(const HostGeo& H, bool sph) {
   size_t n = 0;
-  for (int d = 0; d < 3; ++d) n += 7 * H.idm[d].size() + H.wf[d].size();
+  for (int d = 0; d < 3; ++d) n += 7 * H.idm[d].size() + H.wf[d].size() + H.ppm[d].size();
   if (sph)
     n += 2 * (H.rc.size() + H.rf.size() + H.hr.size() + H.sc.size() + H.sf.size() + H.hs.size()) + H.gam.size();
   size_t b = n * sizeof(R);
   for (int d = 0; d < 3; ++d) b += H.W[d].size() * sizeof(double);
-  return b + 256 * 48;   // 256-byte alignment of each of the (at most 37) tables
+  return b + 256 * 48;   // 256-byte alignment of each of the (at most 40) tables
 }
 
 struct Packer {
@@ -278,6 +347,7 @@ void pack(const HostGeo& H, bool sph, Packer& P, Geo<R>& G) {
     G.iW[d] = P.put<R>(H.iW[d]);
     G.wf[d] = P.put<R>(H.wf[d]);
     G.Wd[d] = P.put<double>(H.W[d]);
+    G.ppm[d] = H.ppm[d].empty() ? nullptr : P.put<R>(H.ppm[d]);
     G.dx[d] = (R)H.dx[d];
     G.idx[d] = (R)(1.0 / H.dx[d]);
   }

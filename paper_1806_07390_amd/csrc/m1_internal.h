@@ -16,6 +16,13 @@ constexpr int BLOCK = 256;       // threads per block of the zone-group kernels
 
 // Geometry tables (device), per axis over the extended zone range e = i + NG,
 // i in [-NG, n + NG); face tables over e in [0, n + 2 NG] (face e is x_{i-1/2}).
+// Weights of the parabolic reconstruction per zone (spherical grids): face states of the
+// parabola with the three averages (lower: 0..2, upper: 3..5, on q_{i-1}, q_i, q_{i+1}), its
+// linear and quadratic coefficients (6..8, 9..11), those of the parabola through the face
+// states and the average (12..14, 15..17, on v_lo, q_i, v_hi), and the reset face states with
+// zero slope at the lower face (18, 19 on q_i, v_hi) and at the upper face (20, 21 on v_lo, q_i).
+constexpr int PPM_TAB = 22;
+
 template <typename R>
 struct Geo {
   const R* idm[3];   // 1 / (X_i - X_{i-1}), X = volume centroid <x^d>
@@ -40,6 +47,9 @@ struct Geo {
   const R* isf;
   const R* ihr;
   const R* ihs;
+  // spherical grids with the parabolic reconstruction: per axis and extended zone, PPM_TAB
+  // weights in the zone's coordinate u = (x - x_i)/dx (see build_geometry), else null
+  const R* ppm[3];
   R dx[3];           // coordinate spacing
   R idx[3];          // 1 / dx
 };
@@ -50,6 +60,7 @@ struct HostGeo {
   std::vector<double> idm[3], idp[3], dlo[3], dhi[3], iW[3], W[3], wf[3], idc[3];
   std::vector<double> rc, rf, hr, sc, sf, hs, gam;
   std::vector<double> irc, irf, isc, isf, ihr, ihs;   // inverses (0 for a zero entry)
+  std::vector<double> ppm[3];
   double dx[3];
 };
 

@@ -1,7 +1,8 @@
-"""GPU parity of the parabolic reconstruction option (FORNAX_LIMITER_PPM, Cartesian grids)
-against the CPU oracle on the same seeded inputs: the step in 1-D, 2-D (the whole-zone kernel
-in double, the tiled kernel in float and for other group counts) and 3-D, both precisions; the
-face-flux entry point; and the calls that refuse the option."""
+"""GPU parity of the parabolic reconstruction option (FORNAX_LIMITER_PPM) against the CPU
+oracle on the same seeded inputs: the step in 1-D, 2-D (the whole-zone kernel in double, the
+tiled kernel in float and for other group counts), 3-D and the spherical grid (volume-coordinate
+weights), both precisions; the face-flux entry point; and the adjoint, which refuses the
+option."""
 import sys
 
 import numpy as np
@@ -37,7 +38,9 @@ def _case(name):
         w.bc_lo = (wl.BC_REFLECT, wl.BC_OUTFLOW, 0)
         w.bc_hi = (wl.BC_OUTFLOW, wl.BC_REFLECT, 0)
         return w
-    return wl.core3d(n=14, G=6, steps=5)
+    if name == "core3d":
+        return wl.core3d(n=14, G=6, steps=5)
+    return wl.sphere3d(nr=14, nth=10, nph=8, G=4, steps=5)
 
 
 # The slab's steep pulse makes the parabolic limiter's branch decisions sensitive to rounding:
@@ -47,7 +50,7 @@ def _case(name):
 TOL_FP64_PPM_SLAB = 1e-10
 
 
-@pytest.mark.parametrize("name", ["slab1d", "blobs2d", "reflect2d", "core3d"])
+@pytest.mark.parametrize("name", ["slab1d", "blobs2d", "reflect2d", "core3d", "sphere3d"])
 def test_parabolic_reconstruction_matches_oracle(m1, name):
     w = _case(name)
     p = problem_of(w, limiter=orc.PPM)
@@ -67,30 +70,28 @@ def test_parabolic_reconstruction_matches_oracle(m1, name):
             assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-12)
 
 
-def test_flux_entry_point_with_parabolic_reconstruction(m1):
-    w = wl.core3d(n=12, G=3, steps=1)
+@pytest.mark.parametrize("grid", ["core3d", "sphere3d"])
+def test_flux_entry_point_with_parabolic_reconstruction(m1, grid):
+    w = wl.core3d(n=12, G=3, steps=1) if grid == "core3d" else wl.sphere3d(nr=12, nth=8, nph=8, G=3, steps=1)
     rng = np.random.default_rng(6)
-    w.E = w.E * (1 + rng.random(w.E.shape))
+    w.E = (w.E if grid == "core3d" else w.B) * (1 + rng.random(w.E.shape))
     w.F = [0.3 * w.E * rng.uniform(-1, 1, w.E.shape) for _ in range(3)]
     p = problem_of(w, limiter=orc.PPM)
     ctx = m1.Context(m1.Config.from_workload(w, limiter=m1.LIMITER_PPM))
     E = to_dev(w.E, torch.float64)
     F = [to_dev(f, torch.float64) for f in w.F]
     k, s, B = (to_dev(x, torch.float64) for x in (w.kappa, w.sigma, w.B))
-    fl = ctx.flux(E, F, k, s, B)
+    inflow = None if w.inflow is None else to_dev(w.inflow, torch.float64)
+    fl = ctx.flux(E, F, k, s, B, inflow=inflow)
     for d in range(3):
-        ref = orc.flux(p, w.E, w.F, w.kappa, w.sigma, w.B, d)
-        ref0 = orc.flux(problem_of(w), w.E, w.F, w.kappa, w.sigma, w.B, d)
+        ref = orc.flux(p, w.E, w.F, w.kappa, w.sigma, w.B, d, inflow=w.inflow)
+        ref0 = orc.flux(problem_of(w), w.E, w.F, w.kappa, w.sigma, w.B, d, inflow=w.inflow)
         scale = np.abs(ref).max()
         assert np.max(np.abs(ref - ref0)) > 1e-6 * scale
         assert np.max(np.abs(to_host(fl[d]) - ref)) <= 1e-13 * scale, d
 
 
-def test_spherical_grid_and_adjoint_refuse_parabolic_reconstruction(m1):
-    w = wl.sphere3d(nr=8, nth=6, nph=4, G=2, steps=1)
-    with pytest.raises(m1.FornaxError) as ei:
-        m1.Context(m1.Config.from_workload(w, limiter=m1.LIMITER_PPM))
-    assert ei.value.code == m1.FORNAX_EUNSUPPORTED
+def test_adjoint_refuses_parabolic_reconstruction(m1):
     w = wl.adjoint2d(n=16, G=2, steps=1)
     ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64, limiter=m1.LIMITER_PPM))
     t = lambda a: to_dev(a, torch.float64)

@@ -64,14 +64,6 @@ def test_argument_checks_need_no_device():
     d.integrator = 5              # no such integrator
     assert lib.fornax_m1_create(ctypes.byref(d), ctypes.byref(h)) == m1.FORNAX_EINVAL
     d.integrator = m1.EULER
-    # the parabolic reconstruction is for Cartesian grids
-    s = m1.Desc()
-    s.ndim, s.n[:], s.ngroups, s.coord = 2, [8, 8, 1], 4, m1.SPHERICAL_LOGR
-    s.lo[:], s.hi[:] = [0.0, 0.5, 0], [1.0, 2.5, 1]
-    s.bc_lo[:], s.bc_hi[:] = [m1.BC_OUTFLOW, m1.BC_REFLECT, 0], [m1.BC_OUTFLOW, m1.BC_REFLECT, 0]
-    s.c = 1.0
-    s.limiter = m1.LIMITER_PPM
-    assert lib.fornax_m1_create(ctypes.byref(s), ctypes.byref(h)) == m1.FORNAX_EUNSUPPORTED
     assert lib.fornax_m1_max_dt(None, 0.4) == m1.FORNAX_EINVAL
     assert lib.fornax_m1_step(None, None, None, None, None, 0.1, None, None) == m1.FORNAX_EINVAL
     assert lib.fornax_m1_copy_probe(None, None, 16, None) == m1.FORNAX_EINVAL
