@@ -584,7 +584,8 @@ __device__ __forceinline__ double source_zone(const StepArgsBase& a, const Geo<R
     zd.fden = up ? cE2 : zd.fden;
     const double u = (sizeof(S) == 8) ? 0x1p-53 : 0x1p-24;
     const double lim = cE * (1.0 + 8.0 * u);
-    zd.nun += (F2 > lim * lim) ? 1 : 0;
+    // |F^| > lim: every state with E < 0 (lim < 0) counts, else compare the squares
+    zd.nun += (lim < 0.0 || F2 > lim * lim) ? 1 : 0;
     zd.nnp += (E1d > 0.0) ? 0 : 1;
   }
   return E1d - Emd;

@@ -272,7 +272,7 @@ def test_whole_zone_kernel_finishes_diagnostics_each_step(m1):
         pos = Eh > 0
         f_ref = float(np.sqrt((F2[pos] / cE[pos] ** 2).max()))
         assert dg["max_f"].item() == pytest.approx(f_ref, rel=1e-13)
-        n_un = int(np.count_nonzero(F2 > (cE * (1 + 8 * u)) ** 2))
+        n_un = int(np.count_nonzero(np.sqrt(F2) > cE * (1 + 8 * u)))
         assert int(dg["n_unrealizable"].item()) == n_un
         assert int(dg["n_nonpositive"].item()) == int(np.count_nonzero(~pos))
 
