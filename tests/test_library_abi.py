@@ -64,6 +64,18 @@ def test_argument_checks_need_no_device():
     d.integrator = 5              # no such integrator
     assert lib.fornax_m1_create(ctypes.byref(d), ctypes.byref(h)) == m1.FORNAX_EINVAL
     d.integrator = m1.EULER
+    # empty grids and groups
+    d.n[0] = 0
+    assert lib.fornax_m1_create(ctypes.byref(d), ctypes.byref(h)) == m1.FORNAX_EINVAL
+    d.n[0] = 8
+    d.ngroups = 0
+    assert lib.fornax_m1_create(ctypes.byref(d), ctypes.byref(h)) == m1.FORNAX_EINVAL
+    # the largest grid the 32-bit zone-group indices allow: (1 + ndim) components of
+    # nzones x G entries must stay below 2^31
+    d.ngroups = 16
+    d.n[:] = [8192, 8192, 1]      # 2^26 zones x 16 groups x 3 components > 2^31
+    assert lib.fornax_m1_create(ctypes.byref(d), ctypes.byref(h)) == m1.FORNAX_EUNSUPPORTED
+    d.n[:] = [8, 8, 1]
     assert lib.fornax_m1_max_dt(None, 0.4) == m1.FORNAX_EINVAL
     assert lib.fornax_m1_step(None, None, None, None, None, 0.1, None, None) == m1.FORNAX_EINVAL
     assert lib.fornax_m1_copy_probe(None, None, 16, None) == m1.FORNAX_EINVAL
