@@ -354,24 +354,27 @@ def main():
         # ---- the reconstruction and wavespeed options on the headline grid -----------------
         if args.only in (None, "extras", "options"):
             wo = wl.blobs2d()
-            inp = device_inputs(wo, torch.float64)
-            opts = {"ppm": dict(limiter=m1.LIMITER_PPM), "m1_speeds": dict(wavespeed=m1.WAVESPEED_M1),
-                    "minmod_tiled": dict(limiter=m1.LIMITER_MINMOD)}
-            for name, kw in opts.items():
-                if name == "minmod_tiled":
+            inps = {m1.FP64: device_inputs(wo, torch.float64), m1.MIXED: device_inputs(wo, torch.float32)}
+            opts = {"fp64_ppm": (m1.FP64, dict(limiter=m1.LIMITER_PPM)),
+                    "fp64_m1_speeds": (m1.FP64, dict(wavespeed=m1.WAVESPEED_M1)),
+                    "fp64_minmod_tiled": (m1.FP64, dict(limiter=m1.LIMITER_MINMOD)),
+                    "mixed": (m1.MIXED, {})}
+            for name, (prec, kw) in opts.items():
+                if name == "fp64_minmod_tiled":
                     os.environ["FORNAX_M1_ROWS"] = "0"
                 try:
-                    ctx = m1.Context(m1.Config.from_workload(wo, precision=m1.FP64, **kw))
+                    ctx = m1.Context(m1.Config.from_workload(wo, precision=prec, **kw))
                 finally:
                     os.environ.pop("FORNAX_M1_ROWS", None)
-                mso, _ = time_steps(ctx, inp, wo.dt, 50, 20, with_diag=True)
-                gbs = wo.zone_groups * algorithmic_bytes(2, 8) / (mso * 1e-3) / 1e9
-                extra[f"blobs2d_512^2x16_fp64_{name}"] = dict(ms_per_step=round(mso, 5),
-                                                              zgu_per_s=wo.zone_groups / (mso * 1e-3),
-                                                              algorithmic_GBps=round(gbs, 1))
-                log(f"  blobs2d fp64 {name}: {mso:.4f} ms/step, {gbs:.0f} GB/s")
+                mso, _ = time_steps(ctx, inps[prec], wo.dt, 50, 20, with_diag=True)
+                el = 8 if prec == m1.FP64 else 4
+                gbs = wo.zone_groups * algorithmic_bytes(2, el) / (mso * 1e-3) / 1e9
+                extra[f"blobs2d_512^2x16_{name}"] = dict(ms_per_step=round(mso, 5),
+                                                         zgu_per_s=wo.zone_groups / (mso * 1e-3),
+                                                         algorithmic_GBps=round(gbs, 1))
+                log(f"  blobs2d {name}: {mso:.4f} ms/step, {gbs:.0f} GB/s")
                 del ctx
-            del inp, wo
+            del inps, wo
             torch.cuda.empty_cache()
         if args.only in (None, "extras", "matter"):
             extra["matter"] = matter_timings()
