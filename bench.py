@@ -289,8 +289,8 @@ def main():
                          "matter, adjoint, extras = all after blobs2d, copy = the copy probe alone)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU path; "
-              "see DESIGN.md for how the step would shard.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the library has no multi-GPU "
+              "path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
