@@ -886,8 +886,9 @@ Tile choose_tile(const fornax_m1_desc& D, int V) {
   }
   // measured on gfx950 (192^3 x 12 and 256 x 64 x 128 x 20): Cartesian FP64 8 x 8 columns of
   // up to 4 groups, 16 planes; Cartesian FP32 pairs of groups per lane, 16 x 16 columns of 2
-  // groups, 8 planes; spherical FP64 16 x 16 columns of 2 groups, 16 planes; spherical FP32
-  // 16 x 8 columns of up to 4 groups, 16 planes
+  // groups, 8 planes; spherical FP64 16 x 8 columns of 2 groups, 16 planes; spherical FP32
+  // 16 x 8 columns of up to 4 groups, 16 planes (in 512-thread blocks: at 256 threads with the
+  // accumulation registers, as in double, it takes 1.8x longer)
   {
     Tile t{};
     const bool sph = D.coord == FORNAX_SPHERICAL_LOGR;
