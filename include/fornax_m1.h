@@ -140,7 +140,9 @@ double fornax_m1_max_dt(const fornax_m1_ctx *ctx, double cfl);
 /* One step U^n -> U^{n+1}: explicit transport (Algorithmic Steps, step 1, v = 0) followed by
  * the implicit interaction update (steps 3 and 4, matter fixed).  `in` and `out` must not
  * alias.  `inflow` is a device array [ngroups][1+ndim] of doubles (E and physical flux of the
- * inflow ghosts) required iff a boundary is FORNAX_BC_INFLOW, else NULL.  `diag` may be NULL.
+ * inflow ghosts) required iff a boundary is FORNAX_BC_INFLOW, else NULL.  `diag` may be NULL;
+ * its totals are summed on the device from per-block partials in a fixed order (deterministic)
+ * in the context's scratch, so calls on one context must not overlap (as for every call).
  * Errors: EINVAL, ECFL (dt <= 0 or dt > max_dt(1)), EDEVICE. */
 int fornax_m1_step(fornax_m1_ctx *ctx, const fornax_m1_state *in, fornax_m1_state *out,
                    const fornax_m1_coeffs *cf, const double *inflow, double dt,
