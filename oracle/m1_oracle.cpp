@@ -356,9 +356,12 @@ static void face_h(const Ctx<T>& C, int d, const int idx[3], int f, double h[3])
   G.h_point(x1, x2, h);
 }
 
+// minmod: 0 unless a and b have the same strict sign, else the one of smaller magnitude (the
+// sign test is written without the product a b, which underflows for tiny differences)
 template <class T>
 static T minmod2(T a, T b) {
-  if (val(a) * val(b) <= 0.0) return T(0.0);
+  const bool same = (val(a) > 0.0 && val(b) > 0.0) || (val(a) < 0.0 && val(b) < 0.0);
+  if (!same) return T(0.0);
   return (std::fabs(val(a)) <= std::fabs(val(b))) ? a : b;
 }
 template <class T>
@@ -548,19 +551,21 @@ static void closure(const Ctx<T>& C, const T q[4], const double h[3], T P[3][3])
     for (int a = 0; a < 3; ++a) P[a][a] = E / T(3.0);
     return;
   }
-  T Fh[3];
-  for (int k = 0; k < 3; ++k) Fh[k] = q[1 + k] / T(h[k] != 0.0 ? h[k] : 1.0);
-  T F2 = Fh[0] * Fh[0] + Fh[1] * Fh[1] + Fh[2] * Fh[2];
+  // the reduced flux f = F^/(cE) is formed before any square, so that states with a tiny E
+  // (whose squares would underflow) get the same tensor as any scaled copy of them
   T cE = T(C.c) * E;
-  T f2 = F2 / (cE * cE);
+  T f[3];
+  for (int k = 0; k < 3; ++k) f[k] = q[1 + k] / T(h[k] != 0.0 ? h[k] : 1.0) / cE;
+  const T fsq = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
+  T f2 = fsq;
   if (val(f2) > 1.0) f2 = T(1.0);
   T chi = (T(3.0) + T(4.0) * f2) / (T(5.0) + T(2.0) * sqrt(T(4.0) - T(3.0) * f2));
   T iso = (T(1.0) - chi) / T(2.0);
   T ani = (T(3.0) * chi - T(1.0)) / T(2.0);
   for (int a = 0; a < 3; ++a) P[a][a] = E * iso;
-  if (val(F2) > 0.0) {
-    T Fm = sqrt(F2);
-    T nn[3] = {Fh[0] / Fm, Fh[1] / Fm, Fh[2] / Fm};
+  if (val(fsq) > 0.0) {
+    T fm = sqrt(fsq);
+    T nn[3] = {f[0] / fm, f[1] / fm, f[2] / fm};
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) P[a][b] = P[a][b] + E * ani * nn[a] * nn[b];
   }
@@ -862,15 +867,22 @@ static void full_step(const OrcDesc* D, const Geom& geo, const T* E, const T* co
         double e = val(Eo[zg]);
         esum += e;
         dsum += e - Em_all[zg];
-        double F2 = 0.0;
-        for (int kk = 0; kk < D->ndim; ++kk) {
-          double fk = val(Fo[kk][zg]) / h[kk];
-          F2 += fk * fk;
+        // f = |F^|/(cE) from the reduced components (no squares of tiny values)
+        if (e > 0.0) {
+          double f2 = 0.0;
+          for (int kk = 0; kk < D->ndim; ++kk) {
+            double fk = val(Fo[kk][zg]) / h[kk] / (C.c * e);
+            f2 += fk * fk;
+          }
+          double fm = std::sqrt(f2);
+          maxf = std::max(maxf, fm);
+          if (fm > 1.0 + 8.0 * u) nun++;
+        } else {
+          nnp++;
+          bool fz = true;
+          for (int kk = 0; kk < D->ndim; ++kk) fz = fz && val(Fo[kk][zg]) == 0.0;
+          if (e < 0.0 || !fz) nun++;
         }
-        double Fm = std::sqrt(F2);
-        if (e > 0.0) maxf = std::max(maxf, Fm / (C.c * e));
-        if (!(e > 0.0)) nnp++;
-        if (Fm > C.c * e * (1.0 + 8.0 * u)) nun++;
       }
       etot += V * esum;
       if (dEm) dEm[z] = -dsum;
