@@ -163,16 +163,15 @@ int fornax_m1_source(fornax_m1_ctx *ctx, fornax_m1_state *inout, const fornax_m1
 
 /* Adjoint of one step (vector-Jacobian product), for gradients of a loss of U^N:
  *   lam_n = (dU^{n+1}/dU^n)^T lam_np1,   dkappa_accum += (dU^{n+1}/dkappa)^T lam_np1.
- * Un is the state the step started from.  Unp1 is NULL or the state fornax_m1_step produced
- * from Un with the same coefficients, inflow and dt (the opacity derivative of the
- * interaction update needs U^{n+1}); when NULL the step is recomputed into scratch owned by
- * the context (allocated by the first such call).  A Unp1 that is not that step's result
- * gives a wrong dkappa, with no error.  lam_np1, lam_n are states of the context's type
- * (lam_n must not alias lam_np1, Un or Unp1); dkappa_accum is a zone-group array of the
- * context's type, accumulated into.  Non-smooth points (minmod, realizability fallback,
+ * Un is the state the step started from.  Unp1 (required) is the state fornax_m1_step produced
+ * from Un with the same coefficients, inflow and dt (the opacity derivative of the interaction
+ * update needs U^{n+1}); a caller without it runs fornax_m1_step first.  A Unp1 that is not
+ * that step's result gives a wrong dkappa, with no error.  The call allocates nothing.
+ * lam_np1, lam_n are states of the context's type (lam_n must not alias lam_np1, Un or Unp1);
+ * dkappa_accum is a zone-group array of the context's type, accumulated into.  Non-smooth points (minmod, realizability fallback,
  * epsilon kink, f clamp) take the derivative of the branch the forward step takes.  Same
  * layout, error and stream rules as fornax_m1_step; FORNAX_EUNSUPPORTED for spherical grids
- * and for 3-D. */
+ * and for 3-D; EINVAL when Unp1 is NULL. */
 int fornax_m1_adjoint(fornax_m1_ctx *ctx, const fornax_m1_state *Un, const fornax_m1_state *Unp1,
                       const fornax_m1_coeffs *cf, const double *inflow, double dt,
                       const fornax_m1_state *lam_np1, fornax_m1_state *lam_n, void *dkappa_accum,

@@ -7,13 +7,15 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfornax_m1.so")
-SOURCES = ["m1_host.cpp", "m1_kernels.hip", "m1_step.hip", "m1_step_rows.hip", "m1_adjoint.hip", "m1_matter.hip"]
+SOURCES = ["m1_host.cpp", "m1_kernels.hip", "m1_step.hip", "m1_step_rows.hip", "m1_step_3d.hip", "m1_adjoint.hip",
+           "m1_matter.hip"]
 ARCH = "gfx950"
 
 
@@ -24,20 +26,27 @@ def hipcc():
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
+    cmds, objs = [], []
     for s in SOURCES:
         src = os.path.join(CSRC, s)
         obj = os.path.join(bdir, s + ".o")
-        lang = ["-x", "hip"]
-        cmd = [hipcc()] + lang + flags + ["-c", src, "-o", obj]
+        cmds.append([hipcc(), "-x", "hip"] + flags + ["-c", src, "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    # the sources compile independently: in parallel, within the host's cores
+    workers = max(1, min(len(cmds), (os.cpu_count() or 1), 8))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for f in [ex.submit(compile_one, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -465,17 +465,8 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
                             double dt, const fornax_m1_state* lam_np1, fornax_m1_state* lam_n, void* dkappa,
                             hipStream_t st) {
   const fornax_m1_desc& D = ctx->desc;
-  // U^{n+1} of the step: the caller's, else by the forward kernel into the context's scratch
-  fornax_m1_state u1;
-  if (Unp1) {
-    u1 = *Unp1;
-  } else {
-    const size_t nzg = (size_t)D.n[0] * D.n[1] * D.n[2] * D.ngroups;
-    u1.E = ctx->adj_u1;
-    for (int k = 0; k < 3; ++k) u1.F[k] = (k < D.ndim) ? (char*)ctx->adj_u1 + (1 + k) * nzg * sizeof(S) : nullptr;
-    const int rc = fm1_launch_step(ctx, Un, &u1, cf, inflow, dt, nullptr, st);
-    if (rc != FORNAX_OK) return rc;
-  }
+  // U^{n+1} of the step, from the caller (required)
+  const fornax_m1_state u1 = *Unp1;
   AdjArgs<S> a;
   for (int d = 0; d < 3; ++d) {
     a.n[d] = D.n[d];
@@ -505,9 +496,6 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
   a.B = (const S*)cf->B;
   a.dEm = nullptr;
   a.p_energy = a.p_maxf2 = nullptr;
-  a.p_ticket = nullptr;
-  a.o_energy = a.o_maxf = nullptr;
-  a.o_nun = a.o_nnp = nullptr;
   a.p_nun = a.p_nnp = nullptr;
   a.lam[0] = (const S*)lam_np1->E;
   a.lamo[0] = (S*)lam_n->E;
@@ -522,16 +510,9 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
     a.gbuf[d] = ctx->adj_gbuf[d];
     a.gplane[d] = ctx->adj_gplane[d];
   }
-  // tiling: FORNAX_M1_ADJ_TILE="TXB,TM" overrides the default (256 threads, planes from the
-  // CU count)
-  int txb = 0, tm = 0;
-  if (const char* env = std::getenv("FORNAX_M1_ADJ_TILE")) {
-    int x = 0, y = 0;
-    if (std::sscanf(env, "%d,%d", &x, &y) == 2 && x >= 4 && y >= 1) {
-      txb = x;
-      tm = y;
-    }
-  }
+  // tiling: the override read at create, else 256 threads and planes from the CU count
+  const int txb = ctx->adj_txb;
+  int tm = ctx->adj_tm;
   if (tm <= 0) tm = choose_adj_planes(D, txb, ctx->cus);
   AdjTile tl = make_adj_tile(D, tm, txb);
   if (tl.TXB * D.ngroups > 512) return FORNAX_EUNSUPPORTED;
@@ -574,15 +555,6 @@ int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const forn
   if (D.integrator != FORNAX_EULER) return FORNAX_EUNSUPPORTED;   // the adjoint is of the Euler push
   if (D.wavespeed != FORNAX_WAVESPEED_LIGHT || D.limiter == FORNAX_LIMITER_PPM) return FORNAX_EUNSUPPORTED;
   if (!ctx->adj_gbuf[0]) return FORNAX_ENOMEM;
-  if (!Unp1 && !ctx->adj_u1) {
-    // first adjoint call on this context: scratch for U^{n+1}
-    const size_t es = D.precision == FORNAX_FP64 ? sizeof(double) : sizeof(float);
-    const size_t bytes = (size_t)(1 + D.ndim) * D.n[0] * D.n[1] * D.n[2] * D.ngroups * es;
-    if (hipMalloc(&ctx->adj_u1, bytes) != hipSuccess) {
-      ctx->adj_u1 = nullptr;
-      return FORNAX_ENOMEM;
-    }
-  }
   if (D.precision == FORNAX_FP64)
     return launch_adjoint_t<double, double>(ctx, ctx->geo_d, Un, Unp1, cf, inflow, dt, lam_np1, lam_n, dkappa,
                                             stream);

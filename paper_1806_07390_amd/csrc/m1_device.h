@@ -344,14 +344,19 @@ __device__ __forceinline__ void closure_row(const R q[4], const R ih[3], int d, 
   if constexpr (sizeof(R) == 8) {
     // double: from E and F directly, with S = cE s = sqrt(4 (cE)^2 - 3 |F|^2),
     //   P = (S - cE)/(3c) delta + 3 F F / (c (2 cE + S)),
-    // one square root and one reciprocal (the squares stay far inside the double range)
+    // one square root and one reciprocal.  The tensor is homogeneous of degree one in
+    // (E, F): a state with cE below 2^-450, whose squares could underflow, is evaluated
+    // scaled by 2^600 (exact) and the row scaled back (only in waves that hold one).
     R Fh[3] = {R(0), R(0), R(0)};
-    R F2 = R(0);
-    for (int k = 0; k < ND; ++k) {
-      Fh[k] = SPH ? q[1 + k] * ih[k] : q[1 + k];
-      F2 += Fh[k] * Fh[k];
+    for (int k = 0; k < ND; ++k) Fh[k] = SPH ? q[1 + k] * ih[k] : q[1 + k];
+    R cE = c * E;
+    const bool tiny = __builtin_amdgcn_ballot_w64(cE < R(0x1p-450)) != 0;
+    if (tiny && cE < R(0x1p-450)) {
+      cE *= R(0x1p600);
+      for (int k = 0; k < ND; ++k) Fh[k] *= R(0x1p600);
     }
-    const R cE = c * E;
+    R F2 = R(0);
+    for (int k = 0; k < ND; ++k) F2 += Fh[k] * Fh[k];
     const R A = cE * cE;
     if (F2 > A) {
       // |f| > 1: the direction of F with |f| = 1
@@ -363,6 +368,8 @@ __device__ __forceinline__ void closure_row(const R q[4], const R ih[3], int d, 
     const R iso = (S - cE) * rcp_(R(3) * c);   // c is uniform: hoisted
     const R af = R(3) * rcp_(c * (R(2) * cE + S)) * Fh[d];
     for (int k = 0; k < ND; ++k) P[k] = af * Fh[k] + (k == d ? iso : R(0));
+    if (tiny && c * E < R(0x1p-450))
+      for (int k = 0; k < ND; ++k) P[k] *= R(0x1p-600);
     return;
   }
   R f[3] = {R(0), R(0), R(0)};
@@ -571,15 +578,22 @@ __device__ __forceinline__ double source_zone(const StepArgsBase& a, const Geo<R
       hd[0] = hd[1] = (double)geo.hr[i + NG];
       hd[2] = hd[0] * (double)geo.hs[j + NG];
     }
+    // |E| below 2^-400: the squares below could underflow; f and the counts are those of the
+    // state scaled by 2^600 (exact), in waves that hold such a zone only
+    double Es = E1d, sc = 1.0;
+    if (__builtin_amdgcn_ballot_w64(fabs(E1d) < 0x1p-400) && fabs(E1d) < 0x1p-400) {
+      sc = 0x1p600;
+      Es = E1d * sc;
+    }
     double F2 = 0.0;
     for (int cc = 0; cc < ND; ++cc) {
-      const double fk = SPH ? F1s[cc] * rcp_(hd[cc]) : F1s[cc];
+      const double fk = (SPH ? F1s[cc] * rcp_(hd[cc]) : F1s[cc]) * sc;
       F2 += fk * fk;
     }
-    const double cE = c * E1d;
+    const double cE = c * Es;
     // f^2 = F2 / (cE)^2 compared by cross-multiplication (one division per thread at the end)
     const double cE2 = cE * cE;
-    const bool up = E1d > 0.0 && F2 * zd.fden > zd.fnum * cE2;
+    const bool up = Es > 0.0 && F2 * zd.fden > zd.fnum * cE2;
     zd.fnum = up ? F2 : zd.fnum;
     zd.fden = up ? cE2 : zd.fden;
     const double u = (sizeof(S) == 8) ? 0x1p-53 : 0x1p-24;

@@ -480,6 +480,14 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
     if (env[0] == '0' && env[1] == 0) ctx->rows = fm1::RowsTile{};
     else if (std::sscanf(env, "%d,%d", &nwx, &tm) == 2) ctx->rows = make_rows_tile(*desc, nwx, tm);
   }
+  // the 3-D Cartesian kernel where the grid qualifies (FORNAX_M1_C3="0" disables it, "NR,TM"
+  // picks its tiling)
+  ctx->c3 = choose_c3_tile(*desc, cus);
+  if (const char* env = std::getenv("FORNAX_M1_C3")) {
+    int nr = 0, tm = 0;
+    if (env[0] == '0' && env[1] == 0) ctx->c3 = fm1::C3Tile{};
+    else if (std::sscanf(env, "%d,%d", &nr, &tm) == 2) ctx->c3 = make_c3_tile(*desc, nr, tm);
+  }
   if (ctx->tile.nblocks <= 0) {
     (void)hipFree(ctx->geo_mem);
     delete ctx;
@@ -490,10 +498,10 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   int zpb = BLOCK / desc->ngroups;
   int64_t nz = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
   ctx->nblocks_step = (int)((nz + zpb - 1) / zpb);
-  size_t nb = (size_t)std::max(std::max(ctx->nblocks_step, ctx->rows.nblocks),
+  size_t nb = (size_t)std::max(std::max(std::max(ctx->nblocks_step, ctx->rows.nblocks), ctx->c3.nblocks),
                                std::max(ctx->tile_v1.nblocks, ctx->tile.nblocks));
   // dE_matter partials when a tile splits the groups of a zone over several blocks
-  const size_t ngbm = (size_t)std::max(ctx->tile.ngb, ctx->tile_v1.ngb);
+  const size_t ngbm = (size_t)std::max(std::max(ctx->tile.ngb, ctx->tile_v1.ngb), ctx->c3.ngb);
   const size_t dzp_bytes = ngbm > 1 ? ngbm * (size_t)nz * sizeof(double) : 0;
   const size_t red_bytes = (nb * (2 * sizeof(double) + 2 * sizeof(int)) + 256 + 1023) & ~(size_t)255;
   void* red = nullptr;
@@ -506,14 +514,6 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   ctx->p_maxf2 = ctx->p_energy + nb;
   ctx->p_nun = (int*)(ctx->p_maxf2 + nb);
   ctx->p_nnp = ctx->p_nun + nb;
-  ctx->ticket = (unsigned*)((((uintptr_t)(ctx->p_nnp + nb)) + 255) & ~(uintptr_t)255);
-  ctx->last_fused_fin = false;
-  if (hipMemset(ctx->ticket, 0, sizeof(unsigned)) != hipSuccess) {
-    (void)hipFree(red);
-    (void)hipFree(ctx->geo_mem);
-    delete ctx;
-    return FORNAX_EDEVICE;
-  }
   ctx->dzp = dzp_bytes ? (double*)((char*)red + red_bytes) : nullptr;
   // SSP-RK2: storage of the first stage's state
   ctx->stage_mem = nullptr;
@@ -526,8 +526,17 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
       return FORNAX_ENOMEM;
     }
   }
-  // adjoint ghost buffers (the adjoint supports 1-D and 2-D Cartesian grids)
-  ctx->adj_u1 = nullptr;
+  // adjoint tiling (FORNAX_M1_ADJ_TILE="TXB,TM" overrides the default, read here once) and
+  // ghost buffers (the adjoint supports 1-D and 2-D Cartesian grids)
+  ctx->adj_txb = 0;
+  ctx->adj_tm = 0;
+  if (const char* env = std::getenv("FORNAX_M1_ADJ_TILE")) {
+    int x = 0, y = 0;
+    if (std::sscanf(env, "%d,%d", &x, &y) == 2 && x >= 4 && y >= 1) {
+      ctx->adj_txb = x;
+      ctx->adj_tm = y;
+    }
+  }
   for (int d = 0; d < 3; ++d) {
     ctx->adj_gbuf[d] = nullptr;
     ctx->adj_gplane[d] = (int)(nz / desc->n[d]);
@@ -555,7 +564,6 @@ int fornax_m1_destroy(fornax_m1_ctx* ctx) {
   (void)hipFree(ctx->p_energy);
   for (int d = 0; d < 3; ++d)
     if (ctx->adj_gbuf[d]) (void)hipFree(ctx->adj_gbuf[d]);
-  if (ctx->adj_u1) (void)hipFree(ctx->adj_u1);
   if (ctx->stage_mem) (void)hipFree(ctx->stage_mem);
   if (ctx->mat_tab) (void)hipFree(ctx->mat_tab);
   delete ctx;
@@ -633,14 +641,12 @@ int fornax_m1_source(fornax_m1_ctx* ctx, fornax_m1_state* inout, const fornax_m1
 int fornax_m1_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const fornax_m1_state* Unp1,
                       const fornax_m1_coeffs* cf, const double* inflow, double dt, const fornax_m1_state* lam_np1,
                       fornax_m1_state* lam_n, void* dkappa_accum, void* stream) {
-  if (!ctx || !dkappa_accum) return FORNAX_EINVAL;
+  if (!ctx || !dkappa_accum || !Unp1) return FORNAX_EINVAL;
   int rc;
   if ((rc = check_state(ctx, Un)) || (rc = check_state(ctx, lam_np1)) || (rc = check_state(ctx, lam_n)) ||
-      (rc = check_coeffs(ctx, cf)))
+      (rc = check_coeffs(ctx, cf)) || (rc = check_state(ctx, Unp1)))
     return rc;
-  if (Unp1 && (rc = check_state(ctx, Unp1))) return rc;
-  if (overlaps(ctx, lam_n, lam_np1) || overlaps(ctx, lam_n, Un)) return FORNAX_EINVAL;
-  if (Unp1 && overlaps(ctx, lam_n, Unp1)) return FORNAX_EINVAL;
+  if (overlaps(ctx, lam_n, lam_np1) || overlaps(ctx, lam_n, Un) || overlaps(ctx, lam_n, Unp1)) return FORNAX_EINVAL;
   if (needs_inflow(ctx->desc) != (inflow != nullptr)) return FORNAX_EINVAL;
   if (!(dt > 0.0) || dt > ctx->max_dt1 * (1.0 + 1e-12)) return FORNAX_ECFL;
   return fm1_launch_adjoint(ctx, Un, Unp1, cf, inflow, dt, lam_np1, lam_n, dkappa_accum, (hipStream_t)stream);

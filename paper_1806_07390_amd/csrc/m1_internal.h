@@ -125,18 +125,11 @@ struct StepArgs : StepArgsBase {
   int src;
   const S* Ea;
   const S* Fa[3];
-  // per-block partial reductions (null: no diagnostics)
+  // per-block partial reductions (null: no diagnostics), summed by a second launch
   double* p_energy;
   double* p_maxf2;
   int* p_nun;
   int* p_nnp;
-  // kernels that finish the reduction themselves: the last block to arrive (ticket counter,
-  // zero between launches) sums the partials into the caller's outputs (each nullable)
-  unsigned* p_ticket;
-  double* o_energy;
-  double* o_maxf;
-  int* o_nun;
-  int* o_nnp;
 };
 
 }  // namespace fm1
@@ -155,6 +148,14 @@ struct Tile {
   int xq, xr;          // nblocks = 8 xq + xr (XCD renumbering)
   int nthreads;        // 64 NW (1-D/2-D) or TXB * TYB * GB (3-D)
   size_t lds;          // dynamic LDS bytes per block (with the dE_matter buffer)
+};
+// Tiling of the 3-D Cartesian step kernel for group counts that are multiples of 4
+// (m1_step_3d.hip): blocks of NR waves, one y row of 16 x columns by 4 groups each (rows 0 and
+// NR - 1 and columns 0 and 15 are halo), TM planes along z, ngb = G / 4 blocks per tile.
+struct C3Tile {
+  int NR, TM;
+  int ntx, nty, ntz, ngb, nblocks;
+  int xq, xr;
 };
 // Tiling of the 2-D, 16-group step kernel that streams whole zones through LDS
 // (m1_step_rows.hip): NWX wave rows of 16 zone columns (4 NWX waves), TM planes per block.
@@ -179,6 +180,7 @@ struct fornax_m1_ctx {
   fm1::Tile tile;              // tiling of the fused step kernel
   fm1::Tile tile_v1;           // one group per lane (arrays not aligned to pairs of groups)
   fm1::RowsTile rows;          // the whole-zone LDS kernel when nblocks > 0 (2-D, 16 groups)
+  fm1::C3Tile c3;              // the 3-D Cartesian kernel when nblocks > 0
   int cus;                     // compute units of the device (0 if unknown)
   fm1::Tile last_tile[1];      // the tile of the last step launch (for inspection)
   // reduction scratch (one partial per block of the step kernel)
@@ -187,8 +189,6 @@ struct fornax_m1_ctx {
   double* p_maxf2;
   int* p_nun;
   int* p_nnp;
-  unsigned* ticket;            // arrival counter of the kernels that finish the reduction
-  bool last_fused_fin;         // the last step launch finished the diagnostics itself
   // dE_matter partials of the group blocks of a tile, [ngb][zones] (null when every tile
   // holds all groups of a zone)
   double* dzp;
@@ -197,11 +197,22 @@ struct fornax_m1_ctx {
   // adjoint: ghost-zone adjoint buffers per direction, [side][layer][plane][G][1+ndim+1]
   double* adj_gbuf[3];
   int adj_gplane[3];
-  void* adj_u1;               // U^{n+1} scratch of the adjoint (allocated by its first call)
+  int adj_txb, adj_tm;        // adjoint tiling override (0: the default choice)
   // matter model (fornax_m1_set_matter_model): device tables nu_edge [G+1], nu_c [G], kg [G]
   double* mat_tab;
   double mat_a, mat_tol;
   int mat_maxn;
+};
+
+// Scratch memory of one step launch: per-block diagnostics partials, the dE_matter partials of
+// split group blocks, the first Runge-Kutta stage.
+struct StepScratch {
+  double* p_energy;
+  double* p_maxf2;
+  int* p_nun;
+  int* p_nnp;
+  double* dzp;
+  void* stage;
 };
 
 // kernel launchers (m1_kernels.hip)

@@ -18,6 +18,7 @@
 
 #include <hip/hip_runtime.h>
 
+
 #include "m1_device.h"
 #include "m1_internal.h"
 #include "m1_step.h"
@@ -196,15 +197,12 @@ void fill_args(const fornax_m1_ctx* ctx, StepArgs<S>& a, const fornax_m1_coeffs*
   a.p_maxf2 = nullptr;
   a.p_nun = nullptr;
   a.p_nnp = nullptr;
-  a.p_ticket = nullptr;
-  a.o_energy = a.o_maxf = nullptr;
-  a.o_nun = a.o_nnp = nullptr;
 }
 
 template <typename S, typename R>
 int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* in, fornax_m1_state* out,
                   const fornax_m1_coeffs* cf, const double* inflow, double dt, const fornax_m1_diag* diag,
-                  hipStream_t st) {
+                  const StepScratch& sc, hipStream_t st) {
   StepArgs<S> a;
   fill_args<S>(ctx, a, cf, inflow, dt);
   a.E = (const S*)in->E;
@@ -215,30 +213,24 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
   }
   bool want = diag && (diag->energy_total || diag->max_f || diag->n_unrealizable || diag->n_nonpositive);
   if (diag) a.dEm = diag->dE_matter;
-  a.dzp = ctx->dzp;
+  a.dzp = sc.dzp;
   if (want) {
-    a.p_energy = ctx->p_energy;
-    a.p_maxf2 = ctx->p_maxf2;
-    a.p_nun = ctx->p_nun;
-    a.p_nnp = ctx->p_nnp;
-    a.p_ticket = ctx->ticket;
-    a.o_energy = diag->energy_total;
-    a.o_maxf = diag->max_f;
-    a.o_nun = diag->n_unrealizable;
-    a.o_nnp = diag->n_nonpositive;
+    a.p_energy = sc.p_energy;
+    a.p_maxf2 = sc.p_maxf2;
+    a.p_nun = sc.p_nun;
+    a.p_nnp = sc.p_nnp;
   }
   if (ctx->desc.integrator == FORNAX_SSPRK2) {
     // stage 1: U* = U^n + dt L(U^n) into the context's stage storage, no interaction update
     StepArgs<S> a1 = a;
     const size_t nzg = (size_t)a.nzones * a.G;
-    S* st_E = (S*)ctx->stage_mem;
+    S* st_E = (S*)sc.stage;
     a1.Eo = st_E;
     for (int k = 0; k < 3; ++k) a1.Fo[k] = (k < ctx->desc.ndim) ? st_E + (1 + k) * nzg : nullptr;
     a1.src = 0;
     a1.dEm = nullptr;
     a1.p_energy = a1.p_maxf2 = nullptr;
     a1.p_nun = a1.p_nnp = nullptr;
-    a1.p_ticket = nullptr;
     const int rc1 = launch_tiled<S, R>(ctx, geo, a1, st);
     if (rc1 != FORNAX_OK) return rc1;
     // stage 2 reads U* and averages with U^n: U^- = (U^n + U* + dt L(U*)) / 2
@@ -255,9 +247,9 @@ int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* 
                        ctx->last_tile->ngb, a.nzones, a.dEm);
     if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
   }
-  if (want && !ctx->last_fused_fin) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, st, ctx->p_energy, ctx->p_maxf2, ctx->p_nun,
-                       ctx->p_nnp, nb,
+  if (want) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, st, sc.p_energy, sc.p_maxf2, sc.p_nun,
+                       sc.p_nnp, nb,
                        diag->energy_total, diag->max_f, diag->n_unrealizable, diag->n_nonpositive);
     if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
   }
@@ -348,10 +340,12 @@ int launch_source_t(fornax_m1_ctx* ctx, fornax_m1_state* io, const fornax_m1_coe
 
 int fm1_launch_step(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out, const fornax_m1_coeffs* cf,
                     const double* inflow, double dt, const fornax_m1_diag* diag, hipStream_t stream) {
+  const StepScratch sc{ctx->p_energy, ctx->p_maxf2, ctx->p_nun, ctx->p_nnp, ctx->dzp, ctx->stage_mem};
   if (ctx->desc.precision == FORNAX_FP64)
-    return launch_step_t<double, double>(ctx, ctx->geo_d, in, out, cf, inflow, dt, diag, stream);
-  return launch_step_t<float, float>(ctx, ctx->geo_f, in, out, cf, inflow, dt, diag, stream);
+    return launch_step_t<double, double>(ctx, ctx->geo_d, in, out, cf, inflow, dt, diag, sc, stream);
+  return launch_step_t<float, float>(ctx, ctx->geo_f, in, out, cf, inflow, dt, diag, sc, stream);
 }
+
 
 int fm1_launch_transport(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
                          const fornax_m1_coeffs* cf, const double* inflow, double dt, hipStream_t stream) {

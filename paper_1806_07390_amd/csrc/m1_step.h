@@ -30,4 +30,12 @@ RowsTile choose_rows_tile(const fornax_m1_desc& D, int cus);
 template <typename S>
 int launch_rows(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipStream_t st);
 
+// The 3-D Cartesian kernel with x neighbours by lane shifts and y neighbours through LDS
+// (m1_step_3d.hip): a tile with nblocks = 0 when the grid does not qualify (3-D Cartesian,
+// groups a multiple of 4, no inflow or axis boundary; NR 8 or 12 in double, 8 or 16 in float).
+C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM);
+C3Tile choose_c3_tile(const fornax_m1_desc& D, int cus);
+template <typename S>
+int launch_c3(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipStream_t st);
+
 }  // namespace fm1

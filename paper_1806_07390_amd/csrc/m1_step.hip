@@ -1020,8 +1020,11 @@ static bool aligned_to(const void* p, size_t n) { return p == nullptr || ((uintp
 template <typename S, typename R>
 int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, hipStream_t st) {
   // the whole-zone kernel does the Euler push; Runge-Kutta stages run on the tiled kernel
-  if constexpr (std::is_same<S, R>::value)
+  if constexpr (std::is_same<S, R>::value) {
     if (ctx->rows.nblocks > 0 && a.src && !a.Ea) return launch_rows<S>(ctx, geo, a, st);
+    // the 3-D Cartesian kernel takes every stage of its grids
+    if (ctx->c3.nblocks > 0) return launch_c3<S>(ctx, geo, a, st);
+  }
   const bool sph = ctx->desc.coord == FORNAX_SPHERICAL_LOGR;
   const int D = ctx->desc.ndim;
   // pairs of groups per lane need arrays aligned to two elements
@@ -1034,7 +1037,6 @@ int launch_tiled(fornax_m1_ctx* ctx, const Geo<R>& geo, const StepArgs<S>& a, hi
   if (tl->nblocks <= 0) return FORNAX_EUNSUPPORTED;
   if (a.dEm && tl->ngb > 1 && !a.dzp) return FORNAX_EUNSUPPORTED;
   *ctx->last_tile = *tl;
-  ctx->last_fused_fin = false;
   return sph ? launch_coord<S, R, true>(geo, a, *tl, D, st) : launch_coord<S, R, false>(geo, a, *tl, D, st);
 }
 

@@ -1,0 +1,474 @@
+// m1_step_3d.hip -- the fused M1 step for 3-D Cartesian grids whose group count is a multiple
+// of 4 (the 192^3 x 12 workload's layout).
+//
+// Same method and arithmetic as k_step_tiled (eq:finite_vol with the reconstruction of
+// eq:recon_constraints, the M1 closure, the HLL flux eq:hll with the correction eq:epsilon, the
+// backward-Euler interaction update eq:be_update); what differs is how neighbours meet:
+//   * a wave is one y row of 16 x columns by 4 consecutive groups, lane = 16 group + column:
+//     the x neighbours of a lane are the lanes next to it in its 16-lane row, reached by DPP
+//     row shifts (no LDS, no barrier).  Columns 0 and 15 are halo: their zones are
+//     reconstructed (their face states close the tile) but not updated, and their own outer
+//     neighbours are loaded by those two lanes;
+//   * a block is NI waves stacked in y and one group quad.  The lower NI - 1 rows are updated;
+//     the top row only computes the flux at its lower face (its zones are the next tile's first
+//     row).  Each row computes the flux at its lower y face from its own reconstruction and
+//     that of the row below, both from the plane's states in LDS; the two rows below the block
+//     and the row above it are loaded into LDS by all waves together.  The fluxes pass up
+//     through LDS;
+//   * the block marches along z over TM planes with a register window: every z face is
+//     computed once, from values each lane loads for its own column one plane ahead;
+//   * x faces are computed once (by the lane above the face), y faces once per block (the
+//     lower row's upper state is recomputed by the row above instead of exchanged), z faces
+//     once; only the halo columns and the top row repeat work of the neighbouring tiles.
+// Two block barriers per plane (after the states, after the y fluxes), which wait for LDS
+// only: the loads of the next plane stay in flight.
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "m1_device.h"
+#include "m1_internal.h"
+#include "m1_step.h"
+
+namespace fm1 {
+
+constexpr int C3_TX = 16;   // x columns of a wave row (14 updated)
+
+// the value of the lane one column lower (row_shr:1) / higher (row_shl:1) in the same 16-lane
+// row; the lanes at the row's ends receive 0 (they never use it)
+template <typename R>
+__device__ __forceinline__ R col_prev(R v) {
+  return __builtin_amdgcn_update_dpp(R(0), v, 0x111, 0xf, 0xf, false);
+}
+template <typename R>
+__device__ __forceinline__ R col_next(R v) {
+  return __builtin_amdgcn_update_dpp(R(0), v, 0x101, 0xf, 0xf, false);
+}
+
+// The ghost rules of one axis, taken from the launch's table at each use (measured: faster
+// than copies of the table held in scalar registers for the whole kernel, which crowd out the
+// other uniform values).
+struct C3Axis {
+  const StepArgsBase* a;
+  int d;
+};
+template <int D>
+__device__ __forceinline__ C3Axis c3_axis(const StepArgsBase& a) { return C3Axis{&a, D}; }
+// Ghost rule of index e (clamped into -2 .. n + 1 first): source zone and flags (bit 0 flips
+// the flux component along the axis), selected without indexing the table by a per-lane value.
+__device__ __forceinline__ void c3_src(const C3Axis& ax, int e, int& src, int& fl) {
+  const StepArgsBase& a = *ax.a;
+  const int D = ax.d;
+  const int n = a.n[D];
+  e = e < -2 ? -2 : (e > n + 1 ? n + 1 : e);
+  src = e;
+  fl = 0;
+  if (e < 0 || e >= n) {
+    const int k = e < 0 ? e + 2 : e - n + 2;
+    src = k == 0 ? a.gsrc[D][0] : k == 1 ? a.gsrc[D][1] : k == 2 ? a.gsrc[D][2] : a.gsrc[D][3];
+    fl = k == 0 ? a.gfl[D][0] : k == 1 ? a.gfl[D][1] : k == 2 ? a.gfl[D][2] : a.gfl[D][3];
+  }
+}
+
+// the sign rules: F_c flipped where bit c - 1 of the mask is set
+template <typename R>
+__device__ __forceinline__ void c3_fix(const R raw[4], int mask, R q[4]) {
+  q[0] = raw[0];
+  for (int c = 1; c < 4; ++c) q[c] = ((mask >> (c - 1)) & 1) ? -raw[c] : raw[c];
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void c3_load(const StepArgs<S>& a, int off, R q[4]) {
+  q[0] = R(a.E[off]);
+  q[1] = R(a.F[0][off]);
+  q[2] = R(a.F[1][off]);
+  q[3] = R(a.F[2][off]);
+}
+
+// LDS barrier: waits for the wave's LDS operations only (the global loads of the next plane
+// stay in flight); the empty asm statements keep the compiler from moving memory accesses
+// across it
+__device__ __forceinline__ void c3_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Rows of the plane held in LDS: the block's NI rows in slots 2 .. NI + 1, the two rows below
+// in slots 0, 1 and the row above in slot NI + 2.  The outer rows are loaded by all waves
+// together, one (slot, component) item per wave and load: the 4 state components of slots 0
+// and NI + 2, and the 4 state components, kappa and sigma of slot 1.
+constexpr int C3_NITEM = 14;
+
+// NI waves per block, W waves per SIMD (register budget 512 / W)
+template <typename S, int NI, int W, int LIM>
+__global__ void __launch_bounds__(64 * NI) __attribute__((amdgpu_waves_per_eu(W)))
+k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
+  using R = S;
+  constexpr int TX = C3_TX;
+  constexpr int NS = NI + 3;                              // LDS row slots
+  constexpr int NHI = (C3_NITEM + NI - 1) / NI;           // outer-row items per wave
+  __shared__ R QS[6][NS][64];    // E, F_x, F_y, F_z, kappa, sigma of the plane's rows
+  __shared__ R FY[4][NI][64];    // y flux at the lower face of each of the block's rows
+  __shared__ double red_e[NI], red_m[NI];
+  __shared__ int red_u[NI], red_p[NI];
+
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave = row (uniform)
+  const int x = lane & (TX - 1), gq = lane >> 4;
+  const int sw = w + 2;                                   // the wave's slot
+  const bool top = w == NI - 1;
+
+  // tile of the block (XCD-aware renumbering; the group quads of a tile adjacent)
+  const int b = blockIdx.x;
+  const int xcd = b & 7, sl = b >> 3;
+  const int L = xcd * tl.xq + min(xcd, tl.xr) + sl;
+  const int gb = L % tl.ngb;
+  int rest = L / tl.ngb;
+  const int tx = rest % tl.ntx;
+  rest /= tl.ntx;
+  const int ty = rest % tl.nty;
+  const int tz = rest / tl.nty;
+
+  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2], G = a.G;
+  const int g = gb * 4 + gq;
+  const int xz = tx * (TX - 2) + x - 1;          // zone of the lane's column
+  const int y0 = ty * (NI - 1);                  // zone of slot 2 (the top row is the next tile's first)
+  const int yz = y0 + w;                         // zone of the wave's row
+  const int mbeg = tz * tl.TM, mend = min(mbeg + tl.TM, n2);
+  const bool upd = !top && yz < n1 && x >= 1 && x <= TX - 2 && xz < n0;
+  const int PL = n0 * n1 * G;                    // elements of a z plane
+
+  const C3Axis ax0 = c3_axis<0>(a), ax1 = c3_axis<1>(a), ax2 = c3_axis<2>(a);
+  // sources and sign rules of the lane's column and of its outer x neighbour (columns 0, 15)
+  int xs, xf, ys, yf;
+  c3_src(ax0, xz, xs, xf);
+  c3_src(ax1, yz, ys, yf);
+  const bool xedge = x == 0 || x == TX - 1;
+  int xef;
+  const int cb = (ys * n0 + xs) * G + g;
+  int xeo;
+  c3_src(ax0, x == 0 ? xz - 1 : xz + 1, xeo, xef);
+  const int ceb = (ys * n0 + xeo) * G + g;
+  const int lm = (xf & 1) | ((yf & 1) << 1);
+  const int lme = (xef & 1) | ((yf & 1) << 1);
+  // B of the lane's own zone (clamped into the domain so every lane may load it)
+  const int cbb = ((min(max(yz, 0), n1 - 1) * n0 + min(max(xz, 0), n0 - 1)) * G + g);
+  // the wave's outer-row items: LDS slot and component (uniform), element offset within a
+  // plane and flip of its row and column (per lane), the array (uniform)
+  int hslot[NHI], hcomp[NHI], hoff[NHI], hmask[NHI];
+  const S* hsrc[NHI];
+  for (int k = 0; k < NHI; ++k) {
+    int it = w + k * NI;
+    if (it >= C3_NITEM) it = -1;
+    int slot = 0, comp = 0;
+    if (it >= 0) {
+      if (it < 4) { slot = 0; comp = it; }
+      else if (it < 10) { slot = 1; comp = it - 4; }
+      else { slot = NI + 2; comp = it - 10; }
+    }
+    int hys, hyf;
+    c3_src(ax1, y0 - 2 + slot, hys, hyf);
+    hslot[k] = it >= 0 ? slot : -1;
+    hcomp[k] = comp;
+    hoff[k] = (hys * n0 + xs) * G + g;
+    hmask[k] = comp >= 1 && comp <= 3 ? ((((xf & 1) | ((hyf & 1) << 1)) >> (comp - 1)) & 1) : 0;
+    hsrc[k] = comp == 0 ? a.E : comp <= 3 ? a.F[comp - 1] : comp == 4 ? a.kap : a.sig;
+  }
+  // plane m (-2 .. n2 + 1, clamped): element offset and flip mask
+  auto plane = [&](int m, int& pm) -> int {
+    int zs, zf;
+    c3_src(ax2, m, zs, zf);
+    pm = (zf & 1) << 2;
+    return zs * PL;
+  };
+
+  const bool want_diag = a.p_energy != nullptr;
+  ZoneDiag zd;
+  const double cdt = a.c * a.dt;
+  const R dtR = R(a.dt);
+  const R idx0 = geo.idx[0], idx1 = geo.idx[1], idx2 = geo.idx[2];
+  const R dx0 = geo.dx[0], dx1 = geo.dx[1], dx2 = geo.dx[2];
+  const R hone[3] = {R(1), R(1), R(1)};
+  const double Vz = want_diag ? geo.Wd[0][NG] * geo.Wd[1][NG] * geo.Wd[2][NG] : 0.0;
+
+  // ---- register window along z: q(m), q(m + 1); the upper z face state of zone m and the
+  // flux at m - 1/2; kappa and sigma of plane m ----
+  R q0[4], q1[4], hiM[4], fPrev[4];
+  R k0, s0;
+  // values in flight: q(m + 2), the outer x neighbour (columns 0, 15) of plane m and the
+  // wave's outer-row items of plane m, loaded at the top of the plane before; kappa, sigma of
+  // m + 1 and B of m, loaded at the end of the plane before
+  R Pr[4], Po[4], Ph[NHI], Pk, Ps, PB;
+  int Ppm, Popm;
+  auto load_items = [&](int off) {
+    for (int k = 0; k < NHI; ++k)
+      if (hslot[k] >= 0) Ph[k] = R(hsrc[k][off + hoff[k]]);
+  };
+  {
+    int pm;
+    R raw[4], qa[4], qb[4];
+    const int o0 = plane(mbeg, pm);
+    c3_load<S, R>(a, o0 + cb, raw);
+    c3_fix(raw, lm ^ pm, q0);
+    k0 = R(a.kap[o0 + cb]);
+    s0 = R(a.sig[o0 + cb]);
+    const int o1 = plane(mbeg + 1, pm);
+    c3_load<S, R>(a, o1 + cb, raw);
+    c3_fix(raw, lm ^ pm, q1);
+    int pa, pb;
+    const int oa = plane(mbeg - 2, pa), ob = plane(mbeg - 1, pb);
+    c3_load<S, R>(a, oa + cb, raw);
+    c3_fix(raw, lm ^ pa, qa);
+    c3_load<S, R>(a, ob + cb, raw);
+    c3_fix(raw, lm ^ pb, qb);
+    const R ksb = R(a.kap[ob + cb]) + R(a.sig[ob + cb]);
+    // face mbeg - 1/2 from zones mbeg - 1 (upper state) and mbeg (lower state)
+    for (int c = 0; c < 4; ++c) hiM[c] = fPrev[c] = R(0);
+    if (!top) {
+      R lo[4], hiP[4];
+      reconstruct<R, false, 3, LIM>(a, geo, 2, 0, qa, qb, q0, hone, hone, true, true, lo, hiP);
+      reconstruct<R, false, 3, LIM>(a, geo, 2, 0, qb, q0, q1, hone, hone, true, true, lo, hiM);
+      hll<R, false, 3, (LIM < 0)>(a, 2, hiP, lo, hone, hone, epsilon_of(ksb, k0 + s0, dx2, dx2), fPrev);
+    }
+    // in flight into the first plane
+    Pk = R(a.kap[o1 + cb]);
+    Ps = R(a.sig[o1 + cb]);
+    PB = R(a.B[mbeg * PL + cbb]);
+    const int o2 = plane(mbeg + 2, Ppm);
+    c3_load<S, R>(a, o2 + cb, Pr);
+    plane(mbeg, Popm);
+    c3_load<S, R>(a, o0 + ceb, Po);
+    load_items(o0);
+  }
+
+  for (int m = mbeg; m < mend; ++m) {
+    // ---- consume the values loaded one plane ago; the plane's rows to LDS ----
+    R q2[4], qo[4];
+    c3_fix(Pr, lm ^ Ppm, q2);            // plane m + 2
+    c3_fix(Po, lme ^ Popm, qo);          // outer x neighbour, plane m
+    for (int c = 0; c < 4; ++c) QS[c][sw][lane] = q0[c];
+    QS[4][sw][lane] = k0;
+    QS[5][sw][lane] = s0;
+    for (int k = 0; k < NHI; ++k)
+      if (hslot[k] >= 0) {
+        const int zflip = (hcomp[k] == 3) ? (Popm >> 2) & 1 : 0;
+        QS[hcomp[k]][hslot[k]][lane] = (hmask[k] ^ zflip) ? -Ph[k] : Ph[k];
+      }
+    // ---- loads for the next plane: q(m + 3), outer neighbours of m + 1, kappa, sigma of m + 2
+    // and B of m + 1 (indices clamped into the ghost range; the last planes' are not used) ----
+    {
+      const int o3 = plane(min(m + 3, n2 + 1), Ppm);
+      c3_load<S, R>(a, o3 + cb, Pr);
+      const int oe = plane(min(m + 1, n2 + 1), Popm);
+      if (xedge) c3_load<S, R>(a, oe + ceb, Po);
+      load_items(oe);
+    }
+    c3_barrier();
+    const R ks0 = k0 + s0;
+    // ---- y: the flux at the lower y face of the row, from the reconstructions of the row
+    // below (upper state) and of the row (lower state) ----
+    R fy[4];
+    {
+      R qa[4], qb[4], qc[4], lo[4], hiP[4], hiY[4], loY[4];
+      for (int c = 0; c < 4; ++c) {
+        qa[c] = QS[c][sw - 2][lane];
+        qb[c] = QS[c][sw - 1][lane];
+      }
+      const R ksb = QS[4][sw - 1][lane] + QS[5][sw - 1][lane];
+      reconstruct<R, false, 3, LIM>(a, geo, 1, 0, qa, qb, q0, hone, hone, true, true, lo, hiP);
+      for (int c = 0; c < 4; ++c) qc[c] = QS[c][sw + 1][lane];
+      reconstruct<R, false, 3, LIM>(a, geo, 1, 0, qb, q0, qc, hone, hone, true, true, loY, hiY);
+      hll<R, false, 3, (LIM < 0)>(a, 1, hiP, loY, hone, hone, epsilon_of(ksb, ks0, dx1, dx1), fy);
+      for (int c = 0; c < 4; ++c) FY[c][w][lane] = fy[c];
+    }
+    R acc[4] = {R(0), R(0), R(0), R(0)};
+    if (!top) {
+      // ---- x: reconstruction, the flux at the lower x face of the column (the upper state
+      // of the column below by a lane shift), the x part of the divergence ----
+      {
+        R qm[4], qp[4], loX[4], hiX[4];
+        for (int c = 0; c < 4; ++c) {
+          const R pv = col_prev(q0[c]), nv = col_next(q0[c]);
+          qm[c] = x == 0 ? qo[c] : pv;
+          qp[c] = x == TX - 1 ? qo[c] : nv;
+        }
+        reconstruct<R, false, 3, LIM>(a, geo, 0, 0, qm, q0, qp, hone, hone, true, true, loX, hiX);
+        R qL[4], fx[4];
+        for (int c = 0; c < 4; ++c) qL[c] = col_prev(hiX[c]);
+        const R ksL = col_prev(ks0);
+        hll<R, false, 3, (LIM < 0)>(a, 0, qL, loX, hone, hone, epsilon_of(ksL, ks0, dx0, dx0), fx);
+        for (int c = 0; c < 4; ++c) acc[c] = (col_next(fx[c]) - fx[c]) * idx0;
+      }
+      // ---- z: reconstruction of zone m + 1, the flux at m + 1/2; the window's face values
+      // move on at once ----
+      {
+        R nLo[4], nHi[4], fNext[4];
+        reconstruct<R, false, 3, LIM>(a, geo, 2, 0, q0, q1, q2, hone, hone, true, true, nLo, nHi);
+        hll<R, false, 3, (LIM < 0)>(a, 2, hiM, nLo, hone, hone, epsilon_of(ks0, Pk + Ps, dx2, dx2), fNext);
+        for (int c = 0; c < 4; ++c) {
+          acc[c] += (fNext[c] - fPrev[c]) * idx2;
+          fPrev[c] = fNext[c];
+          hiM[c] = nHi[c];
+        }
+      }
+    }
+    c3_barrier();
+    // ---- update of the row's zones (every lane of the inner rows computes; the lanes that
+    // hold a zone of the tile store) ----
+    if (!top) {
+      for (int c = 0; c < 4; ++c) acc[c] += (FY[c][top ? w : w + 1][lane] - fy[c]) * idx1;
+      const int zg = upd ? (m * n1 + yz) * n0 * G + xz * G + g : 0;
+      R Um[4];
+      for (int c = 0; c < 4; ++c) Um[c] = q0[c] - dtR * acc[c];
+      if (a.Ea) {
+        // second Runge-Kutta stage: U^- = (U^n + U* + dt L(U*)) / 2
+        Um[0] = R(0.5) * (R(a.Ea[zg]) + Um[0]);
+        for (int c = 0; c < 3; ++c) Um[1 + c] = R(0.5) * (R(a.Fa[c][zg]) + Um[1 + c]);
+      }
+      S Eo, F1[3];
+      double dz = 0.0;
+      if (a.src) {
+        const double ck = cdt * (double)k0;
+        dz = source_zone<S, R, false, 3>(a, geo, xz, yz, Um, ck, cdt * ((double)k0 + (double)s0), ck * (double)PB,
+                                         want_diag && upd, Vz, zd, Eo, F1);
+      } else {
+        Eo = S(Um[0]);
+        for (int c = 0; c < 3; ++c) F1[c] = S(Um[1 + c]);
+      }
+      if (upd) {
+        a.Eo[zg] = Eo;
+        for (int c = 0; c < 3; ++c) a.Fo[c][zg] = F1[c];
+      }
+      if (a.dEm) {
+        // the zone's sum over the block's 4 groups (lanes 16 apart)
+        dz = upd ? dz : 0.0;
+        dz += __shfl_xor(dz, 16);
+        dz += __shfl_xor(dz, 32);
+        if (upd && gq == 0) {
+          const int64_t zone = ((int64_t)m * n1 + yz) * n0 + xz;
+          if (tl.ngb == 1) a.dEm[zone] = -dz;
+          else a.dzp[(int64_t)gb * a.nzones + zone] = dz;
+        }
+      }
+    }
+    // ---- advance the window ----
+    for (int c = 0; c < 4; ++c) {
+      q0[c] = q1[c];
+      q1[c] = q2[c];
+    }
+    k0 = Pk;
+    s0 = Ps;
+    {
+      int pk;
+      const int ok = plane(min(m + 2, n2 + 1), pk);
+      Pk = R(a.kap[ok + cb]);
+      Ps = R(a.sig[ok + cb]);
+      PB = R(a.B[min(m + 1, n2 - 1) * PL + cbb]);
+    }
+  }
+
+  if (!want_diag) return;
+  // ---- block partials of the diagnostics ----
+  double e = zd.energy, mf = zd.maxf2();
+  int un = zd.nun, pnp = zd.nnp;
+  for (int off = 32; off > 0; off >>= 1) {
+    e += __shfl_xor(e, off);
+    mf = fmax(mf, __shfl_xor(mf, off));
+    un += __shfl_xor(un, off);
+    pnp += __shfl_xor(pnp, off);
+  }
+  if (lane == 0) {
+    red_e[w] = e;
+    red_m[w] = mf;
+    red_u[w] = un;
+    red_p[w] = pnp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double se = 0.0, sm = 0.0;
+    int su = 0, sp = 0;
+    for (int k = 0; k < NI; ++k) {
+      se += red_e[k];
+      sm = fmax(sm, red_m[k]);
+      su += red_u[k];
+      sp += red_p[k];
+    }
+    a.p_energy[blockIdx.x] = se;
+    a.p_maxf2[blockIdx.x] = sm;
+    a.p_nun[blockIdx.x] = su;
+    a.p_nnp[blockIdx.x] = sp;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
+  C3Tile tl{};
+  tl.nblocks = 0;
+  if (D.ndim != 3 || D.coord != FORNAX_CARTESIAN || D.ngroups % 4 != 0) return tl;
+  // the instantiated block heights: 6, 8 or 12 rows in double, 4, 8 or 16 in float
+  const bool dbl = D.precision == FORNAX_FP64;
+  if (!(NR == 8 || NR == (dbl ? 6 : 4) || NR == (dbl ? 12 : 16))) return tl;
+  if (TM < 1) return tl;
+  for (int d = 0; d < 3; ++d)
+    if (D.bc_lo[d] == FORNAX_BC_INFLOW || D.bc_hi[d] == FORNAX_BC_INFLOW || D.bc_lo[d] == FORNAX_BC_AXIS ||
+        D.bc_hi[d] == FORNAX_BC_AXIS)
+      return tl;
+  tl.NR = NR;
+  tl.TM = TM;
+  tl.ntx = (D.n[0] + C3_TX - 3) / (C3_TX - 2);
+  tl.nty = (D.n[1] + NR - 2) / (NR - 1);
+  tl.ntz = (D.n[2] + TM - 1) / TM;
+  tl.ngb = D.ngroups / 4;
+  const int64_t nb = (int64_t)tl.ntx * tl.nty * tl.ntz * tl.ngb;
+  if (nb > (int64_t)1 << 30) return C3Tile{};
+  tl.nblocks = (int)nb;
+  tl.xq = tl.nblocks / 8;
+  tl.xr = tl.nblocks % 8;
+  return tl;
+}
+
+C3Tile choose_c3_tile(const fornax_m1_desc& D, int cus) {
+  (void)cus;
+  const int NR = (D.precision == FORNAX_FP64) ? 6 : 8;
+  return make_c3_tile(D, NR, 32);
+}
+
+template <typename S>
+int launch_c3(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipStream_t st) {
+  const C3Tile& tl = ctx->c3;
+  if (tl.nblocks <= 0) return FORNAX_EUNSUPPORTED;
+  if (a.dEm && tl.ngb > 1 && !a.dzp) return FORNAX_EUNSUPPORTED;
+  const bool mm = a.limiter == FORNAX_LIMITER_MINMOD;
+  dim3 grid(tl.nblocks), block(64 * tl.NR);
+#define FM1_C3(NRV, WV)                                                                                  \
+  do {                                                                                                   \
+    if (mm)                                                                                              \
+      hipLaunchKernelGGL((k_step_3d<S, NRV, WV, FORNAX_LIMITER_MINMOD>), grid, block, 0, st, a, geo, tl); \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_step_3d<S, NRV, WV, -1>), grid, block, 0, st, a, geo, tl);                   \
+  } while (0)
+  // waves per SIMD: the register budget of each precision (double: 168 or 256 VGPRs; float: 128)
+  if constexpr (sizeof(S) == 8) {
+    if (tl.NR == 6) FM1_C3(6, 3);
+    else if (tl.NR == 8) FM1_C3(8, 2);
+    else FM1_C3(12, 3);
+  } else {
+    if (tl.NR == 4) FM1_C3(4, 4);
+    else if (tl.NR == 8) FM1_C3(8, 4);
+    else FM1_C3(16, 4);
+  }
+#undef FM1_C3
+  Tile lt{};
+  lt.nblocks = tl.nblocks;
+  lt.ngb = tl.ngb;
+  *ctx->last_tile = lt;
+  return hipGetLastError() == hipSuccess ? FORNAX_OK : FORNAX_EDEVICE;
+}
+
+template int launch_c3<double>(fornax_m1_ctx*, const Geo<double>&, const StepArgs<double>&, hipStream_t);
+template int launch_c3<float>(fornax_m1_ctx*, const Geo<float>&, const StepArgs<float>&, hipStream_t);
+
+}  // namespace fm1

@@ -167,7 +167,6 @@ k_step_rows(StepArgs<S> a, Geo<S> geo, RowsTile tl) {
   __shared__ double DZ[2][4][RTX];                     // dE_matter partials of the waves, per plane parity
   __shared__ double we[NW], wm[NW];
   __shared__ int wu[NW], wp[NW];
-  __shared__ int last_block;
 
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);   // wave index (uniform)
@@ -541,64 +540,10 @@ k_step_rows(StepArgs<S> a, Geo<S> geo, RowsTile tl) {
       su += wu[k];
       sp += wp[k];
     }
-    if (!a.p_ticket) {
-      a.p_energy[blockIdx.x] = se;
-      a.p_maxf2[blockIdx.x] = sm;
-      a.p_nun[blockIdx.x] = su;
-      a.p_nnp[blockIdx.x] = sp;
-    } else {
-      // device-scope stores, complete (vmcnt(0)) before this block takes its ticket
-      __hip_atomic_store(a.p_energy + blockIdx.x, se, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(a.p_maxf2 + blockIdx.x, sm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(a.p_nun + blockIdx.x, su, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(a.p_nnp + blockIdx.x, sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_s_waitcnt(0x0f70);
-      last_block = __hip_atomic_fetch_add(a.p_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                   gridDim.x - 1u;
-    }
-  }
-  if (!a.p_ticket) return;
-  // ---- the last block to take a ticket sums every block's partials, in block order (device-
-  // scope loads: each partial was stored at device scope before its block's ticket) ----
-  __syncthreads();
-  if (!last_block) return;
-  const int nb = (int)gridDim.x;
-  e = 0.0;
-  mf = 0.0;
-  un = pnp = 0;
-  for (int k = t; k < nb; k += (int)blockDim.x) {
-    e += __hip_atomic_load(a.p_energy + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    mf = fmax(mf, __hip_atomic_load(a.p_maxf2 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    un += __hip_atomic_load(a.p_nun + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    pnp += __hip_atomic_load(a.p_nnp + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    e += __shfl_xor(e, off);
-    mf = fmax(mf, __shfl_xor(mf, off));
-    un += __shfl_xor(un, off);
-    pnp += __shfl_xor(pnp, off);
-  }
-  if (lane == 0) {
-    we[w] = e;
-    wm[w] = mf;
-    wu[w] = un;
-    wp[w] = pnp;
-  }
-  __syncthreads();
-  if (t == 0) {
-    double se = 0.0, sm = 0.0;
-    int su = 0, sp = 0;
-    for (int k = 0; k < NW; ++k) {
-      se += we[k];
-      sm = fmax(sm, wm[k]);
-      su += wu[k];
-      sp += wp[k];
-    }
-    if (a.o_energy) *a.o_energy = se;
-    if (a.o_maxf) *a.o_maxf = sqrt(sm);
-    if (a.o_nun) *a.o_nun = su;
-    if (a.o_nnp) *a.o_nnp = sp;
-    __hip_atomic_store(a.p_ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // for the next launch
+    a.p_energy[blockIdx.x] = se;
+    a.p_maxf2[blockIdx.x] = sm;
+    a.p_nun[blockIdx.x] = su;
+    a.p_nnp[blockIdx.x] = sp;
   }
 }
 
@@ -669,13 +614,12 @@ int launch_rows(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hip
     hipLaunchKernelGGL((k_step_rows<S, FORNAX_LIMITER_MINMOD>), grid, block, 0, st, a, geo, tl);
   else
     hipLaunchKernelGGL((k_step_rows<S, -1>), grid, block, 0, st, a, geo, tl);
-  // the reduction bookkeeping of the step (one diagnostics partial per block; every block
-  // holds all groups of its zones)
+  // the reduction bookkeeping of the step (one diagnostics partial per block, summed by the
+  // second launch; every block holds all groups of its zones)
   Tile lt{};
   lt.nblocks = tl.nblocks;
   lt.ngb = 1;
   *ctx->last_tile = lt;
-  ctx->last_fused_fin = true;   // the kernel's last block writes the diagnostics
   return hipGetLastError() == hipSuccess ? FORNAX_OK : FORNAX_EDEVICE;
 }
 

@@ -250,9 +250,9 @@ class Context:
             dg.max_f = _ptr(diag.get("max_f"))
             dg.n_unrealizable = _ptr(diag.get("n_unrealizable"))
             dg.n_nonpositive = _ptr(diag.get("n_nonpositive"))
-        _check(_lib.fornax_m1_step(self._h, ctypes.byref(sin), ctypes.byref(sout), ctypes.byref(cf),
-                                   self._inflow(inflow), dt, ctypes.byref(dg) if dg is not None else None,
-                                   _stream(stream)), "fornax_m1_step")
+        fn, name = _lib.fornax_m1_step, "fornax_m1_step"
+        _check(fn(self._h, ctypes.byref(sin), ctypes.byref(sout), ctypes.byref(cf), self._inflow(inflow), dt,
+                  ctypes.byref(dg) if dg is not None else None, _stream(stream)), name)
         return out
 
     def new_diag(self):
@@ -354,9 +354,12 @@ class Context:
     def adjoint(self, E, F, kappa, sigma, B, dt, lamE, lamF, out=None, dkappa=None, inflow=None, stream=None,
                 U1=None):
         """lam_n = J^T lam_{n+1}; dkappa += (dU^{n+1}/dkappa)^T lam_{n+1}. Returns (lamE_n, [lamF_n], dkappa).
-        U1: optional (E, [F]) of the step's result from (E, F) (recomputed when None)."""
+        U1: optional (E, [F]) of the step's result from (E, F); when None the step is run first
+        (fornax_m1_step into a new state), since the library requires it."""
+        if U1 is None:
+            U1 = self.step(E, F, kappa, sigma, B, dt, inflow=inflow, stream=stream)
         su = self._state(E, F, "Un")
-        s1 = None if U1 is None else self._state(U1[0], U1[1], "Unp1")
+        s1 = self._state(U1[0], U1[1], "Unp1")
         sl = self._state(lamE, lamF, "lam_np1")
         if out is None:
             out = self.empty_state()
@@ -365,7 +368,7 @@ class Context:
             dkappa = torch.zeros(self.shape, dtype=self.dtype, device=self.device)
         self._check_arr(dkappa, "dkappa")
         cf = self._coeffs(kappa, sigma, B)
-        _check(_lib.fornax_m1_adjoint(self._h, ctypes.byref(su), ctypes.byref(s1) if s1 is not None else None,
+        _check(_lib.fornax_m1_adjoint(self._h, ctypes.byref(su), ctypes.byref(s1),
                                       ctypes.byref(cf), self._inflow(inflow), dt,
                                       ctypes.byref(sl), ctypes.byref(so), ctypes.c_void_p(dkappa.data_ptr()),
                                       _stream(stream)), "fornax_m1_adjoint")
@@ -430,25 +433,32 @@ class Context:
     def adjointer(self, U, kappa, sigma, B, dt, lam_in, lam_out, dkappa, inflow=None, stream=None, U1=None):
         """Pre-bound fornax_m1_adjoint call (arguments built once): returns a function that
         computes lam_out = J^T lam_in and accumulates into dkappa for the state U (U1: the
-        step's result from U, when the caller holds it)."""
+        step's result from U, when the caller holds it; when None each call first runs the step
+        into a state held by the returned function)."""
+        pre = None
+        if U1 is None:
+            U1 = self.empty_state()
+            pre = self.bound_step((U[0], U[1]), U1, kappa, sigma, B, dt, inflow=inflow, stream=stream)
         su = self._state(U[0], U[1], "Un")
-        s1 = None if U1 is None else self._state(U1[0], U1[1], "Unp1")
+        s1 = self._state(U1[0], U1[1], "Unp1")
         sl = self._state(lam_in[0], lam_in[1], "lam_np1")
         so = self._state(lam_out[0], lam_out[1], "lam_n")
         self._check_arr(dkappa, "dkappa")
         cf = self._coeffs(kappa, sigma, B)
         infl = self._inflow(inflow)
         st = _stream(stream)
-        args = (self._h, ctypes.byref(su), ctypes.byref(s1) if s1 is not None else None, ctypes.byref(cf), infl, dt,
+        args = (self._h, ctypes.byref(su), ctypes.byref(s1), ctypes.byref(cf), infl, dt,
                 ctypes.byref(sl), ctypes.byref(so), ctypes.c_void_p(dkappa.data_ptr()), st)
         fn = _lib.fornax_m1_adjoint
 
         def call():
+            if pre is not None:
+                pre()
             rc = fn(*args)
             if rc != FORNAX_OK:
                 raise FornaxError(rc, "fornax_m1_adjoint")
 
-        call._keep = (su, s1, sl, so, cf)
+        call._keep = (su, s1, sl, so, cf, U1)
         return call
 
     def run(self, E, F, kappa, sigma, B, dt, nsteps, inflow=None, diag=None):

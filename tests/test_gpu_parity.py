@@ -10,7 +10,8 @@ import torch
 
 from oracle import m1_oracle as orc
 from paper_1806_07390_amd import workloads as wl
-from tests.parity_util import (TOL_FP64, TOL_MIXED_RUN, TOL_MIXED_STEP, gpu_run, problem_of, rel_l1, to_dev,
+from tests.parity_util import (TOL_FP64, TOL_MIXED_RUN, TOL_MIXED_STEP, check_pointwise, gpu_run, problem_of, rel_l1,
+                               to_dev,
                                to_host)
 
 pytestmark = pytest.mark.gpu
@@ -40,7 +41,10 @@ def run_pair(m1, w, precision, nsteps, **opts):
     cfg = m1.Config.from_workload(w, precision=precision, **opts)
     ctx = m1.Context(cfg)
     Eg, Fg = gpu_run(ctx, w, dt, nsteps)
-    return rel_l1(Eg, Fg, E, F, w.c)
+    e = rel_l1(Eg, Fg, E, F, w.c)
+    say(f"  rel-L1 E {e[0]:.2e} F {e[1]:.2e}; element-wise E {e.pE:.2e} F {e.pF:.2e}")
+    check_pointwise(e, precision == m1.FP64, w.name)
+    return e
 
 
 # ------------------------------------------------------------------------------------------
@@ -154,7 +158,9 @@ def test_tile_shapes(m1, case):
             finally:
                 del os.environ["FORNAX_M1_TILE"]
             Eg, Fg, dgg = gpu_run(ctx, w, dt, w.steps, diag=True)
-            eE, eF = rel_l1(Eg, Fg, E, F, w.c)
+            e = rel_l1(Eg, Fg, E, F, w.c)
+            eE, eF = e
+            check_pointwise(e, prec == m1.FP64)
             say("   ", eE, eF)
             assert eE <= tol and eF <= tol, (case, tile, prec)
             # the group sum of dE_matter spans the blocks of a tile's group subsets.  It is a
@@ -218,7 +224,9 @@ def test_whole_zone_kernel(m1, bc, lim):
         Et, Ft, dgt = gpu_run(ctxs[0], w, dt, w.steps, diag=True)
         for ctx in ctxs[1:]:
             Eg, Fg, dgg = gpu_run(ctx, w, dt, w.steps, diag=True)
-            eE, eF = rel_l1(Eg, Fg, E, F, w.c)
+            e = rel_l1(Eg, Fg, E, F, w.c)
+            eE, eF = e
+            check_pointwise(e, prec == m1.FP64)
             say("   ", eE, eF)
             assert eE <= tol and eF <= tol
             tE, tF = rel_l1(Eg, Fg, Et, Ft, w.c)
@@ -234,13 +242,12 @@ def test_whole_zone_kernel(m1, bc, lim):
                 assert np.allclose(dgg["dE_matter"], dEm, rtol=1e-10, atol=1e-12 * np.abs(E).max())
 
 
-def test_whole_zone_kernel_finishes_diagnostics_each_step(m1):
-    """The whole-zone kernel's last block to finish sums every block's diagnostics partials (no
-    separate reduction launch).  Each of several steps on one context reports the totals of its
-    own output -- the volume sum of E, the largest f = |F|/(cE), the realizability and
-    positivity counts -- also when the state changes by a large factor between calls and when
-    steps without diagnostics come in between, so neither a partial of an earlier launch nor
-    the block arrival counter carries over."""
+def test_whole_zone_kernel_diagnostics_each_step(m1):
+    """The whole-zone kernel's block partials of the diagnostics, summed by the second launch:
+    each of several steps on one context reports the totals of its own output -- the volume
+    sum of E, the largest f = |F|/(cE), the realizability and positivity counts -- also when
+    the state changes by a large factor between calls and when steps without diagnostics come
+    in between, so no partial of an earlier launch carries over."""
     import os
     w = _rows_case("periodic")
     p = problem_of(w)
@@ -298,7 +305,9 @@ def test_ssprk2_matches_oracle(m1, case):
     for prec, tol in ((m1.FP64, TOL_FP64), (m1.MIXED, TOL_MIXED_RUN)):
         ctx = m1.Context(m1.Config.from_workload(w, precision=prec, integrator=m1.SSPRK2))
         Eg, Fg, dgg = gpu_run(ctx, w, dt, w.steps, diag=True)
-        eE, eF = rel_l1(Eg, Fg, E, F, w.c)
+        e = rel_l1(Eg, Fg, E, F, w.c)
+        eE, eF = e
+        check_pointwise(e, prec == m1.FP64)
         say(f"ssprk2 {case} prec={prec}", eE, eF)
         assert eE <= tol and eF <= tol
         if prec == m1.FP64:
@@ -408,7 +417,10 @@ def _sampled_step(m1, w, precision, nsample=1500, seed=7):
     Fg = [f.reshape(nz, w.G)[zones] for f in Fg]
     del ctx
     torch.cuda.empty_cache()
-    return rel_l1(Eg, Fg, Es, Fs, w.c)
+    e = rel_l1(Eg, Fg, Es, Fs, w.c)
+    say(f"  sampled zones: rel-L1 E {e[0]:.2e} F {e[1]:.2e}; element-wise E {e.pE:.2e} F {e.pF:.2e}")
+    check_pointwise(e, precision == m1.FP64, w.name)
+    return e
 
 
 def test_full_size_blobs2d_fp64(m1):
