@@ -44,8 +44,13 @@ enum {
   FORNAX_ECFL = -2,         /* dt above fornax_m1_max_dt(ctx, 1.0) */
   FORNAX_EDEVICE = -3,      /* HIP error (launch, copy, no device) */
   FORNAX_ENOMEM = -4,       /* device allocation failed */
-  FORNAX_EUNSUPPORTED = -5  /* option not implemented for this configuration */
+  FORNAX_EUNSUPPORTED = -5, /* option not implemented for this configuration */
+  FORNAX_ESCRATCH = -6      /* fornax_m1_step_noalloc: the step's scratch exceeds the static array */
 };
+
+/* Size of the static device array that fornax_m1_step_noalloc keeps its scratch in (one per
+ * device, held until the process ends). */
+#define FORNAX_M1_NOALLOC_SCRATCH_BYTES (16u << 20)
 
 /* Coordinates.  SPHERICAL_LOGR: x1 = ln r, x2 = theta, x3 = phi (metric of the Appendix,
  * general spherical metric, with r = e^{x1}, theta = x2). */
@@ -147,6 +152,22 @@ double fornax_m1_max_dt(const fornax_m1_ctx *ctx, double cfl);
 int fornax_m1_step(fornax_m1_ctx *ctx, const fornax_m1_state *in, fornax_m1_state *out,
                    const fornax_m1_coeffs *cf, const double *inflow, double dt,
                    const fornax_m1_diag *diag, void *stream);
+
+/* fornax_m1_step for the callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and results,
+ * with every scratch buffer of the step -- the per-block diagnostics partials, the dE_matter
+ * partials of tiles that split a zone's groups, the SSP-RK2 stage -- in one static device array
+ * of FORNAX_M1_NOALLOC_SCRATCH_BYTES per device instead of the context's scratch.  Calls no
+ * allocating routine.  Every call on a device shares that device's array (it keeps the last
+ * call's contents; every launch writes the parts it reads, so nothing needs clearing), so calls
+ * that overlap on one device -- on any contexts or streams -- race.  FORNAX_ESCRATCH,
+ * before any launch, when the scratch of this grid and these options exceeds the array (the
+ * diagnostics partials take 24 bytes per block; dE_matter on tiles that split groups takes 8
+ * bytes per zone and group block; SSP-RK2 takes one state).  Otherwise the arguments, errors and
+ * results of fornax_m1_step. */
+int fornax_m1_step_noalloc(fornax_m1_ctx *ctx, const fornax_m1_state *in, fornax_m1_state *out,
+                           const fornax_m1_coeffs *cf, const double *inflow, double dt,
+                           const fornax_m1_diag *diag, void *stream);
 
 /* Numerical face fluxes of U (eq:hll, eq:epsilon) per direction d < ndim, as coordinate flux
  * densities (the face area is not applied): face_flux[d] is an array

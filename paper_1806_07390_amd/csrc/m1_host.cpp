@@ -385,6 +385,9 @@ const char* fornax_m1_strerror(int code) {
     case FORNAX_EDEVICE: return "HIP device error";
     case FORNAX_ENOMEM: return "device allocation failed";
     case FORNAX_EUNSUPPORTED: return "unsupported configuration";
+    case FORNAX_ESCRATCH:
+      return "the step's scratch does not fit the static array of fornax_m1_step_noalloc "
+             "(FORNAX_M1_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown error";
   }
 }
@@ -398,6 +401,11 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   if (!ctx) return FORNAX_ENOMEM;
   ctx->desc = *desc;
   if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return FORNAX_EDEVICE;
+  }
+  // set-up of the static scratch of fornax_m1_step_noalloc on this device (once per device)
+  if (fm1_static_scratch_setup(ctx->device) != FORNAX_OK) {
     delete ctx;
     return FORNAX_EDEVICE;
   }
@@ -510,6 +518,8 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
     delete ctx;
     return FORNAX_ENOMEM;
   }
+  ctx->nb_partials =
+      (size_t)std::max(std::max(ctx->rows.nblocks, ctx->c3.nblocks), std::max(ctx->tile_v1.nblocks, ctx->tile.nblocks));
   ctx->p_energy = (double*)red;
   ctx->p_maxf2 = ctx->p_energy + nb;
   ctx->p_nun = (int*)(ctx->p_maxf2 + nb);
@@ -616,6 +626,18 @@ int fornax_m1_step(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_stat
   if (needs_inflow(ctx->desc) != (inflow != nullptr)) return FORNAX_EINVAL;
   if (!(dt > 0.0) || dt > ctx->max_dt1 * (1.0 + 1e-12)) return FORNAX_ECFL;
   return fm1_launch_step(ctx, in, out, cf, inflow, dt, diag, (hipStream_t)stream);
+}
+
+int fornax_m1_step_noalloc(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
+                           const fornax_m1_coeffs* cf, const double* inflow, double dt, const fornax_m1_diag* diag,
+                           void* stream) {
+  if (!ctx) return FORNAX_EINVAL;
+  int rc;
+  if ((rc = check_state(ctx, in)) || (rc = check_state(ctx, out)) || (rc = check_coeffs(ctx, cf))) return rc;
+  if (overlaps(ctx, in, out)) return FORNAX_EINVAL;
+  if (needs_inflow(ctx->desc) != (inflow != nullptr)) return FORNAX_EINVAL;
+  if (!(dt > 0.0) || dt > ctx->max_dt1 * (1.0 + 1e-12)) return FORNAX_ECFL;
+  return fm1_launch_step_noalloc(ctx, in, out, cf, inflow, dt, diag, (hipStream_t)stream);
 }
 
 int fornax_m1_flux(fornax_m1_ctx* ctx, const fornax_m1_state* in, const fornax_m1_coeffs* cf, const double* inflow,

@@ -185,6 +185,7 @@ struct fornax_m1_ctx {
   fm1::Tile last_tile[1];      // the tile of the last step launch (for inspection)
   // reduction scratch (one partial per block of the step kernel)
   int nblocks_step;
+  size_t nb_partials;          // partials the step kernels may write (the most blocks of any)
   double* p_energy;
   double* p_maxf2;
   int* p_nun;
@@ -219,6 +220,14 @@ struct StepScratch {
 int fm1_launch_step(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
                     const fornax_m1_coeffs* cf, const double* inflow, double dt,
                     const fornax_m1_diag* diag, hipStream_t stream);
+// the same step with its scratch in the library's static device array (no allocation), whose
+// address fornax_m1_create set up on the context's device
+int fm1_launch_step_noalloc(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
+                            const fornax_m1_coeffs* cf, const double* inflow, double dt,
+                            const fornax_m1_diag* diag, hipStream_t stream);
+// address of the static scratch array on a device (hipGetSymbolAddress, once per device, the
+// device current); FORNAX_OK or FORNAX_EDEVICE
+int fm1_static_scratch_setup(int device);
 int fm1_launch_flux(fornax_m1_ctx* ctx, const fornax_m1_state* in, const fornax_m1_coeffs* cf,
                     const double* inflow, void* face_flux[3], hipStream_t stream);
 int fm1_launch_source(fornax_m1_ctx* ctx, fornax_m1_state* inout, const fornax_m1_coeffs* cf,

@@ -18,6 +18,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
 
 #include "m1_device.h"
 #include "m1_internal.h"
@@ -346,6 +348,74 @@ int fm1_launch_step(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_sta
   return launch_step_t<float, float>(ctx, ctx->geo_f, in, out, cf, inflow, dt, diag, sc, stream);
 }
 
+// ------------------------------------------------------------------------------------------
+// Static scratch of fornax_m1_step_noalloc: one array per device for the callers that cannot
+// allocate.  In host code `scratch` names a host-side stand-in: kernels and copies take the
+// device address obtained once per device with hipGetSymbolAddress (g_scratch_ptr).
+// ------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[FORNAX_M1_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int fm1_static_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return FORNAX_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[device]) return FORNAX_OK;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != device) return FORNAX_EDEVICE;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FORNAX_EDEVICE;
+  g_scratch_ptr[device] = ptr;
+  return FORNAX_OK;
+}
+
+int fm1_launch_step_noalloc(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
+                            const fornax_m1_coeffs* cf, const double* inflow, double dt, const fornax_m1_diag* diag,
+                            hipStream_t stream) {
+  // the address was set up when a context was first created on this device
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (ctx->device >= 0 && ctx->device < kMaxDevices) base = g_scratch_ptr[ctx->device];
+  }
+  if (!base) return FORNAX_EDEVICE;
+  // layout: the partials of every block the step kernels may launch, the dE_matter partials of
+  // split group blocks (when dE_matter is asked for), the Runge-Kutta stage; each part 256-byte
+  // aligned (no part needs clearing: every launch writes what it reads)
+  const fornax_m1_desc& D = ctx->desc;
+  const size_t nb = ctx->nb_partials;
+  const size_t nz = (size_t)D.n[0] * D.n[1] * D.n[2];
+  const size_t es = D.precision == FORNAX_FP64 ? sizeof(double) : sizeof(float);
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t off = 0;
+  const size_t o_energy = off;
+  off += al(nb * sizeof(double));
+  const size_t o_maxf2 = off;
+  off += al(nb * sizeof(double));
+  const size_t o_nun = off;
+  off += al(nb * sizeof(int));
+  const size_t o_nnp = off;
+  off += al(nb * sizeof(int));
+  const size_t ngb = (size_t)std::max(std::max(ctx->tile.ngb, ctx->tile_v1.ngb), ctx->c3.ngb);
+  const bool need_dzp = diag && diag->dE_matter && ngb > 1;
+  const size_t o_dzp = off;
+  if (need_dzp) off += al(ngb * nz * sizeof(double));
+  const bool need_stage = D.integrator == FORNAX_SSPRK2;
+  const size_t o_stage = off;
+  if (need_stage) off += al((size_t)(1 + D.ndim) * nz * D.ngroups * es);
+  if (off > (size_t)FORNAX_M1_NOALLOC_SCRATCH_BYTES) return FORNAX_ESCRATCH;
+  char* b = (char*)base;
+  const StepScratch sc{(double*)(b + o_energy), (double*)(b + o_maxf2), (int*)(b + o_nun), (int*)(b + o_nnp),
+                       need_dzp ? (double*)(b + o_dzp) : nullptr,
+                       need_stage ? (void*)(b + o_stage) : nullptr};
+  if (D.precision == FORNAX_FP64)
+    return launch_step_t<double, double>(ctx, ctx->geo_d, in, out, cf, inflow, dt, diag, sc, stream);
+  return launch_step_t<float, float>(ctx, ctx->geo_f, in, out, cf, inflow, dt, diag, sc, stream);
+}
 
 int fm1_launch_transport(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
                          const fornax_m1_coeffs* cf, const double* inflow, double dt, hipStream_t stream) {

@@ -25,6 +25,8 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 FORNAX_OK, FORNAX_EINVAL, FORNAX_ECFL, FORNAX_EDEVICE, FORNAX_ENOMEM, FORNAX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+FORNAX_ESCRATCH = -6
+NOALLOC_SCRATCH_BYTES = 16 << 20     # FORNAX_M1_NOALLOC_SCRATCH_BYTES
 CARTESIAN, SPHERICAL_LOGR = 0, 1
 BC_OUTFLOW, BC_PERIODIC, BC_REFLECT, BC_INFLOW, BC_AXIS = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
@@ -36,7 +38,7 @@ WAVESPEED_LIGHT, WAVESPEED_M1 = 0, 1
 EXPORTED = ["fornax_m1_create", "fornax_m1_destroy", "fornax_m1_max_dt", "fornax_m1_step", "fornax_m1_flux",
             "fornax_m1_source", "fornax_m1_adjoint", "fornax_m1_copy_probe", "fornax_m1_strerror",
             "fornax_m1_transport", "fornax_m1_set_matter_model", "fornax_m1_matter_coeffs",
-            "fornax_m1_matter_source"]
+            "fornax_m1_matter_source", "fornax_m1_step_noalloc"]
 
 
 class Desc(ctypes.Structure):
@@ -90,6 +92,8 @@ _lib.fornax_m1_destroy.argtypes = [_vp]
 _lib.fornax_m1_max_dt.argtypes = [_vp, ctypes.c_double]
 _lib.fornax_m1_max_dt.restype = ctypes.c_double
 _lib.fornax_m1_step.argtypes = [_vp, _P(State), _P(State), _P(Coeffs), _vp, ctypes.c_double, _P(Diag), _vp]
+_lib.fornax_m1_step_noalloc.argtypes = [_vp, _P(State), _P(State), _P(Coeffs), _vp, ctypes.c_double, _P(Diag),
+                                        _vp]
 _lib.fornax_m1_flux.argtypes = [_vp, _P(State), _P(Coeffs), _vp, _vp * 3, _vp]
 _lib.fornax_m1_source.argtypes = [_vp, _P(State), _P(Coeffs), ctypes.c_double, _vp, _vp]
 _lib.fornax_m1_adjoint.argtypes = [_vp, _P(State), _P(State), _P(Coeffs), _vp, ctypes.c_double, _P(State), _P(State),
@@ -235,8 +239,9 @@ class Context:
             raise FornaxError(int(v), "fornax_m1_max_dt")
         return v
 
-    def step(self, E, F, kappa, sigma, B, dt, out=None, inflow=None, diag=None, stream=None):
-        """One step; returns (E_out, [F_out]).  diag: dict of preallocated tensors (optional)."""
+    def step(self, E, F, kappa, sigma, B, dt, out=None, inflow=None, diag=None, stream=None, noalloc=False):
+        """One step; returns (E_out, [F_out]).  diag: dict of preallocated tensors (optional).
+        noalloc: through fornax_m1_step_noalloc (scratch in the library's static array)."""
         sin = self._state(E, F, "in")
         if out is None:
             out = self.empty_state()
@@ -250,7 +255,8 @@ class Context:
             dg.max_f = _ptr(diag.get("max_f"))
             dg.n_unrealizable = _ptr(diag.get("n_unrealizable"))
             dg.n_nonpositive = _ptr(diag.get("n_nonpositive"))
-        fn, name = _lib.fornax_m1_step, "fornax_m1_step"
+        fn, name = ((_lib.fornax_m1_step_noalloc, "fornax_m1_step_noalloc") if noalloc
+                    else (_lib.fornax_m1_step, "fornax_m1_step"))
         _check(fn(self._h, ctypes.byref(sin), ctypes.byref(sout), ctypes.byref(cf), self._inflow(inflow), dt,
                   ctypes.byref(dg) if dg is not None else None, _stream(stream)), name)
         return out
