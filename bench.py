@@ -1,14 +1,16 @@
 """Benchmark of the M1 radiation-moment step on one MI355X.
 
 Headline (`value`): zone-group updates per second of the full step (explicit transport +
-implicit interaction update + energy/realizability diagnostics) on the 2-D periodic
-512 x 512 zone, 16 group FP64 workload, inputs resident in HBM, timed with HIP events over
-K steps after W warmup steps (default 300, about 30 ms: a GPU that has been idle runs its first
-few milliseconds of work at lower clocks, which a 10-step warm-up still times).  Extra workloads (3-D 192^3 x 12 FP64 vs MIXED, spherical
-256 x 64 x 128 x 20 MIXED) and the adjoint/forward ratio are reported beside it, plus the
-roofline of the dominant kernel and the CPU oracle's rate on this host (a baseline only).
+implicit interaction update + energy/realizability diagnostics) on the 3-D Cartesian
+192^3 zone, 12 group FP64 workload (optically thick core in a thin halo, Planck group
+weights), inputs resident in HBM, timed with HIP events on the launch stream over K steps
+after W warm-up steps.  Beside it: the same grid with float storage (MIXED), the 2-D
+512^2 x 16 periodic blob workload (FP64 and MIXED, options), the spherical 256 x 64 x 128 x 20
+workload, the radiation-matter exchange and the adjoint/forward ratio; the roofline of the
+headline step kernel (algorithmic bytes over its measured duration) and the CPU oracle's rate
+on this host's cores (a baseline only).
 
-    python bench.py [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--no-extra] [--no-cpu] [--only NAME]
 """
 from __future__ import annotations
 
@@ -34,8 +36,9 @@ def log(*a):
 # HBM traffic of the step kernel on the headline workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counters scaled by the copy-kernel calibration (see the file); it applies only
 # while the kernel sources are the ones it was measured on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_rows_blobs2d_512x512x16_fp64_traffic.json")
-KERNEL_SOURCES = ["m1_step_rows.hip", "m1_device.h", "m1_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_3d_core3d_192x192x192x12_fp64_traffic.json")
+KERNEL_SOURCES = ["m1_step_3d.hip", "m1_device.h", "m1_internal.h"]
+HEADLINE_KERNEL = "k_step_3d<double, 8, 2, 0>"
 
 
 def kernel_source_digest():
@@ -182,38 +185,46 @@ def cpu_model():
 
 
 def cpu_baseline(w, dt, target_s=20.0, single_s=8.0):
-    """The CPU oracle on a bounded sample of the same workload: whole steps with OpenMP over
-    the host's cores (the reported value), and whole steps on one thread."""
+    """The CPU oracle on a bounded sample of the same workload: whole steps of the full grid
+    with OpenMP over the host cores this process may use (the reported value), and one step at
+    a random sample of zones on one thread."""
+    import numpy as np
     from oracle import m1_oracle as orc
     ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    ncores = min(ncores, 16)
-    p1 = orc.Problem(ndim=w.ndim, n=w.n, G=w.G, coord=w.coord, lo=w.lo, hi=w.hi, bc_lo=w.bc_lo, bc_hi=w.bc_hi,
-                     c=w.c, nthreads=1)
+    omp = os.environ.get("OMP_NUM_THREADS")
+    nthreads = int(omp) if omp and omp.isdigit() and int(omp) > 0 else ncores
+    kw = dict(ndim=w.ndim, n=w.n, G=w.G, coord=w.coord, lo=w.lo, hi=w.hi, bc_lo=w.bc_lo, bc_hi=w.bc_hi, c=w.c)
+    # one thread: one step at a sample of zones sized to about single_s seconds
+    p1 = orc.Problem(nthreads=1, **kw)
+    nz = w.zone_groups // w.G
+    rng = np.random.default_rng(0)
+    nsel = 2000
+    zones = np.sort(rng.choice(nz, nsel, replace=False))
     t0 = time.perf_counter()
-    orc.run(p1, w.E, w.F, w.kappa, w.sigma, w.B, dt, 1)
+    orc.step_zones(p1, w.E, w.F, w.kappa, w.sigma, w.B, dt, zones, inflow=w.inflow)
     t1 = time.perf_counter()
-    n1 = max(1, min(50, int(single_s / max(t1 - t0, 1e-3))))
+    nsel = int(min(nz, max(2000, nsel * single_s / max(t1 - t0, 1e-3))))
+    zones = np.sort(rng.choice(nz, nsel, replace=False))
     t0 = time.perf_counter()
-    orc.run(p1, w.E, w.F, w.kappa, w.sigma, w.B, dt, n1)
+    orc.step_zones(p1, w.E, w.F, w.kappa, w.sigma, w.B, dt, zones, inflow=w.inflow)
     t1 = time.perf_counter()
-    single = dict(value=w.zone_groups * n1 / (t1 - t0), sample=f"{n1} full steps on 1 thread, {t1 - t0:.1f} s")
-    p = orc.Problem(ndim=w.ndim, n=w.n, G=w.G, coord=w.coord, lo=w.lo, hi=w.hi, bc_lo=w.bc_lo, bc_hi=w.bc_hi,
-                    c=w.c, nthreads=ncores)
-    # probe on a small strip, then size the sample to ~target_s seconds
+    single = dict(value=nsel * w.G / (t1 - t0), sample=f"one step at {nsel} random zones x {w.G} groups on 1 thread, "
+                                                       f"{t1 - t0:.1f} s")
+    # all threads: whole steps of the full grid, as many as fit target_s (at least one)
+    p = orc.Problem(nthreads=nthreads, **kw)
     t0 = time.perf_counter()
-    orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, 1)
+    orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, 1, inflow=w.inflow)
     t1 = time.perf_counter()
-    per_step = t1 - t0
-    nsteps = max(1, int(target_s / max(per_step, 1e-3)))
-    nsteps = min(nsteps, 200)
+    nsteps = max(1, min(200, int(target_s / max(t1 - t0, 1e-3))))
     t0 = time.perf_counter()
-    orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, nsteps)
+    orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, nsteps, inflow=w.inflow)
     t1 = time.perf_counter()
     zgu = w.zone_groups * nsteps / (t1 - t0)
-    return dict(value=zgu, unit="zone-group updates/s", cores=ncores, kind="oracle",
-                sample=f"{nsteps} full steps of the {w.n[0]}x{w.n[1]} x {w.G}-group workload, "
-                       f"{ncores} OpenMP threads, {t1 - t0:.1f} s",
-                single_thread=single, cpu_model=cpu_model())
+    size = "x".join(str(v) for v in w.n[:w.ndim])
+    return dict(value=zgu, unit="zone-group updates/s", cores=nthreads, kind="oracle",
+                sample=f"{nsteps} full steps of the {size} x {w.G}-group workload, {nthreads} OpenMP threads, "
+                       f"{t1 - t0:.1f} s",
+                host_cores_available=ncores, single_thread=single, cpu_model=cpu_model())
 
 
 def matter_timings(reps=10, steps=10):
@@ -277,16 +288,32 @@ def matter_timings(reps=10, steps=10):
     return out
 
 
+def step_timing(w, prec, dtp, steps, warmup, dt=None):
+    """(ms per full step with diagnostics, ms per step-kernel launch alone, final diag) on the
+    workload w in precision prec: HIP events on the launch stream."""
+    import torch
+    from paper_1806_07390_amd import m1
+    ctx = m1.Context(m1.Config.from_workload(w, precision=prec))
+    dt = w.dt if dt is None else dt
+    inp = device_inputs(w, dtp)
+    ms, diag = time_steps(ctx, inp, dt, steps, warmup, with_diag=True)
+    ms_k, _ = time_steps(ctx, inp, dt, steps, 2, with_diag=False)
+    diag = {k: v.cpu() for k, v in diag.items()}
+    del ctx, inp
+    torch.cuda.empty_cache()
+    return ms, ms_k, diag
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default=None,
-                    help="profiling: run only this workload's timed loop (blobs2d, core3d, sphere3d, options, "
-                         "matter, adjoint, extras = all after blobs2d, copy = the copy probe alone)")
+                    help="profiling: run only this workload's timed loop (core3d, core3d_mixed, blobs2d, sphere3d, "
+                         "options, matter, adjoint, extras = all after the headline, copy = the copy probe alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the library has no multi-GPU "
@@ -298,67 +325,61 @@ def main():
 
     torch.cuda.set_device(0)
     res = {}
-    # ---- headline: 2-D 512^2 x 16 groups, FP64 ------------------------------------------
-    w = wl.blobs2d()
-    if args.only in (None, "blobs2d"):
-        log("headline: blobs2d", w.n, w.G)
-        ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64))
-        inp = device_inputs(w, torch.float64)
-        ms, diag = time_steps(ctx, inp, w.dt, args.steps, args.warmup, with_diag=True)
-        ms_k, _ = time_steps(ctx, inp, w.dt, args.steps, 2, with_diag=False)
-        zg = w.zone_groups
-        value = zg / (ms * 1e-3)
-        bpz = algorithmic_bytes(w.ndim, 8)
-        achieved = zg * bpz / (ms_k * 1e-3) / 1e9
-        res["headline"] = dict(ms=ms, value=value, ms_kernel=ms_k, achieved=achieved, bpz=bpz,
-                               energy=float(diag["energy_total"].item()),
-                               n_unrealizable=int(diag["n_unrealizable"].item()))
-        log(f"  {ms:.4f} ms/step, {value:.3e} zgu/s; kernel {ms_k:.4f} ms -> {achieved:.0f} GB/s algorithmic")
-        del ctx, inp
-        torch.cuda.empty_cache()
-    if args.only is not None and args.only != "blobs2d":
-        pass
     extra = {}
+    # ---- headline: 3-D Cartesian 192^3 x 12 groups, FP64 -----------------------------------
+    w = wl.core3d()
+    if args.only in (None, "core3d"):
+        log("headline: core3d", w.n, w.G)
+        ms, ms_k, diag = step_timing(w, m1.FP64, torch.float64, args.steps, args.warmup)
+        zg = w.zone_groups
+        bpz = algorithmic_bytes(w.ndim, 8)
+        res["headline"] = dict(ms=ms, value=zg / (ms * 1e-3), ms_kernel=ms_k, achieved=zg * bpz / (ms_k * 1e-3) / 1e9,
+                               bpz=bpz, energy=float(diag["energy_total"].item()),
+                               n_unrealizable=int(diag["n_unrealizable"].item()))
+        h = res["headline"]
+        log(f"  {ms:.4f} ms/step, {h['value']:.3e} zgu/s; kernel {ms_k:.4f} ms -> {h['achieved']:.0f} GB/s algorithmic")
+    # ---- the same grid with float storage (MIXED) ------------------------------------------
+    if args.only in (None, "core3d_mixed"):
+        ms, ms_k, _ = step_timing(w, m1.MIXED, torch.float32, args.steps, args.warmup)
+        b = algorithmic_bytes(3, 4)
+        extra["core3d_192^3x12_mixed"] = dict(ms_per_step=round(ms, 5), zgu_per_s=w.zone_groups / (ms * 1e-3),
+                                              kernel_ms=round(ms_k, 5), bytes_per_zone_group=b,
+                                              algorithmic_GBps=round(w.zone_groups * b / (ms_k * 1e-3) / 1e9, 1),
+                                              kernel="k_step_3d<float, 8, 4, 0>")
+        log(f"  core3d mixed: {ms:.4f} ms/step, kernel {ms_k:.4f} ms")
     if not args.no_extra:
-        # ---- 3-D 192^3 x 12: FP64 vs MIXED -------------------------------------------------
-        if args.only in (None, "extras", "core3d"):
-            w3 = wl.core3d()
+        # ---- 2-D 512^2 x 16: FP64 (whole-zone kernel) and MIXED ----------------------------
+        if args.only in (None, "extras", "blobs2d"):
+            w2 = wl.blobs2d()
             for prec, name, dt_, el in ((m1.FP64, "fp64", torch.float64, 8), (m1.MIXED, "mixed", torch.float32, 4)):
-                ctx = m1.Context(m1.Config.from_workload(w3, precision=prec))
-                inp = device_inputs(w3, dt_)
-                ms3, _ = time_steps(ctx, inp, w3.dt, 20, 3, with_diag=True)
-                gbs = w3.zone_groups * algorithmic_bytes(3, el) / (ms3 * 1e-3) / 1e9
-                extra[f"core3d_192^3x12_{name}"] = dict(ms_per_step=round(ms3, 5),
-                                                        zgu_per_s=w3.zone_groups / (ms3 * 1e-3),
-                                                        algorithmic_GBps=round(gbs, 1))
-                log(f"  core3d {name}: {ms3:.4f} ms/step, {gbs:.0f} GB/s")
-                del ctx, inp
-                torch.cuda.empty_cache()
-            del w3
-        # ---- spherical 256x64x128 x 20 MIXED -----------------------------------------------
+                ms2, ms2k, _ = step_timing(w2, prec, dt_, 100, 300)
+                b = algorithmic_bytes(2, el)
+                extra[f"blobs2d_512^2x16_{name}"] = dict(ms_per_step=round(ms2, 5), zgu_per_s=w2.zone_groups / (ms2 * 1e-3),
+                                                         kernel_ms=round(ms2k, 5),
+                                                         algorithmic_GBps=round(w2.zone_groups * b / (ms2k * 1e-3) / 1e9, 1))
+                log(f"  blobs2d {name}: {ms2:.4f} ms/step, kernel {ms2k:.4f} ms")
+            del w2
+        # ---- spherical 256x64x128 x 20 ------------------------------------------------------
         if args.only in (None, "extras", "sphere3d"):
             w4 = wl.sphere3d()
             for prec, name, dt_, el in ((m1.MIXED, "mixed", torch.float32, 4), (m1.FP64, "fp64", torch.float64, 8)):
                 ctx = m1.Context(m1.Config.from_workload(w4, precision=prec))
                 dt4 = ctx.max_dt(w4.cfl)
-                inp = device_inputs(w4, dt_)
-                ms4, _ = time_steps(ctx, inp, dt4, 20, 3, with_diag=True)
-                gbs = w4.zone_groups * algorithmic_bytes(3, el) / (ms4 * 1e-3) / 1e9
+                del ctx
+                ms4, ms4k, _ = step_timing(w4, prec, dt_, 20, 3, dt=dt4)
+                gbs = w4.zone_groups * algorithmic_bytes(3, el) / (ms4k * 1e-3) / 1e9
                 extra[f"sphere3d_256x64x128x20_{name}"] = dict(ms_per_step=round(ms4, 5),
                                                                zgu_per_s=w4.zone_groups / (ms4 * 1e-3),
-                                                               algorithmic_GBps=round(gbs, 1))
+                                                               kernel_ms=round(ms4k, 5), algorithmic_GBps=round(gbs, 1))
                 log(f"  sphere3d {name}: {ms4:.4f} ms/step, {gbs:.0f} GB/s")
-                del ctx, inp
-                torch.cuda.empty_cache()
             del w4
-        # ---- the reconstruction and wavespeed options on the headline grid -----------------
+        # ---- the reconstruction and wavespeed options on the 2-D grid ----------------------
         if args.only in (None, "extras", "options"):
             wo = wl.blobs2d()
             inps = {m1.FP64: device_inputs(wo, torch.float64), m1.MIXED: device_inputs(wo, torch.float32)}
             opts = {"fp64_ppm": (m1.FP64, dict(limiter=m1.LIMITER_PPM)),
                     "fp64_m1_speeds": (m1.FP64, dict(wavespeed=m1.WAVESPEED_M1)),
-                    "fp64_minmod_tiled": (m1.FP64, dict(limiter=m1.LIMITER_MINMOD)),
-                    "mixed": (m1.MIXED, {})}
+                    "fp64_minmod_tiled": (m1.FP64, dict(limiter=m1.LIMITER_MINMOD))}
             for name, (prec, kw) in opts.items():
                 if name == "fp64_minmod_tiled":
                     os.environ["FORNAX_M1_ROWS"] = "0"
@@ -382,11 +403,12 @@ def main():
         if args.only in (None, "extras", "adjoint"):
             extra["adjoint"] = adjoint_ratios()
             log("  adjoint:", extra["adjoint"])
-        copy_gbs, copy_ms = copy_bandwidth()
-        extra["copy_probe_GBps"] = round(copy_gbs, 1)
-        if "headline" in res:
-            res["headline"]["frac_of_copy"] = res["headline"]["achieved"] / copy_gbs
-        log(f"  copy probe: {copy_gbs:.0f} GB/s")
+        if args.only in (None, "extras", "copy"):
+            copy_gbs, copy_ms = copy_bandwidth()
+            extra["copy_probe_GBps"] = round(copy_gbs, 1)
+            if "headline" in res:
+                res["headline"]["frac_of_copy"] = res["headline"]["achieved"] / copy_gbs
+            log(f"  copy probe: {copy_gbs:.0f} GB/s")
     if "headline" not in res:
         print(json.dumps(dict(extra=extra)))
         return
@@ -404,12 +426,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "2-D Cartesian periodic 512x512 zones x 16 groups, FP64, lognormal opacity, "
-                               "8 Gaussian blobs (seed 0)", "zones": [512, 512], "groups": 16,
-                   "zone_groups": w.zone_groups, "dt": w.dt},
+        "config": {"workload": "3-D Cartesian 192x192x192 zones x 12 groups, FP64, outflow, optically thick core "
+                               "(kappa 1e3 within r < 0.2) in a thin halo (1e-2), Planck group weights, seeded noise "
+                               "(seed 0)", "zones": list(w.n), "groups": w.G, "zone_groups": w.zone_groups,
+                   "dt": w.dt},
         "roofline": {"bound": "hbm", "achieved": round(h["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(h["achieved"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "k_step_rows<double, 0>", "bytes_per_zone_group": h["bpz"],
+                     "kernel": HEADLINE_KERNEL, "bytes_per_zone_group": h["bpz"],
                      "kernel_ms": round(h["ms_kernel"], 5),
                      "frac_of_copy_probe": (round(h["frac_of_copy"], 4) if "frac_of_copy" in h else None)},
         "extra": extra,

@@ -432,7 +432,7 @@ C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
 
 C3Tile choose_c3_tile(const fornax_m1_desc& D, int cus) {
   (void)cus;
-  const int NR = (D.precision == FORNAX_FP64) ? 6 : 8;
+  const int NR = 8;  // 8 waves per block, one y-row each; the top row only supplies its face flux
   return make_c3_tile(D, NR, 32);
 }
 

@@ -174,6 +174,65 @@ def test_tile_shapes(m1, case):
                 assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-5)
 
 
+def _c3_case(n=(37, 23, 19), G=8, steps=6, seed=11, bcs="outflow"):
+    """A 3-D Cartesian grid for the whole-zone 3-D kernel: x not a multiple of its 14 updated
+    columns, y not a multiple of any block's interior rows, a z run shorter than a plane
+    window; lognormal E with F up to 0.95 cE in random directions, opacities from the
+    free-streaming to the diffusive limit of the HLL flux (tau = kappa dx from 1e-3 to 1e2)."""
+    rng = np.random.default_rng(seed)
+    n0, n1, n2 = n
+    shape = (n2, n1, n0, G)
+    E = np.exp(rng.normal(0.0, 1.0, shape))
+    f = 0.95 * rng.random(shape)
+    d = rng.normal(size=(3,) + shape)
+    d /= np.linalg.norm(d, axis=0)
+    F = [np.ascontiguousarray(f * E * d[k]) for k in range(3)]
+    kappa = 10.0 ** rng.uniform(-3.0, 2.0, shape) * n0
+    sigma = 0.3 * kappa * rng.random(shape)
+    B = np.exp(rng.normal(0.0, 0.5, shape))
+    if bcs == "outflow":
+        lo, hi = (wl.BC_OUTFLOW,) * 3, (wl.BC_OUTFLOW,) * 3
+    else:  # periodic x, reflect/outflow y, outflow/reflect z
+        lo = (wl.BC_PERIODIC, wl.BC_REFLECT, wl.BC_OUTFLOW)
+        hi = (wl.BC_PERIODIC, wl.BC_OUTFLOW, wl.BC_REFLECT)
+    return wl.Workload("c3case", 3, n, G, wl.CARTESIAN, (0.0, 0.0, 0.0), (1.0, n1 / n0, n2 / n0), lo, hi, 1.0, steps,
+                       E, F, kappa, sigma, B, dt=0.3 / (3 * n0))
+
+
+@pytest.mark.parametrize("bcs", ["outflow", "mixed"])
+def test_3d_kernel_tiles(m1, bcs):
+    """The whole-zone 3-D kernel at each block height it is built for (y rows per block, z
+    planes per block): every one gives the oracle's result element by element, with the energy
+    diagnostics and the per-zone interaction energy summed over groups."""
+    import os
+    w = _c3_case(bcs=bcs)
+    p = problem_of(w)
+    dt = dt_of(w, p)
+    E, F, dg, dEm = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, want_dEm=True)
+    cases = ((m1.FP64, TOL_FP64, ["8,32", "6,5", "12,3", "8,1", "8,19"]),
+             (m1.MIXED, TOL_MIXED_RUN, ["8,32", "4,7", "16,2", "8,64"]))
+    for prec, tol, tiles in cases:
+        for tile in tiles:
+            say(f"case 3-D kernel {bcs} tile {tile} prec {prec}")
+            os.environ["FORNAX_M1_C3"] = tile
+            try:
+                ctx = m1.Context(m1.Config.from_workload(w, precision=prec))
+            finally:
+                del os.environ["FORNAX_M1_C3"]
+            Eg, Fg, dgg = gpu_run(ctx, w, dt, w.steps, diag=True)
+            e = rel_l1(Eg, Fg, E, F, w.c)
+            say(f"  rel-L1 E {e[0]:.2e} F {e[1]:.2e}; element-wise E {e.pE:.2e} F {e.pF:.2e}")
+            check_pointwise(e, prec == m1.FP64, f"3-D kernel {tile}")
+            assert e[0] <= tol and e[1] <= tol, (tile, prec)
+            if prec == m1.FP64:
+                atol = 1e-12 * np.abs(E).max()
+                assert np.allclose(dgg["dE_matter"], dEm, rtol=1e-10, atol=atol), tile
+                assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-12)
+                assert int(dgg["n_unrealizable"][0]) == dg["n_unrealizable"]
+            else:
+                assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-5)
+
+
 def _rows_case(bc, n0=70, n1=40, G=16, steps=4):
     """A 2-D, 16-group grid of the whole-zone kernel's kind: 70 columns (five tiles of 14 updated
     columns) by 40 rows (planes per block not dividing it)."""
