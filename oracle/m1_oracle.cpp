@@ -287,6 +287,11 @@ struct Ctx {
   const double* sig;
   const double* B;
   const double* inflow;  // [G][1+ndim]: E and physical flux components of the inflow ghosts
+  // prescribed velocity (null for a static medium): vf[d], d < ndim, holds the coordinate
+  // components v^0..v^{ndim-1} on the d-faces, [ndim][faces_d], faces_d over (k, j, i) with
+  // the d index in 0..n_d, x fastest; nu_edge: the G + 1 group edges in frequency
+  const double* vf[3] = {nullptr, nullptr, nullptr};
+  const double* nu_edge = nullptr;
   size_t zone(const int m[3]) const { return ((size_t)m[2] * n[1] + m[1]) * n[0] + m[0]; }
 };
 
@@ -611,6 +616,60 @@ static T tmin(T a, T b) { return val(b) < val(a) ? b : a; }
 template <class T>
 static T tmax(T a, T b) { return val(b) > val(a) ? b : a; }
 
+// ------------------------------------------------------------------------------------
+// Prescribed velocity (Riemann Solvers subsection, the advective fluxes and the
+// volume-averaged velocity gradient).  The paper takes the face velocities from the
+// hydrodynamics' HLLC solve; here they are an input.
+// ------------------------------------------------------------------------------------
+// Coordinate (contravariant) component v^comp of the velocity on the d-face with face index f
+// of the zone row idx (the input holds coordinate components: on spherical grids
+// v^1 = v^_r / r, v^2 = v^_theta / r, v^3 = v^_phi / (r sin theta), finite on the polar axis).
+// Components along inactive directions are 0.
+template <class T>
+static double face_vc(const Ctx<T>& C, int d, const int idx[3], int f, int comp) {
+  if (comp >= C.ndim) return 0.0;
+  int m[3] = {C.n[0], C.n[1], C.n[2]};
+  m[d] += 1;
+  int fi[3] = {idx[0], idx[1], idx[2]};
+  fi[d] = f;
+  const size_t nf = (size_t)m[0] * m[1] * m[2];
+  const size_t at = ((size_t)fi[2] * m[1] + fi[1]) * m[0] + fi[0];
+  return C.vf[d][(size_t)comp * nf + at];
+}
+
+// Volume-averaged velocity gradient of active zone idx: the paper's approximation
+//   <v^i_{;j}> = <v^i_{,j}> + <Gamma^i_{jk}> <v^k>,
+// with each coordinate component linear in x^j across the zone, so that <v^i_{,j}> is the
+// difference of v^i between the two j-faces over Delta x^j, and <v^k> the volume average of the
+// linear profile of v^k between its two k-faces (its value at the zone's volume centroid
+// <x^k>).  Reading: the connection coefficients are the volume averages used by the geometric
+// source terms (with the paper's overrides), as the paper computes this term "as in" those.
+// Vg[i][j] = <v^i_{;j}>, vbar[k] = <v^k>.
+template <class T>
+static void vel_grad(const Ctx<T>& C, const int idx[3], double Vg[3][3], double vbar[3]) {
+  const Geom& G = *C.geo;
+  double dv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int k = 0; k < 3; ++k) vbar[k] = 0.0;
+  for (int j = 0; j < C.ndim; ++j) {
+    const int e = idx[j] + NG;
+    const double x0 = G.xf[j][e], x1 = G.xf[j][e + 1];
+    for (int i = 0; i < C.ndim; ++i) {
+      const double vlo = face_vc(C, j, idx, idx[j], i);
+      const double vhi = face_vc(C, j, idx, idx[j] + 1, i);
+      dv[i][j] = (vhi - vlo) / (x1 - x0);
+      if (i == j) vbar[j] = vlo + (vhi - vlo) * (G.X[j][e] - x0) / (x1 - x0);
+    }
+  }
+  double Gm[3][3][3];
+  G.gamma(idx[0], idx[1], Gm);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = dv[i][j];
+      for (int k = 0; k < 3; ++k) s += Gm[i][j][k] * vbar[k];
+      Vg[i][j] = s;
+    }
+}
+
 // Numerical flux across the d-face at face index f (between zones f-1 and f along d) of
 // the row idx.  Riemann Solvers subsection: HLL fluxes for the radiation subsystem, the
 // energy flux corrected as in eq:hll with epsilon = min(1, 1/tau_cell) (eq:epsilon).
@@ -673,6 +732,14 @@ static void face_flux(const Ctx<T>& C, int d, const int row[3], int f, int g, T 
     T PdkR = T(C.c * C.c) * PR[d][k] * T(hk / h[d]);
     flux[1 + k] = (SR * PdkL - SL * PdkR + (SR * SL) * (qR[1 + k] - qL[1 + k])) / (SR - SL);
   }
+  // advective fluxes (v E) and (v F_k) of the comoving-frame moments: the face's normal
+  // velocity v^d times the reconstructed state on its upwind side, the left one for v^d >= 0
+  if (C.vf[0]) {
+    const double vd = face_vc(C, d, fi, f, d);
+    const T* qu = (vd >= 0.0) ? qL : qR;
+    flux[0] = flux[0] + T(vd) * qu[0];
+    for (int k = 0; k < C.ndim; ++k) flux[1 + k] = flux[1 + k] + T(vd) * qu[1 + k];
+  }
 }
 
 // Explicit update of one zone-group (Algorithmic Steps, step 1, radiation rows, v = 0):
@@ -711,6 +778,22 @@ static void explicit_update(const Ctx<T>& C, const int idx[3], int g, T Um[4]) {
         for (int m = 0; m < 3; ++m)
           if (Gm[l][k][m] != 0.0) s = s + T(Gm[l][k][m]) * P[m][l] * T(h[l] / h[m]);
       Um[1 + k] = Um[1 + k] + T(C.dt) * T(C.c * C.c) * s;
+    }
+  }
+  if (C.vf[0]) {
+    // velocity terms of the flux rows in Step 1: the connection part of the covariant
+    // divergence (v^i F_k)_{;i}, i.e. + <Gamma^l_{ik}> <v^i> F_l, and - <v^i_{;k}> F_i
+    // (eq:rad_mom2), with the zone's own state
+    double Vg[3][3], vb[3], Gm[3][3][3];
+    vel_grad(C, idx, Vg, vb);
+    G.gamma(idx[0], idx[1], Gm);
+    for (int k = 0; k < C.ndim; ++k) {
+      T s = T(0.0);
+      for (int i = 0; i < 3; ++i)
+        for (int l = 0; l < 3; ++l)
+          if (Gm[l][i][k] != 0.0) s = s + T(Gm[l][i][k] * vb[i]) * q[1 + l];
+      for (int i = 0; i < 3; ++i) s = s - T(Vg[i][k]) * q[1 + i];
+      Um[1 + k] = Um[1 + k] + T(C.dt) * s;
     }
   }
 }
@@ -885,6 +968,150 @@ static void full_step(const OrcDesc* D, const Geom& geo, const T* E, const T* co
         }
       }
       etot += V * esum;
+      if (dEm) dEm[z] = -dsum;
+    }
+    if (diag) {
+      diag->energy_total = etot;
+      diag->max_f = maxf;
+      diag->n_unrealizable = nun;
+      diag->n_nonpositive = nnp;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Velocity-dependent terms (prescribed velocity)
+// ------------------------------------------------------------------------------------
+// Frequency advection of the groups of one zone (Algorithmic Steps, Step 2, eq:freq_adv_system
+// with the upwind intergroup fluxes), applied to the zone's state U[g] after Step 1:
+//   E_g <- E_g + dt ( Phi_{g+1/2} - Phi_{g-1/2} - <v^i_{;j}> P^j_{g i} ),
+//   Phi_{g-1/2} = nu_{g-1/2} sum_{ij} <v^i_{;j}> <P^j_i>_{L or R},
+// the left (lower group) side where <v^i_{;j}> < 0, the right side otherwise, <P>_g = P_g / dnu_g
+// the group's spectral density.  P^j_i = P^^{ji} h_i / h_j (closure of U[g], cell-centred h).
+// Readings:
+//  - Since the side depends only on the zone's <v^i_{;j}>, the edge value is reconstructed for
+//    the two contractions X-_g = sum over (i,j) with <v^i_{;j}> < 0 of <v^i_{;j}> <P^j_i>_g and
+//    X+_g (the rest), each linear in nu across the group with the minmod-limited slope of
+//    the neighbouring groups' values over their centre distances ("TVD slope limiting"), zero
+//    slope in the first and last group; in one Cartesian dimension this is the reconstruction
+//    of <P^x_x> itself.  Phi_{g-1/2} = nu_{g-1/2} (X-_{g-1} at its upper edge + X+_g at its
+//    lower edge).
+//  - The frequency range is closed: Phi = 0 at nu_{1/2} and nu_{G+1/2}, so that the intergroup
+//    fluxes only move energy between groups.
+//  - The flux rows get no intergroup term: the paper gives no closure for the third moment
+//    Q^k_{ji} (and the Q term listed in Step 1 would count it a second time next to
+//    eq:rad_mom2), so the term -<v^i_{;k}> d_nu(nu Q^k_{ji}) is left out.
+static void freq_advect(const Ctx<double>& C, const int idx[3], std::vector<double>& U) {
+  const int G = C.G;
+  double Vg[3][3], vb[3], h[3];
+  vel_grad(C, idx, Vg, vb);
+  C.geo->h_cell(idx[0], idx[1], h);
+  std::vector<double> Xm(G), Xp(G), vP(G), nuc(G), dnu(G);
+  for (int g = 0; g < G; ++g) {
+    nuc[g] = 0.5 * (C.nu_edge[g] + C.nu_edge[g + 1]);
+    dnu[g] = C.nu_edge[g + 1] - C.nu_edge[g];
+    double P[3][3];
+    closure(C, &U[(size_t)4 * g], h, P);
+    double xm = 0.0, xp = 0.0, vp = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double Pji = P[j][i] * h[i] / h[j];
+        const double t = Vg[i][j] * Pji;
+        vp += t;
+        if (Vg[i][j] < 0.0) xm += t;
+        else xp += t;
+      }
+    vP[g] = vp;
+    Xm[g] = xm / dnu[g];
+    Xp[g] = xp / dnu[g];
+  }
+  // slopes in nu and edge values
+  auto slope = [&](const std::vector<double>& X, int g) {
+    if (g == 0 || g == G - 1) return 0.0;
+    return minmod2((X[g + 1] - X[g]) / (nuc[g + 1] - nuc[g]), (X[g] - X[g - 1]) / (nuc[g] - nuc[g - 1]));
+  };
+  std::vector<double> Phi(G + 1, 0.0);
+  for (int g = 1; g < G; ++g) {
+    const double xm_up = Xm[g - 1] + slope(Xm, g - 1) * (0.5 * dnu[g - 1]);
+    const double xp_lo = Xp[g] - slope(Xp, g) * (0.5 * dnu[g]);
+    Phi[g] = C.nu_edge[g] * (xm_up + xp_lo);
+  }
+  for (int g = 0; g < G; ++g) U[(size_t)4 * g] += C.dt * (Phi[g + 1] - Phi[g] - vP[g]);
+}
+
+// One full step with the velocity terms (Algorithmic Steps 1 to 4, Euler push, matter fixed):
+// Step 1 with the advective fluxes and the flux-row velocity terms, Step 2 on its result,
+// then the interaction update (Steps 3 and 4) of U^- = the state after Step 2.
+static void full_step_v(const OrcDesc* D, const Geom& geo, const double* E, const double* const* F,
+                        const double* kap, const double* sig, const double* B, const double* inflow,
+                        const double* const* vf, const double* nu_edge, double dt, double* Eo, double* const* Fo,
+                        double* dEm, OrcDiag* diag) {
+  Ctx<double> C;
+  C.D = D;
+  C.geo = &geo;
+  for (int d = 0; d < 3; ++d) C.n[d] = D->n[d];
+  C.G = D->G;
+  C.ndim = D->ndim;
+  C.c = D->c;
+  C.dt = dt;
+  C.E = E;
+  for (int k = 0; k < 3; ++k) C.F[k] = (k < D->ndim) ? F[k] : nullptr;
+  C.kap = kap;
+  C.sig = sig;
+  C.B = B;
+  C.inflow = inflow;
+  for (int k = 0; k < 3; ++k) C.vf[k] = (k < D->ndim) ? vf[k] : nullptr;
+  C.nu_edge = nu_edge;
+  const long nz = (long)C.n[0] * C.n[1] * C.n[2];
+  const int G = C.G;
+  std::vector<double> Em_all((size_t)nz * G);
+  set_threads(D);
+#pragma omp parallel for schedule(static)
+  for (long z = 0; z < nz; ++z) {
+    int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
+    std::vector<double> U((size_t)4 * G);
+    for (int g = 0; g < G; ++g) explicit_update(C, idx, g, &U[(size_t)4 * g]);
+    freq_advect(C, idx, U);
+    for (int g = 0; g < G; ++g) {
+      double U1[4];
+      source_of(C, idx, g, &U[(size_t)4 * g], U1);
+      const size_t zg = (size_t)z * G + g;
+      Eo[zg] = U1[0];
+      for (int k = 0; k < D->ndim; ++k) Fo[k][zg] = U1[1 + k];
+      Em_all[zg] = U[(size_t)4 * g];
+    }
+  }
+  if (diag || dEm) {
+    double etot = 0.0, maxf = 0.0;
+    int64_t nun = 0, nnp = 0;
+    const double u = std::ldexp(1.0, -53);
+    for (long z = 0; z < nz; ++z) {
+      int i = (int)(z % C.n[0]), j = (int)((z / C.n[0]) % C.n[1]), k = (int)(z / ((long)C.n[0] * C.n[1]));
+      double h[3];
+      geo.h_cell(i, j, h);
+      double esum = 0.0, dsum = 0.0;
+      for (int g = 0; g < G; ++g) {
+        const size_t zg = (size_t)z * G + g;
+        const double e = Eo[zg];
+        esum += e;
+        dsum += e - Em_all[zg];
+        if (e > 0.0) {
+          double f2 = 0.0;
+          for (int kk = 0; kk < D->ndim; ++kk) {
+            double fk = Fo[kk][zg] / h[kk] / (C.c * e);
+            f2 += fk * fk;
+          }
+          double fm = std::sqrt(f2);
+          maxf = std::max(maxf, fm);
+          if (fm > 1.0 + 8.0 * u) nun++;
+        } else {
+          nnp++;
+          bool fz = true;
+          for (int kk = 0; kk < D->ndim; ++kk) fz = fz && Fo[kk][zg] == 0.0;
+          if (e < 0.0 || !fz) nun++;
+        }
+      }
+      etot += geo.volume(i, j, k) * esum;
       if (dEm) dEm[z] = -dsum;
     }
     if (diag) {
@@ -1242,6 +1469,177 @@ extern "C" int orc_explicit(const OrcDesc* D, const double* E, const double* con
       Eo[zg] = Um[0];
       for (int k = 0; k < D->ndim; ++k) Fo[k][zg] = Um[1 + k];
     }
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------
+// Velocity-dependent terms: C API
+// ------------------------------------------------------------------------------------
+static bool velocity_ok(const OrcDesc* D, const double* nu_edge) {
+  if (D->integrator != OI_EULER) return false;
+  if (!nu_edge) return true;
+  for (int g = 0; g < D->G; ++g)
+    if (!(nu_edge[g + 1] > nu_edge[g]) || !std::isfinite(nu_edge[g + 1]) || nu_edge[g] < 0.0) return false;
+  return true;
+}
+
+// nsteps full steps with the velocity terms (forward-Euler push only; -1 otherwise or for bad
+// group edges).  vf: ndim face-velocity arrays (see Ctx::vf); nu_edge: G + 1 finite edges.
+extern "C" int orc_run_v(const OrcDesc* D, const double* E, const double* const* F, const double* kap,
+                         const double* sig, const double* B, const double* inflow, const double* const* vf,
+                         const double* nu_edge, double dt, int nsteps, double* Eo, double* const* Fo, double* dEm,
+                         OrcDiag* diag) {
+  if (!velocity_ok(D, nu_edge) || !nu_edge) return -1;
+  Geom geo;
+  geo.build(*D);
+  size_t nzg = (size_t)D->n[0] * D->n[1] * D->n[2] * D->G;
+  std::vector<double> Ea(E, E + nzg), Eb(nzg);
+  std::vector<std::vector<double>> Fa(3), Fb(3);
+  for (int k = 0; k < D->ndim; ++k) {
+    Fa[k].assign(F[k], F[k] + nzg);
+    Fb[k].assign(nzg, 0.0);
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    const double* Fin[3] = {nullptr, nullptr, nullptr};
+    double* Fout[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < D->ndim; ++k) {
+      Fin[k] = Fa[k].data();
+      Fout[k] = Fb[k].data();
+    }
+    const bool last = (s == nsteps - 1);
+    full_step_v(D, geo, Ea.data(), Fin, kap, sig, B, inflow, vf, nu_edge, dt, Eb.data(), Fout, last ? dEm : nullptr,
+                last ? diag : nullptr);
+    std::swap(Ea, Eb);
+    for (int k = 0; k < D->ndim; ++k) std::swap(Fa[k], Fb[k]);
+  }
+  std::memcpy(Eo, Ea.data(), nzg * sizeof(double));
+  for (int k = 0; k < D->ndim; ++k) std::memcpy(Fo[k], Fa[k].data(), nzg * sizeof(double));
+  return 0;
+}
+
+static void velocity_ctx(Ctx<double>& C, const OrcDesc* D, const Geom& geo, const double* E, const double* const* F,
+                         const double* kap, const double* sig, const double* inflow, const double* const* vf,
+                         const double* nu_edge, double dt) {
+  C.D = D;
+  C.geo = &geo;
+  for (int d = 0; d < 3; ++d) C.n[d] = D->n[d];
+  C.G = D->G;
+  C.ndim = D->ndim;
+  C.c = D->c;
+  C.dt = dt;
+  C.E = E;
+  for (int k = 0; k < 3; ++k) C.F[k] = (F && k < D->ndim) ? F[k] : nullptr;
+  C.kap = kap;
+  C.sig = sig;
+  C.B = nullptr;
+  C.inflow = inflow;
+  for (int k = 0; k < 3; ++k) C.vf[k] = (k < D->ndim) ? vf[k] : nullptr;
+  C.nu_edge = nu_edge;
+}
+
+// Step 1 alone with the velocity terms (advective fluxes, flux-row velocity terms).
+extern "C" int orc_explicit_v(const OrcDesc* D, const double* E, const double* const* F, const double* kap,
+                              const double* sig, const double* inflow, const double* const* vf, double dt, double* Eo,
+                              double* const* Fo) {
+  Geom geo;
+  geo.build(*D);
+  Ctx<double> C;
+  velocity_ctx(C, D, geo, E, F, kap, sig, inflow, vf, nullptr, dt);
+  set_threads(D);
+  const long nz = (long)C.n[0] * C.n[1] * C.n[2];
+#pragma omp parallel for schedule(static)
+  for (long z = 0; z < nz; ++z) {
+    int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
+    for (int g = 0; g < C.G; ++g) {
+      double Um[4];
+      explicit_update(C, idx, g, Um);
+      const size_t zg = (size_t)z * C.G + g;
+      Eo[zg] = Um[0];
+      for (int k = 0; k < D->ndim; ++k) Fo[k][zg] = Um[1 + k];
+    }
+  }
+  return 0;
+}
+
+// Step 2 alone on the state (E, F): the energies after the frequency advection (fluxes are
+// unchanged by it).
+extern "C" int orc_freq_adv(const OrcDesc* D, const double* E, const double* const* F, const double* const* vf,
+                            const double* nu_edge, double dt, double* Eo) {
+  if (!velocity_ok(D, nu_edge) || !nu_edge) return -1;
+  Geom geo;
+  geo.build(*D);
+  Ctx<double> C;
+  velocity_ctx(C, D, geo, E, F, nullptr, nullptr, nullptr, vf, nu_edge, dt);
+  const long nz = (long)C.n[0] * C.n[1] * C.n[2];
+  const int G = C.G;
+  for (long z = 0; z < nz; ++z) {
+    int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
+    std::vector<double> U((size_t)4 * G, 0.0);
+    for (int g = 0; g < G; ++g) {
+      const size_t zg = (size_t)z * G + g;
+      U[(size_t)4 * g] = E[zg];
+      for (int k = 0; k < D->ndim; ++k) U[(size_t)4 * g + 1 + k] = F[k][zg];
+    }
+    freq_advect(C, idx, U);
+    for (int g = 0; g < G; ++g) Eo[(size_t)z * G + g] = U[(size_t)4 * g];
+  }
+  return 0;
+}
+
+// <v^i_{;j}> (row-major [i][j]) and <v^k> of every zone: Vg [nzones][9], vbar [nzones][3].
+extern "C" int orc_vel_grad(const OrcDesc* D, const double* const* vf, double* Vg, double* vbar) {
+  Geom geo;
+  geo.build(*D);
+  Ctx<double> C;
+  velocity_ctx(C, D, geo, nullptr, nullptr, nullptr, nullptr, nullptr, vf, nullptr, 0.0);
+  const long nz = (long)C.n[0] * C.n[1] * C.n[2];
+  for (long z = 0; z < nz; ++z) {
+    int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
+    double V[3][3], vb[3];
+    vel_grad(C, idx, V, vb);
+    for (int i = 0; i < 3; ++i) {
+      for (int j = 0; j < 3; ++j) Vg[(size_t)z * 9 + 3 * i + j] = V[i][j];
+      vbar[(size_t)z * 3 + i] = vb[i];
+    }
+  }
+  return 0;
+}
+
+// Group-summed radiation energy and physical flux of every zone transformed to the laboratory
+// frame to first order in v/c (the comoving-to-lab transformation used for the transparent
+// shock test): with v^_k = h_k <v^k> (cell-centred h),
+//   E_lab = sum_g (E_g + 2 v^ . F^_g / c^2),   F^_lab = sum_g (F^_g + v^ E_g + v^ . P^_g).
+// Elab [nzones], Flab[k] [nzones] for k < ndim (physical components).
+extern "C" int orc_lab_frame(const OrcDesc* D, const double* E, const double* const* F, const double* const* vf,
+                             double* Elab, double* const* Flab) {
+  Geom geo;
+  geo.build(*D);
+  Ctx<double> C;
+  velocity_ctx(C, D, geo, E, F, nullptr, nullptr, nullptr, vf, nullptr, 0.0);
+  const long nz = (long)C.n[0] * C.n[1] * C.n[2];
+  const double c = D->c;
+  for (long z = 0; z < nz; ++z) {
+    int idx[3] = {(int)(z % C.n[0]), (int)((z / C.n[0]) % C.n[1]), (int)(z / ((long)C.n[0] * C.n[1]))};
+    double V[3][3], vb[3], h[3];
+    vel_grad(C, idx, V, vb);
+    geo.h_cell(idx[0], idx[1], h);
+    double v[3];
+    for (int k = 0; k < 3; ++k) v[k] = h[k] * vb[k];
+    double el = 0.0, fl[3] = {0.0, 0.0, 0.0};
+    for (int g = 0; g < D->G; ++g) {
+      const size_t zg = (size_t)z * D->G + g;
+      double q[4] = {E[zg], 0.0, 0.0, 0.0};
+      for (int k = 0; k < D->ndim; ++k) q[1 + k] = F[k][zg];
+      double P[3][3];
+      closure(C, q, h, P);
+      double Fh[3];
+      for (int k = 0; k < 3; ++k) Fh[k] = q[1 + k] / h[k];
+      el += q[0] + 2.0 * (v[0] * Fh[0] + v[1] * Fh[1] + v[2] * Fh[2]) / (c * c);
+      for (int k = 0; k < 3; ++k) fl[k] += Fh[k] + v[k] * q[0] + (v[0] * P[0][k] + v[1] * P[1][k] + v[2] * P[2][k]);
+    }
+    Elab[z] = el;
+    for (int k = 0; k < D->ndim; ++k) Flab[k][z] = fl[k];
   }
   return 0;
 }

@@ -85,6 +85,12 @@ def lib():
         _lib.orc_m1_speeds.argtypes = [P(OrcDesc), d, d, P(d), P(d)]
         _lib.orc_faces.argtypes = [P(OrcDesc), vp, vp, vp, ctypes.c_int, vp]
         _lib.orc_explicit.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, d, vp, vp]
+        _lib.orc_run_v.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, vp, vp, d, ctypes.c_int, vp, vp, vp,
+                                   P(OrcDiag)]
+        _lib.orc_explicit_v.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, d, vp, vp]
+        _lib.orc_freq_adv.argtypes = [P(OrcDesc), vp, vp, vp, vp, d, vp]
+        _lib.orc_vel_grad.argtypes = [P(OrcDesc), vp, vp, vp]
+        _lib.orc_lab_frame.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp]
         _lib.orc_planck_tail.restype = d
         _lib.orc_planck_tail.argtypes = [d]
         _lib.orc_matter_coeffs.argtypes = [ctypes.c_int, vp, vp, vp, d, ctypes.c_long, vp, vp, vp, vp]
@@ -379,3 +385,103 @@ def matter_step(p: Problem, m: MatterModel, E, F, sigma, cv, kappa0, T, dt, infl
     kap, _ = matter_coeffs(m, kappa0, T)
     Em, Fm = explicit(p, E, F, kap, sigma, dt, inflow=inflow)
     return matter_source(m, Em, Fm, sigma, cv, kappa0, T, dt)
+
+
+# ---- velocity-dependent terms (prescribed velocity) ----
+
+def face_shape(p: Problem, d: int):
+    """Shape (n2, n1, n0) of the d-faces, the d extent n_d + 1."""
+    s = list(p.shape[:3])
+    s[2 - d] += 1
+    return tuple(s)
+
+
+def _vel(p: Problem, vf):
+    """The ndim face-velocity arrays, each [ndim, *face_shape(p, d)]: the coordinate
+    (contravariant) components v^0..v^{ndim-1} on the d-faces (on spherical grids v^1 = v_r / r,
+    v^2 = v_theta / r, v^3 = v_phi / (r sin theta))."""
+    vf = [_c(v) for v in vf]
+    if len(vf) != p.ndim:
+        raise ValueError("one face-velocity array per active direction")
+    for d, v in enumerate(vf):
+        if v.shape != (p.ndim,) + face_shape(p, d):
+            raise ValueError(f"face velocity {d}: shape {v.shape}, expected {(p.ndim,) + face_shape(p, d)}")
+    return vf
+
+
+def run_v(p: Problem, E, F, kappa, sigma, B, vf, nu_edge, dt, nsteps=1, inflow=None, want_dEm=False):
+    """nsteps full steps with the velocity terms (Steps 1 to 4). Returns (E, [F_k], diag[, dEm])."""
+    d = p.desc()
+    E = _c(E)
+    F = [_c(f) for f in F]
+    kappa, sigma, B = _c(kappa), _c(sigma), _c(B)
+    inflow = None if inflow is None else _c(inflow)
+    vf = _vel(p, vf)
+    nu = _c(nu_edge)
+    if nu.shape != (p.G + 1,):
+        raise ValueError("nu_edge needs G + 1 entries")
+    Eo = np.empty_like(E)
+    Fo = [np.empty_like(E) for _ in range(p.ndim)]
+    dEm = np.empty(p.nzones) if want_dEm else None
+    diag = OrcDiag()
+    rc = lib().orc_run_v(ctypes.byref(d), _ptr(E), _ptrs(F), _ptr(kappa), _ptr(sigma), _ptr(B), _ptr(inflow),
+                         _ptrs(vf), _ptr(nu), dt, nsteps, _ptr(Eo), _ptrs(Fo), _ptr(dEm), ctypes.byref(diag))
+    if rc != 0:
+        raise ValueError("velocity step: Euler integrator and finite increasing group edges required")
+    dg = dict(energy_total=diag.energy_total, max_f=diag.max_f, n_unrealizable=diag.n_unrealizable,
+              n_nonpositive=diag.n_nonpositive)
+    if want_dEm:
+        return Eo, Fo, dg, dEm
+    return Eo, Fo, dg
+
+
+def explicit_v(p: Problem, E, F, kappa, sigma, vf, dt, inflow=None):
+    """Step 1 with the velocity terms alone. Returns (E, [F_k])."""
+    d = p.desc()
+    E = _c(E)
+    F = [_c(f) for f in F]
+    kappa, sigma = _c(kappa), _c(sigma)
+    inflow = None if inflow is None else _c(inflow)
+    vf = _vel(p, vf)
+    Eo = np.empty_like(E)
+    Fo = [np.empty_like(E) for _ in range(p.ndim)]
+    lib().orc_explicit_v(ctypes.byref(d), _ptr(E), _ptrs(F), _ptr(kappa), _ptr(sigma), _ptr(inflow), _ptrs(vf), dt,
+                         _ptr(Eo), _ptrs(Fo))
+    return Eo, Fo
+
+
+def freq_adv(p: Problem, E, F, vf, nu_edge, dt):
+    """Step 2 alone: the group energies after the frequency advection of (E, F)."""
+    d = p.desc()
+    E = _c(E)
+    F = [_c(f) for f in F]
+    vf = _vel(p, vf)
+    nu = _c(nu_edge)
+    Eo = np.empty_like(E)
+    rc = lib().orc_freq_adv(ctypes.byref(d), _ptr(E), _ptrs(F), _ptrs(vf), _ptr(nu), dt, _ptr(Eo))
+    if rc != 0:
+        raise ValueError("frequency advection: finite increasing group edges required")
+    return Eo
+
+
+def vel_grad(p: Problem, vf):
+    """<v^i_{;j}> [zones..., 3, 3] and <v^k> [zones..., 3] (coordinate components)."""
+    d = p.desc()
+    vf = _vel(p, vf)
+    Vg = np.empty(p.nzones * 9)
+    vb = np.empty(p.nzones * 3)
+    lib().orc_vel_grad(ctypes.byref(d), _ptrs(vf), _ptr(Vg), _ptr(vb))
+    return Vg.reshape(p.shape[:3] + (3, 3)), vb.reshape(p.shape[:3] + (3,))
+
+
+def lab_frame(p: Problem, E, F, vf):
+    """Group-summed lab-frame energy [zones...] and physical flux [ndim][zones...] to O(v/c)."""
+    d = p.desc()
+    E = _c(E)
+    F = [_c(f) for f in F]
+    vf = _vel(p, vf)
+    El = np.empty(p.nzones)
+    Fl = [np.empty(p.nzones) for _ in range(p.ndim)]
+    lib().orc_lab_frame(ctypes.byref(d), _ptr(E), _ptrs(F), _ptrs(vf), _ptr(El), _ptrs(Fl))
+    return El.reshape(p.shape[:3]), [f.reshape(p.shape[:3]) for f in Fl]
+

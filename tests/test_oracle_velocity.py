@@ -1,0 +1,458 @@
+"""Pins of the oracle's velocity-dependent terms (prescribed velocity; Riemann Solvers
+subsection: advective fluxes and the volume-averaged velocity gradient; eq:freq_adv_system and
+Algorithmic Steps 1 and 2) against what fixes them independently of its code:
+
+* a zero velocity field gives the static-medium step exactly (every value equal);
+* the volume-averaged gradient of a linear Cartesian field is its matrix, and in spherical
+  coordinates a homologous flow has <v^i_{;j}> = a delta^i_j and a rigid rotation has a
+  vanishing trace and strain (with the averaged connection coefficients of the paper's
+  overrides);
+* a uniform state in a linear flow changes by the closed forms of Step 1
+  (dE = -dt E tr A, dF_k = -dt (F_k tr A + A_ik F_i)), and the advective face flux takes the
+  reconstructed state on the upwind side of v;
+* the intergroup fluxes of Step 2 telescope: the group sum of the energy change is the
+  compression work -dt <v^i_{;j}> P^j_i alone; a single occupied group feeds the group above
+  it under compression and the group below it under expansion, by the upwind flux worked by
+  hand; a spectral density linear in frequency is reconstructed exactly at interior group
+  edges;
+* uniform isotropic radiation in a homologous expansion loses energy at the adiabatic rate
+  4 a E (E ~ V^(-4/3)), 3 a E in Step 1 and a E in Step 2 on the state Step 1 left, on
+  Cartesian and spherical grids;
+* the first-order lab-frame transformation of isotropic and of free-streaming radiation.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import m1_oracle as orc
+
+
+def face_coords(p, d):
+    """Coordinates (x0, x1, x2) of the d-face centres, arrays of shape face_shape(p, d)."""
+    n = list(p.n) + [1] * (3 - len(p.n))
+    axes = []
+    for e in range(3):
+        dx = (p.hi[e] - p.lo[e]) / n[e]
+        if e == d:
+            axes.append(p.lo[e] + dx * np.arange(n[e] + 1))
+        else:
+            axes.append(p.lo[e] + dx * (np.arange(n[e]) + 0.5))
+    X2, X1, X0 = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return X0, X1, X2
+
+
+def vfield(p, fn):
+    """Face velocities from fn(x0, x1, x2) -> the ndim coordinate components."""
+    out = []
+    for d in range(p.ndim):
+        X = face_coords(p, d)
+        comps = fn(*X)
+        out.append(np.stack([np.broadcast_to(comps[k], X[0].shape) for k in range(p.ndim)]))
+    return out
+
+
+def zero_v(p):
+    return vfield(p, lambda x0, x1, x2: [0.0 * x0] * p.ndim)
+
+
+def random_state(p, rng, fmax=0.9):
+    s = p.shape
+    E = np.exp(rng.normal(0.0, 0.7, s))
+    d = rng.normal(size=(p.ndim,) + s)
+    d /= np.linalg.norm(d, axis=0)
+    f = fmax * rng.random(s)
+    F = [np.ascontiguousarray(f * p.c * E * d[k]) for k in range(p.ndim)]
+    return E, F
+
+
+def scale_factors(p):
+    """Cell-centred scale factors [zones..., 3] from the oracle's geometry."""
+    return orc.geometry(p)["hcell"]
+
+
+def levermore_P(E, Fhat, c=1.0):
+    """Physical pressure tensor of one state, the Levermore closure written out here."""
+    f = np.asarray(Fhat, dtype=float) / (c * E)
+    f2 = min(float(f @ f), 1.0)
+    chi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * math.sqrt(4.0 - 3.0 * f2))
+    P = E * (1.0 - chi) / 2.0 * np.eye(3)
+    fm = math.sqrt(float(f @ f))
+    if fm > 0:
+        n = f / fm
+        P += E * (3.0 * chi - 1.0) / 2.0 * np.outer(n, n)
+    return P
+
+
+# --------------------------------------------------------------------------------------
+# v = 0
+# --------------------------------------------------------------------------------------
+def _problems():
+    cases = []
+    p = orc.Problem(ndim=2, n=(12, 10), G=5, bc_lo=(orc.PERIODIC,) * 3, bc_hi=(orc.PERIODIC,) * 3)
+    cases.append((p, None))
+    p = orc.Problem(ndim=3, n=(7, 6, 5), G=4, bc_lo=(orc.OUTFLOW, orc.REFLECT, orc.OUTFLOW),
+                    bc_hi=(orc.REFLECT, orc.OUTFLOW, orc.OUTFLOW))
+    cases.append((p, None))
+    p = orc.Problem(ndim=2, n=(8, 6), G=3, coord=orc.SPH_LOGR, lo=(0.0, 0.0, 0.0), hi=(math.log(20.0), math.pi, 1.0),
+                    bc_lo=(orc.INFLOW, orc.AXIS, orc.OUTFLOW), bc_hi=(orc.OUTFLOW, orc.AXIS, orc.OUTFLOW))
+    inflow = np.zeros((3, 3))
+    inflow[:, 0] = [1.0, 0.5, 0.2]
+    inflow[:, 1] = 0.5 * inflow[:, 0]
+    cases.append((p, inflow))
+    p = orc.Problem(ndim=3, n=(6, 4, 4), G=2, coord=orc.SPH_LOGR, lo=(0.0, 0.0, 0.0),
+                    hi=(math.log(10.0), math.pi, 2 * math.pi), bc_lo=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC),
+                    bc_hi=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC))
+    cases.append((p, None))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_zero_velocity_is_the_static_step(case):
+    p, inflow = _problems()[case]
+    rng = np.random.default_rng(case)
+    E, F = random_state(p, rng)
+    kap = np.exp(rng.normal(0.0, 2.0, p.shape))
+    sig = 0.5 * kap
+    B = rng.random(p.shape)
+    dt = orc.max_dt(p, 0.3)
+    nu = np.linspace(0.0, 5.0, p.G + 1)
+    a = orc.run(p, E, F, kap, sig, B, dt, 3, inflow=inflow, want_dEm=True)
+    b = orc.run_v(p, E, F, kap, sig, B, zero_v(p), nu, dt, 3, inflow=inflow, want_dEm=True)
+    assert np.array_equal(a[0], b[0])
+    for k in range(p.ndim):
+        assert np.array_equal(a[1][k], b[1][k])
+    assert a[2] == b[2]
+    assert np.array_equal(a[3], b[3])
+
+
+def test_velocity_refuses_ssprk2_and_bad_edges():
+    p = orc.Problem(ndim=1, n=(6,), G=3, integrator=orc.SSPRK2)
+    E, F = random_state(p, np.random.default_rng(0))
+    z = np.zeros(p.shape)
+    with pytest.raises(ValueError):
+        orc.run_v(p, E, F, z, z, z, zero_v(p), [0.0, 1.0, 2.0, 3.0], 1e-3)
+    p = orc.Problem(ndim=1, n=(6,), G=3)
+    for nu in ([0.0, 1.0, 1.0, 3.0], [0.0, 1.0, 2.0, np.inf], [-1.0, 1.0, 2.0, 3.0]):
+        with pytest.raises(ValueError):
+            orc.run_v(p, E, F, z, z, z, zero_v(p), nu, 1e-3)
+
+
+# --------------------------------------------------------------------------------------
+# velocity gradient
+# --------------------------------------------------------------------------------------
+def test_linear_cartesian_field_gradient():
+    p = orc.Problem(ndim=3, n=(5, 4, 3), G=1, hi=(1.0, 0.8, 0.6))
+    A = np.array([[0.3, -1.2, 0.7], [2.1, -0.4, 0.9], [-0.6, 1.5, 0.25]])
+    b = np.array([0.1, -0.2, 0.05])
+    vf = vfield(p, lambda x0, x1, x2: [A[i, 0] * x0 + A[i, 1] * x1 + A[i, 2] * x2 + b[i] for i in range(3)])
+    Vg, vb = orc.vel_grad(p, vf)
+    assert np.allclose(Vg, np.broadcast_to(A, Vg.shape), rtol=0, atol=1e-13)
+    X = face_coords(orc.Problem(ndim=3, n=(5, 4, 3), G=1, hi=(1.0, 0.8, 0.6)), -1)   # zone centres
+    for i in range(3):
+        expect = A[i, 0] * X[0] + A[i, 1] * X[1] + A[i, 2] * X[2] + b[i]
+        assert np.allclose(vb[..., i], expect, rtol=0, atol=1e-14)
+
+
+def _sphere(ndim, n):
+    hi = (math.log(10.0), math.pi, 2 * math.pi)
+    return orc.Problem(ndim=ndim, n=n, G=1, coord=orc.SPH_LOGR, lo=(0.0, 0.0, 0.0), hi=hi,
+                       bc_lo=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC), bc_hi=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC))
+
+
+@pytest.mark.parametrize("ndim,n", [(1, (7,)), (2, (6, 5)), (3, (5, 6, 4))])
+def test_spherical_homologous_flow_gradient_is_isotropic(ndim, n):
+    # v^_r = a r: the coordinate component v^1 = d(ln r)/dt = a everywhere
+    p = _sphere(ndim, n)
+    a = -0.37
+    vf = vfield(p, lambda x0, x1, x2: [a + 0 * x0] + [0 * x0] * (ndim - 1))
+    Vg, vb = orc.vel_grad(p, vf)
+    assert np.allclose(Vg, a * np.eye(3), rtol=0, atol=1e-14)
+    assert np.allclose(vb[..., 0], a, rtol=0, atol=1e-15)
+
+
+def test_spherical_rigid_rotation_has_no_strain():
+    # v^_phi = Omega r sin(theta): v^3 = Omega; trace 0 and g_ii V^i_j + g_jj V^j_i = 0
+    p = _sphere(3, (5, 6, 4))
+    Om = 0.8
+    vf = vfield(p, lambda x0, x1, x2: [0 * x0, 0 * x0, Om + 0 * x0])
+    Vg, _ = orc.vel_grad(p, vf)
+    h = scale_factors(p)
+    g = h ** 2
+    assert np.allclose(np.trace(Vg, axis1=-2, axis2=-1), 0.0, atol=1e-14)
+    for i in range(3):
+        for j in range(3):
+            s = g[..., i] * Vg[..., i, j] + g[..., j] * Vg[..., j, i]
+            assert np.allclose(s, 0.0, atol=1e-12 * np.abs(g[..., i] * Vg[..., i, j]).max() + 1e-14), (i, j)
+    # and it is a rotation: the (r, phi) entries are nonzero
+    assert np.abs(Vg[..., 2, 0]).min() > 0.5 * Om
+
+
+def test_spherical_radial_field_linear_in_ln_r():
+    # v^1 = alpha + beta x1 (x1 = ln r): <v^1_{,1}> = beta, and <v^1> is the profile's value at
+    # the zone's volume centroid <x1> = (b e^{3b} - a e^{3a}) / (e^{3b} - e^{3a}) - 1/3 (weight
+    # r^3 = e^{3 x1}); the diagonal adds <Gamma^1_11> = <Gamma^2_21> = <Gamma^3_31> = 1 times <v^1>
+    n = 6
+    p = _sphere(1, (n,))
+    alpha, beta = 0.2, -0.45
+    vf = vfield(p, lambda x0, x1, x2: [alpha + beta * x0])
+    Vg, vb = orc.vel_grad(p, vf)
+    edges = np.linspace(0.0, math.log(10.0), n + 1)
+    a, b = edges[:-1], edges[1:]
+    cen = (b * np.exp(3 * b) - a * np.exp(3 * a)) / (np.exp(3 * b) - np.exp(3 * a)) - 1.0 / 3.0
+    vbar = alpha + beta * cen
+    assert np.allclose(vb[0, 0, :, 0], vbar, rtol=0, atol=1e-14)
+    assert np.allclose(Vg[0, 0, :, 0, 0], beta + vbar, rtol=0, atol=1e-13)
+    assert np.allclose(Vg[0, 0, :, 1, 1], vbar, rtol=0, atol=1e-14)
+    assert np.allclose(Vg[0, 0, :, 2, 2], vbar, rtol=0, atol=1e-14)
+
+
+# --------------------------------------------------------------------------------------
+# Step 1
+# --------------------------------------------------------------------------------------
+def test_uniform_state_in_linear_flow_step1_closed_form():
+    p = orc.Problem(ndim=3, n=(5, 4, 6), G=2, hi=(1.0, 0.8, 1.2))
+    A = np.array([[0.3, -1.2, 0.7], [2.1, -0.4, 0.9], [-0.6, 1.5, 0.25]])   # not symmetric
+    vf = vfield(p, lambda x0, x1, x2: [A[i, 0] * x0 + A[i, 1] * x1 + A[i, 2] * x2 for i in range(3)])
+    E0 = np.array([1.3, 0.4])
+    F0 = np.array([[0.2, -0.1], [0.3, 0.05], [-0.4, 0.1]])   # [k][g]
+    E = np.broadcast_to(E0, p.shape).copy()
+    F = [np.broadcast_to(F0[k], p.shape).copy() for k in range(3)]
+    z = np.zeros(p.shape)
+    dt = 1e-3
+    Eo, Fo = orc.explicit_v(p, E, F, z, z, vf, dt)
+    tr = np.trace(A)
+    assert np.allclose(Eo, E * (1.0 - dt * tr), rtol=1e-13, atol=0)
+    for k in range(3):
+        expect = F0[k] - dt * (F0[k] * tr + sum(A[i, k] * F0[i] for i in range(3)))
+        assert np.allclose(Fo[k], np.broadcast_to(expect, p.shape), rtol=1e-12, atol=1e-15), k
+
+
+@pytest.mark.parametrize("v", [0.11, -0.07])
+def test_advective_flux_takes_the_upwind_face_state(v):
+    n = 12
+    p = orc.Problem(ndim=1, n=(n,), G=2)
+    rng = np.random.default_rng(5)
+    E, F = random_state(p, rng, fmax=0.6)
+    z = np.zeros(p.shape)
+    vf = vfield(p, lambda x0, x1, x2: [v + 0 * x0])
+    dt, dx = 1e-3, 1.0 / n
+    E0, F0 = orc.explicit(p, E, F, z, z, dt)
+    E1, F1 = orc.explicit_v(p, E, F, z, z, vf, dt)
+    fs = orc.faces(p, E, F, 0)[0, 0]          # [n, G, 2, 2]: zone, group, side, component
+    for i in range(1, n - 1):
+        for comp, (a0, a1) in enumerate(((E0, E1), (F0[0], F1[0]))):
+            up_hi = fs[i, :, 1, comp] if v >= 0 else fs[i + 1, :, 0, comp]
+            up_lo = fs[i - 1, :, 1, comp] if v >= 0 else fs[i, :, 0, comp]
+            expect = -dt * v * (up_hi - up_lo) / dx
+            got = a1[0, 0, i] - a0[0, 0, i]
+            assert np.allclose(got, expect, rtol=1e-9, atol=1e-15), (i, comp)
+
+
+@pytest.mark.parametrize("a", [0.23, -0.31])
+def test_spherical_uniform_expansion_flux_rows(a):
+    # 1-D spherical, v^1 = a (v^_r = a r): <v^1_{,1}> = 0, so the velocity terms of Step 1
+    # reduce to the divergence of the advective fluxes, the connection part of (v^i F_k)_{;i}
+    # cancelling the connection part of <v^i_{;k}> F_i (the connection coefficients are
+    # symmetric in their lower indices): dU = -dt a (A_+ U_up(+) - A_- U_up(-)) / V
+    n = 8
+    p = _sphere(1, (n,))
+    p.G = 2
+    rng = np.random.default_rng(2)
+    E, Fh = random_state(p, rng, fmax=0.7)
+    h = scale_factors(p)
+    F = [np.ascontiguousarray(Fh[0] * h[..., 0][..., None])]
+    z = np.zeros(p.shape)
+    vf = vfield(p, lambda x0, x1, x2: [a + 0 * x0])
+    dt = 1e-4
+    E0, F0 = orc.explicit(p, E, F, z, z, dt)
+    E1, F1 = orc.explicit_v(p, E, F, z, z, vf, dt)
+    geo = orc.geometry(p)
+    A = geo["area"][0][0, 0]          # [n + 1]
+    V = geo["vol"][0, 0]
+    fs = orc.faces(p, E, F, 0)[0, 0]   # [n, G, 2, 2]
+    for i in range(1, n - 1):
+        for comp, (u0, u1) in enumerate(((E0, E1), (F0[0], F1[0]))):
+            up_hi = fs[i, :, 1, comp] if a >= 0 else fs[i + 1, :, 0, comp]
+            up_lo = fs[i - 1, :, 1, comp] if a >= 0 else fs[i, :, 0, comp]
+            expect = -dt * a * (A[i + 1] * up_hi - A[i] * up_lo) / V[i]
+            got = u1[0, 0, i] - u0[0, 0, i]
+            assert np.allclose(got, expect, rtol=1e-8, atol=1e-15 * np.abs(u0[0, 0, i]).max()), (i, comp)
+
+
+# --------------------------------------------------------------------------------------
+# Step 2
+# --------------------------------------------------------------------------------------
+def test_intergroup_fluxes_telescope_to_the_compression_work():
+    p = orc.Problem(ndim=2, n=(6, 5), G=7, hi=(1.0, 0.9, 1.0))
+    rng = np.random.default_rng(3)
+    E, F = random_state(p, rng)
+    vf = [rng.normal(0.0, 0.3, (2,) + orc.face_shape(p, d)) for d in range(2)]
+    nu = np.concatenate([[0.0], np.cumsum(rng.uniform(0.5, 2.0, p.G))])
+    dt = 2e-3
+    Eo = orc.freq_adv(p, E, F, vf, nu, dt)
+    Vg, _ = orc.vel_grad(p, vf)
+    for k in range(p.shape[1]):
+        for i in range(p.shape[2]):
+            work = 0.0
+            for g in range(p.G):
+                Fh = [F[0][0, k, i, g], F[1][0, k, i, g], 0.0]
+                P = levermore_P(E[0, k, i, g], Fh)
+                work += float(np.sum(Vg[0, k, i] * P.T))       # sum_ij V^i_j P^j_i
+            got = float(np.sum(Eo[0, k, i] - E[0, k, i]))
+            scale = dt * np.abs(Vg[0, k, i]).max() * E[0, k, i].sum()
+            assert abs(got - (-dt * work)) <= 1e-12 * scale, (k, i)
+    # the intergroup part moves energy: some group changes by more than its work term
+    assert np.abs(Eo - E).max() > 0
+
+
+def test_spherical_compression_work_uses_the_mixed_pressure():
+    # 3-D spherical, random velocity and radiation: the group sum of the Step 2 change is
+    # -dt sum_ij <v^i_{;j}> P^j_i with the mixed components P^j_i = g_ik P^{jk}
+    # = P^^{ji} h_i / h_j (physical P^ from the closure, cell-centred h)
+    p = orc.Problem(ndim=3, n=(4, 5, 4), G=4, coord=orc.SPH_LOGR, lo=(0.0, 0.0, 0.0),
+                    hi=(math.log(10.0), math.pi, 2 * math.pi), bc_lo=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC),
+                    bc_hi=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC))
+    rng = np.random.default_rng(8)
+    E, Fhat = random_state(p, rng)
+    h = scale_factors(p)
+    F = [np.ascontiguousarray(Fhat[k] * h[..., k][..., None]) for k in range(3)]   # covariant
+    vf = [rng.normal(0.0, 0.3, (3,) + orc.face_shape(p, d)) for d in range(3)]
+    nu = np.linspace(0.0, 4.0, p.G + 1)
+    dt = 1e-3
+    Eo = orc.freq_adv(p, E, F, vf, nu, dt)
+    Vg, _ = orc.vel_grad(p, vf)
+    for z in np.ndindex(*p.shape[:3]):
+        hz = h[z]
+        work = 0.0
+        for g in range(p.G):
+            P = levermore_P(E[z + (g,)], [Fhat[k][z + (g,)] for k in range(3)])
+            for i in range(3):
+                for j in range(3):
+                    work += Vg[z][i, j] * P[j, i] * hz[i] / hz[j]
+        got = float(np.sum(Eo[z] - E[z]))
+        scale = dt * np.abs(Vg[z]).max() * E[z].sum() * (hz.max() / hz.min())
+        assert abs(got + dt * work) <= 1e-12 * scale, z
+
+
+@pytest.mark.parametrize("D", [-2.0, 3.0])
+def test_single_occupied_group_is_donor_upwind(D):
+    # 1-D Cartesian v = D x (v^x_{,x} = D), isotropic radiation (F = 0, P^x_x = E/3) in group g0
+    n, G, g0 = 4, 6, 3
+    p = orc.Problem(ndim=1, n=(n,), G=G)
+    E = np.zeros(p.shape)
+    E[..., g0] = 2.5
+    F = [np.zeros(p.shape)]
+    vf = vfield(p, lambda x0, x1, x2: [D * x0])
+    nu = np.array([0.0, 1.0, 2.5, 3.0, 4.5, 6.0, 8.0])
+    dt = 1e-3
+    Eo = orc.freq_adv(p, E, F, vf, nu, dt)
+    e, dn = 2.5, nu[g0 + 1] - nu[g0]
+    X = D * e / 3.0 / dn                      # the group's spectral density of V^x_x P^x_x
+    dE = Eo - E
+    if D < 0:   # compression: donor g0 feeds g0 + 1 through the edge nu_{g0+1/2}
+        phi = nu[g0 + 1] * X
+        assert np.allclose(dE[..., g0 + 1], -dt * phi, rtol=1e-14)
+        assert np.allclose(dE[..., g0], dt * (phi - D * e / 3.0), rtol=1e-14)
+        assert np.all(dE[..., g0 + 1] > 0)
+        untouched = [g for g in range(G) if g not in (g0, g0 + 1)]
+    else:       # expansion: g0 feeds g0 - 1 through nu_{g0-1/2}
+        phi = nu[g0] * X
+        assert np.allclose(dE[..., g0 - 1], dt * phi, rtol=1e-14)
+        assert np.allclose(dE[..., g0], dt * (-phi - D * e / 3.0), rtol=1e-14)
+        assert np.all(dE[..., g0 - 1] > 0)
+        untouched = [g for g in range(G) if g not in (g0, g0 - 1)]
+    assert np.all(dE[..., untouched] == 0.0)
+
+
+@pytest.mark.parametrize("D", [-1.7, 1.3])
+def test_linear_spectral_density_is_exact_at_interior_edges(D):
+    # rho(nu) = alpha + beta nu, E_g = dnu_g rho(nu_c); isotropic radiation in v = D x: every
+    # interior edge flux from the left (compression, D < 0) or the right (expansion), and both
+    # reconstructions exact at edges 2..G-2: Phi_e = nu_e (D/3) rho(nu_e)
+    G = 9
+    rng = np.random.default_rng(11)
+    nu = np.concatenate([[0.5], 0.5 + np.cumsum(rng.uniform(0.4, 1.6, G))])
+    nuc = 0.5 * (nu[1:] + nu[:-1])
+    dnu = np.diff(nu)
+    alpha, beta = 2.0, 0.35
+    p = orc.Problem(ndim=1, n=(3,), G=G)
+    E = np.broadcast_to(dnu * (alpha + beta * nuc), p.shape).copy()
+    F = [np.zeros(p.shape)]
+    vf = vfield(p, lambda x0, x1, x2: [D * x0])
+    dt = 1e-3
+    Eo = orc.freq_adv(p, E, F, vf, nu, dt)
+    # recover the edge fluxes from the energy changes: Phi_{g+1} = Phi_g + dE_g / dt + V P_g
+    dE = (Eo - E)[0, 0, 1]
+    vP = D * E[0, 0, 1] / 3.0
+    phi = np.zeros(G + 1)
+    for g in range(G):
+        phi[g + 1] = phi[g] + dE[g] / dt + vP[g]
+    for e in range(2, G - 1):
+        expect = nu[e] * (D / 3.0) * (alpha + beta * nu[e])
+        assert phi[e] == pytest.approx(expect, rel=1e-9), e
+    assert abs(phi[G]) <= 1e-9 * np.abs(phi).max()          # closed top edge
+
+
+# --------------------------------------------------------------------------------------
+# Steps 1 and 2 together: adiabatic expansion
+# --------------------------------------------------------------------------------------
+def _adiabatic(p, vf, a):
+    G = p.G
+    Eg = np.linspace(1.0, 2.0, G)
+    E = np.broadcast_to(Eg, p.shape).copy()
+    F = [np.zeros(p.shape) for _ in range(p.ndim)]
+    z = np.zeros(p.shape)
+    nu = np.linspace(0.0, 3.0, G + 1)
+    dt = 1e-4
+    Eo, Fo, _ = orc.run_v(p, E, F, z, z, z, vf, nu, dt, 1)
+    tot = Eo.sum(axis=-1)
+    # Step 1 takes 3 a dt E (advection through the expanding zone), Step 2 the work a dt E on
+    # the state Step 1 left
+    assert np.allclose(tot, Eg.sum() * (1.0 - 3.0 * a * dt) * (1.0 - a * dt), rtol=1e-12, atol=0)
+    for f in Fo:
+        assert np.abs(f).max() <= 1e-12 * Eg.sum()
+
+
+def test_adiabatic_expansion_cartesian():
+    p = orc.Problem(ndim=3, n=(4, 5, 3), G=4)
+    a = 0.9
+    vf = vfield(p, lambda x0, x1, x2: [a * (x0 - 0.5), a * (x1 - 0.5), a * (x2 - 0.5)])
+    _adiabatic(p, vf, a)
+
+
+@pytest.mark.parametrize("ndim,n", [(1, (6,)), (2, (5, 4))])
+def test_adiabatic_expansion_spherical(ndim, n):
+    p = orc.Problem(ndim=ndim, n=n, G=3, coord=orc.SPH_LOGR, lo=(0.0, 0.0, 0.0),
+                    hi=(math.log(10.0), math.pi, 2 * math.pi), bc_lo=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC),
+                    bc_hi=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC))
+    a = 0.6
+    vf = vfield(p, lambda x0, x1, x2: [a + 0 * x0] + [0 * x0] * (ndim - 1))
+    _adiabatic(p, vf, a)
+
+
+# --------------------------------------------------------------------------------------
+# lab frame
+# --------------------------------------------------------------------------------------
+def test_lab_frame_isotropic_and_free_streaming():
+    p = orc.Problem(ndim=3, n=(3, 2, 2), G=2, c=2.0)
+    v = np.array([0.1, -0.05, 0.02])
+    vf = vfield(p, lambda x0, x1, x2: [v[0] + 0 * x0, v[1] + 0 * x0, v[2] + 0 * x0])
+    Eg = np.array([1.5, 0.5])
+    E = np.broadcast_to(Eg, p.shape).copy()
+    # isotropic: E_lab = E, F_lab = (4/3) v E
+    F = [np.zeros(p.shape) for _ in range(3)]
+    El, Fl = orc.lab_frame(p, E, F, vf)
+    assert np.allclose(El, Eg.sum(), rtol=1e-15)
+    for k in range(3):
+        assert np.allclose(Fl[k], 4.0 / 3.0 * v[k] * Eg.sum(), rtol=1e-14)
+    # free streaming along n: F = c E n, P = E n n -> E_lab = E + 2 (v.n) E / c,
+    # F_lab = c E n + v E + (v.n) E n
+    nvec = np.array([0.6, 0.0, 0.8])
+    F = [np.broadcast_to(p.c * Eg * nvec[k], p.shape).copy() for k in range(3)]
+    El, Fl = orc.lab_frame(p, E, F, vf)
+    vn = float(v @ nvec)
+    assert np.allclose(El, Eg.sum() * (1.0 + 2.0 * vn / p.c), rtol=1e-14)
+    for k in range(3):
+        expect = Eg.sum() * (p.c * nvec[k] + v[k] + vn * nvec[k])
+        assert np.allclose(Fl[k], expect, rtol=1e-13, atol=1e-15)
