@@ -253,6 +253,54 @@ int fornax_m1_matter_source(fornax_m1_ctx *ctx, fornax_m1_state *inout, const vo
                             const fornax_m1_matter *m, double dt, double *dE_matter, int32_t *iters,
                             void *stream);
 
+/* ---- Velocity-dependent terms (prescribed velocity) ----
+ * The comoving-frame moment equations to first order in v/c (Formulation of the Equations,
+ * eq:rad_system), with the velocity given on the zone faces instead of by a hydrodynamics
+ * solve.  v[d], d < ndim: DEVICE array of the context's element type holding the coordinate
+ * (contravariant) components v^0..v^{ndim-1} on the d-faces, layout [ndim][faces_d] with faces_d
+ * over (k, j, i), the d index in 0..n[d] (face i-1/2 of zone i), x fastest.  On spherical grids
+ * v^1 = v_r / r (x1 = ln r), v^2 = v_theta / r, v^3 = v_phi / (r sin theta).  The caller owns
+ * the arrays; they are read, never written. */
+typedef struct { const void *v[3]; } fornax_m1_velocity;
+
+/* Group edges in frequency for the intergroup fluxes of the velocity step: HOST array
+ * [ngroups + 1], increasing, finite, nu_edge[0] >= 0 (only ratios matter), copied into the
+ * context (synchronous).  EINVAL for a bad table, ENOMEM. */
+int fornax_m1_set_group_edges(fornax_m1_ctx *ctx, const double *nu_edge);
+
+/* One step U^n -> U^{n+1} with the velocity terms (Algorithmic Steps 1 to 4, Euler push, matter
+ * fixed):
+ *   Step 1: the transport of fornax_m1_step plus the advective fluxes (v E), (v F_k) on every
+ *           face, v^d times the reconstructed state on the upwind side of the face's normal
+ *           component (Riemann Solvers subsection), and in the flux rows the connection part of
+ *           (v^i F_k)_{;i} and -<v^i_{;k}> F_i (eq:rad_mom2);
+ *   Step 2: E_g <- E_g + dt (Phi_{g+1/2} - Phi_{g-1/2} - <v^i_{;j}> P^j_{g i}) (eq:freq_adv_system),
+ *           Phi_{g-1/2} = nu_{g-1/2} (X-_{g-1} at its upper edge + X+_g at its lower edge), X-+
+ *           the parts of sum_ij <v^i_{;j}> P^j_i / dnu_g with <v^i_{;j}> < 0 and >= 0, linear in
+ *           nu across each group with minmod-limited slopes (zero in the first and last group),
+ *           Phi = 0 at both ends of the frequency range; no intergroup term in the flux rows
+ *           (no closure for the third moment);
+ *   Steps 3, 4: the interaction update of fornax_m1_step on the state after Step 2.
+ * <v^i_{;j}> = <v^i_{,j}> + <Gamma^i_{jk}> <v^k>, each coordinate component linear across the
+ * zone (<v^k>: its value at the volume centroid).  dE_matter and the diagnostics as for
+ * fornax_m1_step, against the state after Step 2.  Two launches, in place on `out` between
+ * them.  Errors: EINVAL (also without group edges, or a null v[d]), ECFL, EUNSUPPORTED for the
+ * SSPRK2 integrator, the PPM reconstruction, the M1 wavespeeds or ngroups > 256, EDEVICE.
+ * Stable while dt |v| nu_{g+1/2} <~ dnu (frequency CFL, not checked) and |v| < c. */
+int fornax_m1_step_velocity(fornax_m1_ctx *ctx, const fornax_m1_state *in, fornax_m1_state *out,
+                            const fornax_m1_coeffs *cf, const double *inflow,
+                            const fornax_m1_velocity *vel, double dt, const fornax_m1_diag *diag,
+                            void *stream);
+
+/* Group-summed radiation energy and flux of every zone in the laboratory frame to first order
+ * in v/c: with the physical velocity v^_k = h_k <v^k> (cell-centred h, <v^k> as above),
+ *   E_lab = sum_g (E_g + 2 v^ . F^_g / c^2),  F^_lab = sum_g (F^_g + v^ E_g + v^ . P^_g),
+ * physical components (the transformation behind the lab-frame flux continuity at a
+ * transparent shock).  E_lab [nzones], F_lab[k] [nzones] for k < ndim: device arrays of
+ * doubles.  EINVAL for bad pointers. */
+int fornax_m1_lab_frame(fornax_m1_ctx *ctx, const fornax_m1_state *in, const fornax_m1_velocity *vel,
+                        double *E_lab, double *F_lab[3], void *stream);
+
 /* Measurement utility (not part of the method): plain device-to-device copy of `nbytes`
  * (multiple of 16, 16-byte aligned pointers) with the library's own kernel, used to scale
  * hardware byte counters and to measure achievable HBM bandwidth. */

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfornax_m1.so")
 SOURCES = ["m1_host.cpp", "m1_kernels.hip", "m1_step.hip", "m1_step_rows.hip", "m1_step_3d.hip", "m1_adjoint.hip",
-           "m1_matter.hip"]
+           "m1_matter.hip", "m1_velocity.hip"]
 ARCH = "gfx950"
 
 

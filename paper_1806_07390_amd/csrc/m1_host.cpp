@@ -576,6 +576,7 @@ int fornax_m1_destroy(fornax_m1_ctx* ctx) {
     if (ctx->adj_gbuf[d]) (void)hipFree(ctx->adj_gbuf[d]);
   if (ctx->stage_mem) (void)hipFree(ctx->stage_mem);
   if (ctx->mat_tab) (void)hipFree(ctx->mat_tab);
+  if (ctx->vel_nu) (void)hipFree(ctx->vel_nu);
   delete ctx;
   return FORNAX_OK;
 }
@@ -718,6 +719,60 @@ int fornax_m1_set_matter_model(fornax_m1_ctx* ctx, const fornax_m1_matter_model*
   ctx->mat_tol = mm->tol;
   ctx->mat_maxn = mm->max_newton;
   return FORNAX_OK;
+}
+
+// ---- velocity-dependent terms ----
+int fornax_m1_set_group_edges(fornax_m1_ctx* ctx, const double* nu_edge) {
+  if (!ctx || !nu_edge) return FORNAX_EINVAL;
+  const int G = ctx->desc.ngroups;
+  if (!(nu_edge[0] >= 0.0)) return FORNAX_EINVAL;
+  for (int g = 0; g < G; ++g)
+    if (!(nu_edge[g + 1] > nu_edge[g]) || !std::isfinite(nu_edge[g + 1])) return FORNAX_EINVAL;
+  if (!ctx->vel_nu && hipMalloc((void**)&ctx->vel_nu, (size_t)(G + 1) * sizeof(double)) != hipSuccess) {
+    ctx->vel_nu = nullptr;
+    return FORNAX_ENOMEM;
+  }
+  if (hipMemcpy(ctx->vel_nu, nu_edge, (size_t)(G + 1) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return FORNAX_EDEVICE;
+  return FORNAX_OK;
+}
+
+static int check_velocity(const fornax_m1_ctx* ctx, const fornax_m1_velocity* vel) {
+  if (!vel) return FORNAX_EINVAL;
+  const size_t al = ctx->desc.precision == FORNAX_FP64 ? 8 : 4;
+  for (int d = 0; d < ctx->desc.ndim; ++d)
+    if (!vel->v[d] || !aligned(vel->v[d], al)) return FORNAX_EINVAL;
+  return FORNAX_OK;
+}
+
+int fornax_m1_step_velocity(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
+                            const fornax_m1_coeffs* cf, const double* inflow, const fornax_m1_velocity* vel, double dt,
+                            const fornax_m1_diag* diag, void* stream) {
+  if (!ctx) return FORNAX_EINVAL;
+  int rc;
+  if ((rc = check_state(ctx, in)) || (rc = check_state(ctx, out)) || (rc = check_coeffs(ctx, cf)) ||
+      (rc = check_velocity(ctx, vel)))
+    return rc;
+  if (!ctx->vel_nu) return FORNAX_EINVAL;
+  if (overlaps(ctx, in, out)) return FORNAX_EINVAL;
+  if (needs_inflow(ctx->desc) != (inflow != nullptr)) return FORNAX_EINVAL;
+  const fornax_m1_desc& D = ctx->desc;
+  if (D.integrator != FORNAX_EULER || D.limiter == FORNAX_LIMITER_PPM || D.wavespeed != FORNAX_WAVESPEED_LIGHT ||
+      D.ngroups > fm1::BLOCK)
+    return FORNAX_EUNSUPPORTED;
+  if (!(dt > 0.0) || dt > ctx->max_dt1 * (1.0 + 1e-12)) return FORNAX_ECFL;
+  return fm1_launch_step_velocity(ctx, in, out, cf, inflow, vel, dt, diag, (hipStream_t)stream);
+}
+
+int fornax_m1_lab_frame(fornax_m1_ctx* ctx, const fornax_m1_state* in, const fornax_m1_velocity* vel, double* E_lab,
+                        double* F_lab[3], void* stream) {
+  if (!ctx || !E_lab || !F_lab) return FORNAX_EINVAL;
+  int rc;
+  if ((rc = check_state(ctx, in)) || (rc = check_velocity(ctx, vel))) return rc;
+  if (!aligned(E_lab, 8)) return FORNAX_EINVAL;
+  for (int d = 0; d < ctx->desc.ndim; ++d)
+    if (!F_lab[d] || !aligned(F_lab[d], 8)) return FORNAX_EINVAL;
+  return fm1_launch_lab_frame(ctx, in, vel, E_lab, F_lab, (hipStream_t)stream);
 }
 
 static int check_matter(const fornax_m1_ctx* ctx, const fornax_m1_matter* m) {

@@ -203,6 +203,8 @@ struct fornax_m1_ctx {
   double* mat_tab;
   double mat_a, mat_tol;
   int mat_maxn;
+  // group edges of the velocity step (fornax_m1_set_group_edges): device table [G + 1]
+  double* vel_nu;
 };
 
 // Scratch memory of one step launch: per-block diagnostics partials, the dE_matter partials of
@@ -237,8 +239,23 @@ int fm1_launch_adjoint(fornax_m1_ctx* ctx, const fornax_m1_state* Un, const forn
                        const double* inflow, double dt, const fornax_m1_state* lam_np1,
                        fornax_m1_state* lam_n, void* dkappa, hipStream_t stream);
 int fm1_launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t stream);
+// the diagnostics totals of a step from nb per-block partials (fixed order, deterministic)
+int fm1_launch_finalize(const double* p_energy, const double* p_maxf2, const int* p_nun, const int* p_nnp, int nb,
+                        const fornax_m1_diag* diag, hipStream_t stream);
 int fm1_launch_transport(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
                          const fornax_m1_coeffs* cf, const double* inflow, double dt, hipStream_t stream);
+// m1_velocity.hip
+int fm1_launch_step_velocity(fornax_m1_ctx* ctx, const fornax_m1_state* in, fornax_m1_state* out,
+                             const fornax_m1_coeffs* cf, const double* inflow, const fornax_m1_velocity* vel,
+                             double dt, const fornax_m1_diag* diag, hipStream_t stream);
+int fm1_launch_lab_frame(fornax_m1_ctx* ctx, const fornax_m1_state* in, const fornax_m1_velocity* vel,
+                         double* E_lab, double* const* F_lab, hipStream_t stream);
+namespace fm1 {
+// the kernel arguments common to every step launch (m1_kernels.hip)
+template <typename S>
+void fill_args(const fornax_m1_ctx* ctx, StepArgs<S>& a, const fornax_m1_coeffs* cf, const double* inflow,
+               double dt);
+}  // namespace fm1
 // m1_matter.hip
 int fm1_launch_matter_coeffs(fornax_m1_ctx* ctx, const fornax_m1_matter* m, void* kap, void* B,
                              hipStream_t stream);

@@ -158,7 +158,7 @@ using namespace fm1;
 // ------------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------------
-namespace {
+namespace fm1 {
 
 template <typename S>
 void fill_args(const fornax_m1_ctx* ctx, StepArgs<S>& a, const fornax_m1_coeffs* cf, const double* inflow,
@@ -200,6 +200,14 @@ void fill_args(const fornax_m1_ctx* ctx, StepArgs<S>& a, const fornax_m1_coeffs*
   a.p_nun = nullptr;
   a.p_nnp = nullptr;
 }
+template void fill_args<double>(const fornax_m1_ctx*, StepArgs<double>&, const fornax_m1_coeffs*, const double*,
+                                double);
+template void fill_args<float>(const fornax_m1_ctx*, StepArgs<float>&, const fornax_m1_coeffs*, const double*,
+                               double);
+
+}  // namespace fm1
+
+namespace {
 
 template <typename S, typename R>
 int launch_step_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_m1_state* in, fornax_m1_state* out,
@@ -435,6 +443,13 @@ int fm1_launch_source(fornax_m1_ctx* ctx, fornax_m1_state* inout, const fornax_m
                       hipStream_t stream) {
   if (ctx->desc.precision == FORNAX_FP64) return launch_source_t<double>(ctx, inout, cf, dt, dEm, stream);
   return launch_source_t<float>(ctx, inout, cf, dt, dEm, stream);
+}
+
+int fm1_launch_finalize(const double* p_energy, const double* p_maxf2, const int* p_nun, const int* p_nnp, int nb,
+                        const fornax_m1_diag* diag, hipStream_t stream) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, stream, p_energy, p_maxf2, p_nun, p_nnp, nb,
+                     diag->energy_total, diag->max_f, diag->n_unrealizable, diag->n_nonpositive);
+  return hipGetLastError() == hipSuccess ? FORNAX_OK : FORNAX_EDEVICE;
 }
 
 int fm1_launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t stream) {

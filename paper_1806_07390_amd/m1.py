@@ -38,7 +38,8 @@ WAVESPEED_LIGHT, WAVESPEED_M1 = 0, 1
 EXPORTED = ["fornax_m1_create", "fornax_m1_destroy", "fornax_m1_max_dt", "fornax_m1_step", "fornax_m1_flux",
             "fornax_m1_source", "fornax_m1_adjoint", "fornax_m1_copy_probe", "fornax_m1_strerror",
             "fornax_m1_transport", "fornax_m1_set_matter_model", "fornax_m1_matter_coeffs",
-            "fornax_m1_matter_source", "fornax_m1_step_noalloc"]
+            "fornax_m1_matter_source", "fornax_m1_step_noalloc", "fornax_m1_set_group_edges",
+            "fornax_m1_step_velocity", "fornax_m1_lab_frame"]
 
 
 class Desc(ctypes.Structure):
@@ -79,6 +80,10 @@ class Matter(ctypes.Structure):
     _fields_ = [("cv", ctypes.c_void_p), ("kappa0", ctypes.c_void_p), ("T", ctypes.c_void_p)]
 
 
+class Velocity(ctypes.Structure):
+    _fields_ = [("v", ctypes.c_void_p * 3)]
+
+
 class Diag(ctypes.Structure):
     _fields_ = [("energy_total", ctypes.c_void_p), ("dE_matter", ctypes.c_void_p), ("max_f", ctypes.c_void_p),
                 ("n_unrealizable", ctypes.c_void_p), ("n_nonpositive", ctypes.c_void_p)]
@@ -103,6 +108,10 @@ _lib.fornax_m1_transport.argtypes = [_vp, _P(State), _P(State), _P(Coeffs), _vp,
 _lib.fornax_m1_set_matter_model.argtypes = [_vp, _P(MatterModel)]
 _lib.fornax_m1_matter_coeffs.argtypes = [_vp, _P(Matter), _vp, _vp, _vp]
 _lib.fornax_m1_matter_source.argtypes = [_vp, _P(State), _vp, _P(Matter), ctypes.c_double, _vp, _vp, _vp]
+_lib.fornax_m1_set_group_edges.argtypes = [_vp, _vp]
+_lib.fornax_m1_step_velocity.argtypes = [_vp, _P(State), _P(State), _P(Coeffs), _vp, _P(Velocity), ctypes.c_double,
+                                         _P(Diag), _vp]
+_lib.fornax_m1_lab_frame.argtypes = [_vp, _P(State), _P(Velocity), _vp, _vp * 3, _vp]
 _lib.fornax_m1_strerror.argtypes = [ctypes.c_int]
 _lib.fornax_m1_strerror.restype = ctypes.c_char_p
 
@@ -305,6 +314,69 @@ class Context:
         _check(_lib.fornax_m1_transport(self._h, ctypes.byref(sin), ctypes.byref(sout), ctypes.byref(cf),
                                         self._inflow(inflow), dt, _stream(stream)), "fornax_m1_transport")
         return out
+
+    # -- velocity-dependent terms -------------------------------------------------------------
+    def face_shape(self, d):
+        """Shape (n2, n1, n0) of the d-faces (the d extent n_d + 1)."""
+        s = list(self.shape[:3])
+        s[2 - d] += 1
+        return tuple(s)
+
+    def set_group_edges(self, nu_edge):
+        """Group edges in frequency for the velocity step (host array [G+1], copied)."""
+        import numpy as np
+        ne = np.ascontiguousarray(nu_edge, dtype=np.float64)
+        if ne.shape != (self.cfg.G + 1,):
+            raise ValueError(f"nu_edge needs {self.cfg.G + 1} entries")
+        _check(_lib.fornax_m1_set_group_edges(self._h, ne.ctypes.data), "fornax_m1_set_group_edges")
+
+    def _velocity(self, vf):
+        if len(vf) != self.cfg.ndim:
+            raise ValueError(f"one face-velocity tensor per active direction ({self.cfg.ndim})")
+        vel = Velocity()
+        for d, t in enumerate(vf):
+            shp = (self.cfg.ndim,) + self.face_shape(d)
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != self.dtype \
+                    or tuple(t.shape) != shp or not t.is_contiguous():
+                raise ValueError(f"face velocity {d} must be a contiguous {self.dtype} CUDA tensor {shp}")
+            vel.v[d] = t.data_ptr()
+        return vel
+
+    def step_velocity(self, E, F, kappa, sigma, B, vf, dt, out=None, inflow=None, diag=None, stream=None):
+        """One step with the velocity terms (fornax_m1_step_velocity); vf: ndim tensors
+        [ndim, *face_shape(d)] of coordinate velocity components on the d-faces."""
+        sin = self._state(E, F, "in")
+        if out is None:
+            out = self.empty_state()
+        sout = self._state(out[0], out[1], "out")
+        cf = self._coeffs(kappa, sigma, B)
+        vel = self._velocity(vf)
+        dg = None
+        if diag is not None:
+            dg = Diag()
+            dg.energy_total = _ptr(diag.get("energy_total"))
+            dg.dE_matter = _ptr(diag.get("dE_matter"))
+            dg.max_f = _ptr(diag.get("max_f"))
+            dg.n_unrealizable = _ptr(diag.get("n_unrealizable"))
+            dg.n_nonpositive = _ptr(diag.get("n_nonpositive"))
+        _check(_lib.fornax_m1_step_velocity(self._h, ctypes.byref(sin), ctypes.byref(sout), ctypes.byref(cf),
+                                            self._inflow(inflow), ctypes.byref(vel), dt,
+                                            ctypes.byref(dg) if dg is not None else None, _stream(stream)),
+               "fornax_m1_step_velocity")
+        return out
+
+    def lab_frame(self, E, F, vf, stream=None):
+        """Group-summed lab-frame energy [zones] and physical flux [ndim][zones] (float64)."""
+        sin = self._state(E, F, "in")
+        vel = self._velocity(vf)
+        El = torch.empty(self.shape[:3], dtype=torch.float64, device=self.device)
+        Fl = [torch.empty_like(El) for _ in range(self.cfg.ndim)]
+        arr = (ctypes.c_void_p * 3)()
+        for d, t in enumerate(Fl):
+            arr[d] = t.data_ptr()
+        _check(_lib.fornax_m1_lab_frame(self._h, ctypes.byref(sin), ctypes.byref(vel), El.data_ptr(), arr,
+                                        _stream(stream)), "fornax_m1_lab_frame")
+        return El, Fl
 
     # -- radiation-matter energy exchange ------------------------------------------------------
     def set_matter_model(self, nu_edge, nu_c, kg, a_rad=1.0, tol=1e-6, max_newton=30):

@@ -14,6 +14,10 @@ Workloads (sizes overridable for reduced parity cases):
   * ``adjoint2d`` 2-D periodic 256^2, 16 groups, lognormal per zone-group opacity (40 steps)
   * ``matter2d`` the ``blobs2d`` radiation with a matter temperature, heat capacity and
     opacity scale per zone (the radiation-matter energy exchange)
+
+Velocity fields for the velocity-dependent terms (``face_velocity``) hold coordinate
+components on the zone faces, ``[ndim][n2'][n1'][n0']`` per face direction (the face
+direction's extent one larger); ``velocity_edges`` gives finite group edges in frequency.
 """
 from __future__ import annotations
 
@@ -248,3 +252,50 @@ def matter2d(n=512, G=16, steps=100, seed=0, kappa_scale=1.0):
     w.kappa0 = kappa_scale * np.exp(z[2])
     w.groups = matter_groups(G)
     return w
+
+
+def face_velocity(w, amp=0.1, seed=0, noise=0.3):
+    """A smooth random velocity field on the faces of w's grid plus uncorrelated noise (so that
+    the sign of the face velocities and of their differences changes from zone to zone).
+
+    Each component u_i(x) = amp (a_i . s + b_i + 0.4 sin(2 pi k_i . s + p_i) + noise N(0, 1)) with
+    s the face position scaled to [0, 1] per axis and a, b, k, p drawn once.  Cartesian grids
+    take v^i = c u_i; spherical (ln r, theta, phi) grids v^i = c u_i / r at the face (physical
+    speeds up to about amp c, the phi one times sin theta), finite on the polar axis.
+    Returns ndim arrays, the d-th [ndim][face extents]."""
+    rng = np.random.default_rng(seed + 7919)
+    nd = w.ndim
+    n = list(w.n)
+    A = rng.uniform(-1.0, 1.0, (nd, 3))
+    b = rng.uniform(-0.5, 0.5, nd)
+    kv = rng.integers(1, 3, (nd, 3))
+    ph = rng.uniform(0.0, 2 * math.pi, nd)
+    out = []
+    for d in range(nd):
+        axes = []
+        for e in range(3):
+            dx = (w.hi[e] - w.lo[e]) / n[e]
+            if e == d:
+                x = w.lo[e] + dx * np.arange(n[e] + 1)
+            else:
+                x = w.lo[e] + dx * (np.arange(n[e]) + 0.5)
+            axes.append(x)
+        X2, X1, X0 = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+        X = (X0, X1, X2)
+        S = [(X[e] - w.lo[e]) / (w.hi[e] - w.lo[e]) for e in range(3)]
+        comps = []
+        for i in range(nd):
+            lin = sum(A[i, e] * S[e] for e in range(3)) + b[i]
+            wave = 0.4 * np.sin(2 * math.pi * sum(kv[i, e] * S[e] for e in range(3)) + ph[i])
+            u = amp * (lin + wave + noise * rng.standard_normal(X0.shape))
+            if w.coord == SPHERICAL_LOGR:
+                u = u / np.exp(X0)
+            comps.append(w.c * u)
+        out.append(np.ascontiguousarray(np.stack(comps)))
+    return out
+
+
+def velocity_edges(G, lo=0.5, hi=20.0):
+    """Finite group edges in frequency: 0, G - 1 log-spaced on [lo, hi], and 2 hi on top."""
+    return np.concatenate([[0.0], np.geomspace(lo, hi, G - 1), [2.0 * hi]])
+
