@@ -576,6 +576,51 @@ static void closure(const Ctx<T>& C, const T q[4], const double h[3], T P[3][3])
   }
 }
 
+// Third moment (heat-flux tensor) Q^^{kji} of a state, physical components, in units of F.
+// Reading: the paper uses Q^k_{ji} in the frequency-advection terms of the flux rows without
+// giving its closure.  It is taken from the same interpolation as the M1 pressure tensor
+// (P^ = 3(1 - chi)/2 P_thick + (3 chi - 1)/2 P_thin, P_thick = E/3 I, P_thin = E n n) between
+//   Q_thick = (c E / 5) (f^k delta^{ji} + f^j delta^{ki} + f^i delta^{kj}), the third moment of
+//             the intensity linear in the direction cosine (c E / 4 pi)(1 + 3 f . Omega), and
+//   Q_thin  = c E f n n n, a beam along n (f = 1: c E n n n),
+// with f = F^/(cE) (clamped to 1 in length, as in the closure), n = f/|f|:
+//   Q^ = |F^_clamped| [ 3(1 - chi)/10 (n^k delta^{ji} + n^j delta^{ki} + n^i delta^{kj})
+//                       + (3 chi - 1)/2 n^k n^j n^i ].
+// Contracting two indices gives F^ for every chi (Q^{kjj} = |F^| n^k (3(1 - chi)/2 + (3 chi - 1)/2)),
+// as it must for any intensity.  E <= 0 or F = 0 (and the Eddington closure's F = 0): Q = 0.
+template <class T>
+static void closure3(const Ctx<T>& C, const T q[4], const double h[3], T Q[3][3][3]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int d = 0; d < 3; ++d) Q[a][b][d] = T(0.0);
+  const T E = q[0];
+  if (!(val(E) > 0.0)) return;
+  const T cE = T(C.c) * E;
+  T f[3];
+  for (int k = 0; k < 3; ++k) f[k] = q[1 + k] / T(h[k] != 0.0 ? h[k] : 1.0) / cE;
+  const T fsq = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
+  if (!(val(fsq) > 0.0)) return;
+  const T fm = sqrt(fsq);
+  T f2 = fsq;
+  if (val(f2) > 1.0) f2 = T(1.0);
+  const T fa = (val(fsq) > 1.0) ? T(1.0) : fm;     // |f| after the clamp
+  T chi = T(1.0) / T(3.0);
+  if (C.D->closure != 1) chi = (T(3.0) + T(4.0) * f2) / (T(5.0) + T(2.0) * sqrt(T(4.0) - T(3.0) * f2));
+  const T Fa = cE * fa;
+  const T A = Fa * T(3.0) * (T(1.0) - chi) / T(10.0);
+  const T B = Fa * (T(3.0) * chi - T(1.0)) / T(2.0);
+  const T nn[3] = {f[0] / fm, f[1] / fm, f[2] / fm};
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j)
+      for (int i = 0; i < 3; ++i) {
+        T v = B * nn[k] * nn[j] * nn[i];
+        if (j == i) v = v + A * nn[k];
+        if (k == i) v = v + A * nn[j];
+        if (k == j) v = v + A * nn[i];
+        Q[k][j][i] = v;
+      }
+}
+
 // Characteristic speeds (physical units) of the M1 system along direction d at a face state,
 // the reading of the HLLE speed bounds ("wavespeed estimates for the fastest left- and
 // right-going waves", not given in the paper): the eigenvalues of the flux Jacobian of the
@@ -984,59 +1029,79 @@ static void full_step(const OrcDesc* D, const Geom& geo, const T* E, const T* co
 // ------------------------------------------------------------------------------------
 // Frequency advection of the groups of one zone (Algorithmic Steps, Step 2, eq:freq_adv_system
 // with the upwind intergroup fluxes), applied to the zone's state U[g] after Step 1:
-//   E_g <- E_g + dt ( Phi_{g+1/2} - Phi_{g-1/2} - <v^i_{;j}> P^j_{g i} ),
-//   Phi_{g-1/2} = nu_{g-1/2} sum_{ij} <v^i_{;j}> <P^j_i>_{L or R},
-// the left (lower group) side where <v^i_{;j}> < 0, the right side otherwise, <P>_g = P_g / dnu_g
-// the group's spectral density.  P^j_i = P^^{ji} h_i / h_j (closure of U[g], cell-centred h).
+//   E_g   <- E_g   + dt ( Phi_{g+1/2} - Phi_{g-1/2} - <v^i_{;j}> P^j_{g i} ),
+//   F_g,j <- F_g,j + dt ( Psi_{j,g+1/2} - Psi_{j,g-1/2} ),
+//   Phi_{g-1/2}   = nu_{g-1/2} sum_{ij} <v^i_{;j}> <P^j_i>_{L or R},
+//   Psi_{j,g-1/2} = nu_{g-1/2} sum_{ik} <v^i_{;k}> <Q^k_{ji}>_{L or R},
+// the left (lower group) side where the velocity-gradient component is negative, the right
+// side otherwise; <X>_g = X_g / dnu_g the group's spectral density.  Mixed components from the
+// physical tensors of U[g] with cell-centred h: P^j_i = P^^{ji} h_i / h_j,
+// Q^k_{ji} = Q^^{kji} h_j h_i / h_k (closure3).
 // Readings:
-//  - Since the side depends only on the zone's <v^i_{;j}>, the edge value is reconstructed for
-//    the two contractions X-_g = sum over (i,j) with <v^i_{;j}> < 0 of <v^i_{;j}> <P^j_i>_g and
-//    X+_g (the rest), each linear in nu across the group with the minmod-limited slope of
+//  - Since the side depends only on the zone's <v^i_{;j}>, each edge value is reconstructed for
+//    the two parts of the contraction, over the components with <v^i_{;j}> < 0 (X-, Y-_j) and
+//    the rest (X+, Y+_j): each linear in nu across the group with the minmod-limited slope of
 //    the neighbouring groups' values over their centre distances ("TVD slope limiting"), zero
-//    slope in the first and last group; in one Cartesian dimension this is the reconstruction
-//    of <P^x_x> itself.  Phi_{g-1/2} = nu_{g-1/2} (X-_{g-1} at its upper edge + X+_g at its
-//    lower edge).
-//  - The frequency range is closed: Phi = 0 at nu_{1/2} and nu_{G+1/2}, so that the intergroup
-//    fluxes only move energy between groups.
-//  - The flux rows get no intergroup term: the paper gives no closure for the third moment
-//    Q^k_{ji} (and the Q term listed in Step 1 would count it a second time next to
-//    eq:rad_mom2), so the term -<v^i_{;k}> d_nu(nu Q^k_{ji}) is left out.
+//    slope in the first and last group; in one Cartesian dimension these are <P^x_x> and
+//    <Q^x_{xx}> themselves.  Phi_{g-1/2} = nu_{g-1/2} (X-_{g-1} at its upper edge + X+_g at its
+//    lower edge), Psi likewise.
+//  - The frequency range is closed: Phi = Psi = 0 at nu_{1/2} and nu_{G+1/2}, so the intergroup
+//    fluxes only move energy and momentum between groups.
+//  - The flux rows take the intergroup term of eq:rad_mom2 only; the local term
+//    -<v^i_{;k}> Q^k_{ji} that the listing of Step 1 adds would count it twice (the group sum of
+//    d_nu(nu Q) vanishes) and would break the free-streaming balance F = cE.
 static void freq_advect(const Ctx<double>& C, const int idx[3], std::vector<double>& U) {
   const int G = C.G;
+  const int nd = C.ndim;
   double Vg[3][3], vb[3], h[3];
   vel_grad(C, idx, Vg, vb);
   C.geo->h_cell(idx[0], idx[1], h);
-  std::vector<double> Xm(G), Xp(G), vP(G), nuc(G), dnu(G);
+  // parts: 0 = X-, 1 = X+, 2 + 2 j = Y-_j, 3 + 2 j = Y+_j
+  const int np = 2 + 2 * nd;
+  std::vector<std::vector<double>> X(np, std::vector<double>(G, 0.0));
+  std::vector<double> vP(G), nuc(G), dnu(G);
   for (int g = 0; g < G; ++g) {
     nuc[g] = 0.5 * (C.nu_edge[g] + C.nu_edge[g + 1]);
     dnu[g] = C.nu_edge[g + 1] - C.nu_edge[g];
-    double P[3][3];
-    closure(C, &U[(size_t)4 * g], h, P);
-    double xm = 0.0, xp = 0.0, vp = 0.0;
+    const double* q = &U[(size_t)4 * g];
+    double P[3][3], Q[3][3][3];
+    closure(C, q, h, P);
+    closure3(C, q, h, Q);
+    double vp = 0.0;
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
-        const double Pji = P[j][i] * h[i] / h[j];
-        const double t = Vg[i][j] * Pji;
+        const double t = Vg[i][j] * (P[j][i] * h[i] / h[j]);
         vp += t;
-        if (Vg[i][j] < 0.0) xm += t;
-        else xp += t;
+        X[Vg[i][j] < 0.0 ? 0 : 1][g] += t;
       }
+    for (int j = 0; j < nd; ++j)
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) {
+          const double t = Vg[i][k] * (Q[k][j][i] * h[j] * h[i] / h[k]);
+          X[Vg[i][k] < 0.0 ? 2 + 2 * j : 3 + 2 * j][g] += t;
+        }
     vP[g] = vp;
-    Xm[g] = xm / dnu[g];
-    Xp[g] = xp / dnu[g];
+    for (int a = 0; a < np; ++a) X[a][g] /= dnu[g];
   }
-  // slopes in nu and edge values
-  auto slope = [&](const std::vector<double>& X, int g) {
+  auto slope = [&](const std::vector<double>& Xa, int g) {
     if (g == 0 || g == G - 1) return 0.0;
-    return minmod2((X[g + 1] - X[g]) / (nuc[g + 1] - nuc[g]), (X[g] - X[g - 1]) / (nuc[g] - nuc[g - 1]));
+    return minmod2((Xa[g + 1] - Xa[g]) / (nuc[g + 1] - nuc[g]), (Xa[g] - Xa[g - 1]) / (nuc[g] - nuc[g - 1]));
   };
-  std::vector<double> Phi(G + 1, 0.0);
-  for (int g = 1; g < G; ++g) {
-    const double xm_up = Xm[g - 1] + slope(Xm, g - 1) * (0.5 * dnu[g - 1]);
-    const double xp_lo = Xp[g] - slope(Xp, g) * (0.5 * dnu[g]);
-    Phi[g] = C.nu_edge[g] * (xm_up + xp_lo);
+  // edge fluxes of the energy (row 0) and of the flux components (rows 1 + j)
+  std::vector<std::vector<double>> Phi(1 + nd, std::vector<double>(G + 1, 0.0));
+  for (int r = 0; r <= nd; ++r) {
+    const std::vector<double>& Xm = X[2 * r];
+    const std::vector<double>& Xp = X[2 * r + 1];
+    for (int g = 1; g < G; ++g) {
+      const double xm_up = Xm[g - 1] + slope(Xm, g - 1) * (0.5 * dnu[g - 1]);
+      const double xp_lo = Xp[g] - slope(Xp, g) * (0.5 * dnu[g]);
+      Phi[r][g] = C.nu_edge[g] * (xm_up + xp_lo);
+    }
   }
-  for (int g = 0; g < G; ++g) U[(size_t)4 * g] += C.dt * (Phi[g + 1] - Phi[g] - vP[g]);
+  for (int g = 0; g < G; ++g) {
+    U[(size_t)4 * g] += C.dt * (Phi[0][g + 1] - Phi[0][g] - vP[g]);
+    for (int j = 0; j < nd; ++j) U[(size_t)4 * g + 1 + j] += C.dt * (Phi[1 + j][g + 1] - Phi[1 + j][g]);
+  }
 }
 
 // One full step with the velocity terms (Algorithmic Steps 1 to 4, Euler push, matter fixed):
@@ -1422,6 +1487,21 @@ int orc_closure(const OrcDesc* D, double E, const double* Fphys, double* P) {
   return 0;
 }
 
+// The third moment of one state (Cartesian scale factors): Q [27] as [k][j][i].
+int orc_closure3(const OrcDesc* D, double E, const double* Fphys, double* Q) {
+  Ctx<double> C;
+  C.D = D;
+  C.c = D->c;
+  C.ndim = 3;
+  double q[4] = {E, Fphys[0], Fphys[1], Fphys[2]}, h[3] = {1.0, 1.0, 1.0};
+  double Qm[3][3][3];
+  closure3(C, q, h, Qm);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int d = 0; d < 3; ++d) Q[9 * a + 3 * b + d] = Qm[a][b][d];
+  return 0;
+}
+
 // The M1 characteristic speeds of one state along x (Cartesian): F_x = Fn (physical).
 int orc_m1_speeds(const OrcDesc* D, double E, double Fn, double* lmin, double* lmax) {
   Ctx<double> C;
@@ -1562,10 +1642,9 @@ extern "C" int orc_explicit_v(const OrcDesc* D, const double* E, const double* c
   return 0;
 }
 
-// Step 2 alone on the state (E, F): the energies after the frequency advection (fluxes are
-// unchanged by it).
+// Step 2 alone on the state (E, F): the energies and fluxes after the frequency advection.
 extern "C" int orc_freq_adv(const OrcDesc* D, const double* E, const double* const* F, const double* const* vf,
-                            const double* nu_edge, double dt, double* Eo) {
+                            const double* nu_edge, double dt, double* Eo, double* const* Fo) {
   if (!velocity_ok(D, nu_edge) || !nu_edge) return -1;
   Geom geo;
   geo.build(*D);
@@ -1582,7 +1661,10 @@ extern "C" int orc_freq_adv(const OrcDesc* D, const double* E, const double* con
       for (int k = 0; k < D->ndim; ++k) U[(size_t)4 * g + 1 + k] = F[k][zg];
     }
     freq_advect(C, idx, U);
-    for (int g = 0; g < G; ++g) Eo[(size_t)z * G + g] = U[(size_t)4 * g];
+    for (int g = 0; g < G; ++g) {
+      Eo[(size_t)z * G + g] = U[(size_t)4 * g];
+      for (int k = 0; k < D->ndim; ++k) Fo[k][(size_t)z * G + g] = U[(size_t)4 * g + 1 + k];
+    }
   }
   return 0;
 }

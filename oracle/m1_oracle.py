@@ -88,7 +88,8 @@ def lib():
         _lib.orc_run_v.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, vp, vp, d, ctypes.c_int, vp, vp, vp,
                                    P(OrcDiag)]
         _lib.orc_explicit_v.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp, vp, d, vp, vp]
-        _lib.orc_freq_adv.argtypes = [P(OrcDesc), vp, vp, vp, vp, d, vp]
+        _lib.orc_freq_adv.argtypes = [P(OrcDesc), vp, vp, vp, vp, d, vp, vp]
+        _lib.orc_closure3.argtypes = [P(OrcDesc), d, vp, vp]
         _lib.orc_vel_grad.argtypes = [P(OrcDesc), vp, vp, vp]
         _lib.orc_lab_frame.argtypes = [P(OrcDesc), vp, vp, vp, vp, vp]
         _lib.orc_planck_tail.restype = d
@@ -451,17 +452,28 @@ def explicit_v(p: Problem, E, F, kappa, sigma, vf, dt, inflow=None):
 
 
 def freq_adv(p: Problem, E, F, vf, nu_edge, dt):
-    """Step 2 alone: the group energies after the frequency advection of (E, F)."""
+    """Step 2 alone: (E, [F_k]) after the frequency advection of (E, F)."""
     d = p.desc()
     E = _c(E)
     F = [_c(f) for f in F]
     vf = _vel(p, vf)
     nu = _c(nu_edge)
     Eo = np.empty_like(E)
-    rc = lib().orc_freq_adv(ctypes.byref(d), _ptr(E), _ptrs(F), _ptrs(vf), _ptr(nu), dt, _ptr(Eo))
+    Fo = [np.empty_like(E) for _ in range(p.ndim)]
+    rc = lib().orc_freq_adv(ctypes.byref(d), _ptr(E), _ptrs(F), _ptrs(vf), _ptr(nu), dt, _ptr(Eo), _ptrs(Fo))
     if rc != 0:
         raise ValueError("frequency advection: finite increasing group edges required")
-    return Eo
+    return Eo, Fo
+
+
+def closure3(E, Fphys, c=1.0, eddington=False):
+    """Physical-component third moment Q^ [k][j][i] (3x3x3) of one state (Cartesian)."""
+    p = Problem(ndim=3, n=(1, 1, 1), G=1, c=c, closure=1 if eddington else 0)
+    desc = p.desc()
+    F = np.ascontiguousarray(np.asarray(Fphys, dtype=np.float64).reshape(3))
+    Q = np.empty(27)
+    lib().orc_closure3(ctypes.byref(desc), float(E), _ptr(F), _ptr(Q))
+    return Q.reshape(3, 3, 3)
 
 
 def vel_grad(p: Problem, vf):

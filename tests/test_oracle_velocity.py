@@ -290,7 +290,7 @@ def test_intergroup_fluxes_telescope_to_the_compression_work():
     vf = [rng.normal(0.0, 0.3, (2,) + orc.face_shape(p, d)) for d in range(2)]
     nu = np.concatenate([[0.0], np.cumsum(rng.uniform(0.5, 2.0, p.G))])
     dt = 2e-3
-    Eo = orc.freq_adv(p, E, F, vf, nu, dt)
+    Eo, _ = orc.freq_adv(p, E, F, vf, nu, dt)
     Vg, _ = orc.vel_grad(p, vf)
     for k in range(p.shape[1]):
         for i in range(p.shape[2]):
@@ -320,7 +320,7 @@ def test_spherical_compression_work_uses_the_mixed_pressure():
     vf = [rng.normal(0.0, 0.3, (3,) + orc.face_shape(p, d)) for d in range(3)]
     nu = np.linspace(0.0, 4.0, p.G + 1)
     dt = 1e-3
-    Eo = orc.freq_adv(p, E, F, vf, nu, dt)
+    Eo, _ = orc.freq_adv(p, E, F, vf, nu, dt)
     Vg, _ = orc.vel_grad(p, vf)
     for z in np.ndindex(*p.shape[:3]):
         hz = h[z]
@@ -346,7 +346,7 @@ def test_single_occupied_group_is_donor_upwind(D):
     vf = vfield(p, lambda x0, x1, x2: [D * x0])
     nu = np.array([0.0, 1.0, 2.5, 3.0, 4.5, 6.0, 8.0])
     dt = 1e-3
-    Eo = orc.freq_adv(p, E, F, vf, nu, dt)
+    Eo, _ = orc.freq_adv(p, E, F, vf, nu, dt)
     e, dn = 2.5, nu[g0 + 1] - nu[g0]
     X = D * e / 3.0 / dn                      # the group's spectral density of V^x_x P^x_x
     dE = Eo - E
@@ -381,7 +381,7 @@ def test_linear_spectral_density_is_exact_at_interior_edges(D):
     F = [np.zeros(p.shape)]
     vf = vfield(p, lambda x0, x1, x2: [D * x0])
     dt = 1e-3
-    Eo = orc.freq_adv(p, E, F, vf, nu, dt)
+    Eo, _ = orc.freq_adv(p, E, F, vf, nu, dt)
     # recover the edge fluxes from the energy changes: Phi_{g+1} = Phi_g + dE_g / dt + V P_g
     dE = (Eo - E)[0, 0, 1]
     vP = D * E[0, 0, 1] / 3.0
@@ -456,3 +456,197 @@ def test_lab_frame_isotropic_and_free_streaming():
     for k in range(3):
         expect = Eg.sum() * (p.c * nvec[k] + v[k] + vn * nvec[k])
         assert np.allclose(Fl[k], expect, rtol=1e-13, atol=1e-15)
+
+
+# --------------------------------------------------------------------------------------
+# third moment and the flux rows of Step 2
+# --------------------------------------------------------------------------------------
+def _sym(f):
+    d = np.eye(3)
+    return np.einsum("k,ji->kji", f, d) + np.einsum("j,ki->kji", f, d) + np.einsum("i,kj->kji", f, d)
+
+
+def test_third_moment_limits_and_trace():
+    rng = np.random.default_rng(4)
+    c = 1.7
+    for _ in range(20):
+        E = float(np.exp(rng.normal()))
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        # every state: fully symmetric, and two contracted indices give F (any intensity does)
+        for f in (1e-7, 0.3, 0.77, 1.0):
+            Fh = f * c * E * n
+            Q = orc.closure3(E, Fh, c=c)
+            for perm in ((0, 2, 1), (1, 0, 2), (2, 1, 0)):
+                assert np.allclose(Q, Q.transpose(perm), rtol=0, atol=1e-15 * c * E)
+            assert np.allclose(np.einsum("kjj->k", Q), Fh, rtol=1e-13, atol=1e-15 * c * E)
+        # f -> 0: the third moment of the intensity linear in the direction cosine, c E/5 (sym f)
+        f = 1e-7
+        Q = orc.closure3(E, f * c * E * n, c=c)
+        assert np.allclose(Q, c * E / 5.0 * _sym(f * n), rtol=0, atol=1e-12 * f * c * E)
+        # f = 1: a beam, c E n n n
+        Q = orc.closure3(E, c * E * n, c=c)
+        assert np.allclose(Q, c * E * np.einsum("k,j,i->kji", n, n, n), rtol=0, atol=1e-14 * c * E)
+        # the Eddington closure keeps the diffusion-limit form at every f
+        Q = orc.closure3(E, 0.6 * c * E * n, c=c, eddington=True)
+        assert np.allclose(Q, c * E / 5.0 * _sym(0.6 * n), rtol=0, atol=1e-14 * c * E)
+    assert np.all(orc.closure3(0.0, [0.0, 0.0, 0.0]) == 0.0)
+    assert np.all(orc.closure3(-1.0, [0.1, 0.0, 0.0]) == 0.0)
+
+
+def test_flux_rows_move_a_beam_with_its_energy():
+    # f = 1 beams along x (1-D Cartesian, v = D x): Q^x_xx = c E, so the flux rows' intergroup
+    # fluxes are c times the energy rows': dF_g = c (dE_g + dt V P_g), P^x_x = E
+    p = orc.Problem(ndim=1, n=(5,), G=7, c=1.3)
+    rng = np.random.default_rng(6)
+    E = np.exp(rng.normal(0.0, 1.0, p.shape))
+    F = [p.c * E]
+    for D in (-1.3, 0.8):
+        vf = vfield(p, lambda x0, x1, x2: [D * x0])
+        nu = np.concatenate([[0.0], np.cumsum(rng.uniform(0.5, 1.5, p.G))])
+        dt = 1e-3
+        Eo, Fo = orc.freq_adv(p, E, F, vf, nu, dt)
+        expect = p.c * ((Eo - E) + dt * D * E)
+        assert np.allclose(Fo[0] - F[0], expect, rtol=1e-11, atol=1e-15 * p.c * E.max())
+        assert np.abs(Fo[0] - F[0]).max() > 1e-6 * dt * p.c * E.max()
+
+
+@pytest.mark.parametrize("sph", [False, True])
+def test_flux_row_intergroup_fluxes_telescope(sph):
+    if sph:
+        p = orc.Problem(ndim=3, n=(4, 5, 4), G=5, coord=orc.SPH_LOGR, lo=(0.0, 0.0, 0.0),
+                        hi=(math.log(10.0), math.pi, 2 * math.pi), bc_lo=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC),
+                        bc_hi=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC))
+    else:
+        p = orc.Problem(ndim=2, n=(6, 5), G=6)
+    rng = np.random.default_rng(12)
+    E, F = random_state(p, rng)
+    vf = [rng.normal(0.0, 0.3, (p.ndim,) + orc.face_shape(p, d)) for d in range(p.ndim)]
+    nu = np.concatenate([[0.0], np.cumsum(rng.uniform(0.5, 2.0, p.G))])
+    Eo, Fo = orc.freq_adv(p, E, F, vf, nu, 2e-3)
+    for k in range(p.ndim):
+        dsum = (Fo[k] - F[k]).sum(axis=-1)
+        scale = np.abs(Fo[k] - F[k]).max()
+        assert scale > 0
+        assert np.abs(dsum).max() <= 1e-12 * scale * p.G
+
+
+def test_free_streaming_beam_in_homologous_flow():
+    # 1-D Cartesian, a beam entering at x = 0 (E = 1, F = c E), no matter, v = a x: the
+    # steady comoving solution to first order in v/c is E (1 + a x / c)^2 = E_in (E -> the lab
+    # energy times 1 - 2 v/c), with F = c E
+    n, G, a = 100, 2, -0.05
+    p = orc.Problem(ndim=1, n=(n,), G=G, bc_lo=(orc.INFLOW, 0, 0), bc_hi=(orc.OUTFLOW, 0, 0), nthreads=1)
+    xf = np.linspace(0.0, 1.0, n + 1)
+    vf = [(a * xf).reshape(1, 1, 1, n + 1)]
+    inflow = np.array([[0.5, 0.5], [0.5, 0.5]])
+    E = np.full(p.shape, 1e-8)
+    F = [np.zeros(p.shape)]
+    z = np.zeros(p.shape)
+    dt = orc.max_dt(p, 0.4)
+    Eo, Fo, dg = orc.run_v(p, E, F, z, z, z, vf, [0.0, 1.0, 2.0], dt, int(3.0 / dt), inflow=inflow)
+    xc = 0.5 * (xf[1:] + xf[:-1])
+    Et, Ft = Eo.sum(-1)[0, 0], Fo[0].sum(-1)[0, 0]
+    assert np.allclose(Et * (1.0 + a * xc) ** 2, 1.0, rtol=2e-3, atol=0)
+    assert np.allclose(Ft / Et, 1.0, rtol=1e-4, atol=0)
+    assert dg["max_f"] < 1.0 + 1e-4
+
+
+def test_transparent_standing_shock_is_continuous_in_the_lab_frame():
+    """The paper's transparent-shock test (section on lab-frame flux continuity): a point source
+    at the centre of a spherical grid (r from 10 to 1000), no matter, and the radial velocity of
+    its eq:vprofile, a standing shock at r = 100 where v jumps from -0.01 c to -0.1 c (v_shock =
+    0.1 c).  In steady state the comoving E r^2 and F r^2 jump at the shock, while the
+    first-order lab-frame moments are smooth and follow 1/r^2: here, 2.2 light-crossing times
+    on 120 zones (ln r), the comoving moments jump by more than 15 % between the zones on
+    either side of the shock zone, the lab-frame ones by less than 3 % (E) and 1.5 % (F), and
+    outside the shock zone, the three innermost and the two outermost zones the lab-frame E r^2
+    and F r^2 stay within 3 % and 2 % of their medians."""
+    n, G = 120, 4
+    rin, rmax, rsh, vsh = 10.0, 1000.0, 100.0, 0.1
+    p = orc.Problem(ndim=1, n=(n,), G=G, coord=orc.SPH_LOGR, lo=(math.log(rin), 0.0, 0.0),
+                    hi=(math.log(rmax), math.pi, 2 * math.pi), bc_lo=(orc.INFLOW, orc.AXIS, orc.PERIODIC),
+                    bc_hi=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC), nthreads=1)
+    rf = np.exp(np.linspace(math.log(rin), math.log(rmax), n + 1))
+    v = np.where(rf < rsh, -0.1 * vsh * rf / rsh, -vsh * (np.sqrt(rmax / rf) - 1) / (math.sqrt(rmax / rsh) - 1))
+    vf = [(v / rf).reshape(1, 1, 1, n + 1)]
+    Eg = np.array([0.2, 0.4, 0.3, 0.1])
+    inflow = np.stack([Eg, Eg], axis=1)            # E and physical F = c E (a beam outward)
+    E = np.full(p.shape, 1e-8)
+    F = [np.zeros(p.shape)]
+    z = np.zeros(p.shape)
+    dt = orc.max_dt(p, 0.4)
+    Eo, Fo, _ = orc.run_v(p, E, F, z, z, z, vf, [0.0, 1.0, 2.0, 4.0, 8.0], dt, int(2.2 * (rmax - rin) / dt),
+                          inflow=inflow)
+    El, Fl = orc.lab_frame(p, Eo, Fo, vf)
+    h = scale_factors(p)[0, 0, :, 0]               # sqrt(<r^2>)
+    r2 = h ** 2
+    com_E, com_F = Eo.sum(-1)[0, 0] * r2, Fo[0].sum(-1)[0, 0] / h * r2
+    lab_E, lab_F = El[0, 0] * r2, Fl[0][0, 0] * r2
+    s = int(np.searchsorted(rf, rsh)) - 1          # the zone whose upper face is the shock
+    assert rf[s + 1] == pytest.approx(rsh)
+    below, above = s - 1, s + 1
+    assert com_E[above] / com_E[below] > 1.15 and com_F[above] / com_F[below] > 1.15
+    assert abs(lab_E[above] / lab_E[below] - 1.0) < 0.03
+    assert abs(lab_F[above] / lab_F[below] - 1.0) < 0.015
+    keep = np.ones(n, bool)
+    keep[s] = False
+    keep[:3] = False
+    keep[-2:] = False
+    for prof, tol in ((lab_E, 0.03), (lab_F, 0.02)):
+        med = np.median(prof[keep])
+        assert np.abs(prof[keep] / med - 1.0).max() < tol
+
+
+@pytest.mark.parametrize("sph", [False, True])
+def test_flux_rows_single_occupied_group_closed_form(sph):
+    # only group g0 holds radiation: the edge values are its own spectral densities (zero
+    # slopes), so dF_{g0+1,j} = -dt nu_{g0+1} Y-_j / dnu and dF_{g0-1,j} = dt nu_{g0} Y+_j / dnu with
+    # Y-+_j = sum over (i, k) with <v^i_{;k}> < 0 (>= 0) of <v^i_{;k}> Q^k_{ji},
+    # Q^k_{ji} = Q^^{kji} h_j h_i / h_k (physical third moment of the zone's state)
+    if sph:
+        p = orc.Problem(ndim=3, n=(3, 4, 4), G=5, coord=orc.SPH_LOGR, lo=(0.0, 0.0, 0.0),
+                        hi=(math.log(10.0), math.pi, 2 * math.pi), bc_lo=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC),
+                        bc_hi=(orc.OUTFLOW, orc.AXIS, orc.PERIODIC))
+    else:
+        p = orc.Problem(ndim=3, n=(3, 2, 2), G=5)
+    rng = np.random.default_rng(21)
+    g0 = 2
+    h = scale_factors(p)
+    E = np.zeros(p.shape)
+    E[..., g0] = np.exp(rng.normal(0.0, 0.5, p.shape[:3]))
+    d = rng.normal(size=(3,) + p.shape[:3])
+    d /= np.linalg.norm(d, axis=0)
+    Fh = 0.6 * E[..., g0] * d                            # physical, f = 0.6
+    F = [np.zeros(p.shape) for _ in range(3)]
+    for k in range(3):
+        F[k][..., g0] = Fh[k] * h[..., k]                  # covariant
+    if sph:
+        vf = [rng.normal(0.0, 0.4, (3,) + orc.face_shape(p, dd)) for dd in range(3)]
+    else:
+        A = np.array([[0.3, -1.2, 0.7], [2.1, -0.4, 0.9], [-0.6, 1.5, -0.25]])
+        vf = vfield(p, lambda x0, x1, x2: [A[i, 0] * x0 + A[i, 1] * x1 + A[i, 2] * x2 for i in range(3)])
+    nu = np.array([0.0, 1.0, 2.0, 3.5, 4.5, 6.0])
+    dnu = nu[g0 + 1] - nu[g0]
+    dt = 1e-3
+    Eo, Fo = orc.freq_adv(p, E, F, vf, nu, dt)
+    Vg, _ = orc.vel_grad(p, vf)
+    for z in np.ndindex(*p.shape[:3]):
+        Q = orc.closure3(E[z + (g0,)], Fh[(slice(None),) + z])
+        hz = h[z]
+        Ym, Yp = np.zeros(3), np.zeros(3)
+        for j in range(3):
+            for i in range(3):
+                for k in range(3):
+                    t = Vg[z][i, k] * Q[k, j, i] * hz[j] * hz[i] / hz[k]
+                    if Vg[z][i, k] < 0:
+                        Ym[j] += t
+                    else:
+                        Yp[j] += t
+        for j in range(3):
+            up = Fo[j][z + (g0 + 1,)] - F[j][z + (g0 + 1,)]
+            dn = Fo[j][z + (g0 - 1,)] - F[j][z + (g0 - 1,)]
+            sc = dt * nu[-1] * np.abs(Vg[z]).max() * E[z + (g0,)] * hz.max() ** 2 / hz.min() / dnu
+            assert abs(up - (-dt * nu[g0 + 1] * Ym[j] / dnu)) <= 1e-12 * sc, (z, j)
+            assert abs(dn - dt * nu[g0] * Yp[j] / dnu) <= 1e-12 * sc, (z, j)
+        assert np.all(Fo[0][z][[0, 4]] == 0.0)
