@@ -6,7 +6,8 @@ implicit interaction update + energy/realizability diagnostics) on the 3-D Carte
 weights), inputs resident in HBM, timed with HIP events on the launch stream over K steps
 after W warm-up steps.  Beside it: the same grid with float storage (MIXED), the 2-D
 512^2 x 16 periodic blob workload (FP64 and MIXED, options), the spherical 256 x 64 x 128 x 20
-workload, the radiation-matter exchange and the adjoint/forward ratio; the roofline of the
+workload, the radiation-matter exchange, the adjoint/forward ratio and the step with a
+prescribed velocity field on the headline grid; the roofline of the
 headline step kernel (algorithmic bytes over its measured duration) and the CPU oracle's rate
 on this host's cores (a baseline only).
 
@@ -288,6 +289,49 @@ def matter_timings(reps=10, steps=10):
     return out
 
 
+def velocity_timings(steps=10, warmup=3):
+    """The step with a prescribed velocity field (fornax_m1_step_velocity: Steps 1 to 4) on the
+    192^3 x 12 grid of the headline, a smooth random face velocity up to about 0.1 c with noise,
+    FP64 and MIXED.  Algorithmic bytes: the static step's plus the face velocities (3 faces x 3
+    components per zone)."""
+    import torch
+    from paper_1806_07390_amd import m1, workloads as wl
+    w = wl.core3d()
+    vf = wl.face_velocity(w, amp=0.1, seed=5)
+    nu = wl.velocity_edges(w.G)
+    out = dict(workload="3-D Cartesian 192^3 x 12 (the headline grid), smooth random face velocity |v| <~ 0.1 c "
+                        "plus noise (seed 5), groups edged 0, 0.5 .. 20 (log), 40")
+    for prec, name, dtp, el in ((m1.FP64, "fp64", torch.float64, 8), (m1.MIXED, "mixed", torch.float32, 4)):
+        ctx = m1.Context(m1.Config.from_workload(w, precision=prec))
+        ctx.set_group_edges(nu)
+        E, F, k, s, B, _ = device_inputs(w, dtp)
+        V = [torch.from_numpy(v).to(device="cuda", dtype=dtp) for v in vf]
+        a = (E, F)
+        b = ctx.empty_state()
+        dg = ctx.new_diag()
+        for _ in range(warmup):
+            ctx.step_velocity(a[0], a[1], k, s, B, V, w.dt, out=b, diag=dg)
+            a, b = b, a
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            ctx.step_velocity(a[0], a[1], k, s, B, V, w.dt, out=b, diag=dg)
+            a, b = b, a
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        bpz = algorithmic_bytes(3, el) + 9 * el / w.G
+        out[name] = dict(ms_per_step=round(ms, 5), zgu_per_s=w.zone_groups / (ms * 1e-3),
+                         algorithmic_bytes_per_zone_group=round(bpz, 2),
+                         algorithmic_GBps=round(w.zone_groups * bpz / (ms * 1e-3) / 1e9, 1),
+                         over_static_step=None)
+        del ctx, E, F, k, s, B, V, a, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def step_timing(w, prec, dtp, steps, warmup, dt=None):
     """(ms per full step with diagnostics, ms per step-kernel launch alone, final diag) on the
     workload w in precision prec: HIP events on the launch stream."""
@@ -313,7 +357,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default=None,
                     help="profiling: run only this workload's timed loop (core3d, core3d_mixed, blobs2d, sphere3d, "
-                         "options, matter, adjoint, extras = all after the headline, copy = the copy probe alone)")
+                         "options, matter, adjoint, velocity, extras = all after the headline, copy = the copy "
+                         "probe alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the library has no multi-GPU "
@@ -403,6 +448,15 @@ def main():
         if args.only in (None, "extras", "adjoint"):
             extra["adjoint"] = adjoint_ratios()
             log("  adjoint:", extra["adjoint"])
+        if args.only in (None, "extras", "velocity"):
+            extra["velocity"] = velocity_timings()
+            if "headline" in res:
+                extra["velocity"]["fp64"]["over_static_step"] = round(
+                    extra["velocity"]["fp64"]["ms_per_step"] / res["headline"]["ms"], 3)
+            if "core3d_192^3x12_mixed" in extra:
+                extra["velocity"]["mixed"]["over_static_step"] = round(
+                    extra["velocity"]["mixed"]["ms_per_step"] / extra["core3d_192^3x12_mixed"]["ms_per_step"], 3)
+            log("  velocity:", extra["velocity"])
         if args.only in (None, "extras", "copy"):
             copy_gbs, copy_ms = copy_bandwidth()
             extra["copy_probe_GBps"] = round(copy_gbs, 1)

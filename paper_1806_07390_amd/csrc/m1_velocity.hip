@@ -11,15 +11,19 @@
 //                   every face and, in the flux rows, + <Gamma^l_{ik}> <v^i> F_l - <v^i_{;k}> F_i;
 //                   writes U^(1) to the output state;
 //   k_vel_freq      whole zones per block (BLOCK / G zones of G groups, lanes = groups): Step 2
-//                   on U^(1) (the compression work and the upwind intergroup fluxes of the
-//                   minmod-reconstructed spectral densities, neighbours through LDS), then the
-//                   interaction update, dE_matter and the diagnostics partials, in place.
+//                   on U^(1) (the compression work, and the upwind intergroup fluxes of the
+//                   energy and of the flux components from the minmod-reconstructed spectral
+//                   densities, neighbours through LDS), then the interaction update, dE_matter
+//                   and the diagnostics partials, in place.
 // Readings shared with the CPU definition of the method: the intergroup flux of edge g-1/2
 // takes, for each <v^i_{;j}>, the left (lower-group) spectral density where it is negative and
-// the right one otherwise, which splits sum_ij <v^i_{;j}> P^j_i / dnu into the two parts X-, X+
-// that are reconstructed (linear in nu, minmod slopes over the group-centre distances, none in
-// the first and last group); the frequency range is closed (no flux through its two ends); the
-// flux rows get no intergroup term (the paper gives no closure for the third moment).
+// the right one otherwise, which splits the contractions sum_ij <v^i_{;j}> P^j_i / dnu and
+// sum_ik <v^i_{;k}> Q^k_{ji} / dnu into parts (-, +) that are reconstructed (linear in nu, minmod
+// slopes over the group-centre distances, none in the first and last group); the frequency
+// range is closed (no flux through its two ends); the third moment Q^ is the M1 interpolation
+// A (n d + d n + ...) + B n n n, A = |F^| (1 - chi) 3/10 = |F^| (s - 1)/5,
+// B = |F^| (3 chi - 1)/2 = |F^| (2 - s), s = sqrt(4 - 3 f^2), between the diffusion-limit form
+// (c E / 5)(sym f) and the beam c E n n n; no local Q term in the flux rows.
 //
 // The velocity step is bound by the per-thread recomputation of the face states (two faces per
 // zone and direction) rather than HBM; it is the correctness-first path of the method's
@@ -140,6 +144,41 @@ __device__ __forceinline__ void face_flux_v(const StepArgs<S>& a, const Geo<R>& 
   for (int c = 0; c <= ND; ++c) flux[c] += vd * qu[c];
 }
 
+// Coefficients of the third moment Q^ = A (n^k d^{ji} + n^j d^{ki} + n^i d^{kj}) + B n^k n^j n^i
+// of the state q (physical components, unit direction n of F^, |F^| clamped to cE):
+// A = |F^| (s - 1)/5, B = |F^| (2 - s), s = sqrt(4 - 3 f^2), written without cancellation
+// (s - 1 = 3 (1 - f^2)/(1 + s), 2 - s = 3 f^2/(2 + s)); the Eddington closure gives A = |F^|/5,
+// B = 0.  E <= 0 or F = 0: A = B = 0.
+template <typename R, bool SPH, int ND>
+__device__ __forceinline__ void third_moment(const R q[4], const R ih[3], R c, int eddington, R& A, R& B, R n[3]) {
+  A = R(0);
+  B = R(0);
+  n[0] = n[1] = n[2] = R(0);
+  const R E = q[0];
+  if (!(E > R(0))) return;
+  const R icE = rcp_(c * E);
+  R f[3] = {R(0), R(0), R(0)};
+  R f2 = R(0);
+  for (int k = 0; k < ND; ++k) {
+    f[k] = (SPH ? q[1 + k] * ih[k] : q[1 + k]) * icE;
+    f2 += f[k] * f[k];
+  }
+  if (!(f2 > R(0))) return;
+  const R fm = sqrt_(f2);
+  const R ifm = rcp_(fm);
+  for (int k = 0; k < ND; ++k) n[k] = f[k] * ifm;
+  const R fa = (f2 > R(1)) ? R(1) : fm;
+  const R f2c = (f2 > R(1)) ? R(1) : f2;
+  const R Fa = c * E * fa;
+  if (eddington) {
+    A = Fa * R(0.2);
+    return;
+  }
+  const R s = sqrt_(R(4) - R(3) * f2c);
+  A = Fa * R(0.6) * (R(1) - f2c) * rcp_(R(1) + s);
+  B = Fa * R(3) * f2c * rcp_(R(2) + s);
+}
+
 // ------------------------------------------------------------------------------------------
 // Step 1 with the velocity terms, one thread per zone-group; U^(1) into a.Eo, a.Fo.
 // ------------------------------------------------------------------------------------------
@@ -211,12 +250,15 @@ __global__ void __launch_bounds__(BLOCK) k_vel_explicit(StepArgs<S> a, Geo<R> ge
 // ------------------------------------------------------------------------------------------
 template <typename S, typename R, bool SPH, int ND>
 __global__ void __launch_bounds__(BLOCK) k_vel_freq(StepArgs<S> a, Geo<R> geo, VelArgs<S> va, int want_diag) {
+  // parts of the contractions: 0 = X- and 1 = X+ (energy row), 2 + 2 j = Y-_j and 3 + 2 j = Y+_j
+  // (flux row j); the - parts are taken at a group's upper edge, the + parts at its lower edge
+  constexpr int NP = 2 + 2 * ND;
   const int G = a.G;
   const int zpb = a.zones_per_block;
   const int t = threadIdx.x;
   const int lz = t / G, grp = t - lz * G;
   const bool lane_ok = lz < zpb;
-  __shared__ R sXm[BLOCK], sXp[BLOCK], sEm[BLOCK], sEp[BLOCK];
+  __shared__ R sV[NP][BLOCK], sEd[NP][BLOCK];
   __shared__ double sdz[BLOCK];
   // the group's frequency geometry (double)
   double nlo = 0.0, nhi = 1.0, cm = 0.0, cp = 0.0;
@@ -240,7 +282,9 @@ __global__ void __launch_bounds__(BLOCK) k_vel_freq(StepArgs<S> a, Geo<R> geo, V
     const int64_t z = zb + lz;
     const bool act = lane_ok && z < a.nzones;
     R U[4] = {R(0), R(0), R(0), R(0)};
-    R vP = R(0), xm = R(0), xp = R(0);
+    R vP = R(0);
+    R val[NP];
+    for (int pp = 0; pp < NP; ++pp) val[pp] = R(0);
     int i = 0, j = 0, k = 0;
     int64_t zg = 0;
     if (act) {
@@ -258,39 +302,63 @@ __global__ void __launch_bounds__(BLOCK) k_vel_freq(StepArgs<S> a, Geo<R> geo, V
         cell_h<R, SPH>(geo, i + NG, j + NG, h);
         cell_ih<R, SPH>(geo, i + NG, j + NG, ih);
       }
+      // the gradient in the frame of the physical components, Vt_ik = <v^i_{;k}> h_i / h_k, split
+      // by sign into Wm (< 0) and Wp (>= 0)
+      R Wm[9], Wp[9];
+      for (int ic = 0; ic < 3; ++ic)
+        for (int kc = 0; kc < 3; ++kc) {
+          const R v = SPH ? Vg[3 * ic + kc] * (h[ic] * ih[kc]) : Vg[3 * ic + kc];
+          Wm[3 * ic + kc] = (Vg[3 * ic + kc] < R(0)) ? v : R(0);
+          Wp[3 * ic + kc] = (Vg[3 * ic + kc] < R(0)) ? R(0) : v;
+        }
+      // energy row: sum_ij W_ij P^^{ji}
       R P[9];
       closure_full<R, SPH, ND>(U, ih, c, a.closure, P);
-      // sum_ij <v^i_{;j}> P^j_i, P^j_i = P^^{ji} h_i / h_j, split by the sign of <v^i_{;j}>
+      R xm = R(0), xp = R(0);
       for (int ic = 0; ic < 3; ++ic)
         for (int jd = 0; jd < 3; ++jd) {
-          const R Pji = SPH ? P[3 * jd + ic] * (h[ic] * ih[jd]) : P[3 * jd + ic];
-          const R tv = Vg[3 * ic + jd] * Pji;
-          vP += tv;
-          if (Vg[3 * ic + jd] < R(0)) xm += tv;
-          else xp += tv;
+          xm += Wm[3 * ic + jd] * P[3 * jd + ic];
+          xp += Wp[3 * ic + jd] * P[3 * jd + ic];
         }
-      xm *= idnu;
-      xp *= idnu;
+      vP = xm + xp;
+      val[0] = xm * idnu;
+      val[1] = xp * idnu;
+      // flux rows: h_j [A ((W n)_j + n_j tr W + (W^T n)_j) + B n_j (n W n)]
+      R A, B, n[3];
+      third_moment<R, SPH, ND>(U, ih, c, a.closure, A, B, n);
+      for (int sd = 0; sd < 2; ++sd) {
+        const R* W = sd == 0 ? Wm : Wp;
+        R Wn[3], WTn[3];
+        for (int r = 0; r < 3; ++r) {
+          Wn[r] = W[3 * r] * n[0] + W[3 * r + 1] * n[1] + W[3 * r + 2] * n[2];
+          WTn[r] = W[r] * n[0] + W[3 + r] * n[1] + W[6 + r] * n[2];
+        }
+        const R tr = W[0] + W[4] + W[8];
+        const R nWn = n[0] * Wn[0] + n[1] * Wn[1] + n[2] * Wn[2];
+        for (int jd = 0; jd < ND; ++jd) {
+          const R y = A * (Wn[jd] + n[jd] * tr + WTn[jd]) + B * n[jd] * nWn;
+          val[2 + 2 * jd + sd] = (SPH ? h[jd] * y : y) * idnu;
+        }
+      }
     }
-    sXm[t] = xm;
-    sXp[t] = xp;
+    for (int pp = 0; pp < NP; ++pp) sV[pp][t] = val[pp];
     __syncthreads();
-    // edge values: X- at the group's upper edge, X+ at its lower edge
-    R em_up = xm, ep_lo = xp;
-    if (act && interior) {
-      const R sm = minmod((xm - sXm[t - 1]) * idm, (sXm[t + 1] - xm) * idp);
-      const R sp = minmod((xp - sXp[t - 1]) * idm, (sXp[t + 1] - xp) * idp);
-      em_up = xm + sm * half;
-      ep_lo = xp - sp * half;
+    // edge values: the - parts at the group's upper edge, the + parts at its lower edge
+    R ed[NP];
+    for (int pp = 0; pp < NP; ++pp) {
+      R sl = R(0);
+      if (act && interior) sl = minmod((val[pp] - sV[pp][t - 1]) * idm, (sV[pp][t + 1] - val[pp]) * idp);
+      ed[pp] = (pp & 1) ? val[pp] - sl * half : val[pp] + sl * half;
+      sEd[pp][t] = ed[pp];
     }
-    sEm[t] = em_up;
-    sEp[t] = ep_lo;
     __syncthreads();
     double dz = 0.0;
     if (act) {
-      const R phlo = (grp > 0) ? Rnlo * (sEm[t - 1] + ep_lo) : R(0);
-      const R phhi = (grp < G - 1) ? Rnhi * (em_up + sEp[t + 1]) : R(0);
-      U[0] += dtR * (phhi - phlo - vP);
+      for (int r = 0; r <= ND; ++r) {
+        const R flo = (grp > 0) ? Rnlo * (sEd[2 * r][t - 1] + ed[2 * r + 1]) : R(0);
+        const R fhi = (grp < G - 1) ? Rnhi * (ed[2 * r] + sEd[2 * r + 1][t + 1]) : R(0);
+        U[r] += dtR * ((fhi - flo) - (r == 0 ? vP : R(0)));
+      }
       // Steps 3 and 4
       const double kd = (double)a.kap[zg], sd = (double)a.sig[zg], Bd = (double)a.B[zg];
       const double ck = cdt * kd, cks = cdt * (kd + sd), jB = ck * Bd;

@@ -198,3 +198,61 @@ def test_velocity_argument_errors(m1):
             c2.step_velocity(E, F, k, s, B, V, w.dt)
         assert ei.value.code == m1.FORNAX_EUNSUPPORTED
     torch.cuda.synchronize()
+
+
+def test_transparent_shock_long_run(m1):
+    """The transparent standing shock (spherical 1-D, 120 zones, a beam from the inner boundary,
+    no matter, the paper's velocity profile with a shock at r = 100): 2.2 light-crossing times
+    (13911 steps) on the GPU in FP64 against the oracle within 1e-10 of the largest E and F,
+    with the lab-frame moments from the GPU state; MIXED against the oracle after 200 steps
+    within its run gate, and at steady state the comoving jump (> 15 %) and the lab-frame
+    continuity (< 3 %) across the shock."""
+    n, G = 120, 4
+    rin, rmax, rsh, vsh = 10.0, 1000.0, 100.0, 0.1
+    w = wl.Workload("shock1d", 1, (n, 1, 1), G, wl.SPHERICAL_LOGR, (math.log(rin), 0.0, 0.0),
+                    (math.log(rmax), math.pi, 2 * math.pi), (wl.BC_INFLOW, wl.BC_AXIS, wl.BC_PERIODIC),
+                    (wl.BC_OUTFLOW, wl.BC_AXIS, wl.BC_PERIODIC), 1.0, 0, np.full((1, 1, n, G), 1e-8),
+                    [np.zeros((1, 1, n, G))], np.zeros((1, 1, n, G)), np.zeros((1, 1, n, G)),
+                    np.zeros((1, 1, n, G)))
+    Eg = np.array([0.2, 0.4, 0.3, 0.1])
+    w.inflow = np.stack([Eg, Eg], axis=1)
+    rf = np.exp(np.linspace(math.log(rin), math.log(rmax), n + 1))
+    v = np.where(rf < rsh, -0.1 * vsh * rf / rsh, -vsh * (np.sqrt(rmax / rf) - 1) / (math.sqrt(rmax / rsh) - 1))
+    vf = [(v / rf).reshape(1, 1, 1, n + 1)]
+    nu = np.array([0.0, 1.0, 2.0, 4.0, 8.0])
+    p = problem_of(w)
+    p.nthreads = 1
+    dt = orc.max_dt(p, 0.4)
+    nsteps = int(2.2 * (rmax - rin) / dt)
+    E, F, dg, _ = oracle_v(w, vf, nu, dt, nsteps)
+    say(f"case transparent shock FP64 steps={nsteps}")
+    ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64))
+    Eg_, Fg_, _ = gpu_v(m1, ctx, w, vf, nu, dt, nsteps)
+    eE = np.abs(Eg_ - E).max() / np.abs(E).max()
+    eF = np.abs(Fg_[0] - F[0]).max() / np.abs(F[0]).max()
+    say(f"  max |dE| / max E {eE:.2e}, max |dF| / max F {eF:.2e}")
+    assert eE <= 1e-10 and eF <= 1e-10
+    El, Fl = orc.lab_frame(p, E, F, vf)
+    Elg, Flg = ctx.lab_frame(to_dev(Eg_, torch.float64), [to_dev(Fg_[0], torch.float64)],
+                             [to_dev(vf[0], torch.float64)])
+    assert np.abs(to_host(Elg) - El).max() <= 1e-9 * np.abs(El).max()
+    assert np.abs(to_host(Flg[0]) - Fl[0]).max() <= 1e-9 * np.abs(Fl[0]).max()
+    # MIXED: parity over the first 200 steps, the physics at steady state
+    E2, F2, _, _ = oracle_v(w, vf, nu, dt, 200)
+    ctx = m1.Context(m1.Config.from_workload(w, precision=m1.MIXED))
+    Em, Fm, _ = gpu_v(m1, ctx, w, vf, nu, dt, 200)
+    e = rel_l1(Em, Fm, E2, F2, w.c)
+    say(f"  MIXED 200 steps: rel-L1 E {e[0]:.2e} F {e[1]:.2e}; element-wise E {e.pE:.2e} F {e.pF:.2e}")
+    assert e[0] <= TOL_MIXED_RUN and e[1] <= TOL_MIXED_RUN
+    Em, Fm, _ = gpu_v(m1, ctx, w, vf, nu, dt, nsteps)
+    eE = np.abs(Em - E).max() / np.abs(E).max()
+    at = int(np.unravel_index(np.argmax(np.abs(Em - E)), E.shape)[2])
+    say(f"  MIXED {nsteps} steps: max |dE| / max E {eE:.2e} at zone {at}")
+    h = np.sqrt(np.exp(2 * np.log(rf[:-1] * rf[1:]) / 2))          # geometric-mean radius
+    Elm, Flm = ctx.lab_frame(to_dev(Em, torch.float32), [to_dev(Fm[0], torch.float32)],
+                             [to_dev(vf[0], torch.float32)])
+    s = int(np.searchsorted(rf, rsh)) - 1
+    com = Em.sum(-1)[0, 0] * h ** 2
+    lab = to_host(Elm)[0, 0] * h ** 2
+    assert com[s + 1] / com[s - 1] > 1.15
+    assert abs(lab[s + 1] / lab[s - 1] - 1.0) < 0.03
