@@ -72,8 +72,8 @@ enum { FORNAX_FP64 = 0, FORNAX_MIXED = 1 };
 
 /* Reconstruction (Reconstruction subsection).  MINMOD (the method's default here), MC: linear
  * profiles in the volume coordinate with limited slopes (eq:recon_constraints, n = 1); NONE:
- * piecewise constant; PPM: the paper's piecewise-parabolic reconstruction (n = 2): constant at
- * a local extremum of the data, else the parabola with the three zones' averages
+ * piecewise constant; PPM: the paper's piecewise-parabolic reconstruction (n = 2): constant
+ * where a zone's average is not between its neighbours', else the parabola with the three zones' averages
  * (eq:recon_system1), each face state reset where that parabola turns between the zone's and
  * its neighbour's centres (monotone there, zero slope at the neighbour's centre), and the face
  * state nearer to an extremum of the parabola through both face states and the average
@@ -91,8 +91,8 @@ enum { FORNAX_CLOSURE_M1 = 0, FORNAX_CLOSURE_EDDINGTON = 1 };
  * U^{n+1} once per step, and dE_matter is taken against that U^-. */
 enum { FORNAX_EULER = 0, FORNAX_SSPRK2 = 1 };
 
-/* Wavespeed bounds of the HLL fluxes (Riemann Solvers subsection, eq:hll: the paper names the
- * fastest left- and right-going wave speeds S_L, S_R without giving them).  LIGHT: S_L = -c,
+/* Wavespeed bounds of the HLL fluxes (Riemann Solvers subsection, eq:hll takes the speeds S_L,
+ * S_R of the fastest waves moving left and right, with no formula for them).  LIGHT: S_L = -c,
  * S_R = +c, the bound of every M1 characteristic speed (the method's default here).  M1:
  * HLLE bounds S_L = min(0, l-(L), l-(R)), S_R = max(0, l+(L), l+(R)) from the eigenvalues of the
  * flux Jacobian of the one-dimensional M1 system at each face state, taken with the state's

@@ -418,7 +418,7 @@ static void solve3(const double A[3][3], const T r[3], T c[3]) {
 
 // Parabolic reconstruction of one component along d (Reconstruction subsection, n = 2), in
 // the local coordinate u = x - x_i (x_i the zone's coordinate centre, x_{i-+1/2} = x_i -+ dx/2):
-//  1. if q_i is a local extremum of (q_{i-1}, q_i, q_{i+1}) the zone is piecewise constant;
+//  1. where q_i is not between q_{i-1} and q_{i+1} the zone is piecewise constant;
 //  2. else the parabola p(u) = c0 + c1 u + c2 u^2 with the three zones' volume averages
 //     (eq:recon_system1, <u^j> over each zone with the volume element) gives the face states
 //     p(u_{i-1/2}) and p(u_{i+1/2});
@@ -622,8 +622,8 @@ static void closure3(const Ctx<T>& C, const T q[4], const double h[3], T Q[3][3]
 }
 
 // Characteristic speeds (physical units) of the M1 system along direction d at a face state,
-// the reading of the HLLE speed bounds ("wavespeed estimates for the fastest left- and
-// right-going waves", not given in the paper): the eigenvalues of the flux Jacobian of the
+// the reading of the HLLE speed bounds (eq:hll names the fastest left- and right-moving wave
+// speeds without a formula for them): the eigenvalues of the flux Jacobian of the
 // one-dimensional system U = (E, F), flux (F, c^2 chi(f) E), f = F / (c E), taken with the
 // state's normal reduced flux f = F^_d / (c E):
 //   dFlux/dU = [[0, 1], [c^2 (chi - f chi'), c chi']],
@@ -726,7 +726,8 @@ static void vel_grad(const Ctx<T>& C, const int idx[3], double Vg[3][3], double 
 // both face states, S_L = min(0, lambda_-(L), lambda_-(R)), S_R = max(0, lambda_+(L),
 // lambda_+(R)) (m1_speeds), also divided by h_d.  Reading (tau_cell): arithmetic mean of (kappa + sigma) of the two
 // zones times the mean proper zone width h_d Delta x^d of the two.  Reading: epsilon enters
-// the energy flux only ("a correction to the energy fluxes").
+// the energy flux only (the Riemann Solvers subsection applies it to the energy fluxes,
+// eq:hll with eq:epsilon).
 // A face of zero area returns a zero flux.
 
 template <class T>
@@ -1041,7 +1042,8 @@ static void full_step(const OrcDesc* D, const Geom& geo, const T* E, const T* co
 //  - Since the side depends only on the zone's <v^i_{;j}>, each edge value is reconstructed for
 //    the two parts of the contraction, over the components with <v^i_{;j}> < 0 (X-, Y-_j) and
 //    the rest (X+, Y+_j): each linear in nu across the group with the minmod-limited slope of
-//    the neighbouring groups' values over their centre distances ("TVD slope limiting"), zero
+//    the neighbouring groups' values over their centre distances (a TVD limiter, as the
+//    paper's Doppler test describes for its frequency advection), zero
 //    slope in the first and last group; in one Cartesian dimension these are <P^x_x> and
 //    <Q^x_{xx}> themselves.  Phi_{g-1/2} = nu_{g-1/2} (X-_{g-1} at its upper edge + X+_g at its
 //    lower edge), Psi likewise.
