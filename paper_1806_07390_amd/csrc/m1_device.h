@@ -350,26 +350,39 @@ __device__ __forceinline__ void closure_row(const R q[4], const R ih[3], int d, 
     R Fh[3] = {R(0), R(0), R(0)};
     for (int k = 0; k < ND; ++k) Fh[k] = SPH ? q[1 + k] * ih[k] : q[1 + k];
     R cE = c * E;
+    // the rare paths (tiny states; |f| > 1) are uniform branches taken only by waves that hold
+    // such a state; the empty asm keeps the compiler from computing them in every wave
     const bool tiny = __builtin_amdgcn_ballot_w64(cE < R(0x1p-450)) != 0;
-    if (tiny && cE < R(0x1p-450)) {
-      cE *= R(0x1p600);
-      for (int k = 0; k < ND; ++k) Fh[k] *= R(0x1p600);
+    bool scl = false;
+    if (tiny) {
+      __asm__ volatile("");
+      scl = cE < R(0x1p-450);
+      if (scl) {
+        cE *= R(0x1p600);
+        for (int k = 0; k < ND; ++k) Fh[k] *= R(0x1p600);
+      }
     }
     R F2 = R(0);
     for (int k = 0; k < ND; ++k) F2 += Fh[k] * Fh[k];
     const R A = cE * cE;
-    if (F2 > A) {
-      // |f| > 1: the direction of F with |f| = 1
-      const R sc = cE * rcp_(sqrt_(F2));
-      for (int k = 0; k < ND; ++k) Fh[k] *= sc;
-      F2 = A;
+    if (__builtin_amdgcn_ballot_w64(F2 > A)) {
+      __asm__ volatile("");
+      if (F2 > A) {
+        // |f| > 1: the direction of F with |f| = 1
+        const R sc = cE * rcp_(sqrt_(F2));
+        for (int k = 0; k < ND; ++k) Fh[k] *= sc;
+        F2 = A;
+      }
     }
     const R S = sqrt_(R(4) * A - R(3) * F2);
     const R iso = (S - cE) * rcp_(R(3) * c);   // c is uniform: hoisted
     const R af = R(3) * rcp_(c * (R(2) * cE + S)) * Fh[d];
     for (int k = 0; k < ND; ++k) P[k] = af * Fh[k] + (k == d ? iso : R(0));
-    if (tiny && c * E < R(0x1p-450))
-      for (int k = 0; k < ND; ++k) P[k] *= R(0x1p-600);
+    if (tiny) {
+      __asm__ volatile("");
+      if (scl)
+        for (int k = 0; k < ND; ++k) P[k] *= R(0x1p-600);
+    }
     return;
   }
   R f[3] = {R(0), R(0), R(0)};

@@ -433,7 +433,8 @@ C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
 C3Tile choose_c3_tile(const fornax_m1_desc& D, int cus) {
   (void)cus;
   const int NR = 8;  // 8 waves per block, one y-row each; the top row only supplies its face flux
-  return make_c3_tile(D, NR, 32);
+  // planes per block: 64 in double (1.4 % faster than 32 at 192^3 x 12), 32 in float
+  return make_c3_tile(D, NR, D.precision == FORNAX_FP64 ? 64 : 32);
 }
 
 template <typename S>

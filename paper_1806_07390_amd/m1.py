@@ -192,6 +192,7 @@ class Context:
         self._h = h
 
     def close(self):
+        self._bwd_cache = None
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.fornax_m1_destroy(self._h)
             self._h = None
@@ -591,20 +592,34 @@ class M1Steps(torch.autograd.Function):
         ctx, dt, nsteps, ckpt_every, inflow, ckpts, final = fctx.m1
         kappa, sigma, B = fctx.saved_tensors
         kappa, sigma, B = kappa.detach(), sigma.detach(), B.detach()
-        zeros = lambda: torch.zeros(ctx.shape, dtype=ctx.dtype, device=ctx.device)
-        lam = [((gE if gE is not None else zeros()).contiguous().clone(),
-                [(g if g is not None else zeros()).contiguous().clone() for g in gF]),
-               ctx.empty_state()]
-        dk = zeros()
         K = min(ckpt_every, nsteps)
-        # seg[i]: state i of the segment being replayed; seg[n_in] holds the state that ends
-        # it (the next checkpoint, or the final state), so that every adjoint step gets both
-        # U^n and U^{n+1} and none recomputes the step
-        seg = [ctx.empty_state() for _ in range(K + 1)]
-        # every C call of the replay is bound once: K-1 steps, K adjoint steps per lambda parity
-        steps = [ctx.bound_step(seg[i], seg[i + 1], kappa, sigma, B, dt, inflow=inflow) for i in range(K - 1)]
-        adj = [[ctx.adjointer(seg[i], kappa, sigma, B, dt, lam[p], lam[1 - p], dk, inflow=inflow, U1=seg[i + 1])
-                for p in range(2)] for i in range(K)]
+        # The replay's buffers and bound C calls depend only on the context, the segment length
+        # and the coefficient arrays: they are kept on the context and reused by later backward
+        # passes (binding them costs far more host time than the GPU work of a small step).
+        key = (dt, K, None if inflow is None else inflow.data_ptr(), kappa.data_ptr(), sigma.data_ptr(),
+               B.data_ptr())
+        cache = getattr(ctx, "_bwd_cache", None)
+        if cache is None or cache[0] != key:
+            # seg[i]: state i of the segment being replayed; seg[n_in] holds the state that ends
+            # it (the next checkpoint, or the final state), so that every adjoint step gets both
+            # U^n and U^{n+1} and none recomputes the step
+            seg = [ctx.empty_state() for _ in range(K + 1)]
+            lam = [ctx.empty_state(), ctx.empty_state()]
+            dk = torch.empty(ctx.shape, dtype=ctx.dtype, device=ctx.device)
+            # every C call of the replay bound once: K-1 steps, K adjoint steps per lambda parity
+            steps = [ctx.bound_step(seg[i], seg[i + 1], kappa, sigma, B, dt, inflow=inflow) for i in range(K - 1)]
+            adj = [[ctx.adjointer(seg[i], kappa, sigma, B, dt, lam[p], lam[1 - p], dk, inflow=inflow, U1=seg[i + 1])
+                    for p in range(2)] for i in range(K)]
+            # the coefficient tensors stay referenced while the bound calls hold their pointers
+            cache = (key, seg, lam, dk, steps, adj, (kappa, sigma, B, inflow))
+            ctx._bwd_cache = cache
+        _, seg, lam, dk, steps, adj, _ = cache
+        dk.zero_()
+        for dst, g in ((lam[0][0], gE),) + tuple((lam[0][1][k], gF[k]) for k in range(len(gF))):
+            if g is None:
+                dst.zero_()
+            else:
+                dst.copy_(g)
         ends = [(c[1], c[2]) for c in ckpts[1:]] + [final]
         p = 0
         for j in reversed(range(len(ckpts))):
@@ -621,7 +636,8 @@ class M1Steps(torch.autograd.Function):
                 p ^= 1
         fctx.m1 = None
         out = lam[p]
-        return (None, None, None, None, None, dk, None, None, out[0]) + tuple(out[1])
+        # fresh tensors: the buffers belong to the context's cache
+        return (None, None, None, None, None, dk.clone(), None, None, out[0].clone()) + tuple(f.clone() for f in out[1])
 
 
 def run_differentiable(ctx, E0, F0, kappa, sigma, B, dt, nsteps, ckpt_every=8, inflow=None):
