@@ -524,3 +524,41 @@ def test_mixed_accuracy_against_the_fp64_closure_threshold(m1, case):
     for fstar in (0.5, 0.9):
         assert max(errs[fstar]) <= TOL_MIXED_RUN
     assert all(np.isfinite(errs[math.inf]))
+
+
+@pytest.mark.parametrize("G", [4, 8])
+def test_3d_kernel_spherical(m1, G):
+    """The whole-zone 3-D kernel on spherical (ln r, theta, phi) grids: inflow at the inner
+    radius, polar axes on both theta boundaries (the ghost rows come from the plane shifted by
+    n_phi / 2), periodic phi; a grid ragged in every direction (r not a multiple of the 14
+    updated columns, theta not of the 7 updated rows, phi not of the plane count) against the
+    oracle element by element, and against the tiled kernel, FP64 and MIXED."""
+    import os
+    w = wl.sphere3d(nr=31, nth=17, nph=10, G=G, steps=6)
+    rng = np.random.default_rng(G)
+    w.E = np.exp(rng.normal(0.0, 0.8, w.E.shape)) * w.B
+    p = problem_of(w)
+    dt = dt_of(w, p)
+    E, F, dg, dEm = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow, want_dEm=True)
+    for prec, tol in ((m1.FP64, TOL_FP64), (m1.MIXED, TOL_MIXED_RUN)):
+        outs = {}
+        for c3 in (None, "0", "8,4"):
+            say(f"case spherical 3-D kernel G={G} C3={c3} prec={prec}")
+            if c3 is not None:
+                os.environ["FORNAX_M1_C3"] = c3
+            try:
+                ctx = m1.Context(m1.Config.from_workload(w, precision=prec))
+            finally:
+                os.environ.pop("FORNAX_M1_C3", None)
+            Eg, Fg, dgg = gpu_run(ctx, w, dt, w.steps, diag=True)
+            e = rel_l1(Eg, Fg, E, F, w.c)
+            say(f"  rel-L1 E {e[0]:.2e} F {e[1]:.2e}; element-wise E {e.pE:.2e} F {e.pF:.2e}")
+            check_pointwise(e, prec == m1.FP64, f"spherical 3-D kernel {c3}")
+            assert e[0] <= tol and e[1] <= tol
+            if prec == m1.FP64:
+                assert dgg["energy_total"][0] == pytest.approx(dg["energy_total"], rel=1e-12)
+                assert int(dgg["n_unrealizable"][0]) == dg["n_unrealizable"]
+                assert np.allclose(dgg["dE_matter"], dEm, rtol=1e-10, atol=1e-12 * np.abs(E).max())
+            outs[c3] = Eg
+        # the default is the 3-D kernel; "0" the tiled kernel
+        assert np.array_equal(outs[None], outs["8,4"])
