@@ -575,7 +575,8 @@ int launch_c3(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipSt
   const C3Tile& tl = ctx->c3;
   if (tl.nblocks <= 0) return FORNAX_EUNSUPPORTED;
   if (a.dEm && tl.ngb > 1 && !a.dzp) return FORNAX_EUNSUPPORTED;
-  const bool mm = a.limiter == FORNAX_LIMITER_MINMOD;
+  // the minmod instantiation has the -+c bounds built in; the other takes both options at run time
+  const bool mm = a.limiter == FORNAX_LIMITER_MINMOD && a.wavespeed == FORNAX_WAVESPEED_LIGHT;
   const bool sph = ctx->desc.coord == FORNAX_SPHERICAL_LOGR;
   dim3 grid(tl.nblocks), block(64 * tl.NR);
 #define FM1_C3(NRV, WV, SP)                                                                                   \

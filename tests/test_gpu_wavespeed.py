@@ -40,13 +40,15 @@ def _case(name):
         return w
     if name == "core3d":
         return wl.core3d(n=14, G=6, steps=5)
+    if name == "core3d_g8":                     # a group count the 3-D whole-zone kernel takes
+        return wl.core3d(n=14, G=8, steps=5)
     return wl.sphere3d(nr=14, nth=10, nph=8, G=4, steps=5)
 
 
 # (the Eddington closure's speeds, -+c/sqrt(3), do not bound the beams of the slab and of the
 # reflecting box, whose states then leave the realizable set: those pairs are left out)
 @pytest.mark.parametrize("name,closure", [("slab1d", "m1"), ("blobs2d", "m1"), ("reflect2d", "m1"),
-                                          ("core3d", "m1"), ("sphere3d", "m1"), ("blobs2d", "eddington"),
+                                          ("core3d", "m1"), ("core3d_g8", "m1"), ("sphere3d", "m1"), ("blobs2d", "eddington"),
                                           ("core3d", "eddington"), ("sphere3d", "eddington")])
 def test_m1_speed_bounds_match_oracle(m1, name, closure):
     w = _case(name)
