@@ -10,19 +10,24 @@
 //     row shifts (no LDS, no barrier).  Columns 0 and 15 are halo: their zones are
 //     reconstructed (their face states close the tile) but not updated, and their own outer
 //     neighbours are loaded by those two lanes;
-//   * a block is NI waves stacked in y and one group quad.  The lower NI - 1 rows are updated;
-//     the top row only computes the flux at its lower face (its zones are the next tile's first
-//     row).  Each row computes the flux at its lower y face from its own reconstruction and
-//     that of the row below, both from the plane's states in LDS; the two rows below the block
-//     and the row above it are loaded into LDS by all waves together.  The fluxes pass up
-//     through LDS;
+//   * a block is NI waves stacked in y and one group quad.  Each row computes the flux at its
+//     lower y face from its own reconstruction and that of the row below, both from the
+//     plane's states in LDS.  With AR (all rows) the NI rows are updated and the top row also
+//     computes the flux at the block's upper face (from the reconstruction of the row above;
+//     two rows above the block in LDS); without (the float blocks of 8 and 16 rows, whose
+//     register budget at four waves per SIMD has no room for the extra loads) the lower NI - 1
+//     rows are updated and the top row only computes the flux at its lower face (its zones are
+//     the next tile's first row; one row above the block in LDS).
+//     The two rows below the block and those above it are loaded into LDS by all waves
+//     together.  The fluxes pass through LDS;
 //   * the block marches along z over TM planes with a register window: every z face is
 //     computed once, from values each lane loads for its own column one plane ahead;
 //   * x faces are computed once (by the lane above the face), y faces once per block (the
 //     lower row's upper state is recomputed by the row above instead of exchanged), z faces
-//     once; only the halo columns and the top row repeat work of the neighbouring tiles.
-// Two block barriers per plane (after the states, after the y fluxes), which wait for LDS
-// only: the loads of the next plane stay in flight.
+//     once; only the halo columns and the faces between tiles repeat work of the neighbouring
+//     tiles.
+// One block barrier per plane (after the states), which waits for LDS only: the loads of the
+// next plane stay in flight.  The update of a plane follows the next plane's barrier.
 // Spherical grids (SPH): the same structure with the geometry of the lane's zone read from the
 // per-axis tables (volume-coordinate slopes, face scale factors for the realizability checks and
 // the fluxes, face weights and zone widths for the divergence, proper widths for the optical
@@ -44,14 +49,15 @@ namespace fm1 {
 constexpr int C3_TX = 16;   // x columns of a wave row (14 updated)
 
 // the value of the lane one column lower (row_shr:1) / higher (row_shl:1) in the same 16-lane
-// row; the lanes at the row's ends receive 0 (they never use it)
+// row; the lanes at the row's ends receive 0 (bound_ctrl: they never use it, and no register
+// has to be cleared first)
 template <typename R>
 __device__ __forceinline__ R col_prev(R v) {
-  return __builtin_amdgcn_update_dpp(R(0), v, 0x111, 0xf, 0xf, false);
+  return __builtin_amdgcn_update_dpp(R(0), v, 0x111, 0xf, 0xf, true);
 }
 template <typename R>
 __device__ __forceinline__ R col_next(R v) {
-  return __builtin_amdgcn_update_dpp(R(0), v, 0x101, 0xf, 0xf, false);
+  return __builtin_amdgcn_update_dpp(R(0), v, 0x101, 0xf, 0xf, true);
 }
 
 // The ghost rules of one axis, taken from the launch's table at each use (measured: faster
@@ -105,21 +111,26 @@ __device__ __forceinline__ void c3_barrier() {
 }
 
 // Rows of the plane held in LDS: the block's NI rows in slots 2 .. NI + 1, the two rows below
-// in slots 0, 1 and the row above in slot NI + 2.  The outer rows are loaded by all waves
-// together, one (slot, component) item per wave and load: the 4 state components of slots 0
-// and NI + 2, and the 4 state components, kappa and sigma of slot 1.
-constexpr int C3_NITEM = 14;
+// in slots 0, 1 and those above in slots NI + 2 (and NI + 3 where every row is updated).  The
+// outer rows are loaded by all waves together, one (slot, component) item per wave and load:
+// the 4 state components of slot 0, the 4 state components, kappa and sigma of slot 1; above
+// the block either those of slot NI + 2 and the 4 state components of NI + 3 (every row
+// updated), or the 4 state components of slot NI + 2.
+template <bool AR>
+constexpr int c3_nitem() { return AR ? 20 : 14; }
 
 // NI waves per block, W waves per SIMD (register budget 512 / W)
-template <typename S, int NI, int W, int LIM, bool SPH>
+template <typename S, int NI, int W, int LIM, bool SPH, bool AR>
 __global__ void __launch_bounds__(64 * NI) __attribute__((amdgpu_waves_per_eu(W)))
 k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
   using R = S;
   constexpr int TX = C3_TX;
-  constexpr int NS = NI + 3;                              // LDS row slots
-  constexpr int NHI = (C3_NITEM + NI - 1) / NI;           // outer-row items per wave
-  __shared__ R QS[6][NS][64];    // E, F_x, F_y, F_z, kappa, sigma of the plane's rows
-  __shared__ R FY[4][NI][64];    // y flux at the lower face of each of the block's rows
+  constexpr int NS = NI + (AR ? 4 : 3);                   // LDS row slots
+  constexpr int NIT = c3_nitem<AR>();
+  constexpr int NHI = (NIT + NI - 1) / NI;                // outer-row items per wave
+  // double-buffered by plane parity: one barrier per plane (see the plane loop)
+  __shared__ R QS[2][6][NS][64];    // E, F_x, F_y, F_z, kappa, sigma of the plane's rows
+  __shared__ R FY[2][4][NI + AR][64];  // y flux at the lower face of each row (and the block's upper face)
   __shared__ double red_e[NI], red_m[NI];
   __shared__ int red_u[NI], red_p[NI];
 
@@ -128,6 +139,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
   const int x = lane & (TX - 1), gq = lane >> 4;
   const int sw = w + 2;                                   // the wave's slot
   const bool top = w == NI - 1;
+  const bool idle = !AR && top;          // a row that only computes its lower face flux
 
   // tile of the block (XCD-aware renumbering; the group quads of a tile adjacent)
   const int b = blockIdx.x;
@@ -143,10 +155,10 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
   const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2], G = a.G;
   const int g = gb * 4 + gq;
   const int xz = tx * (TX - 2) + x - 1;          // zone of the lane's column
-  const int y0 = ty * (NI - 1);                  // zone of slot 2 (the top row is the next tile's first)
+  const int y0 = ty * (AR ? NI : NI - 1);        // zone of slot 2
   const int yz = y0 + w;                         // zone of the wave's row
   const int mbeg = tz * tl.TM, mend = min(mbeg + tl.TM, n2);
-  const bool upd = !top && yz < n1 && x >= 1 && x <= TX - 2 && xz < n0;
+  const bool upd = !idle && yz < n1 && x >= 1 && x <= TX - 2 && xz < n0;
   const int PL = n0 * n1 * G;                    // elements of a z plane
 
   const C3Axis ax0 = c3_axis<0>(a), ax1 = c3_axis<1>(a), ax2 = c3_axis<2>(a);
@@ -178,12 +190,13 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
   const S* hsrc[NHI];
   for (int k = 0; k < NHI; ++k) {
     int it = w + k * NI;
-    if (it >= C3_NITEM) it = -1;
+    if (it >= NIT) it = -1;
     int slot = 0, comp = 0;
     if (it >= 0) {
       if (it < 4) { slot = 0; comp = it; }
       else if (it < 10) { slot = 1; comp = it - 4; }
-      else { slot = NI + 2; comp = it - 10; }
+      else if (!AR || it < 16) { slot = NI + 2; comp = it - 10; }
+      else { slot = NI + 3; comp = it - 16; }
     }
     int hys, hyf;
     c3_src(ax1, y0 - 2 + slot, hys, hyf);
@@ -294,7 +307,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
     const R ksb = R(a.kap[ob + cb]) + R(a.sig[ob + cb]);
     // face mbeg - 1/2 from zones mbeg - 1 (upper state) and mbeg (lower state)
     for (int c = 0; c < 4; ++c) hiM[c] = fPrev[c] = R(0);
-    if (!top) {
+    if (!idle) {
       R lo[4], hiP[4];
       reconstruct<R, SPH, 3, LIM>(a, geo, 2, NG, qa, qb, q0, ihz, ihz, true, true, lo, hiP);
       reconstruct<R, SPH, 3, LIM>(a, geo, 2, NG, qb, q0, q1, ihz, ihz, true, true, lo, hiM);
@@ -313,24 +326,34 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
     load_items(plane(mbeg, pmu), mbeg);
   }
 
-  for (int m = mbeg; m < mend; ++m) {
-    // ---- consume the values loaded one plane ago; the plane's rows to LDS ----
+  // The update of plane m needs the y flux that the row above computes for plane m: it runs
+  // after the next plane's barrier, from values the lane keeps (the state, the x and z part of
+  // the divergence and the flux at its lower y face, kappa, sigma, B).  With the LDS arrays
+  // double-buffered by plane parity, the one barrier per plane orders every LDS access: a
+  // buffer written for plane m was last read for plane m - 2, before the barrier of m - 1.
+  R qU[4], accU[4], fyU[4], kU = R(0), sU = R(0), BU = R(0);
+  for (int c = 0; c < 4; ++c) qU[c] = accU[c] = fyU[c] = R(0);
+  for (int m = mbeg; m <= mend; ++m) {
+    const int buf = m & 1;
+    const bool live = m < mend;       // the last pass only updates plane mend - 1
     R q2[4], qo[4];
-    c3_fix(Pr, lm ^ Ppm, q2);            // plane m + 2
-    c3_fix(Po, lme ^ Popm, qo);          // outer x neighbour, plane m
-    if (SPH && xinf) inflow_state(ex, ey, q2);
-    if (SPH && xinfe) inflow_state(ex - 1, ey, qo);
-    for (int c = 0; c < 4; ++c) QS[c][sw][lane] = q0[c];
-    QS[4][sw][lane] = k0;
-    QS[5][sw][lane] = s0;
-    for (int k = 0; k < NHI; ++k)
-      if (hslot[k] >= 0) {
-        const int zflip = (hcomp[k] == 3) ? (Popm >> 2) & 1 : 0;
-        QS[hcomp[k]][hslot[k]][lane] = (hmask[k] ^ zflip) ? -Ph[k] : Ph[k];
-      }
-    // ---- loads for the next plane: q(m + 3), outer neighbours of m + 1, kappa, sigma of m + 2
-    // and B of m + 1 (indices clamped into the ghost range; the last planes' are not used) ----
-    {
+    if (live) {
+      // ---- consume the values loaded one plane ago; the plane's rows to LDS ----
+      c3_fix(Pr, lm ^ Ppm, q2);            // plane m + 2
+      c3_fix(Po, lme ^ Popm, qo);          // outer x neighbour, plane m
+      if (SPH && xinf) inflow_state(ex, ey, q2);
+      if (SPH && xinfe) inflow_state(ex - 1, ey, qo);
+      for (int c = 0; c < 4; ++c) QS[buf][c][sw][lane] = q0[c];
+      QS[buf][4][sw][lane] = k0;
+      QS[buf][5][sw][lane] = s0;
+      for (int k = 0; k < NHI; ++k)
+        if (hslot[k] >= 0) {
+          const int zflip = (hcomp[k] == 3) ? (Popm >> 2) & 1 : 0;
+          QS[buf][hcomp[k]][hslot[k]][lane] = (hmask[k] ^ zflip) ? -Ph[k] : Ph[k];
+        }
+      // ---- loads for the next plane: q(m + 3), outer neighbours of m + 1, kappa, sigma of
+      // m + 2 and B of m + 1 (indices clamped into the ghost range; the last planes' are not
+      // used) ----
       const int o3 = plane_s(min(m + 3, n2 + 1), zsh, Ppm);
       c3_load<S, R>(a, o3 + cb, Pr);
       const int oe = plane_s(min(m + 1, n2 + 1), zsh, Popm);
@@ -339,6 +362,61 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
       load_items(SPH ? plane(min(m + 1, n2 + 1), pmu) : oe, min(m + 1, n2 + 1));
     }
     c3_barrier();
+    // ---- update of plane m - 1 (every lane of the inner rows computes; the lanes that hold a
+    // zone of the tile store) ----
+    if (m > mbeg && !idle) {
+      const int mu = m - 1;
+      R acc[4];
+      if constexpr (SPH) {
+        const R wl = geo.wf[1][ey], wh = geo.wf[1][ey + 1], iW = geo.iW[1][ey];
+        for (int c = 0; c < 4; ++c) acc[c] = accU[c] + (wh * FY[buf ^ 1][c][w + 1][lane] - wl * fyU[c]) * iW;
+      } else {
+        for (int c = 0; c < 4; ++c) acc[c] = accU[c] + (FY[buf ^ 1][c][w + 1][lane] - fyU[c]) * idx1;
+      }
+      const int zg = upd ? (mu * n1 + yz) * n0 * G + xz * G + g : 0;
+      R Um[4];
+      for (int c = 0; c < 4; ++c) Um[c] = qU[c] - dtR * acc[c];
+      if constexpr (SPH) {
+        // geometric source terms of the covariant flux components (cell-centred h)
+        R h[3], ih[3], P[9], Sg[3];
+        cell_h<R, SPH>(geo, ex, ey, h);
+        cell_ih<R, SPH>(geo, ex, ey, ih);
+        closure_full<R, SPH, 3>(qU, ih, R(a.c), a.closure, P);
+        geometric_source<R>(P, h, ih, geo.gam + 4 * min(max(yz, 0), n1 - 1), R(a.c), Sg);
+        for (int cc = 0; cc < 3; ++cc) Um[1 + cc] += dtR * Sg[cc];
+      }
+      if (a.Ea) {
+        // second Runge-Kutta stage: U^- = (U^n + U* + dt L(U*)) / 2
+        Um[0] = R(0.5) * (R(a.Ea[zg]) + Um[0]);
+        for (int c = 0; c < 3; ++c) Um[1 + c] = R(0.5) * (R(a.Fa[c][zg]) + Um[1 + c]);
+      }
+      S Eo, F1[3];
+      double dz = 0.0;
+      if (a.src) {
+        const double ck = cdt * (double)kU;
+        dz = source_zone<S, R, SPH, 3>(a, geo, xz, yz, Um, ck, cdt * ((double)kU + (double)sU), ck * (double)BU,
+                                         want_diag && upd, Vz, zd, Eo, F1);
+      } else {
+        Eo = S(Um[0]);
+        for (int c = 0; c < 3; ++c) F1[c] = S(Um[1 + c]);
+      }
+      if (upd) {
+        a.Eo[zg] = Eo;
+        for (int c = 0; c < 3; ++c) a.Fo[c][zg] = F1[c];
+      }
+      if (a.dEm) {
+        // the zone's sum over the block's 4 groups (lanes 16 apart)
+        dz = upd ? dz : 0.0;
+        dz += __shfl_xor(dz, 16);
+        dz += __shfl_xor(dz, 32);
+        if (upd && gq == 0) {
+          const int64_t zone = ((int64_t)mu * n1 + yz) * n0 + xz;
+          if (tl.ngb == 1) a.dEm[zone] = -dz;
+          else a.dzp[(int64_t)gb * a.nzones + zone] = dz;
+        }
+      }
+    }
+    if (!live) break;
     const R ks0 = k0 + s0;
     // ---- y: the flux at the lower y face of the row, from the reconstructions of the row
     // below (upper state) and of the row (lower state) ----
@@ -346,11 +424,11 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
     {
       R qa[4], qb[4], qc[4], lo[4], hiP[4], hiY[4], loY[4];
       for (int c = 0; c < 4; ++c) {
-        qa[c] = QS[c][sw - 2][lane];
-        qb[c] = QS[c][sw - 1][lane];
+        qa[c] = QS[buf][c][sw - 2][lane];
+        qb[c] = QS[buf][c][sw - 1][lane];
       }
-      const R ksb = QS[4][sw - 1][lane] + QS[5][sw - 1][lane];
-      for (int c = 0; c < 4; ++c) qc[c] = QS[c][sw + 1][lane];
+      const R ksb = QS[buf][4][sw - 1][lane] + QS[buf][5][sw - 1][lane];
+      for (int c = 0; c < 4; ++c) qc[c] = QS[buf][c][sw + 1][lane];
       if constexpr (SPH) {
         // theta faces: scale factors at the face centres of the lane's column; a face on the
         // polar axis is closed (no flux, its face states not checked)
@@ -370,15 +448,43 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
                                                proper_width<R, SPH>(geo, 1, ex, ey)),
                                     fy);
         }
+        if (AR && top && yz < n1) {
+          // the block's upper face (ey + 1 <= n1 - 1 + NG + 1: inside the face tables)
+          R qd[4], loA[4], hiA[4], ih2[3], fu[4];
+          for (int c = 0; c < 4; ++c) qd[c] = QS[buf][c][sw + 2][lane];
+          const R ksa = QS[buf][4][sw + 1][lane] + QS[buf][5][sw + 1][lane];
+          face_ih<R, SPH>(geo, 1, ex, ey, ey + 2, ih2);
+          const bool o2f = geo.wf[1][ey + 2] != R(0);
+          reconstruct<R, SPH, 3, LIM>(a, geo, 1, ey + 1, q0, qc, qd, ih1, ih2, o1f, o2f, loA, hiA);
+          for (int c = 0; c < 4; ++c) fu[c] = R(0);
+          if (o1f) {
+            R hf[3];
+            face_h<R, SPH>(geo, 1, ex, ey, ey + 1, hf);
+            hll<R, SPH, 3, (LIM < 0)>(a, 1, hiY, loA, hf, ih1,
+                                      epsilon_of(ks0, ksa, proper_width<R, SPH>(geo, 1, ex, ey),
+                                                 proper_width<R, SPH>(geo, 1, ex, ey + 1)),
+                                      fu);
+          }
+          for (int c = 0; c < 4; ++c) FY[buf][c][NI][lane] = fu[c];
+        }
       } else {
         reconstruct<R, false, 3, LIM>(a, geo, 1, 0, qa, qb, q0, hone, hone, true, true, lo, hiP);
         reconstruct<R, false, 3, LIM>(a, geo, 1, 0, qb, q0, qc, hone, hone, true, true, loY, hiY);
         hll<R, false, 3, (LIM < 0)>(a, 1, hiP, loY, hone, hone, epsilon_of(ksb, ks0, dx1, dx1), fy);
+        if (AR && top && yz < n1) {
+          // the block's upper face
+          R qd[4], loA[4], hiA[4], fu[4];
+          for (int c = 0; c < 4; ++c) qd[c] = QS[buf][c][sw + 2][lane];
+          const R ksa = QS[buf][4][sw + 1][lane] + QS[buf][5][sw + 1][lane];
+          reconstruct<R, false, 3, LIM>(a, geo, 1, 0, q0, qc, qd, hone, hone, true, true, loA, hiA);
+          hll<R, false, 3, (LIM < 0)>(a, 1, hiY, loA, hone, hone, epsilon_of(ks0, ksa, dx1, dx1), fu);
+          for (int c = 0; c < 4; ++c) FY[buf][c][NI][lane] = fu[c];
+        }
       }
-      for (int c = 0; c < 4; ++c) FY[c][w][lane] = fy[c];
+      for (int c = 0; c < 4; ++c) FY[buf][c][w][lane] = fy[c];
     }
     R acc[4] = {R(0), R(0), R(0), R(0)};
-    if (!top) {
+    if (!idle) {
       // ---- x: reconstruction, the flux at the lower x face of the column (the upper state
       // of the column below by a lane shift), the x part of the divergence ----
       {
@@ -424,64 +530,17 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
         }
       }
     }
-    c3_barrier();
-    // ---- update of the row's zones (every lane of the inner rows computes; the lanes that
-    // hold a zone of the tile store) ----
-    if (!top) {
-      if constexpr (SPH) {
-        const R wl = geo.wf[1][ey], wh = geo.wf[1][ey + 1], iW = geo.iW[1][ey];
-        for (int c = 0; c < 4; ++c) acc[c] += (wh * FY[c][top ? w : w + 1][lane] - wl * fy[c]) * iW;
-      } else {
-        for (int c = 0; c < 4; ++c) acc[c] += (FY[c][top ? w : w + 1][lane] - fy[c]) * idx1;
-      }
-      const int zg = upd ? (m * n1 + yz) * n0 * G + xz * G + g : 0;
-      R Um[4];
-      for (int c = 0; c < 4; ++c) Um[c] = q0[c] - dtR * acc[c];
-      if constexpr (SPH) {
-        // geometric source terms of the covariant flux components (cell-centred h)
-        R h[3], ih[3], P[9], Sg[3];
-        cell_h<R, SPH>(geo, ex, ey, h);
-        cell_ih<R, SPH>(geo, ex, ey, ih);
-        closure_full<R, SPH, 3>(q0, ih, R(a.c), a.closure, P);
-        geometric_source<R>(P, h, ih, geo.gam + 4 * min(max(yz, 0), n1 - 1), R(a.c), Sg);
-        for (int cc = 0; cc < 3; ++cc) Um[1 + cc] += dtR * Sg[cc];
-      }
-      if (a.Ea) {
-        // second Runge-Kutta stage: U^- = (U^n + U* + dt L(U*)) / 2
-        Um[0] = R(0.5) * (R(a.Ea[zg]) + Um[0]);
-        for (int c = 0; c < 3; ++c) Um[1 + c] = R(0.5) * (R(a.Fa[c][zg]) + Um[1 + c]);
-      }
-      S Eo, F1[3];
-      double dz = 0.0;
-      if (a.src) {
-        const double ck = cdt * (double)k0;
-        dz = source_zone<S, R, SPH, 3>(a, geo, xz, yz, Um, ck, cdt * ((double)k0 + (double)s0), ck * (double)PB,
-                                         want_diag && upd, Vz, zd, Eo, F1);
-      } else {
-        Eo = S(Um[0]);
-        for (int c = 0; c < 3; ++c) F1[c] = S(Um[1 + c]);
-      }
-      if (upd) {
-        a.Eo[zg] = Eo;
-        for (int c = 0; c < 3; ++c) a.Fo[c][zg] = F1[c];
-      }
-      if (a.dEm) {
-        // the zone's sum over the block's 4 groups (lanes 16 apart)
-        dz = upd ? dz : 0.0;
-        dz += __shfl_xor(dz, 16);
-        dz += __shfl_xor(dz, 32);
-        if (upd && gq == 0) {
-          const int64_t zone = ((int64_t)m * n1 + yz) * n0 + xz;
-          if (tl.ngb == 1) a.dEm[zone] = -dz;
-          else a.dzp[(int64_t)gb * a.nzones + zone] = dz;
-        }
-      }
-    }
-    // ---- advance the window ----
+    // ---- keep what the update of plane m needs; advance the window ----
     for (int c = 0; c < 4; ++c) {
+      qU[c] = q0[c];
+      accU[c] = acc[c];
+      fyU[c] = fy[c];
       q0[c] = q1[c];
       q1[c] = q2[c];
     }
+    kU = k0;
+    sU = s0;
+    BU = PB;
     k0 = Pk;
     s0 = Ps;
     {
@@ -527,6 +586,9 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
 }
 
 // ------------------------------------------------------------------------------------------
+// every row of a block updated: double blocks, and float blocks of 4 rows (three waves per SIMD)
+static bool c3_all_rows(const fornax_m1_desc& D, int NR) { return D.precision == FORNAX_FP64 || NR == 4; }
+
 C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
   C3Tile tl{};
   tl.nblocks = 0;
@@ -534,9 +596,9 @@ C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
   const bool sph = D.coord == FORNAX_SPHERICAL_LOGR;
   if (!sph && D.coord != FORNAX_CARTESIAN) return tl;
   // the instantiated block heights: 6, 8 or 12 rows in double, 4, 8 or 16 in float (spherical
-  // grids: 8 rows)
+  // grids: 8 rows, or 4 in float)
   const bool dbl = D.precision == FORNAX_FP64;
-  if (!(NR == 8 || (!sph && (NR == (dbl ? 6 : 4) || NR == (dbl ? 12 : 16))))) return tl;
+  if (!(NR == 8 || (!dbl && NR == 4) || (!sph && (NR == (dbl ? 6 : 4) || NR == (dbl ? 12 : 16))))) return tl;
   if (TM < 1) return tl;
   // inflow only on the lower x1 boundary of spherical grids; a polar axis (theta, spherical
   // grids) needs a periodic phi axis of even length
@@ -550,7 +612,8 @@ C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
   tl.NR = NR;
   tl.TM = TM;
   tl.ntx = (D.n[0] + C3_TX - 3) / (C3_TX - 2);
-  tl.nty = (D.n[1] + NR - 2) / (NR - 1);
+  // tiles of NR rows, or NR - 1 (the top row is the next tile's first)
+  tl.nty = c3_all_rows(D, NR) ? (D.n[1] + NR - 1) / NR : (D.n[1] + NR - 2) / (NR - 1);
   tl.ntz = (D.n[2] + TM - 1) / TM;
   tl.ngb = D.ngroups / 4;
   const int64_t nb = (int64_t)tl.ntx * tl.nty * tl.ntz * tl.ngb;
@@ -563,11 +626,14 @@ C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
 
 C3Tile choose_c3_tile(const fornax_m1_desc& D, int cus) {
   (void)cus;
-  const int NR = 8;  // 8 waves per block, one y-row each; the top row only supplies its face flux
-  // planes per block: Cartesian 64 in double (1.4 % faster than 32 at 192^3 x 12), 32 in float;
-  // spherical 16 (at 256 x 64 x 128 x 20: 4.66 ms in double against 5.00 with 64 planes)
-  if (D.coord == FORNAX_SPHERICAL_LOGR) return make_c3_tile(D, NR, 16);
-  return make_c3_tile(D, NR, D.precision == FORNAX_FP64 ? 64 : 32);
+  // one y row per wave.  Cartesian: 8 rows and 64 planes per block (at 192^3 x 12, 2.5 % faster
+  // than 32 planes in double, 0.7 % in float; float blocks of 4 rows at three waves per SIMD:
+  // 11 % slower).  Spherical (256 x 64 x 128 x 20): double 8 rows and 32 planes (1 % faster
+  // than 16); float 4 rows (every row updated, three waves per SIMD) and 16 planes, 14 % faster
+  // than 8 rows at four waves per SIMD, which spill registers.
+  const bool dbl = D.precision == FORNAX_FP64;
+  if (D.coord == FORNAX_SPHERICAL_LOGR) return dbl ? make_c3_tile(D, 8, 32) : make_c3_tile(D, 4, 16);
+  return make_c3_tile(D, 8, 64);
 }
 
 template <typename S>
@@ -579,24 +645,26 @@ int launch_c3(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipSt
   const bool mm = a.limiter == FORNAX_LIMITER_MINMOD && a.wavespeed == FORNAX_WAVESPEED_LIGHT;
   const bool sph = ctx->desc.coord == FORNAX_SPHERICAL_LOGR;
   dim3 grid(tl.nblocks), block(64 * tl.NR);
-#define FM1_C3(NRV, WV, SP)                                                                                   \
-  do {                                                                                                        \
-    if (mm)                                                                                                   \
-      hipLaunchKernelGGL((k_step_3d<S, NRV, WV, FORNAX_LIMITER_MINMOD, SP>), grid, block, 0, st, a, geo, tl); \
-    else                                                                                                      \
-      hipLaunchKernelGGL((k_step_3d<S, NRV, WV, -1, SP>), grid, block, 0, st, a, geo, tl);                    \
+#define FM1_C3(NRV, WV, SP, AR)                                                                                   \
+  do {                                                                                                            \
+    if (mm)                                                                                                       \
+      hipLaunchKernelGGL((k_step_3d<S, NRV, WV, FORNAX_LIMITER_MINMOD, SP, AR>), grid, block, 0, st, a, geo, tl); \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_step_3d<S, NRV, WV, -1, SP, AR>), grid, block, 0, st, a, geo, tl);                    \
   } while (0)
-  // waves per SIMD: the register budget of each precision (double: 168 or 256 VGPRs; float: 128)
+  // waves per SIMD: the register budget of each shape (double: 168 or 256 VGPRs; float: 128,
+  // or 168 for the 4-row blocks)
   if constexpr (sizeof(S) == 8) {
-    if (sph) FM1_C3(8, 2, true);
-    else if (tl.NR == 6) FM1_C3(6, 3, false);
-    else if (tl.NR == 8) FM1_C3(8, 2, false);
-    else FM1_C3(12, 3, false);
+    if (sph) FM1_C3(8, 2, true, true);
+    else if (tl.NR == 6) FM1_C3(6, 3, false, true);
+    else if (tl.NR == 8) FM1_C3(8, 2, false, true);
+    else FM1_C3(12, 3, false, true);
   } else {
-    if (sph) FM1_C3(8, 4, true);
-    else if (tl.NR == 4) FM1_C3(4, 4, false);
-    else if (tl.NR == 8) FM1_C3(8, 4, false);
-    else FM1_C3(16, 4, false);
+    if (sph && tl.NR == 4) FM1_C3(4, 3, true, true);
+    else if (sph) FM1_C3(8, 4, true, false);
+    else if (tl.NR == 4) FM1_C3(4, 3, false, true);
+    else if (tl.NR == 8) FM1_C3(8, 4, false, false);
+    else FM1_C3(16, 4, false, false);
   }
 #undef FM1_C3
   Tile lt{};
