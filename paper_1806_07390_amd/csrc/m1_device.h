@@ -349,39 +349,44 @@ __device__ __forceinline__ void closure_row(const R q[4], const R ih[3], int d, 
     // scaled by 2^600 (exact) and the row scaled back (only in waves that hold one).
     R Fh[3] = {R(0), R(0), R(0)};
     for (int k = 0; k < ND; ++k) Fh[k] = SPH ? q[1 + k] * ih[k] : q[1 + k];
-    R cE = c * E;
-    // the rare paths (tiny states; |f| > 1) are uniform branches taken only by waves that hold
-    // such a state; the empty asm keeps the compiler from computing them in every wave
-    const bool tiny = __builtin_amdgcn_ballot_w64(cE < R(0x1p-450)) != 0;
-    bool scl = false;
-    if (tiny) {
-      __asm__ volatile("");
-      scl = cE < R(0x1p-450);
-      if (scl) {
-        cE *= R(0x1p600);
-        for (int k = 0; k < ND; ++k) Fh[k] *= R(0x1p600);
-      }
-    }
+    const R cE = c * E;
     R F2 = R(0);
     for (int k = 0; k < ND; ++k) F2 += Fh[k] * Fh[k];
     const R A = cE * cE;
-    if (__builtin_amdgcn_ballot_w64(F2 > A)) {
-      __asm__ volatile("");
-      if (F2 > A) {
-        // |f| > 1: the direction of F with |f| = 1
-        const R sc = cE * rcp_(sqrt_(F2));
-        for (int k = 0; k < ND; ++k) Fh[k] *= sc;
-        F2 = A;
-      }
+    {
+      const R S = sqrt_(R(4) * A - R(3) * F2);
+      const R iso = (S - cE) * rcp_(R(3) * c);   // c is uniform: hoisted
+      const R af = R(3) * rcp_(c * (R(2) * cE + S)) * Fh[d];
+      for (int k = 0; k < ND; ++k) P[k] = af * Fh[k] + (k == d ? iso : R(0));
     }
-    const R S = sqrt_(R(4) * A - R(3) * F2);
-    const R iso = (S - cE) * rcp_(R(3) * c);   // c is uniform: hoisted
-    const R af = R(3) * rcp_(c * (R(2) * cE + S)) * Fh[d];
-    for (int k = 0; k < ND; ++k) P[k] = af * Fh[k] + (k == d ? iso : R(0));
-    if (tiny) {
+    // the rare states are evaluated again, in a branch taken only by waves that hold one (the
+    // empty asm keeps the compiler from computing it in every wave): |f| > 1 with the direction
+    // of F at |f| = 1, and states with cE below 2^-450, whose squares could underflow, scaled
+    // by 2^600 (exact) and the row scaled back
+    const bool rare = cE < R(0x1p-450) || F2 > A;
+    if (__builtin_amdgcn_ballot_w64(rare)) {
       __asm__ volatile("");
-      if (scl)
-        for (int k = 0; k < ND; ++k) P[k] *= R(0x1p-600);
+      if (rare) {
+        const bool scl = cE < R(0x1p-450);
+        const R sc0 = scl ? R(0x1p600) : R(1);
+        const R cEs = cE * sc0;
+        R F2s = R(0);
+        for (int k = 0; k < ND; ++k) {
+          Fh[k] *= sc0;
+          F2s += Fh[k] * Fh[k];
+        }
+        const R As = cEs * cEs;
+        if (F2s > As) {
+          const R sc = cEs * rcp_(sqrt_(F2s));
+          for (int k = 0; k < ND; ++k) Fh[k] *= sc;
+          F2s = As;
+        }
+        const R S = sqrt_(R(4) * As - R(3) * F2s);
+        const R iso = (S - cEs) * rcp_(R(3) * c);
+        const R af = R(3) * rcp_(c * (R(2) * cEs + S)) * Fh[d];
+        const R sb = scl ? R(0x1p-600) : R(1);
+        for (int k = 0; k < ND; ++k) P[k] = (af * Fh[k] + (k == d ? iso : R(0))) * sb;
+      }
     }
     return;
   }

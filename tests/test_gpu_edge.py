@@ -105,3 +105,90 @@ def test_unrealizable_nonpositive_and_extreme_opacity_inputs(m1, G):
     w.sigma = np.where(rng.random(shape) > 0.95, 1e6, w.sigma)
     dg = _run_both(m1, w, f"unrealizable G={G}")
     assert dg["n_nonpositive"] >= 0 and dg["n_unrealizable"] >= 0
+
+
+def _rare_case(geom, steps):
+    """A 3-D grid of the whole-zone 3-D kernel's kind (group count a multiple of 4) with random
+    positive states; h: the scale factors at the zone centres (covariant F = h F^)."""
+    if geom == "core3d":
+        w = wl.core3d(n=20, G=8, steps=steps)
+        h = [np.ones(w.E.shape)] * 3
+    else:
+        w = wl.sphere3d(nr=20, nth=12, nph=8, G=4, steps=steps)
+        r = np.exp(wl._centres(w.lo[0], w.hi[0], w.n[0]))
+        th = wl._centres(w.lo[1], w.hi[1], w.n[1])
+        R, TH = r[None, None, :, None], th[None, :, None, None]
+        h = [np.broadcast_to(R, w.E.shape), np.broadcast_to(R, w.E.shape), np.broadcast_to(R * np.sin(TH), w.E.shape)]
+    rng = np.random.default_rng(33)
+    w.E = np.exp(rng.normal(0.0, 0.8, w.E.shape)) * w.B
+    return w, h, rng
+
+
+def _unit_vectors(rng, shape):
+    v = rng.normal(size=(3,) + shape)
+    return v / np.linalg.norm(v, axis=0)
+
+
+@pytest.mark.parametrize("geom", ["core3d", "sphere3d"])
+def test_3d_kernel_rare_states(m1, geom):
+    """The whole-zone 3-D kernel (Cartesian and spherical) on states that take the closure's
+    rare path: a quarter of the zone-groups start with E <= 0 or |F^| = 1.5 cE, opacities span
+    0 to 1e12.  FP64 and MIXED against the oracle, with the counts."""
+    w, h, rng = _rare_case(geom, steps=3)
+    shape = w.E.shape
+    pick = rng.random(shape)
+    w.E = np.where(pick < 0.08, -0.1 * w.E, w.E)
+    w.E = np.where((pick >= 0.08) & (pick < 0.12), 0.0, w.E)
+    over = (pick >= 0.12) & (pick < 0.25)
+    v = _unit_vectors(rng, shape)
+    w.F = [np.where(over, 1.5 * w.c * np.abs(w.E) * v[k] * h[k], 0.2 * w.c * w.E * v[k] * h[k]) for k in range(3)]
+    kap = rng.random(shape)
+    w.kappa = np.where(kap < 0.2, 0.0, np.where(kap > 0.9, 1e12, w.kappa))
+    dg = _run_both(m1, w, f"3-D kernel rare states {geom}")
+    assert dg["n_unrealizable"] > 0 and dg["n_nonpositive"] > 0
+
+
+@pytest.mark.parametrize("geom", ["core3d", "sphere3d"])
+def test_3d_kernel_tiny_states(m1, geom):
+    """States scaled by 1e-140 (cE below 2^-450: the closure evaluates them scaled by 2^600),
+    a fifth of them also not realizable (|F^| = 1.5 cE), in a block of zones without emission;
+    FP64, one step: the zones whose stencil lies inside the block agree with the oracle to the
+    element-wise FP64 gate relative to their own energy (floor PW_FLOOR |E| for E, PW_FLOOR c |E| h
+    for F), the whole grid element by element."""
+    from tests.parity_util import PW_FLOOR, TOL_PW_FP64, check_pointwise
+    w, h, rng = _rare_case(geom, steps=1)
+    shape = w.E.shape
+    v = _unit_vectors(rng, shape)
+    over = rng.random(shape) < 0.2
+    w.F = [np.where(over, 1.5, 0.3) * w.c * w.E * v[k] * h[k] for k in range(3)]
+    # array axes: z (phi), y (theta), x (r), group; the inner zones are 2 zones inside the
+    # block in every direction (the whole periodic phi range on the spherical grid)
+    blk = np.zeros(shape, dtype=bool)
+    inner = np.zeros(shape, dtype=bool)
+    if geom == "core3d":
+        blk[2:12, 2:12, 2:12] = True
+        inner[4:10, 4:10, 4:10] = True
+    else:
+        blk[:, 2:10, 3:15] = True
+        inner[:, 4:8, 5:13] = True
+    sc = np.where(blk, 1e-140, 1.0)
+    w.E = w.E * sc
+    w.F = [f * sc for f in w.F]
+    w.B = np.where(blk, 0.0, w.B)
+    p = problem_of(w)
+    dt = w.dt if w.dt is not None else orc.max_dt(p, w.cfl)
+    E, F, dg = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, 1, inflow=w.inflow)
+    ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64))
+    Eg, Fg, dgg = gpu_run(ctx, w, dt, 1, diag=True)
+    e = rel_l1(Eg, Fg, E, F, w.c)
+    check_pointwise(e, True, f"tiny states {geom}")
+    assert 0 < np.abs(E[inner]).max() < 1e-130
+    relE = np.abs(Eg[inner] - E[inner]) / ((1.0 + PW_FLOOR) * np.abs(E[inner]))
+    relF = [np.abs(Fg[k][inner] - F[k][inner]) / (np.abs(F[k][inner]) + PW_FLOOR * w.c * np.abs(E[inner]) * h[k][inner])
+            for k in range(3)]
+    say(f"tiny states {geom}: rel-L1 {e[0]:.2e} {e[1]:.2e}; inner zones element-wise E {relE.max():.2e} "
+        f"F {max(r.max() for r in relF):.2e}")
+    assert relE.max() <= TOL_PW_FP64
+    for k in range(3):
+        assert relF[k].max() <= TOL_PW_FP64, k
+    assert int(dgg["n_unrealizable"][0]) == dg["n_unrealizable"]
