@@ -259,9 +259,9 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
   R q0[4], q1[4], hiM[4], fPrev[4];
   R k0, s0;
   // values in flight: q(m + 2), the outer x neighbour (columns 0, 15) of plane m and the
-  // wave's outer-row items of plane m, loaded at the top of the plane before; kappa, sigma of
-  // m + 1 and B of m, loaded at the end of the plane before
-  R Pr[4], Po[4], Ph[NHI], Pk, Ps, PB;
+  // wave's outer-row items of plane m, kappa, sigma of m + 1 (Pk, Ps) and B of m (PB), all
+  // loaded at the top of the plane before (Pk2, Ps2, PB2: those of the next plane)
+  R Pr[4], Po[4], Ph[NHI], Pk, Ps, PB, Pk2, Ps2, PB2;
   int Ppm, Popm;
   // the wave's outer-row items of plane m (element offset off of the unshifted plane m)
   auto load_items = [&](int off, int m) {
@@ -360,6 +360,12 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
       if (xedge) c3_load<S, R>(a, oe + ceb, Po);
       int pmu;
       load_items(SPH ? plane(min(m + 1, n2 + 1), pmu) : oe, min(m + 1, n2 + 1));
+      // kappa, sigma of m + 2 and B of m + 1 (they move into the window at the end of the plane:
+      // loaded here, a plane before, so that no wait for the loads in flight falls there)
+      const int ok = plane_s(min(m + 2, n2 + 1), zsh, pmu);
+      Pk2 = R(a.kap[ok + cb]);
+      Ps2 = R(a.sig[ok + cb]);
+      PB2 = R(a.B[min(m + 1, n2 - 1) * PL + cbb]);
     }
     c3_barrier();
     // ---- update of plane m - 1 (every lane of the inner rows computes; the lanes that hold a
@@ -543,13 +549,9 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
     BU = PB;
     k0 = Pk;
     s0 = Ps;
-    {
-      int pk;
-      const int ok = plane_s(min(m + 2, n2 + 1), zsh, pk);
-      Pk = R(a.kap[ok + cb]);
-      Ps = R(a.sig[ok + cb]);
-      PB = R(a.B[min(m + 1, n2 - 1) * PL + cbb]);
-    }
+    Pk = Pk2;
+    Ps = Ps2;
+    PB = PB2;
   }
 
   if (!want_diag) return;
