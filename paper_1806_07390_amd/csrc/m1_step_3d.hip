@@ -60,6 +60,29 @@ __device__ __forceinline__ R col_next(R v) {
   return __builtin_amdgcn_update_dpp(R(0), v, 0x101, 0xf, 0xf, true);
 }
 
+// v of this lane plus v of the lane 16 (S = 16) or 32 (S = 32) apart, by the row swaps of
+// gfx950 (VALU; the lane sums are formed in the same order as a shuffle sum would)
+template <int S>
+__device__ __forceinline__ double lane_pair_sum(double v) {
+  struct W {
+    unsigned lo, hi;
+  };
+  const W w = __builtin_bit_cast(W, v);
+  W a, b;
+  if constexpr (S == 16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(w.lo, w.lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(w.hi, w.hi, false, false);
+    a = W{l[0], h[0]};
+    b = W{l[1], h[1]};
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(w.lo, w.lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(w.hi, w.hi, false, false);
+    a = W{l[0], h[0]};
+    b = W{l[1], h[1]};
+  }
+  return __builtin_bit_cast(double, a) + __builtin_bit_cast(double, b);
+}
+
 // The ghost rules of one axis, taken from the launch's table at each use (measured: faster
 // than copies of the table held in scalar registers for the whole kernel, which crowd out the
 // other uniform values).
@@ -413,8 +436,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
       if (a.dEm) {
         // the zone's sum over the block's 4 groups (lanes 16 apart)
         dz = upd ? dz : 0.0;
-        dz += __shfl_xor(dz, 16);
-        dz += __shfl_xor(dz, 32);
+        dz = lane_pair_sum<32>(lane_pair_sum<16>(dz));
         if (upd && gq == 0) {
           const int64_t zone = ((int64_t)mu * n1 + yz) * n0 + xz;
           if (tl.ngb == 1) a.dEm[zone] = -dz;
