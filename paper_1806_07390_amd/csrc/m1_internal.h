@@ -132,6 +132,17 @@ struct StepArgs : StepArgsBase {
   int* p_nnp;
 };
 
+// The prescribed velocity of the velocity step: coordinate components on the faces of each
+// direction, the group edges; Fn (nullable): the flux components of U^n, given when the
+// transport of Step 1 ran without the zone-local velocity terms of the flux rows, which the
+// frequency step then adds.
+template <typename S>
+struct VelArgs {
+  const S* v[3];      // [ND][faces_d]: coordinate components on the d-faces
+  const double* nu;   // [G + 1] group edges
+  const S* Fn[3];
+};
+
 }  // namespace fm1
 
 namespace fm1 {

@@ -28,6 +28,10 @@
 //     tiles.
 // One block barrier per plane (after the states), which waits for LDS only: the loads of the
 // next plane stay in flight.  The update of a plane follows the next plane's barrier.
+// With VEL (Cartesian grids), Step 1 of the velocity step: the same transport without the
+// interaction update, each face flux with the advective flux v^d U of the upwind face state
+// added (the face's left state where v^d >= 0), from the normal velocity component on the face;
+// the zone-local velocity terms of the flux rows follow in the frequency step.
 // Spherical grids (SPH): the same structure with the geometry of the lane's zone read from the
 // per-axis tables (volume-coordinate slopes, face scale factors for the realizability checks and
 // the fluxes, face weights and zone widths for the divergence, proper widths for the optical
@@ -81,6 +85,14 @@ __device__ __forceinline__ double lane_pair_sum(double v) {
     b = W{l[1], h[1]};
   }
   return __builtin_bit_cast(double, a) + __builtin_bit_cast(double, b);
+}
+
+// the advective flux v U of the upwind face state added to a face flux (the left state where
+// v >= 0)
+template <typename R>
+__device__ __forceinline__ void add_upwind(R v, const R qL[4], const R qR[4], R flux[4]) {
+  const bool left = v >= R(0);
+  for (int c = 0; c < 4; ++c) flux[c] += v * (left ? qL[c] : qR[c]);
 }
 
 // The ghost rules of one axis, taken from the launch's table at each use (measured: faster
@@ -143,9 +155,9 @@ template <bool AR>
 constexpr int c3_nitem() { return AR ? 20 : 14; }
 
 // NI waves per block, W waves per SIMD (register budget 512 / W)
-template <typename S, int NI, int W, int LIM, bool SPH, bool AR>
+template <typename S, int NI, int W, int LIM, bool SPH, bool AR, bool VEL = false>
 __global__ void __launch_bounds__(64 * NI) __attribute__((amdgpu_waves_per_eu(W)))
-k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
+k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl, VelArgs<S> va) {
   using R = S;
   constexpr int TX = C3_TX;
   constexpr int NS = NI + (AR ? 4 : 3);                   // LDS row slots
@@ -304,6 +316,15 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
         }
       }
   };
+  // VEL: normal velocity components on the lane's faces (indices clamped into the face arrays:
+  // lanes and rows outside the grid compute but never store).  x faces [n2][n1][n0 + 1], y faces
+  // [n2][n1 + 1][n0] after the n0 (n1 + 1) n2 x components of v[1], z faces [n2 + 1][n1][n0]
+  // after 2 n0 n1 (n2 + 1) components of v[2].
+  const int64_t vxc = min(max(xz, 0), n0), vxz = min(max(xz, 0), n0 - 1);
+  const int64_t vyr = min(max(yz, 0), n1 - 1), vyf = min(max(yz, 0), n1), vyt = min(max(yz + 1, 0), n1);
+  const int64_t nfy = (int64_t)n0 * (n1 + 1) * n2, nfz = (int64_t)n0 * n1 * (n2 + 1);
+  auto vel_z = [&](int f) -> R { return R(va.v[2][2 * nfz + ((int64_t)f * n1 + vyr) * n0 + vxz]); };
+  R Ux = R(0), Uy = R(0), Uyt = R(0), Uz = R(0);   // face velocities of the plane
   {
     int pm;
     R raw[4], qa[4], qb[4];
@@ -335,6 +356,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
       reconstruct<R, SPH, 3, LIM>(a, geo, 2, NG, qa, qb, q0, ihz, ihz, true, true, lo, hiP);
       reconstruct<R, SPH, 3, LIM>(a, geo, 2, NG, qb, q0, q1, ihz, ihz, true, true, lo, hiM);
       hll<R, SPH, 3, (LIM < 0)>(a, 2, hiP, lo, hz, ihz, epsilon_of(ksb, k0 + s0, dlz, dlz), fPrev);
+      if constexpr (VEL) add_upwind(vel_z(mbeg), hiP, lo, fPrev);
     }
     // in flight into the first plane
     Pk = R(a.kap[o1 + cb]);
@@ -389,6 +411,13 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
       Pk2 = R(a.kap[ok + cb]);
       Ps2 = R(a.sig[ok + cb]);
       PB2 = R(a.B[min(m + 1, n2 - 1) * PL + cbb]);
+      if constexpr (VEL) {
+        // this plane's face velocities (used after the barrier)
+        Ux = R(va.v[0][((int64_t)m * n1 + vyr) * (n0 + 1) + vxc]);
+        Uy = R(va.v[1][nfy + ((int64_t)m * (n1 + 1) + vyf) * n0 + vxz]);
+        if (AR && top) Uyt = R(va.v[1][nfy + ((int64_t)m * (n1 + 1) + vyt) * n0 + vxz]);
+        Uz = vel_z(m + 1);
+      }
     }
     c3_barrier();
     // ---- update of plane m - 1 (every lane of the inner rows computes; the lanes that hold a
@@ -499,6 +528,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
         reconstruct<R, false, 3, LIM>(a, geo, 1, 0, qa, qb, q0, hone, hone, true, true, lo, hiP);
         reconstruct<R, false, 3, LIM>(a, geo, 1, 0, qb, q0, qc, hone, hone, true, true, loY, hiY);
         hll<R, false, 3, (LIM < 0)>(a, 1, hiP, loY, hone, hone, epsilon_of(ksb, ks0, dx1, dx1), fy);
+        if constexpr (VEL) add_upwind(Uy, hiP, loY, fy);
         if (AR && top && yz < n1) {
           // the block's upper face
           R qd[4], loA[4], hiA[4], fu[4];
@@ -506,6 +536,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
           const R ksa = QS[buf][4][sw + 1][lane] + QS[buf][5][sw + 1][lane];
           reconstruct<R, false, 3, LIM>(a, geo, 1, 0, q0, qc, qd, hone, hone, true, true, loA, hiA);
           hll<R, false, 3, (LIM < 0)>(a, 1, hiY, loA, hone, hone, epsilon_of(ks0, ksa, dx1, dx1), fu);
+          if constexpr (VEL) add_upwind(Uyt, hiY, loA, fu);
           for (int c = 0; c < 4; ++c) FY[buf][c][NI][lane] = fu[c];
         }
       }
@@ -542,6 +573,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
           for (int c = 0; c < 4; ++c) qL[c] = col_prev(hiX[c]);
           const R ksL = col_prev(ks0);
           hll<R, false, 3, (LIM < 0)>(a, 0, qL, loX, hone, hone, epsilon_of(ksL, ks0, dx0, dx0), fx);
+          if constexpr (VEL) add_upwind(Ux, qL, loX, fx);
           for (int c = 0; c < 4; ++c) acc[c] = (col_next(fx[c]) - fx[c]) * idx0;
         }
       }
@@ -551,6 +583,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl) {
         R nLo[4], nHi[4], fNext[4];
         reconstruct<R, SPH, 3, LIM>(a, geo, 2, NG, q0, q1, q2, ihz, ihz, true, true, nLo, nHi);
         hll<R, SPH, 3, (LIM < 0)>(a, 2, hiM, nLo, hz, ihz, epsilon_of(ks0, Pk + Ps, dlz, dlz), fNext);
+        if constexpr (VEL) add_upwind(Uz, hiM, nLo, fNext);
         for (int c = 0; c < 4; ++c) {
           acc[c] += (fNext[c] - fPrev[c]) * idx2;
           fPrev[c] = fNext[c];
@@ -669,12 +702,13 @@ int launch_c3(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipSt
   const bool mm = a.limiter == FORNAX_LIMITER_MINMOD && a.wavespeed == FORNAX_WAVESPEED_LIGHT;
   const bool sph = ctx->desc.coord == FORNAX_SPHERICAL_LOGR;
   dim3 grid(tl.nblocks), block(64 * tl.NR);
-#define FM1_C3(NRV, WV, SP, AR)                                                                                   \
-  do {                                                                                                            \
-    if (mm)                                                                                                       \
-      hipLaunchKernelGGL((k_step_3d<S, NRV, WV, FORNAX_LIMITER_MINMOD, SP, AR>), grid, block, 0, st, a, geo, tl); \
-    else                                                                                                          \
-      hipLaunchKernelGGL((k_step_3d<S, NRV, WV, -1, SP, AR>), grid, block, 0, st, a, geo, tl);                    \
+  const VelArgs<S> nova{};
+#define FM1_C3(NRV, WV, SP, AR)                                                                                       \
+  do {                                                                                                                \
+    if (mm)                                                                                                           \
+      hipLaunchKernelGGL((k_step_3d<S, NRV, WV, FORNAX_LIMITER_MINMOD, SP, AR>), grid, block, 0, st, a, geo, tl, nova); \
+    else                                                                                                              \
+      hipLaunchKernelGGL((k_step_3d<S, NRV, WV, -1, SP, AR>), grid, block, 0, st, a, geo, tl, nova);                    \
   } while (0)
   // waves per SIMD: the register budget of each shape (double: 168 or 256 VGPRs; float: 128,
   // or 168 for the 4-row blocks)
@@ -700,5 +734,32 @@ int launch_c3(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipSt
 
 template int launch_c3<double>(fornax_m1_ctx*, const Geo<double>&, const StepArgs<double>&, hipStream_t);
 template int launch_c3<float>(fornax_m1_ctx*, const Geo<float>&, const StepArgs<float>&, hipStream_t);
+
+// Step 1 of the velocity step (transport with the advective fluxes, no interaction update, no
+// diagnostics) on 3-D Cartesian grids of the kernel's kind: 8-row blocks of 64 planes in
+// double, 4-row blocks (three waves per SIMD) in float.
+template <typename S>
+int launch_c3_vel(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, const VelArgs<S>& va, hipStream_t st) {
+  const fornax_m1_desc& D = ctx->desc;
+  if (D.coord != FORNAX_CARTESIAN || D.ndim != 3) return FORNAX_EUNSUPPORTED;
+  if (a.src || a.dEm || a.p_energy || a.Ea) return FORNAX_EUNSUPPORTED;
+  constexpr bool dbl = sizeof(S) == 8;
+  const C3Tile tl = make_c3_tile(D, dbl ? 8 : 4, 64);
+  if (tl.nblocks <= 0) return FORNAX_EUNSUPPORTED;
+  const bool mm = a.limiter == FORNAX_LIMITER_MINMOD && a.wavespeed == FORNAX_WAVESPEED_LIGHT;
+  dim3 grid(tl.nblocks), block(64 * tl.NR);
+  constexpr int NRV = dbl ? 8 : 4, WV = dbl ? 2 : 3;
+  if (mm)
+    hipLaunchKernelGGL((k_step_3d<S, NRV, WV, FORNAX_LIMITER_MINMOD, false, true, true>), grid, block, 0, st, a, geo, tl,
+                       va);
+  else
+    hipLaunchKernelGGL((k_step_3d<S, NRV, WV, -1, false, true, true>), grid, block, 0, st, a, geo, tl, va);
+  return hipGetLastError() == hipSuccess ? FORNAX_OK : FORNAX_EDEVICE;
+}
+
+template int launch_c3_vel<double>(fornax_m1_ctx*, const Geo<double>&, const StepArgs<double>&,
+                                   const VelArgs<double>&, hipStream_t);
+template int launch_c3_vel<float>(fornax_m1_ctx*, const Geo<float>&, const StepArgs<float>&, const VelArgs<float>&,
+                                  hipStream_t);
 
 }  // namespace fm1

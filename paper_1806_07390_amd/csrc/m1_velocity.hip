@@ -10,6 +10,10 @@
 //                   of the reconstructed face states, geometric sources) plus v^d U_upwind on
 //                   every face and, in the flux rows, + <Gamma^l_{ik}> <v^i> F_l - <v^i_{;k}> F_i;
 //                   writes U^(1) to the output state;
+//                   On 3-D Cartesian grids of the whole-zone 3-D kernel's kind (groups a multiple
+//                   of 4) Step 1 runs on that kernel instead (m1_step_3d.hip: the transport with
+//                   the advective fluxes), and the zone-local velocity terms of the flux rows
+//                   move to k_vel_freq, which reads F^n for them;
 //   k_vel_freq      whole zones per block (BLOCK / G zones of G groups, lanes = groups): Step 2
 //                   on U^(1) (the compression work, and the upwind intergroup fluxes of the
 //                   energy and of the flux components from the minmod-reconstructed spectral
@@ -25,22 +29,17 @@
 // B = |F^| (3 chi - 1)/2 = |F^| (2 - s), s = sqrt(4 - 3 f^2), between the diffusion-limit form
 // (c E / 5)(sym f) and the beam c E n n n; no local Q term in the flux rows.
 //
-// The velocity step is bound by the per-thread recomputation of the face states (two faces per
-// zone and direction) rather than HBM; it is the correctness-first path of the method's
-// velocity terms, separate from the tuned static-medium kernels.
+// k_vel_explicit is bound by the per-thread recomputation of the face states (two faces per zone
+// and direction) rather than HBM: the general path of the method's velocity terms.
 
 #include <algorithm>
+#include <type_traits>
 
 #include "m1_device.h"
 #include "m1_internal.h"
+#include "m1_step.h"
 
 namespace fm1 {
-
-template <typename S>
-struct VelArgs {
-  const S* v[3];      // [ND][faces_d]: coordinate components on the d-faces
-  const double* nu;   // [G + 1] group edges
-};
 
 // coordinate component `comp` of the velocity on the lower (up = 0) or upper (up = 1) d-face of
 // zone (i, j, k)
@@ -297,6 +296,19 @@ __global__ void __launch_bounds__(BLOCK) k_vel_freq(StepArgs<S> a, Geo<R> geo, V
       R Gm[27], Vg[9], vb[3];
       connection<R, SPH>(geo, j, Gm);
       vel_grad<S, R, SPH, ND>(a, geo, va, i, j, k, Gm, Vg, vb);
+      if (va.Fn[0]) {
+        // Step 1 ran on the transport kernel: its zone-local velocity terms of the flux rows,
+        // + <Gamma^l_{ik}> <v^i> F_l - <v^i_{;k}> F_i of U^n, are added here
+        R Fn[3] = {R(0), R(0), R(0)};
+        for (int cc = 0; cc < ND; ++cc) Fn[cc] = R(va.Fn[cc][zg]);
+        for (int kk = 0; kk < ND; ++kk) {
+          R sv = R(0);
+          for (int ic = 0; ic < 3; ++ic)
+            for (int l = 0; l < 3; ++l) sv += Gm[9 * l + 3 * ic + kk] * vb[ic] * Fn[l];
+          for (int ic = 0; ic < 3; ++ic) sv -= Vg[3 * ic + kk] * Fn[ic];
+          U[1 + kk] += dtR * sv;
+        }
+      }
       R h[3] = {R(1), R(1), R(1)}, ih[3] = {R(1), R(1), R(1)};
       if constexpr (SPH) {
         cell_h<R, SPH>(geo, i + NG, j + NG, h);
@@ -462,7 +474,10 @@ namespace {
 template <typename S>
 VelArgs<S> vel_args(const fornax_m1_ctx* ctx, const fornax_m1_velocity* vel) {
   VelArgs<S> va;
-  for (int d = 0; d < 3; ++d) va.v[d] = (d < ctx->desc.ndim) ? (const S*)vel->v[d] : nullptr;
+  for (int d = 0; d < 3; ++d) {
+    va.v[d] = (d < ctx->desc.ndim) ? (const S*)vel->v[d] : nullptr;
+    va.Fn[d] = nullptr;
+  }
   va.nu = ctx->vel_nu;
   return va;
 }
@@ -470,10 +485,31 @@ VelArgs<S> vel_args(const fornax_m1_ctx* ctx, const fornax_m1_velocity* vel) {
 template <typename S, typename R, bool SPH, int ND>
 int launch_vel_nd(fornax_m1_ctx* ctx, const Geo<R>& geo, StepArgs<S>& a, const VelArgs<S>& va,
                   const fornax_m1_diag* diag, hipStream_t st) {
-  const int64_t nzg = a.nzones * a.G;
-  hipLaunchKernelGGL((k_vel_explicit<S, R, SPH, ND>), dim3((unsigned)((nzg + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st,
-                     a, geo, va);
-  if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
+  VelArgs<S> vf = va;
+  bool fused = false;
+  if constexpr (!SPH && ND == 3 && std::is_same<S, R>::value) {
+    // Step 1 on the whole-zone 3-D kernel where the grid is of its kind: transport with the
+    // advective fluxes; the flux rows' zone-local velocity terms move to the frequency step
+    StepArgs<S> s1 = a;
+    s1.src = 0;
+    s1.Ea = nullptr;
+    s1.dEm = nullptr;
+    s1.p_energy = s1.p_maxf2 = nullptr;
+    s1.p_nun = s1.p_nnp = nullptr;
+    const int rc = launch_c3_vel<S>(ctx, geo, s1, va, st);
+    if (rc == FORNAX_OK) {
+      fused = true;
+      for (int k = 0; k < 3; ++k) vf.Fn[k] = a.F[k];
+    } else if (rc != FORNAX_EUNSUPPORTED) {
+      return rc;
+    }
+  }
+  if (!fused) {
+    const int64_t nzg = a.nzones * a.G;
+    hipLaunchKernelGGL((k_vel_explicit<S, R, SPH, ND>), dim3((unsigned)((nzg + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       st, a, geo, va);
+    if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
+  }
   // Step 2 and the interaction update, in place on the output
   StepArgs<S> b = a;
   b.E = b.Eo;
@@ -486,7 +522,7 @@ int launch_vel_nd(fornax_m1_ctx* ctx, const Geo<R>& geo, StepArgs<S>& a, const V
   b.p_maxf2 = ctx->p_maxf2;
   b.p_nun = ctx->p_nun;
   b.p_nnp = ctx->p_nnp;
-  hipLaunchKernelGGL((k_vel_freq<S, R, SPH, ND>), dim3(nb), dim3(BLOCK), 0, st, b, geo, va, want ? 1 : 0);
+  hipLaunchKernelGGL((k_vel_freq<S, R, SPH, ND>), dim3(nb), dim3(BLOCK), 0, st, b, geo, vf, want ? 1 : 0);
   if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
   if (want) return fm1_launch_finalize(ctx->p_energy, ctx->p_maxf2, ctx->p_nun, ctx->p_nnp, nb, diag, st);
   return FORNAX_OK;

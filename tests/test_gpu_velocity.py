@@ -55,6 +55,11 @@ def case(name):
     elif name == "cart3d":
         from tests.test_gpu_parity import _c3_case
         w = _c3_case(n=(17, 13, 10), G=5, steps=3, seed=4, bcs="mixed")
+    elif name == "cart3d_k":
+        # a group count of the whole-zone 3-D kernel: Step 1 runs on it, the flux rows' velocity
+        # terms in the frequency step
+        from tests.test_gpu_parity import _c3_case
+        w = _c3_case(n=(17, 13, 10), G=8, steps=3, seed=4, bcs="mixed")
     elif name == "sph2d":
         w = wl.sphere3d(nr=18, nth=10, nph=1, G=4, ndim=2)
     else:
@@ -87,7 +92,7 @@ def gpu_v(m1, ctx, w, vf, nu, dt, nsteps):
     return to_host(A[0]), [to_host(f) for f in A[1]], {kk: v.cpu().numpy() for kk, v in dg.items()}
 
 
-@pytest.mark.parametrize("name", ["cart1d", "cart2d", "cart3d", "sph2d", "sph3d"])
+@pytest.mark.parametrize("name", ["cart1d", "cart2d", "cart3d", "cart3d_k", "sph2d", "sph3d"])
 def test_velocity_step_matches_oracle(m1, name):
     w = case(name)
     vf = wl.face_velocity(w, amp=0.15, seed=3)
@@ -138,8 +143,9 @@ def test_velocity_step_48cube_12_groups(m1):
             assert e[0] <= TOL_MIXED_RUN and e[1] <= TOL_MIXED_RUN
 
 
-def test_zero_velocity_is_the_static_step(m1):
-    w = case("cart3d")
+@pytest.mark.parametrize("name", ["cart3d", "cart3d_k"])
+def test_zero_velocity_is_the_static_step(m1, name):
+    w = case(name)
     vf = [np.zeros_like(v) for v in wl.face_velocity(w)]
     nu = wl.velocity_edges(w.G)
     ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64))
