@@ -39,7 +39,7 @@ def log(*a):
 # while the kernel sources are the ones it was measured on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_3d_core3d_192x192x192x12_fp64_traffic.json")
 KERNEL_SOURCES = ["m1_step_3d.hip", "m1_device.h", "m1_internal.h"]
-HEADLINE_KERNEL = "k_step_3d<double, 8, 2, 0, false, true>"
+HEADLINE_KERNEL = "k_step_3d<double, 8, 2, 0, false, true, false>"
 
 
 def kernel_source_digest():
@@ -394,7 +394,7 @@ def main():
         extra["core3d_192^3x12_mixed"] = dict(ms_per_step=round(ms, 5), zgu_per_s=w.zone_groups / (ms * 1e-3),
                                               kernel_ms=round(ms_k, 5), bytes_per_zone_group=b,
                                               algorithmic_GBps=round(w.zone_groups * b / (ms_k * 1e-3) / 1e9, 1),
-                                              kernel="k_step_3d<float, 8, 4, 0, false, false>")
+                                              kernel="k_step_3d<float, 8, 4, 0, false, false, false>")
         log(f"  core3d mixed: {ms:.4f} ms/step, kernel {ms_k:.4f} ms")
     if not args.no_extra:
         # ---- 2-D 512^2 x 16: FP64 (whole-zone kernel) and MIXED ----------------------------
@@ -420,8 +420,8 @@ def main():
                 extra[f"sphere3d_256x64x128x20_{name}"] = dict(ms_per_step=round(ms4, 5),
                                                                zgu_per_s=w4.zone_groups / (ms4 * 1e-3),
                                                                kernel_ms=round(ms4k, 5), algorithmic_GBps=round(gbs, 1),
-                                                               kernel=("k_step_3d<double, 8, 2, 0, true, true>" if el == 8 else
-                                                                       "k_step_3d<float, 4, 3, 0, true, true>"))
+                                                               kernel=("k_step_3d<double, 8, 2, 0, true, true, false>" if el == 8 else
+                                                                       "k_step_3d<float, 12, 3, 0, true, true, false>"))
                 log(f"  sphere3d {name}: {ms4:.4f} ms/step, {gbs:.0f} GB/s")
             del w4
         # ---- the reconstruction and wavespeed options on the 2-D grid ----------------------

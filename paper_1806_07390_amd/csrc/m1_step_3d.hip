@@ -643,8 +643,9 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl, VelArgs<S> va) {
 }
 
 // ------------------------------------------------------------------------------------------
-// every row of a block updated: double blocks, and float blocks of 4 rows (three waves per SIMD)
-static bool c3_all_rows(const fornax_m1_desc& D, int NR) { return D.precision == FORNAX_FP64 || NR == 4; }
+// every row of a block updated: double blocks, and float blocks of 4 and 12 rows (three waves
+// per SIMD)
+static bool c3_all_rows(const fornax_m1_desc& D, int NR) { return D.precision == FORNAX_FP64 || NR == 4 || NR == 12; }
 
 C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
   C3Tile tl{};
@@ -652,10 +653,11 @@ C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
   if (D.ndim != 3 || D.ngroups % 4 != 0) return tl;
   const bool sph = D.coord == FORNAX_SPHERICAL_LOGR;
   if (!sph && D.coord != FORNAX_CARTESIAN) return tl;
-  // the instantiated block heights: 6, 8 or 12 rows in double, 4, 8 or 16 in float (spherical
-  // grids: 8 rows, or 4 in float)
+  // the instantiated block heights: 6, 8 or 12 rows in double, 4, 8, 12 or 16 in float
+  // (spherical grids: 8 rows, or 4, 8 or 12 in float)
   const bool dbl = D.precision == FORNAX_FP64;
-  if (!(NR == 8 || (!dbl && NR == 4) || (!sph && (NR == (dbl ? 6 : 4) || NR == (dbl ? 12 : 16))))) return tl;
+  if (!(NR == 8 || (!dbl && (NR == 4 || NR == 12)) || (!sph && (NR == (dbl ? 6 : 4) || NR == (dbl ? 12 : 16)))))
+    return tl;
   if (TM < 1) return tl;
   // inflow only on the lower x1 boundary of spherical grids; a polar axis (theta, spherical
   // grids) needs a periodic phi axis of even length
@@ -684,12 +686,13 @@ C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
 C3Tile choose_c3_tile(const fornax_m1_desc& D, int cus) {
   (void)cus;
   // one y row per wave.  Cartesian: 8 rows and 64 planes per block (at 192^3 x 12, 2.5 % faster
-  // than 32 planes in double, 0.7 % in float; float blocks of 4 rows at three waves per SIMD:
-  // 11 % slower).  Spherical (256 x 64 x 128 x 20): double 8 rows and 32 planes (1 % faster
-  // than 16); float 4 rows (every row updated, three waves per SIMD) and 16 planes, 14 % faster
-  // than 8 rows at four waves per SIMD, which spill registers.
+  // than 32 planes in double, 0.7 % in float; float blocks of 12 or 4 rows at three waves per
+  // SIMD: 3 % and 11 % slower).  Spherical (256 x 64 x 128 x 20): double 8 rows and 32 planes
+  // (1 % faster than 16); float 12 rows (every row updated, three waves per SIMD) and 16
+  // planes, 9 % faster than 4 rows and 22 % faster than 8 rows at four waves per SIMD, which
+  // spill registers.
   const bool dbl = D.precision == FORNAX_FP64;
-  if (D.coord == FORNAX_SPHERICAL_LOGR) return dbl ? make_c3_tile(D, 8, 32) : make_c3_tile(D, 4, 16);
+  if (D.coord == FORNAX_SPHERICAL_LOGR) return dbl ? make_c3_tile(D, 8, 32) : make_c3_tile(D, 12, 16);
   return make_c3_tile(D, 8, 64);
 }
 
@@ -711,7 +714,7 @@ int launch_c3(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipSt
       hipLaunchKernelGGL((k_step_3d<S, NRV, WV, -1, SP, AR>), grid, block, 0, st, a, geo, tl, nova);                    \
   } while (0)
   // waves per SIMD: the register budget of each shape (double: 168 or 256 VGPRs; float: 128,
-  // or 168 for the 4-row blocks)
+  // or 168 for the 4- and 12-row blocks)
   if constexpr (sizeof(S) == 8) {
     if (sph) FM1_C3(8, 2, true, true);
     else if (tl.NR == 6) FM1_C3(6, 3, false, true);
@@ -719,9 +722,11 @@ int launch_c3(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipSt
     else FM1_C3(12, 3, false, true);
   } else {
     if (sph && tl.NR == 4) FM1_C3(4, 3, true, true);
+    else if (sph && tl.NR == 12) FM1_C3(12, 3, true, true);
     else if (sph) FM1_C3(8, 4, true, false);
     else if (tl.NR == 4) FM1_C3(4, 3, false, true);
     else if (tl.NR == 8) FM1_C3(8, 4, false, false);
+    else if (tl.NR == 12) FM1_C3(12, 3, false, true);
     else FM1_C3(16, 4, false, false);
   }
 #undef FM1_C3

@@ -210,7 +210,7 @@ def test_3d_kernel_tiles(m1, bcs):
     dt = dt_of(w, p)
     E, F, dg, dEm = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, want_dEm=True)
     cases = ((m1.FP64, TOL_FP64, ["8,32", "6,5", "12,3", "8,1", "8,19"]),
-             (m1.MIXED, TOL_MIXED_RUN, ["8,32", "4,7", "16,2", "8,64"]))
+             (m1.MIXED, TOL_MIXED_RUN, ["8,32", "4,7", "16,2", "8,64", "12,5"]))
     for prec, tol, tiles in cases:
         for tile in tiles:
             say(f"case 3-D kernel {bcs} tile {tile} prec {prec}")
@@ -531,9 +531,9 @@ def test_3d_kernel_spherical(m1, G):
     """The whole-zone 3-D kernel on spherical (ln r, theta, phi) grids: inflow at the inner
     radius, polar axes on both theta boundaries (the ghost rows come from the plane shifted by
     n_phi / 2), periodic phi; a grid ragged in every direction (r not a multiple of the 14
-    updated columns, theta not of the 8, 7 or 4 updated rows, phi not of the plane count)
-    against the oracle element by element, and against the tiled kernel, FP64 and MIXED (4-row
-    blocks are built for float only: in FP64 "4,5" runs the tiled kernel)."""
+    updated columns, theta not of the 12, 8, 7 or 4 updated rows, phi not of the plane count)
+    against the oracle element by element, and against the tiled kernel, FP64 and MIXED (4- and
+    12-row blocks are built for float only: in FP64 "4,5" and "12,3" run the tiled kernel)."""
     import os
     w = wl.sphere3d(nr=31, nth=17, nph=10, G=G, steps=6)
     rng = np.random.default_rng(G)
@@ -543,7 +543,7 @@ def test_3d_kernel_spherical(m1, G):
     E, F, dg, dEm = orc.run(p, w.E, w.F, w.kappa, w.sigma, w.B, dt, w.steps, inflow=w.inflow, want_dEm=True)
     for prec, tol in ((m1.FP64, TOL_FP64), (m1.MIXED, TOL_MIXED_RUN)):
         outs = {}
-        for c3 in (None, "0", "8,4", "4,5"):
+        for c3 in (None, "0", "8,4", "4,5", "12,3"):
             say(f"case spherical 3-D kernel G={G} C3={c3} prec={prec}")
             if c3 is not None:
                 os.environ["FORNAX_M1_C3"] = c3
