@@ -49,14 +49,23 @@ __device__ __forceinline__ double sqrt_(double x) {
 }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// A read of a geometry table.  The tables are written once, when the context is created, and
+// never by a kernel: reads go through the constant address space, which lets the compiler use
+// scalar loads where the index is uniform over the wave and keep the values across the
+// kernel's own stores.
+template <typename R>
+__device__ __forceinline__ R gld(const R* p, int i) {
+  return ((const __attribute__((address_space(4))) R*)p)[i];
+}
+
 // cell-centred scale factors sqrt(<g_kk>) at extended indices (ei, ej)
 template <typename R, bool SPH>
 __device__ __forceinline__ void cell_h(const Geo<R>& geo, int ei, int ej, R h[3]) {
   if constexpr (SPH) {
-    R r = geo.hr[ei];
+    R r = gld(geo.hr, ei);
     h[0] = r;
     h[1] = r;
-    h[2] = r * geo.hs[ej];
+    h[2] = r * gld(geo.hs, ej);
   } else {
     h[0] = h[1] = h[2] = R(1);
   }
@@ -66,8 +75,8 @@ __device__ __forceinline__ void cell_h(const Geo<R>& geo, int ei, int ej, R h[3]
 template <typename R, bool SPH>
 __device__ __forceinline__ void face_h(const Geo<R>& geo, int d, int ei, int ej, int ef, R h[3]) {
   if constexpr (SPH) {
-    R r = (d == 0) ? geo.rf[ef] : geo.rc[ei];
-    R s = (d == 1) ? geo.sf[ef] : geo.sc[ej];
+    R r = (d == 0) ? gld(geo.rf, ef) : gld(geo.rc, ei);
+    R s = (d == 1) ? gld(geo.sf, ef) : gld(geo.sc, ej);
     h[0] = r;
     h[1] = r;
     h[2] = r * s;
@@ -80,10 +89,10 @@ __device__ __forceinline__ void face_h(const Geo<R>& geo, int d, int ei, int ej,
 template <typename R, bool SPH>
 __device__ __forceinline__ void cell_ih(const Geo<R>& geo, int ei, int ej, R ih[3]) {
   if constexpr (SPH) {
-    const R ir = geo.ihr[ei];
+    const R ir = gld(geo.ihr, ei);
     ih[0] = ir;
     ih[1] = ir;
-    ih[2] = ir * geo.ihs[ej];
+    ih[2] = ir * gld(geo.ihs, ej);
   } else {
     ih[0] = ih[1] = ih[2] = R(1);
   }
@@ -94,8 +103,8 @@ __device__ __forceinline__ void cell_ih(const Geo<R>& geo, int ei, int ej, R ih[
 template <typename R, bool SPH>
 __device__ __forceinline__ void face_ih(const Geo<R>& geo, int d, int ei, int ej, int ef, R ih[3]) {
   if constexpr (SPH) {
-    const R ir = (d == 0) ? geo.irf[ef] : geo.irc[ei];
-    const R is = (d == 1) ? geo.isf[ef] : geo.isc[ej];
+    const R ir = (d == 0) ? gld(geo.irf, ef) : gld(geo.irc, ei);
+    const R is = (d == 1) ? gld(geo.isf, ef) : gld(geo.isc, ej);
     ih[0] = ir;
     ih[1] = ir;
     ih[2] = ir * is;
@@ -108,8 +117,8 @@ __device__ __forceinline__ void face_ih(const Geo<R>& geo, int d, int ei, int ej
 template <typename R, bool SPH>
 __device__ __forceinline__ R proper_width(const Geo<R>& geo, int d, int ei, int ej) {
   if constexpr (SPH) {
-    R r = geo.hr[ei];
-    return (d == 2) ? r * geo.hs[ej] * geo.dx[2] : r * geo.dx[d];
+    R r = gld(geo.hr, ei);
+    return (d == 2) ? r * gld(geo.hs, ej) * geo.dx[2] : r * geo.dx[d];
   } else {
     return geo.dx[d];
   }
@@ -216,15 +225,15 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
       }
     }
     // slopes between volume centroids, face offsets from the centroid
-    const R idm = geo.idm[d][e], idp = geo.idp[d][e];
-    dl = geo.dlo[d][e];
-    dh = geo.dhi[d][e];
+    const R idm = gld(geo.idm[d], e), idp = gld(geo.idp[d], e);
+    dl = gld(geo.dlo[d], e);
+    dh = gld(geo.dhi[d], e);
     for (int cp = 0; cp <= ND; ++cp) {
       const R sa = (q0[cp] - qm[cp]) * idm, sb = (qp[cp] - q0[cp]) * idp;
       if (limiter == FORNAX_LIMITER_MINMOD) {
         s[cp] = minmod(sa, sb);
       } else if (limiter == FORNAX_LIMITER_MC) {
-        s[cp] = minmod(R(2) * sa, minmod(R(2) * sb, (qp[cp] - qm[cp]) * geo.idc[d][e]));
+        s[cp] = minmod(R(2) * sa, minmod(R(2) * sb, (qp[cp] - qm[cp]) * gld(geo.idc[d], e)));
       } else {
         s[cp] = R(0);
       }
@@ -520,14 +529,14 @@ __device__ __forceinline__ void face_flux(const StepArgs<S>& a, const Geo<R>& ge
                                           const R q[4][4], R ksL, R ksR, R flux[4]) {
   const int ef = f + NG;
   for (int c = 0; c < 4; ++c) flux[c] = R(0);
-  if (SPH && geo.wf[d][ef] == R(0)) return;
+  if (SPH && gld(geo.wf[d], ef) == R(0)) return;
   const int ei = i + NG, ej = j + NG;
   R ih0[3], h1[3], ih1[3], ih2[3];
   face_ih<R, SPH>(geo, d, ei, ej, ef - 1, ih0);
   face_h<R, SPH>(geo, d, ei, ej, ef, h1);
   face_ih<R, SPH>(geo, d, ei, ej, ef, ih1);
   face_ih<R, SPH>(geo, d, ei, ej, ef + 1, ih2);
-  const bool o0 = !SPH || geo.wf[d][ef - 1] != R(0), o2 = !SPH || geo.wf[d][ef + 1] != R(0);
+  const bool o0 = !SPH || gld(geo.wf[d], ef - 1) != R(0), o2 = !SPH || gld(geo.wf[d], ef + 1) != R(0);
   R Llo[4], Lhi[4], Rlo[4], Rhi[4];
   reconstruct<R, SPH, ND>(a, geo, d, ef - 1, q[0], q[1], q[2], ih0, ih1, o0, true, Llo, Lhi);
   reconstruct<R, SPH, ND>(a, geo, d, ef, q[1], q[2], q[3], ih1, ih2, true, o2, Rlo, Rhi);
@@ -543,7 +552,7 @@ __device__ __forceinline__ void face_flux(const StepArgs<S>& a, const Geo<R>& ge
 template <typename R>
 __device__ __forceinline__ void geometric_source(const R P[9], const R h[3], const R ih[3], const R* gam, R c,
                                                  R Sg[3]) {
-  const R G323 = gam[0], G133 = gam[1], G233 = gam[2], G222 = gam[3];
+  const R G323 = gld(gam, 0), G133 = gld(gam, 1), G233 = gld(gam, 2), G222 = gld(gam, 3);
   const R c2 = c * c;
   // F_1: Gamma^1_11 = Gamma^2_12 = Gamma^3_13 = 1
   Sg[0] = c2 * (P[0] + P[4] + P[8]);
@@ -593,8 +602,8 @@ __device__ __forceinline__ double source_zone(const StepArgsBase& a, const Geo<R
     zd.energy += V * E1d;
     double hd[3] = {1.0, 1.0, 1.0};
     if constexpr (SPH) {
-      hd[0] = hd[1] = (double)geo.hr[i + NG];
-      hd[2] = hd[0] * (double)geo.hs[j + NG];
+      hd[0] = hd[1] = (double)gld(geo.hr, i + NG);
+      hd[2] = hd[0] * (double)gld(geo.hs, j + NG);
     }
     // |E| below 2^-400: the squares below could underflow; f and the counts are those of the
     // state scaled by 2^600 (exact), in waves that hold such a zone only

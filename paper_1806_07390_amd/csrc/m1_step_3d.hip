@@ -426,7 +426,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl, VelArgs<S> va) {
       const int mu = m - 1;
       R acc[4];
       if constexpr (SPH) {
-        const R wl = geo.wf[1][ey], wh = geo.wf[1][ey + 1], iW = geo.iW[1][ey];
+        const R wl = gld(geo.wf[1], ey), wh = gld(geo.wf[1], ey + 1), iW = gld(geo.iW[1], ey);
         for (int c = 0; c < 4; ++c) acc[c] = accU[c] + (wh * FY[buf ^ 1][c][w + 1][lane] - wl * fyU[c]) * iW;
       } else {
         for (int c = 0; c < 4; ++c) acc[c] = accU[c] + (FY[buf ^ 1][c][w + 1][lane] - fyU[c]) * idx1;
@@ -493,7 +493,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl, VelArgs<S> va) {
         face_ih<R, SPH>(geo, 1, ex, ey, ey - 1, ihm);
         face_ih<R, SPH>(geo, 1, ex, ey, ey, ih0);
         face_ih<R, SPH>(geo, 1, ex, ey, ey + 1, ih1);
-        const bool om = geo.wf[1][ey - 1] != R(0), o0f = geo.wf[1][ey] != R(0), o1f = geo.wf[1][ey + 1] != R(0);
+        const bool om = gld(geo.wf[1], ey - 1) != R(0), o0f = gld(geo.wf[1], ey) != R(0), o1f = gld(geo.wf[1], ey + 1) != R(0);
         reconstruct<R, SPH, 3, LIM>(a, geo, 1, ey - 1, qa, qb, q0, ihm, ih0, om, o0f, lo, hiP);
         reconstruct<R, SPH, 3, LIM>(a, geo, 1, ey, qb, q0, qc, ih0, ih1, o0f, o1f, loY, hiY);
         for (int c = 0; c < 4; ++c) fy[c] = R(0);
@@ -511,7 +511,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl, VelArgs<S> va) {
           for (int c = 0; c < 4; ++c) qd[c] = QS[buf][c][sw + 2][lane];
           const R ksa = QS[buf][4][sw + 1][lane] + QS[buf][5][sw + 1][lane];
           face_ih<R, SPH>(geo, 1, ex, ey, ey + 2, ih2);
-          const bool o2f = geo.wf[1][ey + 2] != R(0);
+          const bool o2f = gld(geo.wf[1], ey + 2) != R(0);
           reconstruct<R, SPH, 3, LIM>(a, geo, 1, ey + 1, q0, qc, qd, ih1, ih2, o1f, o2f, loA, hiA);
           for (int c = 0; c < 4; ++c) fu[c] = R(0);
           if (o1f) {
@@ -566,7 +566,7 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl, VelArgs<S> va) {
           const R dlL = col_prev(dlx);
           face_h<R, SPH>(geo, 0, ex, ey, ex, hf);
           hll<R, SPH, 3, (LIM < 0)>(a, 0, qL, loX, hf, ihl, epsilon_of(ksL, ks0, dlL, dlx), fx);
-          const R wl = geo.wf[0][ex], wh = geo.wf[0][ex + 1], iW = geo.iW[0][ex];
+          const R wl = gld(geo.wf[0], ex), wh = gld(geo.wf[0], ex + 1), iW = gld(geo.iW[0], ex);
           for (int c = 0; c < 4; ++c) acc[c] = (wh * col_next(fx[c]) - wl * fx[c]) * iW;
         } else {
           reconstruct<R, false, 3, LIM>(a, geo, 0, 0, qm, q0, qp, hone, hone, true, true, loX, hiX);
