@@ -96,12 +96,21 @@ __device__ __forceinline__ void vel_grad(const StepArgsBase& a, const Geo<R>& ge
   R dv[9];
   for (int t = 0; t < 9; ++t) dv[t] = R(0);
   for (int t = 0; t < 3; ++t) vb[t] = R(0);
+  // the zone's lower face in each direction's face array and the stride to the upper face
+  // (the face arrays of direction d have one more entry along d), and each array's
+  // component stride
+  const int64_t n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+  const int64_t lo[3] = {((int64_t)k * n1 + j) * (n0 + 1) + i, ((int64_t)k * (n1 + 1) + j) * n0 + i,
+                         ((int64_t)k * n1 + j) * n0 + i};
+  const int64_t up[3] = {1, n0, n0 * n1};
+  const int64_t nf[3] = {(n0 + 1) * n1 * n2, n0 * (n1 + 1) * n2, n0 * n1 * (n2 + 1)};
   for (int jd = 0; jd < ND; ++jd) {
     const R idx = geo.idx[jd];
-    const R w = -geo.dlo[jd][ez[jd]] * idx;   // (<x> - x_{-1/2}) / dx
+    const R w = -gld(geo.dlo[jd], ez[jd]) * idx;   // (<x> - x_{-1/2}) / dx
     for (int ic = 0; ic < ND; ++ic) {
-      const R vlo = face_v<S, R>(a, va, jd, ic, i, j, k, 0);
-      const R vhi = face_v<S, R>(a, va, jd, ic, i, j, k, 1);
+      const S* vp = va.v[jd] + ic * nf[jd] + lo[jd];
+      const R vlo = R(vp[0]);
+      const R vhi = R(vp[up[jd]]);
       dv[3 * ic + jd] = (vhi - vlo) * idx;
       if (ic == jd) vb[jd] = vlo + (vhi - vlo) * w;
     }
