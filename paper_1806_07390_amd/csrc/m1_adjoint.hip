@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "m1_adjoint_device.h"
 #include "m1_device.h"
@@ -134,16 +135,29 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
     for (int v = 0; v < 4; ++v) mu[v] = R(0);
     if (p >= 0 && p < nM) load_mu<S, R, DIM>(a, zgi(gx, p), mu);
   };
-  // march face f (between planes f-1 and f) from window planes f-2 .. f+1 in wq[0..3]
-  auto march_face = [&](int f, R fl[4], R C[4][4], R& dkL, R& dkR) {
+  // march face f (between planes f-1 and f) from window planes f-2 .. f+1 (q0 .. q3), the total
+  // opacities and mu of planes f-1, f
+  auto march_face_r = [&](int f, const R q0[4], const R q1[4], const R q2[4], const R q3[4], R ks1, R ks2,
+                          const R mu1[4], const R mu2[4], R fl[4], R C[4][4], R& dkL, R& dkR) {
     for (int v = 0; v < 4; ++v) fl[v] = R(0);
     for (int p = 0; p < 4; ++p)
       for (int v = 0; v < 4; ++v) C[p][v] = R(0);
     dkL = dkR = R(0);
     if (f < 0 || f > nM) return;
     R nu[4] = {R(0), R(0), R(0), R(0)};
-    for (int v = 0; v < NC; ++v) nu[v] = nuy * (wmu[2][v] - wmu[1][v]);
-    face_vjp_cart<R, DIM, LIM>(a, MD < 0 ? 0 : MD, geo.dx[MD < 0 ? 0 : MD], wq, wks[1], wks[2], nu, fl, C, dkL, dkR);
+    for (int v = 0; v < NC; ++v) nu[v] = nuy * (mu2[v] - mu1[v]);
+    R qq[4][4];
+    for (int v = 0; v < 4; ++v) {
+      qq[0][v] = q0[v];
+      qq[1][v] = q1[v];
+      qq[2][v] = q2[v];
+      qq[3][v] = q3[v];
+    }
+    face_vjp_cart<R, DIM, LIM>(a, MD < 0 ? 0 : MD, geo.dx[MD < 0 ? 0 : MD], qq, ks1, ks2, nu, fl, C, dkL, dkR);
+  };
+  // (the window rows in ring order)
+  auto march_face = [&](int f, R fl[4], R C[4][4], R& dkL, R& dkR) {
+    march_face_r(f, wq[0], wq[1], wq[2], wq[3], wks[1], wks[2], wmu[1], wmu[2], fl, C, dkL, dkR);
   };
   if constexpr (DIM >= 2) {
     if (colin) {
@@ -188,18 +202,24 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
     }
   }
 
-  for (int m = mbeg; m < mend; ++m) {
+  // One plane of the march.  The rings are not shifted: ring slot i of the plane is array entry
+  // (i + RT) & 3, RT the plane's offset from the tile's first plane modulo 4 (a compile-time
+  // constant: the loop below is unrolled by four), so no values move between registers.
+  auto plane_step = [&](auto rt_c, const int m) {
+    constexpr int RT = decltype(rt_c)::value;
+    auto sl = [](int i) { return (i + RT) & 3; };
     const bool rowin = (DIM < 2) || (m >= 0 && m < nM);
     // ---- march: load plane m+3, face m+2 ----
     if constexpr (DIM >= 2) {
       if (colin) {
-        load_plane_w(m + 3, wq[3], wks[3], wmu[3]);
+        load_plane_w(m + 3, wq[sl(3)], wks[sl(3)], wmu[sl(3)]);
         R fl[4], C[4][4], dkL, dkR;
-        march_face(m + 2, fl, C, dkL, dkR);
+        march_face_r(m + 2, wq[sl(0)], wq[sl(1)], wq[sl(2)], wq[sl(3)], wks[sl(1)], wks[sl(2)], wmu[sl(1)],
+                     wmu[sl(2)], fl, C, dkL, dkR);
         for (int p = 0; p < 4; ++p)
-          for (int v = 0; v < NC; ++v) racc[p][v] += C[p][v];
-        rdk[1] += dkL;
-        rdk[2] += dkR;
+          for (int v = 0; v < NC; ++v) racc[sl(p)][v] += C[p][v];
+        rdk[sl(1)] += dkL;
+        rdk[sl(2)] += dkR;
       }
     }
     // ---- stage plane m: own column (LDS col cx + 3) and halo columns 0..2 ----
@@ -207,10 +227,10 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
       R q[4], ks, mu[4] = {R(0), R(0), R(0), R(0)};
       if ((DIM >= 2) && colin) {
         for (int v = 0; v < 4; ++v) {
-          q[v] = wq[0][v];
-          mu[v] = wmu[0][v];
+          q[v] = wq[sl(0)][v];
+          mu[v] = wmu[sl(0)][v];
         }
-        ks = wks[0];
+        ks = wks[sl(0)];
       } else {
         state(gx, m, q, ks);
         if (colin) load_mu<S, R, DIM>(a, zgi(gx, m), mu);
@@ -266,8 +286,8 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
       }
       if constexpr (DIM >= 2) {
         if (colin) {
-          for (int v = 0; v < NC; ++v) gsum[v] += racc[0][v];
-          dks += rdk[0];
+          for (int v = 0; v < NC; ++v) gsum[v] += racc[sl(0)][v];
+          dks += rdk[sl(0)];
         }
       }
       if (colin && rowin) {
@@ -295,23 +315,28 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
         gb[NC] = (double)dks;
       }
     }
-    // ---- advance the march rings ----
+    // ---- the finalised zone's ring slot starts the plane four ahead ----
     if constexpr (DIM >= 2) {
-      for (int i = 0; i < 3; ++i) {
-        for (int v = 0; v < 4; ++v) {
-          wq[i][v] = wq[i + 1][v];
-          wmu[i][v] = wmu[i + 1][v];
-          racc[i][v] = racc[i + 1][v];
-        }
-        wks[i] = wks[i + 1];
-        rdk[i] = rdk[i + 1];
-      }
-      for (int v = 0; v < 4; ++v) racc[3][v] = R(0);
-      rdk[3] = R(0);
+      for (int v = 0; v < 4; ++v) racc[sl(0)][v] = R(0);
+      rdk[sl(0)] = R(0);
     }
     __syncthreads();
+  };
+  if constexpr (DIM >= 2) {
+    for (int m = mbeg; m < mend; m += 4) {
+      plane_step(std::integral_constant<int, 0>{}, m);
+      if (m + 1 >= mend) break;
+      plane_step(std::integral_constant<int, 1>{}, m + 1);
+      if (m + 2 >= mend) break;
+      plane_step(std::integral_constant<int, 2>{}, m + 2);
+      if (m + 3 >= mend) break;
+      plane_step(std::integral_constant<int, 3>{}, m + 3);
+    }
+  } else {
+    for (int m = mbeg; m < mend; ++m) plane_step(std::integral_constant<int, 0>{}, m);
   }
 }
+
 
 // Ghost-zone adjoints of direction d that fold into zone dst along d (plane index pidx in the
 // plane normal to d): the four ghost entries visited in a fixed order through the boundary
