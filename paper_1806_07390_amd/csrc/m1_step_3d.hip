@@ -742,18 +742,18 @@ template int launch_c3<float>(fornax_m1_ctx*, const Geo<float>&, const StepArgs<
 
 // Step 1 of the velocity step (transport with the advective fluxes, no interaction update, no
 // diagnostics) on 3-D Cartesian grids of the kernel's kind: 8-row blocks of 64 planes in
-// double, 4-row blocks (three waves per SIMD) in float.
+// double, 12-row blocks (three waves per SIMD) in float.
 template <typename S>
 int launch_c3_vel(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, const VelArgs<S>& va, hipStream_t st) {
   const fornax_m1_desc& D = ctx->desc;
   if (D.coord != FORNAX_CARTESIAN || D.ndim != 3) return FORNAX_EUNSUPPORTED;
   if (a.src || a.dEm || a.p_energy || a.Ea) return FORNAX_EUNSUPPORTED;
   constexpr bool dbl = sizeof(S) == 8;
-  const C3Tile tl = make_c3_tile(D, dbl ? 8 : 4, 64);
+  const C3Tile tl = make_c3_tile(D, dbl ? 8 : 12, 64);
   if (tl.nblocks <= 0) return FORNAX_EUNSUPPORTED;
   const bool mm = a.limiter == FORNAX_LIMITER_MINMOD && a.wavespeed == FORNAX_WAVESPEED_LIGHT;
   dim3 grid(tl.nblocks), block(64 * tl.NR);
-  constexpr int NRV = dbl ? 8 : 4, WV = dbl ? 2 : 3;
+  constexpr int NRV = dbl ? 8 : 12, WV = dbl ? 2 : 3;
   if (mm)
     hipLaunchKernelGGL((k_step_3d<S, NRV, WV, FORNAX_LIMITER_MINMOD, false, true, true>), grid, block, 0, st, a, geo, tl,
                        va);
