@@ -189,11 +189,12 @@ __device__ __forceinline__ bool realizable(const R q[4], const R ih[3], R c) {
 // option: face states at its lower and upper faces, with the piecewise-constant fallback when
 // either is not realizable.
 // LIM: the limiter when known at compile time (a FORNAX_LIMITER_* value), -1 to read it from
-// the arguments.
+// the arguments.  vs (spherical grids, nullable): the zone's idm, idp, dlo, dhi, idc of the
+// tables, when the caller already holds them.
 template <typename R, bool SPH, int ND, int LIM = -1>
 __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>& geo, int d, int e, const R qm[4],
                                             const R q0[4], const R qp[4], const R ihlo[3], const R ihhi[3],
-                                            bool lo_open, bool hi_open, R lo[4], R hi[4]) {
+                                            bool lo_open, bool hi_open, R lo[4], R hi[4], const R* vs = nullptr) {
   const R c = R(a.c);
   const int limiter = (LIM >= 0) ? LIM : a.limiter;
   R s[4];
@@ -225,15 +226,15 @@ __device__ __forceinline__ void reconstruct(const StepArgsBase& a, const Geo<R>&
       }
     }
     // slopes between volume centroids, face offsets from the centroid
-    const R idm = gld(geo.idm[d], e), idp = gld(geo.idp[d], e);
-    dl = gld(geo.dlo[d], e);
-    dh = gld(geo.dhi[d], e);
+    const R idm = vs ? vs[0] : gld(geo.idm[d], e), idp = vs ? vs[1] : gld(geo.idp[d], e);
+    dl = vs ? vs[2] : gld(geo.dlo[d], e);
+    dh = vs ? vs[3] : gld(geo.dhi[d], e);
     for (int cp = 0; cp <= ND; ++cp) {
       const R sa = (q0[cp] - qm[cp]) * idm, sb = (qp[cp] - q0[cp]) * idp;
       if (limiter == FORNAX_LIMITER_MINMOD) {
         s[cp] = minmod(sa, sb);
       } else if (limiter == FORNAX_LIMITER_MC) {
-        s[cp] = minmod(R(2) * sa, minmod(R(2) * sb, (qp[cp] - qm[cp]) * gld(geo.idc[d], e)));
+        s[cp] = minmod(R(2) * sa, minmod(R(2) * sb, (qp[cp] - qm[cp]) * (vs ? vs[4] : gld(geo.idc[d], e))));
       } else {
         s[cp] = R(0);
       }

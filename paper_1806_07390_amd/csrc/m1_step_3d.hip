@@ -288,6 +288,32 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl, VelArgs<S> va) {
     face_ih<R, SPH>(geo, 2, ex, ey, 0, ihz);
     dlz = proper_width<R, SPH>(geo, 2, ex, ey);
   }
+  // spherical grids: the radial tables at the block's 16 columns, staged in LDS once (the first
+  // plane's barrier orders the reads): the plane loop reads them from LDS rather than from the
+  // tables (the theta tables, indexed by the wave's row, are scalar loads)
+  enum { RG_IRC, RG_RC, RG_HR, RG_IHR, RG_IRF0, RG_IRF1, RG_RF, RG_IDM, RG_IDP, RG_DLO, RG_DHI, RG_IDC, RG_WF0,
+         RG_WF1, RG_IW, RG_N };
+  __shared__ R RGT[SPH ? RG_N : 1][TX];
+  if constexpr (SPH) {
+    if (w == 0 && gq == 0) {
+      RGT[RG_IRC][x] = gld(geo.irc, ex);
+      RGT[RG_RC][x] = gld(geo.rc, ex);
+      RGT[RG_HR][x] = gld(geo.hr, ex);
+      RGT[RG_IHR][x] = gld(geo.ihr, ex);
+      RGT[RG_IRF0][x] = gld(geo.irf, ex);
+      RGT[RG_IRF1][x] = gld(geo.irf, ex + 1);
+      RGT[RG_RF][x] = gld(geo.rf, ex);
+      RGT[RG_IDM][x] = gld(geo.idm[0], ex);
+      RGT[RG_IDP][x] = gld(geo.idp[0], ex);
+      RGT[RG_DLO][x] = gld(geo.dlo[0], ex);
+      RGT[RG_DHI][x] = gld(geo.dhi[0], ex);
+      RGT[RG_IDC][x] = gld(geo.idc[0], ex);
+      RGT[RG_WF0][x] = gld(geo.wf[0], ex);
+      RGT[RG_WF1][x] = gld(geo.wf[0], ex + 1);
+      RGT[RG_IW][x] = gld(geo.iW[0], ex);
+    }
+  }
+  auto rg = [&](int k) -> R { return RGT[SPH ? k : 0][x]; };
 
   // ---- register window along z: q(m), q(m + 1); the upper z face state of zone m and the
   // flux at m - 1/2; kappa and sigma of plane m ----
@@ -437,8 +463,10 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl, VelArgs<S> va) {
       if constexpr (SPH) {
         // geometric source terms of the covariant flux components (cell-centred h)
         R h[3], ih[3], P[9], Sg[3];
-        cell_h<R, SPH>(geo, ex, ey, h);
-        cell_ih<R, SPH>(geo, ex, ey, ih);
+        h[0] = h[1] = rg(RG_HR);
+        h[2] = rg(RG_HR) * gld(geo.hs, ey);
+        ih[0] = ih[1] = rg(RG_IHR);
+        ih[2] = rg(RG_IHR) * gld(geo.ihs, ey);
         closure_full<R, SPH, 3>(qU, ih, R(a.c), a.closure, P);
         geometric_source<R>(P, h, ih, geo.gam + 4 * min(max(yz, 0), n1 - 1), R(a.c), Sg);
         for (int cc = 0; cc < 3; ++cc) Um[1 + cc] += dtR * Sg[cc];
@@ -489,38 +517,43 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl, VelArgs<S> va) {
       if constexpr (SPH) {
         // theta faces: scale factors at the face centres of the lane's column; a face on the
         // polar axis is closed (no flux, its face states not checked)
+        // (theta faces: 1/h_r = 1/h_theta = 1/r at the column's centre, 1/h_phi with 1/sin theta
+        // of the face)
+        const R irc = rg(RG_IRC), rc = rg(RG_RC), dly = rg(RG_HR) * geo.dx[1];
+        auto ih_th = [&](int ef, R ih[3]) {
+          ih[0] = ih[1] = irc;
+          ih[2] = irc * gld(geo.isf, ef);
+        };
+        auto h_th = [&](int ef, R h[3]) {
+          h[0] = h[1] = rc;
+          h[2] = rc * gld(geo.sf, ef);
+        };
         R ihm[3], ih0[3], ih1[3];
-        face_ih<R, SPH>(geo, 1, ex, ey, ey - 1, ihm);
-        face_ih<R, SPH>(geo, 1, ex, ey, ey, ih0);
-        face_ih<R, SPH>(geo, 1, ex, ey, ey + 1, ih1);
+        ih_th(ey - 1, ihm);
+        ih_th(ey, ih0);
+        ih_th(ey + 1, ih1);
         const bool om = gld(geo.wf[1], ey - 1) != R(0), o0f = gld(geo.wf[1], ey) != R(0), o1f = gld(geo.wf[1], ey + 1) != R(0);
         reconstruct<R, SPH, 3, LIM>(a, geo, 1, ey - 1, qa, qb, q0, ihm, ih0, om, o0f, lo, hiP);
         reconstruct<R, SPH, 3, LIM>(a, geo, 1, ey, qb, q0, qc, ih0, ih1, o0f, o1f, loY, hiY);
         for (int c = 0; c < 4; ++c) fy[c] = R(0);
         if (o0f) {
           R hf[3];
-          face_h<R, SPH>(geo, 1, ex, ey, ey, hf);
-          hll<R, SPH, 3, (LIM < 0)>(a, 1, hiP, loY, hf, ih0,
-                                    epsilon_of(ksb, ks0, proper_width<R, SPH>(geo, 1, ex, ey - 1),
-                                               proper_width<R, SPH>(geo, 1, ex, ey)),
-                                    fy);
+          h_th(ey, hf);
+          hll<R, SPH, 3, (LIM < 0)>(a, 1, hiP, loY, hf, ih0, epsilon_of(ksb, ks0, dly, dly), fy);
         }
         if (AR && top && yz < n1) {
           // the block's upper face (ey + 1 <= n1 - 1 + NG + 1: inside the face tables)
           R qd[4], loA[4], hiA[4], ih2[3], fu[4];
           for (int c = 0; c < 4; ++c) qd[c] = QS[buf][c][sw + 2][lane];
           const R ksa = QS[buf][4][sw + 1][lane] + QS[buf][5][sw + 1][lane];
-          face_ih<R, SPH>(geo, 1, ex, ey, ey + 2, ih2);
+          ih_th(ey + 2, ih2);
           const bool o2f = gld(geo.wf[1], ey + 2) != R(0);
           reconstruct<R, SPH, 3, LIM>(a, geo, 1, ey + 1, q0, qc, qd, ih1, ih2, o1f, o2f, loA, hiA);
           for (int c = 0; c < 4; ++c) fu[c] = R(0);
           if (o1f) {
             R hf[3];
-            face_h<R, SPH>(geo, 1, ex, ey, ey + 1, hf);
-            hll<R, SPH, 3, (LIM < 0)>(a, 1, hiY, loA, hf, ih1,
-                                      epsilon_of(ks0, ksa, proper_width<R, SPH>(geo, 1, ex, ey),
-                                                 proper_width<R, SPH>(geo, 1, ex, ey + 1)),
-                                      fu);
+            h_th(ey + 1, hf);
+            hll<R, SPH, 3, (LIM < 0)>(a, 1, hiY, loA, hf, ih1, epsilon_of(ks0, ksa, dly, dly), fu);
           }
           for (int c = 0; c < 4; ++c) FY[buf][c][NI][lane] = fu[c];
         }
@@ -557,16 +590,21 @@ k_step_3d(StepArgs<S> a, Geo<S> geo, C3Tile tl, VelArgs<S> va) {
         if constexpr (SPH) {
           // r faces of the lane's zone; the flux at its lower face
           R ihl[3], ihr[3], hf[3];
-          face_ih<R, SPH>(geo, 0, ex, ey, ex, ihl);
-          face_ih<R, SPH>(geo, 0, ex, ey, ex + 1, ihr);
-          reconstruct<R, SPH, 3, LIM>(a, geo, 0, ex, qm, q0, qp, ihl, ihr, true, true, loX, hiX);
+          const R isc = gld(geo.isc, ey);
+          ihl[0] = ihl[1] = rg(RG_IRF0);
+          ihl[2] = rg(RG_IRF0) * isc;
+          ihr[0] = ihr[1] = rg(RG_IRF1);
+          ihr[2] = rg(RG_IRF1) * isc;
+          const R vs[5] = {rg(RG_IDM), rg(RG_IDP), rg(RG_DLO), rg(RG_DHI), rg(RG_IDC)};
+          reconstruct<R, SPH, 3, LIM>(a, geo, 0, ex, qm, q0, qp, ihl, ihr, true, true, loX, hiX, vs);
           for (int c = 0; c < 4; ++c) qL[c] = col_prev(hiX[c]);
           const R ksL = col_prev(ks0);
-          const R dlx = proper_width<R, SPH>(geo, 0, ex, ey);
+          const R dlx = rg(RG_HR) * geo.dx[0];
           const R dlL = col_prev(dlx);
-          face_h<R, SPH>(geo, 0, ex, ey, ex, hf);
+          hf[0] = hf[1] = rg(RG_RF);
+          hf[2] = rg(RG_RF) * gld(geo.sc, ey);
           hll<R, SPH, 3, (LIM < 0)>(a, 0, qL, loX, hf, ihl, epsilon_of(ksL, ks0, dlL, dlx), fx);
-          const R wl = gld(geo.wf[0], ex), wh = gld(geo.wf[0], ex + 1), iW = gld(geo.iW[0], ex);
+          const R wl = rg(RG_WF0), wh = rg(RG_WF1), iW = rg(RG_IW);
           for (int c = 0; c < 4; ++c) acc[c] = (wh * col_next(fx[c]) - wl * fx[c]) * iW;
         } else {
           reconstruct<R, false, 3, LIM>(a, geo, 0, 0, qm, q0, qp, hone, hone, true, true, loX, hiX);
@@ -688,11 +726,11 @@ C3Tile choose_c3_tile(const fornax_m1_desc& D, int cus) {
   // one y row per wave.  Cartesian: 8 rows and 64 planes per block (at 192^3 x 12, 2.5 % faster
   // than 32 planes in double, 0.7 % in float; float blocks of 12 or 4 rows at three waves per
   // SIMD: 3 % and 11 % slower).  Spherical (256 x 64 x 128 x 20): double 8 rows and 32 planes
-  // (1 % faster than 16); float 12 rows (every row updated, three waves per SIMD) and 16
-  // planes, 9 % faster than 4 rows and 22 % faster than 8 rows at four waves per SIMD, which
-  // spill registers.
+  // (4 % faster than 16); float 12 rows (every row updated, three waves per SIMD) and 32
+  // planes (2 % faster than 16; 12 rows were 9 % faster than 4 rows and 22 % faster than 8 rows
+  // at four waves per SIMD, which spill registers).
   const bool dbl = D.precision == FORNAX_FP64;
-  if (D.coord == FORNAX_SPHERICAL_LOGR) return dbl ? make_c3_tile(D, 8, 32) : make_c3_tile(D, 12, 16);
+  if (D.coord == FORNAX_SPHERICAL_LOGR) return dbl ? make_c3_tile(D, 8, 32) : make_c3_tile(D, 12, 32);
   return make_c3_tile(D, 8, 64);
 }
 
