@@ -32,10 +32,11 @@
 // interaction update, each face flux with the advective flux v^d U of the upwind face state
 // added (the face's left state where v^d >= 0), from the normal velocity component on the face;
 // the zone-local velocity terms of the flux rows follow in the frequency step.
-// Spherical grids (SPH): the same structure with the geometry of the lane's zone read from the
+// Spherical grids (SPH): the same structure with the geometry of the lane's zone from the
 // per-axis tables (volume-coordinate slopes, face scale factors for the realizability checks and
 // the fluxes, face weights and zone widths for the divergence, proper widths for the optical
-// depth), the geometric source terms after the divergence, theta faces on the polar axis
+// depth; the radial values of the block's columns staged in LDS once, the theta values of the
+// wave's row read by scalar loads), the geometric source terms after the divergence, theta faces on the polar axis
 // closed; a polar-axis ghost row takes the mirrored row of the plane n_phi/2 away (with F_theta
 // and F_phi flipped), and an inflow ghost column the prescribed state with its own scale
 // factors.
