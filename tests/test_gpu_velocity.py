@@ -262,3 +262,29 @@ def test_transparent_shock_long_run(m1):
     lab = to_host(Elm)[0, 0] * h ** 2
     assert com[s + 1] / com[s - 1] > 1.15
     assert abs(lab[s + 1] / lab[s - 1] - 1.0) < 0.03
+
+
+def test_velocity_step_mc_limiter_on_the_3d_kernel(m1):
+    """The MC limiter (the 3-D kernel's instantiation that reads the limiter at run time) in the
+    velocity step on a grid of the 3-D kernel's kind, FP64 and MIXED, against the oracle."""
+    w = case("cart3d_k")
+    vf = wl.face_velocity(w, amp=0.15, seed=3)
+    nu = wl.velocity_edges(w.G)
+    p = problem_of(w, limiter=orc.MC)
+    dt = w.dt if w.dt is not None else orc.max_dt(p, 0.4)
+    E, F, dg, dEm = orc.run_v(p, w.E, w.F, w.kappa, w.sigma, w.B, vf, nu, dt, w.steps, inflow=w.inflow,
+                              want_dEm=True)
+    E0, _, _, _ = oracle_v(w, vf, nu, dt, w.steps)
+    assert np.abs(E - E0).max() > 1e-8 * np.abs(E).max()     # the limiter changes the result
+    for prec in (m1.FP64, m1.MIXED):
+        say(f"case velocity cart3d_k MC prec={prec}")
+        ctx = m1.Context(m1.Config.from_workload(w, precision=prec, limiter=m1.LIMITER_MC))
+        Eg, Fg, dgg = gpu_v(m1, ctx, w, vf, nu, dt, w.steps)
+        e = rel_l1(Eg, Fg, E, F, w.c)
+        say(f"  rel-L1 E {e[0]:.2e} F {e[1]:.2e}; element-wise E {e.pE:.2e} F {e.pF:.2e}")
+        if prec == m1.FP64:
+            check_pointwise(e, True, "cart3d_k MC")
+            assert e[0] <= TOL_FP64 and e[1] <= TOL_FP64
+            assert np.allclose(dgg["dE_matter"], dEm.ravel(), rtol=1e-10, atol=1e-12 * np.abs(E).max())
+        else:
+            assert e[0] <= TOL_MIXED_RUN and e[1] <= TOL_MIXED_RUN
