@@ -11,9 +11,11 @@
 // columns in x and marches along y (2-D).  The thread of column cx recomputes the face
 // x0 - 1 + cx (forward flux and its VJP) and exchanges through LDS; along the march a
 // register ring carries the contributions of the last four faces.  Each tile finalises
-// TXB - 3 columns.  Tiles also cover the two ghost layers on each side: contributions to a
-// ghost zone go to a per-direction ghost buffer that k_adj_fold maps back through the
-// boundary rule (periodic wrap, outflow copy, reflection with the normal flux flipped;
+// TXB - 3 columns.  A direction periodic at both ends (and at least four zones long) has no
+// ghost zones here: its zone indices wrap and its face 0 is face n, so the tiles cover the
+// domain only.  Along any other direction the tiles also cover the two ghost layers on each
+// side: contributions to a ghost zone go to a per-direction ghost buffer that k_adj_fold maps
+// back through the boundary rule (outflow copy, reflection with the normal flux flipped;
 // inflow ghosts are constant, so only their opacity dependence folds).  No atomics: every
 // sum is taken in a fixed order, so the result is deterministic.
 
@@ -38,7 +40,13 @@ struct AdjArgs : StepArgs<S> {
   const S* U1[3 + 1];     // U^{n+1} of the step (E, F_1..F_ND)
   double* gbuf[3];        // ghost adjoints per direction: [side][layer][plane][G][NC+1]
   int gplane[3];          // zones of the plane normal to direction d
+  int wrap[3];            // 1: direction d is periodic at both ends and wraps (no ghosts)
 };
+
+// whether direction d of the grid wraps in the adjoint (periodic at both ends, n >= 4)
+static inline bool adj_wraps(const fornax_m1_desc& D, int d) {
+  return d < D.ndim && D.bc_lo[d] == FORNAX_BC_PERIODIC && D.bc_hi[d] == FORNAX_BC_PERIODIC && D.n[d] >= 4;
+}
 
 struct AdjTile {
   int TXB, W;             // thread columns, finalised columns per tile (TXB - 3)
@@ -72,8 +80,10 @@ __device__ __forceinline__ void load_mu(const AdjArgs<S>& a, int zg, R mu[4]) {
 
 // Three waves per SIMD (at most 168 VGPRs): measured faster on gfx950 than the unconstrained
 // allocation (two waves) despite a few spilled registers.  LIM: the limiter when known at
-// compile time, -1 to read it from the arguments.
-template <typename S, typename R, int DIM, int LIM>
+// compile time, -1 to read it from the arguments.  PER: every direction wraps (a periodic
+// grid), so no index can leave the domain; with it fixed at compile time the kernel fits the
+// register budget without spills.
+template <typename S, typename R, int DIM, int LIM, bool PER>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
 k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -99,12 +109,21 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
   const int tm = Lb / tl.ntx;
   const int n0 = a.n[0];
   const int nM = (DIM >= 2) ? a.n[MD] : 1;
-  const int x0 = -2 + tx * W;
-  const int mbeg = (DIM >= 2) ? -2 + tm * tl.TM : 0;
-  const int mend = (DIM >= 2) ? min(mbeg + tl.TM, nM + 2) : 1;
+  const bool wx = PER || a.wrap[0] != 0;
+  const bool wy = (DIM >= 2) && (PER || a.wrap[MD] != 0);
+  const int x0 = (wx ? 0 : -2) + tx * W;
+  const int mbeg = (DIM >= 2) ? (wy ? 0 : -2) + tm * tl.TM : 0;
+  const int mend = (DIM >= 2) ? min(mbeg + tl.TM, wy ? nM : nM + 2) : 1;
   const int gx = x0 + cx;
-  const bool colin = gx >= 0 && gx < n0;            // column inside the domain
-  const bool fin = cx < W && gx >= -2 && gx < n0 + 2; // this thread finalises (gx, m)
+  // a wrapping direction's zone index taken into [0, n): columns once (they stay fixed), planes
+  // with one step (a block reads planes -3 .. nM + 2, and nM >= 4)
+  auto wrapi = [](int i, int n) { return ((i % n) + n) % n; };
+  auto wrapm = [&](int m) { return wy ? (m < 0 ? m + nM : (m >= nM ? m - nM : m)) : m; };
+  const int gxl = wx ? wrapi(gx, n0) : gx;          // the column's zone (x index)
+  const int hxl = wx ? wrapi(x0 - 3 + cx, n0) : x0 - 3 + cx;   // halo column of threads cx < 3
+  const bool colin = gxl >= 0 && gxl < n0;          // column inside the domain
+  // this thread finalises (gx, m)
+  const bool fin = cx < W && (wx ? gx < n0 : (gx >= -2 && gx < n0 + 2));
   const R dx0 = geo.dx[0];
   const R nux = R(a.dt) * rcp_(dx0);
 
@@ -114,8 +133,8 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
   auto state = [&](int x, int m, R q[4], R& ks) {
     for (int v = 0; v < 4; ++v) q[v] = R(0);
     ks = R(0);
-    if (x < -2 || x > n0 + 1 || m < -2 || m > nM + 1) return;
-    const bool xin = x >= 0 && x < n0, min_ = m >= 0 && m < nM;
+    if (!PER && (x < -2 || x > n0 + 1 || m < -2 || m > nM + 1)) return;
+    const bool xin = PER || (x >= 0 && x < n0), min_ = PER || (m >= 0 && m < nM);
     if (!xin && !min_) return;
     if (!xin) fetch<S, R, false, DIM>(a, geo, 0, x, x, (DIM >= 2 ? m : 0), 0, grp, q, &ks);
     else fetch<S, R, false, DIM>(a, geo, MD < 0 ? 0 : MD, (DIM >= 2 ? m : x), x, (DIM >= 2 ? m : 0), 0, grp, q, &ks);
@@ -131,9 +150,10 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
   }
   const R nuy = (DIM >= 2) ? R(a.dt) * rcp_(geo.dx[MD]) : R(0);
   auto load_plane_w = [&](int p, R q[4], R& ks, R mu[4]) {
-    state(gx, p, q, ks);
+    p = wrapm(p);
+    state(gxl, p, q, ks);
     for (int v = 0; v < 4; ++v) mu[v] = R(0);
-    if (p >= 0 && p < nM) load_mu<S, R, DIM>(a, zgi(gx, p), mu);
+    if (p >= 0 && p < nM) load_mu<S, R, DIM>(a, zgi(gxl, p), mu);
   };
   // march face f (between planes f-1 and f) from window planes f-2 .. f+1 (q0 .. q3), the total
   // opacities and mu of planes f-1, f
@@ -143,7 +163,7 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
     for (int p = 0; p < 4; ++p)
       for (int v = 0; v < 4; ++v) C[p][v] = R(0);
     dkL = dkR = R(0);
-    if (f < 0 || f > nM) return;
+    if (!wy && (f < 0 || f > nM)) return;
     R nu[4] = {R(0), R(0), R(0), R(0)};
     for (int v = 0; v < NC; ++v) nu[v] = nuy * (mu2[v] - mu1[v]);
     R qq[4][4];
@@ -232,8 +252,8 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
         }
         ks = wks[sl(0)];
       } else {
-        state(gx, m, q, ks);
-        if (colin) load_mu<S, R, DIM>(a, zgi(gx, m), mu);
+        state(gxl, m, q, ks);
+        if (colin) load_mu<S, R, DIM>(a, zgi(gxl, m), mu);
       }
       for (int v = 0; v < NC; ++v) {
         pv(v, cx + 3) = q[v];
@@ -241,10 +261,9 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
       }
       pv(NC, cx + 3) = ks;
       if (cx < 3) {
-        const int hx = x0 - 3 + cx;
         R hq[4], hks, hmu[4] = {R(0), R(0), R(0), R(0)};
-        state(hx, m, hq, hks);
-        if (hx >= 0 && hx < n0) load_mu<S, R, DIM>(a, zgi(hx, m), hmu);
+        state(hxl, m, hq, hks);
+        if (hxl >= 0 && hxl < n0) load_mu<S, R, DIM>(a, zgi(hxl, m), hmu);
         for (int v = 0; v < NC; ++v) {
           pv(v, cx) = hq[v];
           pv(NC + 1 + v, cx) = hmu[v];
@@ -259,7 +278,7 @@ k_adjoint(AdjArgs<S> a, Geo<R> geo, AdjTile tl) {
       R fl[4] = {R(0), R(0), R(0), R(0)}, C[4][4], dkL = R(0), dkR = R(0);
       for (int p = 0; p < 4; ++p)
         for (int v = 0; v < 4; ++v) C[p][v] = R(0);
-      if (rowin && f >= 0 && f <= n0) {
+      if (rowin && (wx || (f >= 0 && f <= n0))) {
         R q[4][4];
         for (int o = 0; o < 4; ++o) {
           for (int v = 0; v < NC; ++v) q[o][v] = pv(v, cx + o);
@@ -391,22 +410,22 @@ __device__ __forceinline__ int edge_zone(int k, int n) {
 
 __device__ __forceinline__ bool near_edge(int z, int n) { return z < 2 || z >= n - 2; }
 
-// Fold the ghost-zone adjoints into the zones they copy, both directions in one launch.  One
-// thread per (edge zone along d, plane, group): threads of direction 0 take the zones away
-// from the y edges; a thread of direction 1 whose zone is also near an x edge applies the x
-// fold first, then its own, so that every zone sees the same additions, in the same order,
-// as with one launch per direction.
+// Fold the ghost-zone adjoints into the zones they copy, both directions in one launch (a
+// wrapping direction has none).  One thread per (edge zone along d, plane, group): threads of
+// direction 0 take the zones away from the y edges; a thread of direction 1 whose zone is also
+// near an x edge applies the x fold first, then its own, so that every zone sees the same
+// additions, in the same order, as with one launch per direction.
 template <typename S, int ND>
 __global__ void __launch_bounds__(256) k_adj_fold(AdjArgs<S> a) {
   constexpr int NC = 1 + ND;
   const int G = a.G;
   const int n0 = a.n[0];
   const int n1 = (ND >= 2) ? a.n[1] : 1;
-  const int nx = 4 * a.gplane[0] * G;
+  const int nx = a.wrap[0] ? 0 : 4 * a.gplane[0] * G;
   int id = blockIdx.x * 256 + threadIdx.x;
   int d = 0;
   if (id >= nx) {
-    if (ND < 2) return;
+    if (ND < 2 || a.wrap[1]) return;
     id -= nx;
     d = 1;
     if (id >= 4 * a.gplane[1] * G) return;
@@ -419,10 +438,11 @@ __global__ void __launch_bounds__(256) k_adj_fold(AdjArgs<S> a) {
   // zone (x, y) of this thread
   const int x = (d == 0) ? dst : pidx;
   const int y = (ND < 2) ? 0 : ((d == 0) ? pidx : dst);
-  if (ND >= 2 && d == 0 && near_edge(y, n1)) return;   // folded by the direction-1 thread
+  // folded by the direction-1 thread
+  if (ND >= 2 && d == 0 && !a.wrap[1] && near_edge(y, n1)) return;
   const int zg = (y * n0 + x) * G + grp;
   double acc[4], dka;
-  if (ND >= 2 && d == 1 && near_edge(x, n0) && fold_sum<S, ND>(a, 0, x, y, grp, acc, dka)) {
+  if (ND >= 2 && d == 1 && !a.wrap[0] && near_edge(x, n0) && fold_sum<S, ND>(a, 0, x, y, grp, acc, dka)) {
     for (int v = 0; v < NC; ++v) a.lamo[v][zg] = (S)((double)a.lamo[v][zg] + acc[v]);
     a.dk[zg] = (S)((double)a.dk[zg] + dka);
   }
@@ -437,8 +457,9 @@ static AdjTile make_adj_tile(const fornax_m1_desc& D, int TM, int TXB);
 // Planes per block: a block walks TM + 3 faces along y (three to fill its rings) one after the
 // other, each waiting on loads it has just issued, so the kernel's time is about the number of
 // rounds of block slots times TM + 3.  Take the TM with the least such cost (three blocks of
-// at most four waves per CU: three waves per SIMD), e.g. 7 planes at 256^2 (760 blocks, one
-// round on 256 CUs), measured 8 % faster than 8 planes (660 blocks) and 12 % faster than 4.
+// at most four waves per CU: three waves per SIMD), e.g. 7 planes on the periodic 256^2 grid
+// (740 blocks, one round on 256 CUs); with ghost layers, 7 planes measured 8 % faster than 8
+// (660 blocks) and 12 % faster than 4.
 static int choose_adj_planes(const fornax_m1_desc& D, int TXB, int cus) {
   if (D.ndim < 2) return 1;
   const int G = D.ngroups;
@@ -468,9 +489,10 @@ static AdjTile make_adj_tile(const fornax_m1_desc& D, int TM, int TXB) {
   if (tl.TXB < 4) tl.TXB = 4;
   tl.W = tl.TXB - 3;
   tl.TM = TM;
-  tl.ntx = (D.n[0] + 4 + tl.W - 1) / tl.W;
+  // a wrapping direction's tiles cover its zones, any other's the two ghost layers too
+  tl.ntx = (D.n[0] + (adj_wraps(D, 0) ? 0 : 4) + tl.W - 1) / tl.W;
   const int nM = (D.ndim >= 2) ? D.n[D.ndim - 1] : 1;
-  tl.ntm = (D.ndim >= 2) ? (nM + 4 + TM - 1) / TM : 1;
+  tl.ntm = (D.ndim >= 2) ? (nM + (adj_wraps(D, D.ndim - 1) ? 0 : 4) + TM - 1) / TM : 1;
   tl.nblocks = tl.ntx * tl.ntm;
   tl.xq = tl.nblocks / 8;
   tl.xr = tl.nblocks % 8;
@@ -534,6 +556,7 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
   for (int d = 0; d < 3; ++d) {
     a.gbuf[d] = ctx->adj_gbuf[d];
     a.gplane[d] = ctx->adj_gplane[d];
+    a.wrap[d] = adj_wraps(D, d) ? 1 : 0;
   }
   // tiling: the override read at create, else 256 threads and planes from the CU count
   const int txb = ctx->adj_txb;
@@ -545,20 +568,25 @@ static int launch_adjoint_t(fornax_m1_ctx* ctx, const Geo<R>& geo, const fornax_
   if (lds > 65536) return FORNAX_EUNSUPPORTED;
   // the method's default limiter is a compile-time constant of its own instantiation
   const bool mm = D.limiter == FORNAX_LIMITER_MINMOD;
+  // every direction wrapping (a periodic grid) is an instantiation of its own for 2-D minmod
+  const bool per = a.wrap[0] && a.wrap[1];
+  constexpr int MM = FORNAX_LIMITER_MINMOD;
+  const dim3 gr(tl.nblocks), bl(tl.nthreads);
   if (D.ndim == 1 && mm)
-    hipLaunchKernelGGL((k_adjoint<S, R, 1, FORNAX_LIMITER_MINMOD>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a,
-                       geo, tl);
+    hipLaunchKernelGGL((k_adjoint<S, R, 1, MM, false>), gr, bl, lds, st, a, geo, tl);
   else if (D.ndim == 1)
-    hipLaunchKernelGGL((k_adjoint<S, R, 1, -1>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a, geo, tl);
+    hipLaunchKernelGGL((k_adjoint<S, R, 1, -1, false>), gr, bl, lds, st, a, geo, tl);
+  else if (mm && per)
+    hipLaunchKernelGGL((k_adjoint<S, R, 2, MM, true>), gr, bl, lds, st, a, geo, tl);
   else if (mm)
-    hipLaunchKernelGGL((k_adjoint<S, R, 2, FORNAX_LIMITER_MINMOD>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a,
-                       geo, tl);
+    hipLaunchKernelGGL((k_adjoint<S, R, 2, MM, false>), gr, bl, lds, st, a, geo, tl);
   else
-    hipLaunchKernelGGL((k_adjoint<S, R, 2, -1>), dim3(tl.nblocks), dim3(tl.nthreads), lds, st, a, geo, tl);
+    hipLaunchKernelGGL((k_adjoint<S, R, 2, -1, false>), gr, bl, lds, st, a, geo, tl);
   if (hipGetLastError() != hipSuccess) return FORNAX_EDEVICE;
-  {
-    int nt = 4 * a.gplane[0] * a.G;
-    if (D.ndim >= 2) nt += 4 * a.gplane[1] * a.G;
+  // the ghost adjoints of the directions that do not wrap
+  int nt = a.wrap[0] ? 0 : 4 * a.gplane[0] * a.G;
+  if (D.ndim >= 2 && !a.wrap[1]) nt += 4 * a.gplane[1] * a.G;
+  if (nt > 0) {
     if (D.ndim == 1)
       hipLaunchKernelGGL((k_adj_fold<S, 1>), dim3((nt + 255) / 256), dim3(256), 0, st, a);
     else

@@ -223,6 +223,13 @@ class Context:
             s.F[k] = f.data_ptr()
         return s
 
+    def _point(self, s, E, F, name="state"):
+        """Point the existing State structure s (held by a bound call) at (E, [F])."""
+        t = self._state(E, F, name)
+        s.E = t.E
+        for k in range(3):
+            s.F[k] = t.F[k]
+
     def _coeffs(self, kappa, sigma, B):
         for t, nm in ((kappa, "kappa"), (sigma, "sigma"), (B, "B")):
             self._check_arr(t, nm)
@@ -507,6 +514,7 @@ class Context:
                 raise FornaxError(rc, "fornax_m1_step")
 
         call._keep = (sa, sb, cf)
+        call.src = sa      # the input's structure, which _point may re-aim
         return call
 
     def adjointer(self, U, kappa, sigma, B, dt, lam_in, lam_out, dkappa, inflow=None, stream=None, U1=None):
@@ -538,6 +546,7 @@ class Context:
                 raise FornaxError(rc, "fornax_m1_adjoint")
 
         call._keep = (su, s1, sl, so, cf, U1)
+        call.Un, call.Unp1 = su, s1      # the structures _point may re-aim
         return call
 
     def run(self, E, F, kappa, sigma, B, dt, nsteps, inflow=None, diag=None):
@@ -600,9 +609,12 @@ class M1Steps(torch.autograd.Function):
                B.data_ptr())
         cache = getattr(ctx, "_bwd_cache", None)
         if cache is None or cache[0] != key:
-            # seg[i]: state i of the segment being replayed; seg[n_in] holds the state that ends
-            # it (the next checkpoint, or the final state), so that every adjoint step gets both
-            # U^n and U^{n+1} and none recomputes the step
+            # seg[i]: state i of the segment being replayed.  The segment's first state (its
+            # checkpoint) and the state that closes it (the next checkpoint, or the final state)
+            # are read where they are: the first replay step and adjoint step are pointed at the
+            # checkpoint and the last adjoint step at the closing state, so that every adjoint
+            # step gets both U^n and U^{n+1}, none recomputes the step, and nothing is copied.
+            # seg[0] and seg[K] only hold the bindings' default targets.
             seg = [ctx.empty_state() for _ in range(K + 1)]
             lam = [ctx.empty_state(), ctx.empty_state()]
             dk = torch.empty(ctx.shape, dtype=ctx.dtype, device=ctx.device)
@@ -625,15 +637,21 @@ class M1Steps(torch.autograd.Function):
         for j in reversed(range(len(ckpts))):
             s0, E, F = ckpts[j]
             n_in = min(s0 + ckpt_every, nsteps) - s0
-            for dst, src in ((seg[0], (E, F)), (seg[n_in], ends[j])):
-                dst[0].copy_(src[0])
-                for k in range(len(src[1])):
-                    dst[1][k].copy_(src[1][k])
-            for i in range(n_in - 1):
-                steps[i]()
-            for i in reversed(range(n_in)):
-                adj[i][p]()
-                p ^= 1
+            if n_in > 1:
+                ctx._point(steps[0].src, E, F, "checkpoint")
+            for q in range(2):
+                ctx._point(adj[0][q].Un, E, F, "checkpoint")
+                ctx._point(adj[n_in - 1][q].Unp1, ends[j][0], ends[j][1], "checkpoint")
+            try:
+                for i in range(n_in - 1):
+                    steps[i]()
+                for i in reversed(range(n_in)):
+                    adj[i][p]()
+                    p ^= 1
+            finally:
+                # a later (longer) segment reads U^{n+1} of this step from the replay buffers
+                for q in range(2):
+                    ctx._point(adj[n_in - 1][q].Unp1, seg[n_in][0], seg[n_in][1])
         fctx.m1 = None
         out = lam[p]
         # fresh tensors: the buffers belong to the context's cache

@@ -60,24 +60,43 @@ def one_step_dot(m1, w, precision, seed=3, local=None):
     return lhs, rhs, scale
 
 
-@pytest.mark.parametrize("bc", ["periodic", "outflow", "reflect"])
+# (lower, upper) boundary rules per direction (x, y).  A direction periodic at both ends wraps
+# in the adjoint kernel (no ghost zones); "x_periodic" and "y_periodic" have one wrapping
+# direction and ghost zones along the other.
+_BCS = {
+    "periodic": ((wl.BC_PERIODIC, wl.BC_PERIODIC), (wl.BC_PERIODIC, wl.BC_PERIODIC)),
+    "outflow": ((wl.BC_OUTFLOW, wl.BC_OUTFLOW), (wl.BC_OUTFLOW, wl.BC_OUTFLOW)),
+    "reflect": ((wl.BC_REFLECT, wl.BC_OUTFLOW), (wl.BC_REFLECT, wl.BC_REFLECT)),
+    "x_periodic": ((wl.BC_PERIODIC, wl.BC_OUTFLOW), (wl.BC_PERIODIC, wl.BC_REFLECT)),
+    "y_periodic": ((wl.BC_REFLECT, wl.BC_PERIODIC), (wl.BC_OUTFLOW, wl.BC_PERIODIC)),
+}
+
+
+def _set_bcs(w, bc):
+    lo, hi = _BCS[bc]
+    w.bc_lo = lo + (0,)
+    w.bc_hi = hi + (0,)
+
+
+@pytest.mark.parametrize("bc", list(_BCS))
 def test_one_step_dot_product_2d_fp64(m1, bc):
     w = wl.adjoint2d(n=24, G=3, steps=1)
-    code = {"periodic": wl.BC_PERIODIC, "outflow": wl.BC_OUTFLOW, "reflect": wl.BC_REFLECT}[bc]
-    w.bc_lo = (code, code if bc != "reflect" else wl.BC_OUTFLOW, 0)
-    w.bc_hi = (code, code, 0)
+    _set_bcs(w, bc)
     for local in (None, (slice(None), slice(None), slice(0, 3)), (slice(None), slice(20, 24), slice(None))):
         lhs, rhs, scale = one_step_dot(m1, w, m1.FP64, local=local)
         say(bc, local, lhs, rhs, scale)
         assert abs(lhs - rhs) <= 1e-12 * scale
 
 
-def test_one_step_dot_product_1d_fp64(m1):
+@pytest.mark.parametrize("bc", ["outflow", "periodic"])
+def test_one_step_dot_product_1d_fp64(m1, bc):
     w = wl.slab1d(n=40, G=2)
     w.dt = 0.4 / 40
+    if bc == "periodic":
+        w.bc_lo = w.bc_hi = (wl.BC_PERIODIC,) * 3
     for local in (None, (slice(None), slice(None), slice(0, 3)), (slice(None), slice(None), slice(36, 40))):
         lhs, rhs, scale = one_step_dot(m1, w, m1.FP64, local=local)
-        say("1d", local, lhs, rhs, scale)
+        say("1d", bc, local, lhs, rhs, scale)
         assert abs(lhs - rhs) <= 1e-12 * scale
 
 
@@ -153,7 +172,7 @@ def test_adjoint_with_given_next_state(m1, precision):
     assert torch.equal(a[0], c[0]) and not torch.equal(a[2], c[2])
 
 
-@pytest.mark.parametrize("bc", ["periodic", "reflect"])
+@pytest.mark.parametrize("bc", ["periodic", "reflect", "x_periodic", "y_periodic"])
 def test_adjoint_independent_of_tiling(m1, bc):
     """The adjoint kernel's blocks of TXB zone columns by TM planes (FORNAX_M1_ADJ_TILE="TXB,TM" when
     the context is created; the default takes TM from the CU count): one plane per block, the fewest columns, tiles
@@ -168,6 +187,8 @@ def test_adjoint_independent_of_tiling(m1, bc):
     if bc == "reflect":
         w.bc_lo = (wl.BC_REFLECT, wl.BC_OUTFLOW, 0)
         w.bc_hi = (wl.BC_OUTFLOW, wl.BC_REFLECT, 0)
+    elif bc != "periodic":
+        _set_bcs(w, bc)
     ctx = m1.Context(m1.Config.from_workload(w, precision=m1.FP64))
     dtp = ctx.dtype
     rng = np.random.default_rng(9)
@@ -370,6 +391,32 @@ def test_checkpoint_interval_does_not_change_gradient(m1):
     _, gkA, gEA = window_loss_grad(m1, w, m1.FP64, 12)
     assert np.array_equal(gk1, gk8) and np.array_equal(gE1, gE8)
     assert np.array_equal(gk1, gkA) and np.array_equal(gE1, gEA)
+
+
+def test_backward_replay_reused_across_runs(m1):
+    """One context and one set of coefficient tensors: the replay's bound calls are kept between
+    backward passes and pointed at each run's checkpoints.  Runs with different segment mixes
+    in a row (8 + 4, 8 + 8, 8 + 4 steps) each give a fresh context's gradient bit for bit."""
+    w12 = wl.adjoint2d(n=24, G=2, steps=12, window=8)
+    ix, iy, ww = w12.extra["window"]
+    ctx = m1.Context(m1.Config.from_workload(w12, precision=m1.FP64))
+    dtp = ctx.dtype
+    k = to_dev(w12.kappa, dtp).requires_grad_(True)
+    s, B = to_dev(w12.sigma, dtp), to_dev(w12.B, dtp)
+
+    def run(nsteps):
+        k.grad = None
+        E0 = to_dev(w12.E, dtp).requires_grad_(True)
+        F0 = [to_dev(f, dtp) for f in w12.F]
+        EN, _ = m1.run_differentiable(ctx, E0, F0, k, s, B, w12.dt, nsteps, ckpt_every=8)
+        EN[0, iy:iy + ww, ix:ix + ww, :].sum().backward()
+        torch.cuda.synchronize()
+        return to_host(k.grad), to_host(E0.grad)
+
+    for n in (12, 16, 12):
+        gk, gE = run(n)
+        _, rk, rE = window_loss_grad(m1, wl.adjoint2d(n=24, G=2, steps=n, window=8), m1.FP64, 1)
+        assert np.array_equal(gk, rk) and np.array_equal(gE, rE), n
 
 
 def test_mixed_gradient_close_to_fp64_oracle(m1):
