@@ -491,6 +491,7 @@ int fornax_m1_create(const fornax_m1_desc* desc, fornax_m1_ctx** out) {
   // the 3-D Cartesian kernel where the grid qualifies (FORNAX_M1_C3="0" disables it, "NR,TM"
   // picks its tiling)
   ctx->c3 = choose_c3_tile(*desc, cus);
+  ctx->c3v = choose_c3_vel_tile(*desc, cus);
   if (const char* env = std::getenv("FORNAX_M1_C3")) {
     int nr = 0, tm = 0;
     if (env[0] == '0' && env[1] == 0) ctx->c3 = fm1::C3Tile{};

@@ -192,6 +192,7 @@ struct fornax_m1_ctx {
   fm1::Tile tile_v1;           // one group per lane (arrays not aligned to pairs of groups)
   fm1::RowsTile rows;          // the whole-zone LDS kernel when nblocks > 0 (2-D, 16 groups)
   fm1::C3Tile c3;              // the 3-D Cartesian kernel when nblocks > 0
+  fm1::C3Tile c3v;             // the same kernel's tiling for Step 1 of the velocity step
   int cus;                     // compute units of the device (0 if unknown)
   fm1::Tile last_tile[1];      // the tile of the last step launch (for inspection)
   // reduction scratch (one partial per block of the step kernel)

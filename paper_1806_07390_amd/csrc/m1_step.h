@@ -34,9 +34,11 @@ int launch_rows(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hip
 // (m1_step_3d.hip): a tile with nblocks = 0 when the grid does not qualify (3-D, groups a
 // multiple of 4; Cartesian without inflow or axis boundaries, or spherical with inflow at the
 // inner radius and polar axes over a periodic phi of even length; NR 6, 8 or 12 in double,
-// 4, 8 or 16 in float, 8 (double) or 4 and 8 (float) on spherical grids).
+// 4, 8 or 16 in float, 8 (double) or 4, 8 and 12 (float) on spherical grids).
 C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM);
+// the step's tiling, and Step 1 of the velocity step's (planes per block from the CU count)
 C3Tile choose_c3_tile(const fornax_m1_desc& D, int cus);
+C3Tile choose_c3_vel_tile(const fornax_m1_desc& D, int cus);
 template <typename S>
 int launch_c3(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, hipStream_t st);
 // Step 1 of the velocity step on the same kernel (3-D Cartesian grids it takes; StepArgs without

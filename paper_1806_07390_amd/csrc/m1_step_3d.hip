@@ -43,6 +43,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "m1_device.h"
@@ -722,17 +723,49 @@ C3Tile make_c3_tile(const fornax_m1_desc& D, int NR, int TM) {
   return tl;
 }
 
+// Planes per block: a block walks its TM planes (and about three planes' worth of start-up: the
+// first planes' loads and the face below its first plane, the last deferred update) one after
+// the other, so the kernel takes about the number of rounds of block slots times TM + 3.  The
+// tile of NR rows with the least such cost (ties: the longer tile), the slots from the shape's
+// W waves per SIMD and the CU count.  Measured on MI355X this picks the fastest of the lengths
+// tried in each case: 192 planes at 192^3 x 12 FP64 (one tile along z: 2.6 % faster than 64
+// and 1 % than 96), 64 in MIXED (7 % faster than 96, 1 % than 32), 128 on the 256 x 64 x 128 x
+// 20 spherical grid in FP64 (1 % faster than 32 and 64) and 32 in MIXED (12 % faster than 64).
+static C3Tile c3_tile_by_rounds(const fornax_m1_desc& D, int NR, int W, int cus) {
+  const int per_cu = std::max(1, 4 * W / NR);
+  const long slots = (long)per_cu * (cus > 0 ? cus : 256);
+  C3Tile best{};
+  double best_cost = 0.0;
+  for (int TM = std::min(8, D.n[2]); TM <= D.n[2]; ++TM) {
+    const C3Tile t = make_c3_tile(D, NR, TM);
+    if (t.nblocks <= 0) continue;
+    const double cost = (double)((t.nblocks + slots - 1) / slots) * (TM + 3);
+    if (best.nblocks <= 0 || cost <= best_cost) {
+      best = t;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 C3Tile choose_c3_tile(const fornax_m1_desc& D, int cus) {
-  (void)cus;
-  // one y row per wave.  Cartesian: 8 rows and 64 planes per block (at 192^3 x 12, 2.5 % faster
-  // than 32 planes in double, 0.7 % in float; float blocks of 12 or 4 rows at three waves per
-  // SIMD: 3 % and 11 % slower).  Spherical (256 x 64 x 128 x 20): double 8 rows and 32 planes
-  // (4 % faster than 16); float 12 rows (every row updated, three waves per SIMD) and 32
-  // planes (2 % faster than 16; 12 rows were 9 % faster than 4 rows and 22 % faster than 8 rows
-  // at four waves per SIMD, which spill registers).
+  // one y row per wave: 8 rows (spherical grids in float: 12, every row updated at three waves
+  // per SIMD).  Measured at 192^3 x 12 (Cartesian) and 256 x 64 x 128 x 20 (spherical): float
+  // Cartesian blocks of 12 or 4 rows at three waves per SIMD 3 % and 11 % slower than 8 rows;
+  // spherical float 12 rows 9 % faster than 4 rows and 22 % faster than 8 rows at four waves
+  // per SIMD, which spill registers.  Waves per SIMD as launch_c3 instantiates the shapes:
+  // double 2, float Cartesian 4, float spherical 3.
   const bool dbl = D.precision == FORNAX_FP64;
-  if (D.coord == FORNAX_SPHERICAL_LOGR) return dbl ? make_c3_tile(D, 8, 32) : make_c3_tile(D, 12, 32);
-  return make_c3_tile(D, 8, 64);
+  const bool sph = D.coord == FORNAX_SPHERICAL_LOGR;
+  return c3_tile_by_rounds(D, (sph && !dbl) ? 12 : 8, dbl ? 2 : (sph ? 3 : 4), cus);
+}
+
+// Step 1 of the velocity step: 8 rows at two waves per SIMD in double, 12 rows at three in
+// float (launch_c3_vel)
+C3Tile choose_c3_vel_tile(const fornax_m1_desc& D, int cus) {
+  const bool dbl = D.precision == FORNAX_FP64;
+  if (D.coord != FORNAX_CARTESIAN) return C3Tile{};
+  return c3_tile_by_rounds(D, dbl ? 8 : 12, dbl ? 2 : 3, cus);
 }
 
 template <typename S>
@@ -780,19 +813,19 @@ template int launch_c3<double>(fornax_m1_ctx*, const Geo<double>&, const StepArg
 template int launch_c3<float>(fornax_m1_ctx*, const Geo<float>&, const StepArgs<float>&, hipStream_t);
 
 // Step 1 of the velocity step (transport with the advective fluxes, no interaction update, no
-// diagnostics) on 3-D Cartesian grids of the kernel's kind: 8-row blocks of 64 planes in
-// double, 12-row blocks (three waves per SIMD) in float.
+// diagnostics) on 3-D Cartesian grids of the kernel's kind: 8-row blocks in double, 12-row
+// blocks (three waves per SIMD) in float, planes per block chosen at create.
 template <typename S>
 int launch_c3_vel(fornax_m1_ctx* ctx, const Geo<S>& geo, const StepArgs<S>& a, const VelArgs<S>& va, hipStream_t st) {
   const fornax_m1_desc& D = ctx->desc;
   if (D.coord != FORNAX_CARTESIAN || D.ndim != 3) return FORNAX_EUNSUPPORTED;
   if (a.src || a.dEm || a.p_energy || a.Ea) return FORNAX_EUNSUPPORTED;
   constexpr bool dbl = sizeof(S) == 8;
-  const C3Tile tl = make_c3_tile(D, dbl ? 8 : 12, 64);
-  if (tl.nblocks <= 0) return FORNAX_EUNSUPPORTED;
+  const C3Tile tl = ctx->c3v;
+  constexpr int NRV = dbl ? 8 : 12, WV = dbl ? 2 : 3;
+  if (tl.nblocks <= 0 || tl.NR != NRV) return FORNAX_EUNSUPPORTED;
   const bool mm = a.limiter == FORNAX_LIMITER_MINMOD && a.wavespeed == FORNAX_WAVESPEED_LIGHT;
   dim3 grid(tl.nblocks), block(64 * tl.NR);
-  constexpr int NRV = dbl ? 8 : 12, WV = dbl ? 2 : 3;
   if (mm)
     hipLaunchKernelGGL((k_step_3d<S, NRV, WV, FORNAX_LIMITER_MINMOD, false, true, true>), grid, block, 0, st, a, geo, tl,
                        va);
