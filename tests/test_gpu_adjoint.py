@@ -88,6 +88,22 @@ def test_one_step_dot_product_2d_fp64(m1, bc):
         assert abs(lhs - rhs) <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("n0,n1", [(4, 4), (5, 7), (3, 6)])
+def test_one_step_dot_product_small_periodic(m1, n0, n1):
+    """Periodic grids at the smallest sizes: a direction of four or more zones wraps in the
+    adjoint kernel (no ghost zones; its stencils reach around the whole axis), one of three
+    keeps its ghost zones and the fold; the dot-product identity holds on each."""
+    w = wl.adjoint2d(n=max(n0, n1), G=3, steps=1)
+    cut = lambda a: np.ascontiguousarray(a[..., :n1, :n0, :])
+    w.E, w.kappa, w.sigma, w.B = cut(w.E), cut(w.kappa), cut(w.sigma), cut(w.B)
+    w.F = [cut(f) for f in w.F]
+    w.n = (n0, n1, 1)
+    for local in (None, (slice(None), slice(0, 1), slice(None))):
+        lhs, rhs, scale = one_step_dot(m1, w, m1.FP64, local=local)
+        say("small periodic", n0, n1, local, lhs, rhs, scale)
+        assert abs(lhs - rhs) <= 1e-12 * scale
+
+
 @pytest.mark.parametrize("bc", ["outflow", "periodic"])
 def test_one_step_dot_product_1d_fp64(m1, bc):
     w = wl.slab1d(n=40, G=2)
